@@ -1,0 +1,223 @@
+"""Benchmark of the discrete flow mapping hot path on one MI355X.
+
+One step = the whole path on the 3072-tetrahedron box (8x8x8 Kuhn cells, jitter
+0.15h, piecewise-linear position basis x Legendre momentum basis of degree 8,
+12-point Gauss rule per cell, mu = 0.05, walls R = 0.9, Gaussian patch source):
+    mesh build -> assembly of B -> source projection -> solve (I - B) rho = rho0
+to a relative residual of 1e-8 (FP64 GMRES).  Inputs are resident in HBM before
+the timed region starts.
+
+Prints ONE JSON line (rank 0).  `value` is B-assembly face-pair blocks per
+second (12 blocks per tet) over the timed steps; the solve time per right-hand
+side is reported beside it.  `roofline` describes the kernel that takes the most
+time per step; `cpu_baseline` is the CPU oracle timed on a bounded sample of the
+same workload on this host (before the GPU is touched).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "B-assembly face-pair blocks/s; (I-B)rho solve ms/RHS at 1e-8 residual vs plain FP64"
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--rule", choices=["seam", "paper"], default="seam")
+    ap.add_argument("--restart", type=int, default=50)
+    ap.add_argument("--cpu-tets", type=int, default=24, help="tets in the oracle's timed sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true", help="only run a plain device copy of known size")
+    return ap.parse_args()
+
+
+# --------------------------------------------------------------------------- CPU oracle baseline
+
+_ORACLE = {}
+
+
+def _oracle_init(verts, tets, refl, rule):
+    os.environ["OMP_NUM_THREADS"] = "1"
+    from oracle import assemble as oa
+    from oracle import mesh as om
+    _ORACLE["mesh"] = om.build_mesh(verts, tets, refl)
+    _ORACLE["bs"] = oa.Basis(1, 0, 8, 12, rule)
+
+
+def _oracle_tet(args):
+    j, mu = args
+    from oracle import assemble as oa
+    oa.assemble(_ORACLE["mesh"], _ORACLE["bs"], mu, tets=[j])
+    return 12
+
+
+def cpu_baseline(prob, rule, ntets):
+    """Blocks/s of the unmodified oracle on `ntets` sampled tets, one process per core."""
+    import multiprocessing as mp
+
+    import numpy as np
+    cores = min(16, len(os.sched_getaffinity(0)))
+    sample = np.random.default_rng(6).choice(prob.nt, ntets, replace=False)
+    ctx = mp.get_context("fork")
+    with ctx.Pool(cores, initializer=_oracle_init, initargs=(prob.verts, prob.tets, prob.refl, rule)) as pool:
+        pool.map(_oracle_tet, [(int(sample[0]), prob.mu)] * cores)      # warm every worker
+        t0 = time.perf_counter()
+        blocks = sum(pool.map(_oracle_tet, [(int(j), prob.mu) for j in sample], chunksize=1))
+        dt = time.perf_counter() - t0
+    return {"value": blocks / dt, "unit": "blocks/s", "cores": cores, "kind": "oracle",
+            "sample": f"{ntets} tets ({blocks} blocks) drawn with seed 6 from the same 3072-tet box, "
+                      f"FP64 NumPy oracle, {cores} worker processes, {dt:.1f} s"}
+
+
+# --------------------------------------------------------------------------- GPU path
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (--gpus {args.gpus} requested); "
+              "the multi-GPU sharding of the path is described in DESIGN.md, not implemented.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+
+    import synth
+    prob = synth.problem_c2()
+    rule = 1 if args.rule == "seam" else 0
+    base = None
+    if not args.no_cpu_baseline and not args.copy_calib:
+        base = cpu_baseline(prob, rule, args.cpu_tets)
+
+    import torch
+
+    from paper_1608_04607_amd import dfm
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    if args.copy_calib:
+        # plain copy of 1 GiB for calibrating the HBM byte counters
+        x = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": x.numel() * 8, "copy_bytes_written": y.numel() * 8, "launches": 5}))
+        return
+
+    verts = torch.tensor(prob.verts, device=dev)
+    tets = torch.tensor(prob.tets, device=dev)
+    refl = torch.tensor(prob.refl, device=dev)
+    mu = torch.tensor(prob.mu, device=dev)
+    src = (0.0, 0.5, 0.5, 0.1)
+    torch.cuda.synchronize()
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    def step(record):
+        e = [ev() for _ in range(5)]
+        e[0].record(stream)
+        mesh = dfm.Mesh(verts, tets, refl=refl)
+        e[1].record(stream)
+        op = dfm.Operator(mesh, mu, prob.pos_order, dfm.LEGENDRE, prob.mom_degree, prob.quad_n, rule=rule)
+        e[2].record(stream)
+        rho0 = op.source_plane(0, 0.0, profile=1, params=src)
+        e[3].record(stream)
+        rho, info = op.solve(rho0, method="gmres", rtol=1e-8, restart=args.restart, max_iter=20000)
+        e[4].record(stream)
+        if record is not None:
+            record.append((e, info, op.nodes, op.nblocks, op.K, op.ndof))
+        op.close()
+        mesh.close()
+        return rho
+
+    for _ in range(args.warmup):
+        step(None)
+    torch.cuda.synchronize()
+    recs = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(recs)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    phase = np.array([[r[0][i].elapsed_time(r[0][i + 1]) for i in range(4)] for r in recs])  # ms
+    t_mesh, t_asm, t_src, t_solve = phase.mean(axis=0)
+    info = recs[-1][1][0]
+    nodes, nblocks, K, ndof = recs[-1][2:]
+    blocks_per_s = nblocks * args.steps / (phase[:, 1].sum() / 1e3)
+
+    # SpMV kernel: one dfm_apply launch per call, timed with events on the same stream
+    op_mesh = dfm.Mesh(verts, tets, refl=refl)
+    op = dfm.Operator(op_mesh, mu, prob.pos_order, dfm.LEGENDRE, prob.mom_degree, prob.quad_n, rule=rule)
+    x = torch.rand(ndof, dtype=torch.float64, device=dev)
+    for _ in range(3):
+        op.apply(x)
+    e0, e1 = ev(), ev()
+    nrep = 20
+    e0.record(stream)
+    for _ in range(nrep):
+        op.apply(x)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_spmv = e0.elapsed_time(e1) / nrep
+    op.close()
+    op_mesh.close()
+
+    flops_asm = 2.0 * nodes * K * K
+    asm_tflops = flops_asm / (t_asm / 1e3) / 1e12
+    spmv_bytes = 8.0 * (12 * (ndof // (4 * K)) * K * K + 2 * ndof)
+    spmv_gbs = spmv_bytes / (t_spmv / 1e3) / 1e9
+    t_spmv_step = t_spmv * info[0]
+    roof_asm = {"kernel": "k_assemble", "bound": "mfma", "achieved": asm_tflops, "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": asm_tflops / FP64_PEAK_TFLOPS, "traffic": None,
+                "algorithmic": f"2*Q*K^2 flop per block, Q summed over blocks = {nodes}, K = {K}"}
+    roof_spmv = {"kernel": "k_spmv", "bound": "hbm", "achieved": spmv_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                 "frac": spmv_gbs / HBM_PEAK_GBS, "traffic": None,
+                 "algorithmic": "8*(12*N*K^2 + 2*ndof) bytes per launch (B once, x and y once)"}
+    dominant, other = (roof_asm, roof_spmv) if t_asm >= t_spmv_step else (roof_spmv, roof_asm)
+    out = {
+        "metric": METRIC,
+        "value": blocks_per_s,
+        "unit": "blocks/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"box8x8x8-kuhn-3072tets-jitter0.15_P1xLegendreD8_n12_{args.rule}-rule"
+                               "_mu0.05_R0.9_gauss-patch_gmres1e-8",
+                   "tets": int(prob.nt), "blocks": int(nblocks), "K": int(K), "ndof": int(ndof),
+                   "quadrature_directions": int(nodes)},
+        "phase_ms": {"mesh_build": t_mesh, "assemble": t_asm, "source": t_src, "solve": t_solve},
+        "solve_ms_per_rhs": t_solve,
+        "solve_iters": info[0],
+        "solve_restarts": info[1],
+        "solve_relres": info[2],
+        "solve_precision": "fp64",
+        "spmv_ms": t_spmv,
+        "roofline": dominant,
+        "roofline_other": other,
+        "cpu_baseline": base,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,180 @@
+/*
+ * dfm.h -- C ABI of the MI355X discrete flow mapping (DFM) library.
+ *
+ * Discrete flow mapping on tetrahedral meshes (Bajars, Chappell, Sondergaard,
+ * Tanner): a boundary phase-space density rho(s, p) on the faces of every
+ * tetrahedron is transported straight across each tetrahedron, attenuated by
+ * exp(-mu L) over the chord length L, and handed to the neighbour (or reflected
+ * back with a wall coefficient R).  The transfer operator B is discretised by
+ * Galerkin projection (Sec. 3.2, Eq. Bapprox / B4DInt) onto an orthonormal
+ * position basis per face times an orthogonal-polynomial momentum basis, and the
+ * stationary density solves (I - B) rho = rho0 (Sec. 2, Eq. NSum / GovIE).
+ *
+ * Conventions shared by every entry point
+ *   - Every call returns a dfm_status; DFM_OK (0) on success, a negative code on
+ *     failure, with a message available from dfm_last_error() (per thread).
+ *   - Array arguments marked "device" are caller-owned device pointers to
+ *     contiguous row-major memory; the library never frees or retains them
+ *     beyond the call.  Arguments marked "host" are host pointers.
+ *   - Opaque handles (dfm_mesh, dfm_op) own the device memory they allocate
+ *     until the matching *_destroy call.  An operator refers to the mesh it was
+ *     assembled on: destroy the operator first.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     All work is enqueued on it.  Calls that must report data-dependent
+ *     errors or solver statistics synchronise that stream before returning.
+ *   - Mesh numbering: face l of tetrahedron j is the face opposite its local
+ *     vertex l.  Slot 4*j + l carries the density entering tet j through face l.
+ *   - Unknowns are ordered rho[rhs][slot][p][k], p = position function of the
+ *     face (1 or 3), k = momentum function (see dfm_basis); ndof = 4*nt*K with
+ *     K = P*M.
+ *   - The face frame of (tet j, face l) has its origin at the face vertex with
+ *     the lowest global id, x towards the next-lowest, z the unit normal into tet
+ *     j, y = z x x (Sec. 3.3 fixes origin, x and z only up to this choice).
+ */
+#ifndef DFM_H
+#define DFM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int dfm_status;
+#define DFM_OK 0
+#define DFM_E_INVALID (-1)     /* bad argument, size or shape                          */
+#define DFM_E_MESH (-2)        /* face in more than two tets, zero/NaN volume, bad id   */
+#define DFM_E_NOMEM (-3)       /* device allocation failed                             */
+#define DFM_E_HIP (-4)         /* a HIP runtime call failed                             */
+#define DFM_E_NOCONV (-5)      /* solver stopped at max_iter above the tolerance        */
+#define DFM_E_UNSUPPORTED (-6) /* request outside what is implemented (see call doc)   */
+#define DFM_E_NUMERIC (-7)     /* NaN/Inf produced, or a cell table overflowed          */
+
+typedef struct dfm_mesh_s *dfm_mesh;
+typedef struct dfm_op_s *dfm_op;
+
+/* Discretisation (Sec. 3.1 product basis; Sec. 3.4 quadrature). */
+typedef struct {
+  int pos_order;  /* 0: orthonormal piecewise constant per face, 1/sqrt|face| (Sec. 3.1);
+                     1: orthonormal linear per face (the higher-order option of Sec. 4.1):
+                        1/sqrt(A), sqrt(6/A)(l1-l0), sqrt(2/A)(3 l2-1), barycentrics of the
+                        face's vertices in increasing global id                          */
+  int mom_family; /* 0: tensor Legendre p_a(2cos(theta)-1) p_b(phi/pi-1), p_a = sqrt(2a+1)P_a,
+                        ordered t = a+b = 0..D then b = 0..t;
+                     1: Zernike Z_n^m(sin(theta), phi) of Sec. 3.1, ordered n = 0..D then
+                        m = -n, -n+2, ..., n                                             */
+  int mom_degree; /* total degree D (the paper's N_p), 0..16; M = (D+1)(D+2)/2          */
+  int quad_n;     /* Gauss-Legendre points per dimension per quadrature cell, 1..32     */
+  int rule;       /* 0: the seven direction regions of Sec. 3.4 (four reach each face);
+                     1: those regions cut at the momentum-basis seams and around both
+                        poles, each cell touching a pole fanned from it                 */
+  int dtype;      /* 0: FP64 assembly and storage of B (the only value implemented)     */
+} dfm_basis;
+
+/* Solver options for (I - B) rho = rho0 (Sec. 2, Eq. NSum / GovIE). */
+typedef struct {
+  int method;     /* 0: Neumann partial sums (Eq. NSum); 1: restarted GMRES             */
+  int restart;    /* GMRES restart length (Krylov vectors kept), 1..200                 */
+  int max_iter;   /* total iteration cap (operator applications)                        */
+  double rtol;    /* stop when ||rho0 - (I-B) rho||_2 <= rtol ||rho0||_2                */
+  int precision;  /* 0: FP64 throughout (the only value implemented)                   */
+} dfm_solve_opts;
+
+typedef struct {
+  int iters;      /* operator applications used                                        */
+  int restarts;   /* GMRES restarts (0 for Neumann)                                     */
+  double relres;  /* final true relative residual                                      */
+} dfm_solve_info;
+
+/* Build face adjacency and per-face geometry (Sec. 2: the mesh, the faces that
+ * carry the density and the neighbour a ray enters).
+ *   verts  device f64 [nv][3] vertex coordinates
+ *   tets   device i64 [nt][4] global vertex ids (0 <= id < nv, nv <= 2^21)
+ *   refl   device f64 [nt][4] reflection coefficient R of face l of tet j, used on
+ *          boundary faces only (R = 0 makes an open/absorbing face); NULL -> all 1
+ *   c, rho_f  device f64 [nt] phase velocity and fluid density, or NULL (-> 1).
+ *          They enter B only through the impedance contrast of Sec. 3.3 (Snell's
+ *          law, transmission probability); non-uniform values -> DFM_E_UNSUPPORTED.
+ *          With uniform values every interior face transmits with probability 1.
+ *   out    receives the handle.
+ * Errors: DFM_E_INVALID (sizes), DFM_E_MESH (a face in three or more tets, a
+ * vertex id out of range, a tet with zero or NaN volume).  Synchronises `stream`. */
+dfm_status dfm_mesh_build(const double *verts, int64_t nv, const int64_t *tets, int64_t nt,
+                          const double *refl, const double *c, const double *rho_f,
+                          void *stream, dfm_mesh *out);
+void dfm_mesh_destroy(dfm_mesh mesh);
+
+/* Sizes of a mesh: number of tets and of boundary faces (host outputs, may be NULL). */
+dfm_status dfm_mesh_info(dfm_mesh mesh, int64_t *nt, int64_t *n_boundary);
+
+/* Copy the mesh tables out (for inspection and tests), any pointer may be NULL:
+ *   nbr   device i32 [nt][4]  slot 4*i+l'' of the other copy of the face, -1 on the boundary
+ *   area  device f64 [nt][4]
+ *   frame device f64 [nt][4][3][3] rows x, y, z of the face frame (z into the tet)
+ *   vol   device f64 [nt] */
+dfm_status dfm_mesh_export(dfm_mesh mesh, int32_t *nbr, double *area, double *frame, double *vol,
+                           void *stream);
+
+/* Assemble B (Sec. 3.2-3.4): for every tet j and ordered face pair (l_in -> l_out),
+ * l_in != l_out, the K x K block
+ *   B = w (I_P kron G^-1) sum_q W_q S_q[p',p] psi'_k'(d'_q) psi_k(d_q)
+ * where q runs over the quadrature directions d of the block's cells with flux
+ * weight W (cos(theta) dOmega), S is the analytic integral over the start points
+ * whose ray leaves through l_out of b'_p'(exit point) b_p(start) exp(-mu_j L),
+ * psi / psi' the momentum basis in the inbound / destination face frame
+ * (d' = d when transmitted, its mirror image when reflected), w = 1 (interior)
+ * or R (boundary) and G the momentum Gram matrix under cos(theta) dOmega.
+ *   mu   device f64 [nt] damping per unit length (>= 0)
+ * Errors: DFM_E_INVALID / DFM_E_UNSUPPORTED on bad basis fields, DFM_E_NOMEM,
+ * DFM_E_NUMERIC if a block's cell table overflows.  Synchronises `stream`. */
+dfm_status dfm_assemble(dfm_mesh mesh, const dfm_basis *basis, const double *mu, void *stream,
+                        dfm_op *out);
+void dfm_op_destroy(dfm_op op);
+
+/* Operator sizes (host outputs, may be NULL): unknowns, K, blocks (12*nt),
+ * quadrature directions summed over all blocks, bytes of B. */
+dfm_status dfm_op_info(dfm_op op, int64_t *ndof, int64_t *K, int64_t *nblocks, int64_t *nodes,
+                       int64_t *bytes);
+
+/* Copy B out: blocks device f64 [nt][4 (l_out)][3 (l_in ascending, != l_out)][K][K]
+ * (row = destination unknown (p',k'), column = source unknown (p,k)) and dest
+ * device i32 [nt][4], the slot that receives what leaves tet j through face l_out. */
+dfm_status dfm_op_export(dfm_op op, double *blocks, int32_t *dest, void *stream);
+
+/* y = B x (transpose = 0) or y = B^T x (transpose = 1) for nrhs right-hand sides,
+ * x and y device f64 [nrhs][ndof], not aliased. */
+dfm_status dfm_apply(dfm_op op, const double *x, double *y, int nrhs, int transpose, void *stream);
+
+/* Solve (I - B) rho = rho0 for nrhs right-hand sides, one after the other.
+ *   rho0, rho  device f64 [nrhs][ndof]; info host [nrhs] or NULL.
+ * Returns DFM_E_NOCONV (rho holds the last iterate) if any right-hand side did
+ * not reach opts->rtol within opts->max_iter.  Synchronises `stream`. */
+dfm_status dfm_solve(dfm_op op, const double *rho0, double *rho, int nrhs, const dfm_solve_opts *opts,
+                     dfm_solve_info *info, void *stream);
+
+/* Project sources onto the basis (Galerkin in ds cos(theta)dOmega, as the initial
+ * densities of Sec. 4 are projected onto Eq. FBApprox).
+ *
+ * dfm_source_points: isotropic point sources on the boundary, rho0 = flux *
+ *   delta(s - s0) / pi (unit flux per source), one right-hand side per point.
+ *     xyz  device f64 [ns][3], each on a boundary face (|distance| <= 1e-12 * size)
+ *     rho0 device f64 [ns][ndof] (overwritten)
+ *   DFM_E_INVALID if a point lies on no boundary face.
+ * dfm_source_plane: one right-hand side on the boundary faces lying in the plane
+ *   x[axis] == value: rho0 = flux * sigma(s) * (3/(2 pi)) cos(theta), with
+ *   sigma = 1/(total area of those faces) (profile 0) or the unit Gaussian
+ *   exp(-|s-c|^2/(2 s^2))/(2 pi s^2), params (host) = {cx, cy, cz, s} (profile 1).
+ *     rho0 device f64 [ndof] (overwritten) */
+dfm_status dfm_source_points(dfm_op op, const double *xyz, int64_t ns, double flux, double *rho0,
+                             void *stream);
+dfm_status dfm_source_plane(dfm_op op, int axis, double value, int profile, const double *params,
+                            double flux, double *rho0, void *stream);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *dfm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DFM_H */

@@ -1,0 +1,97 @@
+// Application of the block-sparse B (Sec. 2: B couples only the faces of one tet
+// to the slots its rays enter next, so the matrix is 12 dense K x K blocks per tet).
+//
+// Storage: block (j, l_out, s) is column-major K x K at ((4j + l_out)*3 + s)*K*K;
+// s enumerates l_in != l_out in increasing order.  Block row (j, l_out) writes
+// exactly one destination slot dest[4j + l_out] (a bijection of slots), so the
+// forward product needs no atomics: one thread per destination unknown streams the
+// 3K columns of its block row (consecutive threads read consecutive doubles).
+#include <hip/hip_runtime.h>
+
+#include "dfm_internal.h"
+
+namespace dfm {
+
+namespace {
+
+__device__ inline int in_face(int l_out, int s) { return s < l_out ? s : s + 1; }
+
+// y[dest(br)][row] = alpha * v[dest(br)][row] + beta * sum_{s,col} B[br,s][col][row] x[4j+l_in(s)][col]
+// (v may be null when alpha == 0).
+__global__ void k_spmv(const double *__restrict__ B, const int32_t *__restrict__ dest, int64_t nrows, int K,
+                       const double *__restrict__ x, const double *__restrict__ v, double *__restrict__ y,
+                       double alpha, double beta) {
+  int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g >= nrows) return;
+  int64_t br = g / K;
+  int row = (int)(g - br * K);
+  int64_t j = br >> 2;
+  int l_out = (int)(br & 3);
+  const int64_t KK = (int64_t)K * K;
+  double acc = 0.0;
+  for (int s = 0; s < 3; ++s) {
+    const double *Bb = B + (br * 3 + s) * KK + row;
+    const double *xs = x + (4 * j + in_face(l_out, s)) * (int64_t)K;
+#pragma unroll 8
+    for (int col = 0; col < K; ++col) acc = fma(Bb[(int64_t)col * K], xs[col], acc);
+  }
+  int64_t o = (int64_t)dest[br] * K + row;
+  double r = beta * acc;
+  if (v) r = fma(alpha, v[o], r);
+  y[o] = r;
+}
+
+// y[4j + l_in][col] = sum_{l_out != l_in} sum_row B[j,l_out,s(l_in)][col][row] x[dest(j,l_out)][row]
+__global__ void k_spmv_t(const double *__restrict__ B, const int32_t *__restrict__ dest, int64_t nrows, int K,
+                         const double *__restrict__ x, double *__restrict__ y) {
+  int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g >= nrows) return;
+  int64_t slot = g / K;
+  int col = (int)(g - slot * K);
+  int64_t j = slot >> 2;
+  int l_in = (int)(slot & 3);
+  const int64_t KK = (int64_t)K * K;
+  double acc = 0.0;
+  for (int l_out = 0; l_out < 4; ++l_out) {
+    if (l_out == l_in) continue;
+    int s = l_in < l_out ? l_in : l_in - 1;
+    int64_t br = 4 * j + l_out;
+    const double *Bb = B + (br * 3 + s) * KK + (int64_t)col * K;
+    const double *xs = x + (int64_t)dest[br] * K;
+    for (int row = 0; row < K; ++row) acc = fma(Bb[row], xs[row], acc);
+  }
+  y[g] = acc;
+}
+
+}  // namespace
+
+hipError_t spmv(dfm_op op, const double *x, const double *v, double *y, double alpha, double beta, hipStream_t st) {
+  int64_t nrows = op->ndof;
+  unsigned grid = (unsigned)((nrows + 255) / 256);
+  hipLaunchKernelGGL(k_spmv, dim3(grid), dim3(256), 0, st, op->B, op->dest, nrows, op->K, x, v, y, alpha, beta);
+  return hipGetLastError();
+}
+
+hipError_t spmv_t(dfm_op op, const double *x, double *y, hipStream_t st) {
+  int64_t nrows = op->ndof;
+  unsigned grid = (unsigned)((nrows + 255) / 256);
+  hipLaunchKernelGGL(k_spmv_t, dim3(grid), dim3(256), 0, st, op->B, op->dest, nrows, op->K, x, y);
+  return hipGetLastError();
+}
+
+}  // namespace dfm
+
+using namespace dfm;
+
+extern "C" dfm_status dfm_apply(dfm_op op, const double *x, double *y, int nrhs, int transpose, void *stream_) {
+  DFM_REQUIRE(op && x && y, DFM_E_INVALID, "null argument");
+  DFM_REQUIRE(nrhs >= 1, DFM_E_INVALID, "nrhs must be >= 1");
+  DFM_REQUIRE(x != y, DFM_E_INVALID, "x and y must not alias");
+  hipStream_t st = (hipStream_t)stream_;
+  for (int r = 0; r < nrhs; ++r) {
+    const double *xr = x + (int64_t)r * op->ndof;
+    double *yr = y + (int64_t)r * op->ndof;
+    DFM_HIP(transpose ? spmv_t(op, xr, yr, st) : spmv(op, xr, nullptr, yr, 0.0, 1.0, st));
+  }
+  return DFM_OK;
+}

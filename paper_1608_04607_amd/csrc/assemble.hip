@@ -1,0 +1,931 @@
+// Assembly of the Galerkin matrix B (Sec. 3.2 Eq. Bapprox / B4DInt, Sec. 3.3, Sec. 3.4).
+//
+// One workgroup per block (tet j, inbound face l_in, outbound face l_out):
+//   1. cells: the four of the seven direction regions (Sec. 3.4) from which l_out
+//      is reachable, or those regions cut at the momentum-basis seams and around
+//      the two poles (rule 1), each a spherical triangle/quadrilateral patch;
+//   2. per chunk of quadrature directions, waves take one role each:
+//        wave 0  direction, flux weight (Eq. Parametr map + Jacobian) and the
+//                analytic spatial integral S[p',p] of Sec. 3.3 (closed form, below)
+//        wave 1  inbound momentum basis psi_k(d)
+//        wave 2  destination momentum basis psi'_k'(d'), premultiplied by G^-1
+//      staged in LDS;
+//   3. all waves contract T[k'][(p',p,k)] += sum_q psi'_k' (W S_p'p psi_k) on the
+//      FP64 matrix cores (v_mfma_f64_16x16x4), accumulators in registers;
+//   4. the block is scaled by the transmission / reflection weight and written
+//      column-major.
+//
+// Spatial integral, closed form used here (projected areas).  For a direction d
+// entering through face l_in, c_g = |F_g| (d . n_g) is the signed area of face g
+// seen along d.  The faces with c_g > 0 are the exit faces and their shadows tile
+// the tet's silhouette of area A = sum_g max(c_g, 0).  The start points whose rays
+// leave through F_X (opposite base vertex X) form the triangle O Y Z of Sec. 3.3,
+// with O = sum_X w_X X, w_X = max(c_X,0)/A, area w_X |F_in|; the chord length is
+// linear on it, L_max at O, L_max = 3 V / A (the tet volume is a pyramid over the
+// silhouette), zero on Y Z.  Moving from O along d changes the tet barycentric
+// coordinates by -L c_V/(3V), so the exit point of the ray from O has barycentric
+// coordinates max(-c_Y,0)/A, max(-c_Z,0)/A and |F_in| cos(theta)/A on F_X's
+// vertices Y, Z, D.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "dfm_internal.h"
+#include "basis_dev.h"
+
+namespace dfm {
+
+void free_op(dfm_op op);
+
+namespace {
+
+constexpr int CMAX = 80;       // quadrature cells per block
+constexpr int PPOLY = 32;      // polygons per region while cutting (2^5 cuts)
+constexpr int VMAX = 12;       // corners per polygon
+constexpr int NTHREADS = 256;  // 4 waves
+constexpr int NPLANES = 5;
+constexpr double TOL = 1e-12;
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+struct AsmArgs {
+  const double *verts;
+  const int32_t *tets;
+  const int32_t *nbr;
+  const double *refl;
+  const double *face;
+  const double *vol;
+  const double *mu;
+  const double *gl;     // [2][32]: nodes, weights (ascending)
+  const double *thom;   // [3][DMAX+1][DMAX+1]: Jacobi off-diagonal, Thomas c', 1/denominator
+  double *B;
+  unsigned *flags;
+  unsigned long long *nodes;
+  int64_t nblocks;
+  int P, D, M, Mp, K, n, family, rule;
+  int chunk;
+  int nsplit, tiles_per_split, total_tiles, row_tiles;
+};
+
+struct BlockGeo {
+  double P[4][3];
+  double area[4];
+  double nrm[4][3];
+  double xin[3], yin[3], zin[3];
+  double xd[3], yd[3], zd[3];
+  double vol, mu, weight;
+  int gid[4];
+  int l_in, l_out, xb;
+  int base[3];
+  int oface[3];
+  int transmit;
+  int ncells;
+  int overflow;
+};
+
+__device__ inline double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+__device__ inline void cross3(const double *a, const double *b, double *c) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+__device__ inline void unit3(double *v) {
+  double n = sqrt(dot3(v, v));
+  v[0] /= n;
+  v[1] /= n;
+  v[2] /= n;
+}
+
+// I_{i,m}(a) = int_0^1 u^i (1-u)^m exp(-a u) du.
+// Power series in a for a <= 2 (term ratio (-a)/(r+1) (i+r+1)/(i+r+m+2)); for
+// larger a the binomial expansion of (1-u)^m over J_n(a) = int_0^1 u^n e^{-au} du =
+// n!/a^{n+1} (1 - e^{-a} sum_{k<=n} a^k/k!).
+__device__ double moment_I(int i, int m, double a) {
+  double fi = 1.0, fm = 1.0, fs = 1.0;
+  for (int k = 2; k <= i; ++k) fi *= k;
+  for (int k = 2; k <= m; ++k) fm *= k;
+  for (int k = 2; k <= i + m + 1; ++k) fs *= k;
+  if (a <= 2.0) {
+    double t = fi * fm / fs;
+    double sum = t;
+    for (int r = 0; r < 40; ++r) {
+      t *= (-a) / (r + 1) * (double)(i + r + 1) / (double)(i + r + m + 2);
+      sum += t;
+    }
+    return sum;
+  }
+  double ea = exp(-a);
+  double sum = 0.0;
+  double binom = 1.0;
+  for (int j = 0; j <= m; ++j) {
+    int nn = i + j;
+    double ek = 1.0, term = 1.0, fact = 1.0;
+    for (int k = 1; k <= nn; ++k) {
+      term *= a / k;
+      ek += term;
+      fact *= k;
+    }
+    double Jn = fact / pow(a, (double)(nn + 1)) * (1.0 - ea * ek);
+    sum += ((j & 1) ? -binom : binom) * Jn;
+    binom = binom * (m - j) / (j + 1);
+  }
+  return sum;
+}
+
+// ---------------------------------------------------------------------------
+// Cells (lane 0 of the workgroup)
+// ---------------------------------------------------------------------------
+
+__device__ int patch_polygon(const double (*v)[3], double (*out)[3]) {
+  int m = 0;
+  for (int k = 0; k < 4; ++k) {
+    bool dup = false;
+    if (m > 0) {
+      double dx = v[k][0] - out[m - 1][0], dy = v[k][1] - out[m - 1][1], dz = v[k][2] - out[m - 1][2];
+      dup = sqrt(dx * dx + dy * dy + dz * dz) <= TOL;
+    }
+    if (!dup) {
+      out[m][0] = v[k][0];
+      out[m][1] = v[k][1];
+      out[m][2] = v[k][2];
+      ++m;
+    }
+  }
+  if (m > 1) {
+    double dx = out[0][0] - out[m - 1][0], dy = out[0][1] - out[m - 1][1], dz = out[0][2] - out[m - 1][2];
+    if (sqrt(dx * dx + dy * dy + dz * dz) <= TOL) --m;
+  }
+  return m;
+}
+
+// Split a convex spherical polygon by the great circle normal to nrm; a part
+// with no corner strictly on its side is dropped (count 0).
+__device__ void clip_poly(const double (*in)[3], int m, const double *nrm, double (*pos)[3], int &mp,
+                          double (*neg)[3], int &mn) {
+  double s[VMAX];
+  bool anyp = false, anyn = false;
+  for (int k = 0; k < m; ++k) {
+    s[k] = dot3(in[k], nrm);
+    anyp |= s[k] > TOL;
+    anyn |= s[k] < -TOL;
+  }
+  mp = 0;
+  mn = 0;
+  for (int k = 0; k < m; ++k) {
+    int k1 = (k + 1 == m) ? 0 : k + 1;
+    double sa = s[k], sb = s[k1];
+    if (sa >= -TOL && mp < VMAX) {
+      pos[mp][0] = in[k][0]; pos[mp][1] = in[k][1]; pos[mp][2] = in[k][2]; ++mp;
+    }
+    if (sa <= TOL && mn < VMAX) {
+      neg[mn][0] = in[k][0]; neg[mn][1] = in[k][1]; neg[mn][2] = in[k][2]; ++mn;
+    }
+    if ((sa > TOL && sb < -TOL) || (sa < -TOL && sb > TOL)) {
+      double den = sa - sb;
+      double p[3] = {(sa * in[k1][0] - sb * in[k][0]) / den, (sa * in[k1][1] - sb * in[k][1]) / den,
+                     (sa * in[k1][2] - sb * in[k][2]) / den};
+      unit3(p);
+      if (mp < VMAX) { pos[mp][0] = p[0]; pos[mp][1] = p[1]; pos[mp][2] = p[2]; ++mp; }
+      if (mn < VMAX) { neg[mn][0] = p[0]; neg[mn][1] = p[1]; neg[mn][2] = p[2]; ++mn; }
+    }
+  }
+  if (!(anyp && mp >= 3)) mp = 0;
+  if (!(anyn && mn >= 3)) mn = 0;
+}
+
+// 0: not on the closed polygon, 1: at corner k, 2: on edge k -> k+1, 3: inside.
+__device__ int locate_pole(const double (*poly)[3], int m, const double *p, int &k_out) {
+  for (int k = 0; k < m; ++k) {
+    double dx = poly[k][0] - p[0], dy = poly[k][1] - p[1], dz = poly[k][2] - p[2];
+    if (sqrt(dx * dx + dy * dy + dz * dz) <= TOL) {
+      k_out = k;
+      return 1;
+    }
+  }
+  double ctr[3] = {0.0, 0.0, 0.0};
+  for (int k = 0; k < m; ++k) {
+    ctr[0] += poly[k][0];
+    ctr[1] += poly[k][1];
+    ctr[2] += poly[k][2];
+  }
+  int on_edge = -1;
+  for (int k = 0; k < m; ++k) {
+    int k1 = (k + 1 == m) ? 0 : k + 1;
+    double nr[3];
+    cross3(poly[k], poly[k1], nr);
+    unit3(nr);
+    if (dot3(nr, ctr) < 0.0) {
+      nr[0] = -nr[0]; nr[1] = -nr[1]; nr[2] = -nr[2];
+    }
+    double e = dot3(nr, p);
+    if (e < -TOL) return 0;
+    if (e <= TOL && on_edge < 0) on_edge = k;
+  }
+  if (on_edge >= 0) {
+    k_out = on_edge;
+    return 2;
+  }
+  k_out = -1;
+  return 3;
+}
+
+__device__ void emit_cell(BlockGeo &G, double (*cells)[4][3], const double *a, const double *b, const double *c,
+                          const double *d) {
+  if (G.ncells >= CMAX) {
+    G.overflow = 1;
+    return;
+  }
+  double(*o)[3] = cells[G.ncells];
+  for (int i = 0; i < 3; ++i) {
+    o[0][i] = a[i];
+    o[1][i] = b[i];
+    o[2][i] = c[i];
+    o[3][i] = d[i];
+  }
+  G.ncells++;
+}
+
+__device__ void fan_polygon(BlockGeo &G, double (*cells)[4][3], const double (*poly)[3], int m,
+                            const double *pole0, const double *pole1) {
+  const double *poles[2] = {pole0, pole1};
+  for (int pi = 0; pi < 2; ++pi) {
+    const double *p = poles[pi];
+    int k;
+    int kind = locate_pole(poly, m, p, k);
+    if (kind == 0) continue;
+    if (kind == 1) {
+      for (int i = 1; i < m - 1; ++i) {
+        int a = (k + i) % m, b = (k + i + 1) % m;
+        emit_cell(G, cells, poly[k], poly[a], poly[b], poly[k]);
+      }
+      return;
+    }
+    if (kind == 2) {
+      // ring: p, v_{k+1}, ..., v_{m-1}, v_0, ..., v_k
+      for (int i = 1; i < m; ++i) {
+        int a = (k + i) % m, b = (k + i + 1) % m;
+        emit_cell(G, cells, p, poly[a], poly[b], p);
+      }
+      return;
+    }
+    for (int i = 0; i < m; ++i) emit_cell(G, cells, p, poly[i], poly[(i + 1) % m], p);
+    return;
+  }
+  if (m == 3) {
+    emit_cell(G, cells, poly[0], poly[1], poly[2], poly[0]);
+  } else if (m == 4) {
+    emit_cell(G, cells, poly[0], poly[1], poly[2], poly[3]);
+  } else {
+    for (int i = 1; i < m - 1; ++i) emit_cell(G, cells, poly[0], poly[i], poly[i + 1], poly[0]);
+  }
+}
+
+// The seven regions of Sec. 3.4 for base A, B, C (increasing id) and apex D;
+// region r's patch written to out (v4 = v1 for triangles).
+__device__ void region_patch(const BlockGeo &G, int r, double (*out)[3]) {
+  double dD[3][3], V[3][3];
+  for (int x = 0; x < 3; ++x)
+    for (int i = 0; i < 3; ++i) V[x][i] = G.P[G.base[x]][i];
+  for (int x = 0; x < 3; ++x) {
+    for (int i = 0; i < 3; ++i) dD[x][i] = G.P[G.l_in][i] - V[x][i];
+    unit3(dD[x]);
+  }
+  if (r == 0) {
+    for (int i = 0; i < 3; ++i) {
+      out[0][i] = dD[0][i];
+      out[1][i] = dD[1][i];
+      out[2][i] = dD[2][i];
+      out[3][i] = dD[0][i];
+    }
+    return;
+  }
+  int x = (r - 1) % 3, y = (x + 1) % 3, z = (x + 2) % 3;
+  double u1[3], u2[3];
+  if (r <= 3) {
+    for (int i = 0; i < 3; ++i) {
+      u1[i] = V[z][i] - V[y][i];
+      u2[i] = V[z][i] - V[x][i];
+    }
+    unit3(u1);
+    unit3(u2);
+    for (int i = 0; i < 3; ++i) {
+      out[0][i] = dD[x][i];
+      out[1][i] = dD[y][i];
+      out[2][i] = u1[i];
+      out[3][i] = u2[i];
+    }
+  } else {
+    for (int i = 0; i < 3; ++i) {
+      u1[i] = V[y][i] - V[x][i];
+      u2[i] = V[z][i] - V[x][i];
+    }
+    unit3(u1);
+    unit3(u2);
+    for (int i = 0; i < 3; ++i) {
+      out[0][i] = dD[x][i];
+      out[1][i] = u1[i];
+      out[2][i] = u2[i];
+      out[3][i] = dD[x][i];
+    }
+  }
+}
+
+__device__ void build_cells(BlockGeo &G, double (*cells)[4][3], double *work, int rule) {
+  int xb = G.xb;
+  int qa = 1 + xb, qb = 1 + (xb + 2) % 3;
+  int regions[4] = {0, qa < qb ? qa : qb, qa < qb ? qb : qa, 4 + xb};
+  G.ncells = 0;
+  G.overflow = 0;
+  if (rule == 0) {
+    for (int r = 0; r < 4; ++r) region_patch(G, regions[r], cells[r]);
+    G.ncells = 4;
+    return;
+  }
+  double planes[NPLANES][3];
+  for (int i = 0; i < 3; ++i) {
+    planes[0][i] = G.yin[i];
+    planes[1][i] = G.xin[i];
+    planes[2][i] = G.yd[i];
+    planes[3][i] = G.xd[i];
+    planes[4][i] = G.zin[i] - G.nrm[G.l_out][i];
+  }
+  double pole_d[3] = {G.nrm[G.l_out][0], G.nrm[G.l_out][1], G.nrm[G.l_out][2]};
+  double(*bufA)[VMAX][3] = (double(*)[VMAX][3])work;
+  double(*bufB)[VMAX][3] = (double(*)[VMAX][3])(work + PPOLY * VMAX * 3);
+  int cntA[PPOLY], cntB[PPOLY];
+  for (int r = 0; r < 4; ++r) {
+    double patch[4][3];
+    region_patch(G, regions[r], patch);
+    int na = 1;
+    cntA[0] = patch_polygon(patch, bufA[0]);
+    for (int pl = 0; pl < NPLANES; ++pl) {
+      int nb = 0;
+      for (int pi = 0; pi < na; ++pi) {
+        int mp, mn;
+        if (nb + 2 > PPOLY) {
+          G.overflow = 1;
+          break;
+        }
+        clip_poly(bufA[pi], cntA[pi], planes[pl], bufB[nb], mp, bufB[nb + 1], mn);
+        if (mp > 0) {
+          cntB[nb] = mp;
+          ++nb;
+          if (mn > 0) {
+            // the negative part was written one slot further; move it down
+            cntB[nb] = mn;
+            ++nb;
+          }
+        } else if (mn > 0) {
+          for (int k = 0; k < mn; ++k)
+            for (int i = 0; i < 3; ++i) bufB[nb][k][i] = bufB[nb + 1][k][i];
+          cntB[nb] = mn;
+          ++nb;
+        }
+      }
+      // swap
+      for (int pi = 0; pi < nb; ++pi) {
+        for (int k = 0; k < cntB[pi]; ++k)
+          for (int i = 0; i < 3; ++i) bufA[pi][k][i] = bufB[pi][k][i];
+        cntA[pi] = cntB[pi];
+      }
+      na = nb;
+    }
+    for (int pi = 0; pi < na; ++pi) fan_polygon(G, cells, bufA[pi], cntA[pi], G.zin, pole_d);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Per-direction work
+// ---------------------------------------------------------------------------
+
+__device__ inline void node_direction(const double (*cells)[4][3], const double *glx, const double *glw, int n,
+                                      const double *zin, int q, double *d, double &W) {
+  int nn = n * n;
+  int c = q / nn;
+  int r = q - c * nn;
+  int i = r / n;
+  int k = r - i * n;
+  double xi = glx[i], eta = glx[k];
+  double w = glw[i] * glw[k];
+  const double(*v)[3] = cells[c];
+  double f[3], fx[3], fe[3];
+  for (int t = 0; t < 3; ++t) {
+    double a = 0.25 * (v[0][t] + v[1][t] + v[2][t] + v[3][t]);
+    double b = 0.25 * (v[1][t] - v[0][t] + v[2][t] - v[3][t]);
+    double cc = 0.25 * (v[2][t] + v[3][t] - v[0][t] - v[1][t]);
+    double dd = 0.25 * (v[2][t] - v[3][t] + v[0][t] - v[1][t]);
+    f[t] = a + b * xi + cc * eta + dd * xi * eta;
+    fx[t] = b + dd * eta;
+    fe[t] = cc + dd * xi;
+  }
+  double cr[3];
+  cross3(fx, fe, cr);
+  double det = dot3(f, cr);
+  double nf2 = dot3(f, f);
+  double nf = sqrt(nf2);
+  W = w * dot3(f, zin) * fabs(det) / (nf2 * nf2);
+  d[0] = f[0] / nf;
+  d[1] = f[1] / nf;
+  d[2] = f[2] / nf;
+}
+
+// W * S[p'][p] for one direction (P = 1 or 3) into sw[0..P*P)
+__device__ void spatial_weights(const BlockGeo &G, const double *d, double W, int P, double *sw) {
+  const int li = G.l_in, lo = G.l_out;
+  double c[4];
+  double A = 0.0;
+  for (int g = 0; g < 4; ++g) {
+    c[g] = (g == li) ? 0.0 : G.area[g] * dot3(d, G.nrm[g]);
+    if (g != li) A += fmax(c[g], 0.0);
+  }
+  double om = fmax(c[lo], 0.0) / A;
+  double L = 3.0 * G.vol / A;
+  double a = G.mu * L;
+  double Ain = G.area[li], Aout = G.area[lo];
+  if (P == 1) {
+    sw[0] = (om > 0.0) ? W * 2.0 * om * moment_I(0, 1, a) * sqrt(Ain / Aout) : 0.0;
+    return;
+  }
+  if (!(om > 0.0)) {
+    for (int i = 0; i < 9; ++i) sw[i] = 0.0;
+    return;
+  }
+  const int xb = G.xb, y = (xb + 1) % 3, z = (xb + 2) % 3;
+  double lamO[3] = {fmax(c[G.base[0]], 0.0) / A, fmax(c[G.base[1]], 0.0) / A, fmax(c[G.base[2]], 0.0) / A};
+  double lamY[3] = {0.0, 0.0, 0.0}, lamZ[3] = {0.0, 0.0, 0.0};
+  lamY[y] = 1.0;
+  lamZ[z] = 1.0;
+  double bin[3][3];
+  pos_basis(lamO, Ain, bin[0]);
+  pos_basis(lamY, Ain, bin[1]);
+  pos_basis(lamZ, Ain, bin[2]);
+  double cos_in = dot3(d, G.zin);
+  double lamE[3], lamYo[3], lamZo[3];
+  for (int t = 0; t < 3; ++t) {
+    int v = G.oface[t];
+    lamE[t] = (v == li) ? Ain * cos_in / A : fmax(-c[v], 0.0) / A;
+    lamYo[t] = (v == G.base[y]) ? 1.0 : 0.0;
+    lamZo[t] = (v == G.base[z]) ? 1.0 : 0.0;
+  }
+  double bout[3][3];
+  pos_basis(lamE, Aout, bout[0]);
+  pos_basis(lamYo, Aout, bout[1]);
+  pos_basis(lamZo, Aout, bout[2]);
+  double T = om * Ain;
+  double I21 = moment_I(2, 1, a), I12 = moment_I(1, 2, a), I03 = moment_I(0, 3, a);
+  double Gm[3][3];
+  Gm[0][0] = 2.0 * T * I21;
+  Gm[0][1] = Gm[1][0] = Gm[0][2] = Gm[2][0] = T * I12;
+  Gm[1][1] = Gm[2][2] = 2.0 * T / 3.0 * I03;
+  Gm[1][2] = Gm[2][1] = T / 3.0 * I03;
+  for (int pp = 0; pp < 3; ++pp) {
+    for (int p = 0; p < 3; ++p) {
+      double s = 0.0;
+      for (int al = 0; al < 3; ++al)
+        for (int be = 0; be < 3; ++be) s += bout[al][pp] * Gm[al][be] * bin[be][p];
+      sw[pp * 3 + p] = W * s;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The kernel
+// ---------------------------------------------------------------------------
+
+template <int MAXT, int PQ>
+__global__ __launch_bounds__(NTHREADS) void k_assemble(AsmArgs A) {
+  __shared__ BlockGeo G;
+  __shared__ double cells[CMAX][4][3];
+  __shared__ double glx[32], glw[32];
+  __shared__ double thom[3 * (DMAX + 1) * (DMAX + 1)];
+  extern __shared__ double dyn[];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int64_t blk = blockIdx.x / A.nsplit;
+  const int split = blockIdx.x % A.nsplit;
+  const int j = (int)(blk / 12);
+  const int r = (int)(blk % 12);
+  const int l_out = r / 3;
+  const int sidx = r % 3;
+  const int l_in = (sidx < l_out) ? sidx : sidx + 1;
+  const int P = PQ == 1 ? 1 : 3;
+  const int Mp = A.Mp, M = A.M, K = A.K, n = A.n, D = A.D;
+
+  if (tid < 32) {
+    glx[tid] = A.gl[tid];
+    glw[tid] = A.gl[32 + tid];
+  }
+  for (int i = tid; i < 3 * (DMAX + 1) * (DMAX + 1); i += NTHREADS) thom[i] = A.thom[i];
+  if (tid == 0) {
+    const int32_t *t = A.tets + 4 * (int64_t)j;
+    for (int m = 0; m < 4; ++m) {
+      G.gid[m] = t[m];
+      for (int i = 0; i < 3; ++i) G.P[m][i] = A.verts[3 * (int64_t)t[m] + i];
+      const double *f = A.face + FACE_REC * (4 * (int64_t)j + m);
+      G.area[m] = f[0];
+      for (int i = 0; i < 3; ++i) G.nrm[m][i] = f[1 + i];
+    }
+    const double *fi = A.face + FACE_REC * (4 * (int64_t)j + l_in);
+    for (int i = 0; i < 3; ++i) {
+      G.xin[i] = fi[4 + i];
+      G.yin[i] = fi[7 + i];
+      G.zin[i] = -fi[1 + i];
+    }
+    G.l_in = l_in;
+    G.l_out = l_out;
+    // base vertices of the inbound face in increasing global id
+    int b3[3], nb = 0;
+    for (int m = 0; m < 4; ++m)
+      if (m != l_in) b3[nb++] = m;
+    for (int a = 0; a < 3; ++a)
+      for (int b = a + 1; b < 3; ++b)
+        if (G.gid[b3[b]] < G.gid[b3[a]]) {
+          int tmp = b3[a]; b3[a] = b3[b]; b3[b] = tmp;
+        }
+    for (int a = 0; a < 3; ++a) {
+      G.base[a] = b3[a];
+      if (b3[a] == l_out) G.xb = a;
+    }
+    int o3[3], no = 0;
+    for (int m = 0; m < 4; ++m)
+      if (m != l_out) o3[no++] = m;
+    for (int a = 0; a < 3; ++a)
+      for (int b = a + 1; b < 3; ++b)
+        if (G.gid[o3[b]] < G.gid[o3[a]]) {
+          int tmp = o3[a]; o3[a] = o3[b]; o3[b] = tmp;
+        }
+    for (int a = 0; a < 3; ++a) G.oface[a] = o3[a];
+    int nb_slot = A.nbr[4 * (int64_t)j + l_out];
+    const double *fo = A.face + FACE_REC * (4 * (int64_t)j + l_out);
+    if (nb_slot >= 0) {
+      const double *fn = A.face + FACE_REC * (int64_t)nb_slot;
+      G.transmit = 1;
+      G.weight = 1.0;
+      for (int i = 0; i < 3; ++i) {
+        G.xd[i] = fn[4 + i];
+        G.yd[i] = fn[7 + i];
+        G.zd[i] = -fn[1 + i];
+      }
+    } else {
+      G.transmit = 0;
+      G.weight = A.refl[4 * (int64_t)j + l_out];
+      for (int i = 0; i < 3; ++i) {
+        G.xd[i] = fo[4 + i];
+        G.yd[i] = fo[7 + i];
+        G.zd[i] = -fo[1 + i];
+      }
+    }
+    G.vol = A.vol[j];
+    G.mu = A.mu[j];
+    build_cells(G, cells, dyn, A.rule);
+    if (G.overflow) atomicOr(A.flags, FLAG_CELL_OVERFLOW);
+    if (split == 0) atomicAdd(A.nodes, (unsigned long long)G.ncells * (unsigned long long)(n * n));
+  }
+  __syncthreads();
+
+  const int chunk = A.chunk;
+  double *Apsi = dyn;                    // [chunk][Mp]  G^-1 psi'(d')
+  double *Bpsi = dyn + chunk * Mp;       // [chunk][Mp]  psi(d)
+  double *Sw = dyn + 2 * chunk * Mp;     // [chunk][PQ]  W S
+  const int Q = G.ncells * n * n;
+  const int tile0 = split * A.tiles_per_split;
+  int tile1 = tile0 + A.tiles_per_split;
+  if (tile1 > A.total_tiles) tile1 = A.total_tiles;
+  const int R = A.row_tiles;
+
+  v4d acc[MAXT];
+#pragma unroll
+  for (int i = 0; i < MAXT; ++i) acc[i] = v4d{0.0, 0.0, 0.0, 0.0};
+
+  for (int q0 = 0; q0 < Q; q0 += chunk) {
+    const int q = q0 + lane;
+    if (lane < chunk && wave < 3) {
+      if (q < Q) {
+        double d[3], W;
+        node_direction(cells, glx, glw, n, G.zin, q, d, W);
+        if (wave == 0) {
+          double sw[PQ];
+          spatial_weights(G, d, W, P, sw);
+#pragma unroll
+          for (int i = 0; i < PQ; ++i) Sw[lane * PQ + i] = sw[i];
+        } else if (wave == 1) {
+          double *o = Bpsi + lane * Mp;
+          momentum_basis(dot3(d, G.xin), dot3(d, G.yin), dot3(d, G.zin), D, A.family, o);
+          for (int k = M; k < Mp; ++k) o[k] = 0.0;
+        } else if (wave == 2) {
+          double dd[3] = {d[0], d[1], d[2]};
+          if (!G.transmit) {
+            double dn = dot3(d, G.nrm[l_out]);
+            for (int i = 0; i < 3; ++i) dd[i] = d[i] - 2.0 * dn * G.nrm[l_out][i];
+          }
+          double *o = Apsi + lane * Mp;
+          momentum_basis(dot3(dd, G.xd), dot3(dd, G.yd), dot3(dd, G.zd), D, A.family, o);
+          apply_gram_inverse(o, D, A.family, thom);
+          for (int k = M; k < Mp; ++k) o[k] = 0.0;
+        }
+      } else {
+        if (wave == 0) {
+          for (int i = 0; i < PQ; ++i) Sw[lane * PQ + i] = 0.0;
+        } else if (wave == 1) {
+          for (int k = 0; k < Mp; ++k) Bpsi[lane * Mp + k] = 0.0;
+        } else if (wave == 2) {
+          for (int k = 0; k < Mp; ++k) Apsi[lane * Mp + k] = 0.0;
+        }
+      }
+    }
+    __syncthreads();
+    const int steps = (Q - q0 >= chunk) ? chunk / 4 : (Q - q0 + 3) / 4;
+    for (int s = 0; s < steps; ++s) {
+      const int qq = 4 * s + (lane >> 4);
+      const int col = lane & 15;
+#pragma unroll
+      for (int i = 0; i < MAXT; ++i) {
+        const int t = tile0 + wave + 4 * i;
+        if (t < tile1) {
+          const int tr = t % R, tc = t / R;
+          double a = Apsi[qq * Mp + tr * 16 + col];
+          const int c = tc * 16 + col;
+          const int pq = c / Mp;
+          const int kk = c - pq * Mp;
+          double b = Bpsi[qq * Mp + kk] * Sw[qq * PQ + pq];
+          acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[i], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // write out: lane holds rows lane/16 + 4e (e = 0..3), column lane%16 of each tile
+  double *Bb = A.B + (int64_t)blk * K * K;
+  const double wgt = G.weight;
+  bool bad = false;
+#pragma unroll
+  for (int i = 0; i < MAXT; ++i) {
+    const int t = tile0 + wave + 4 * i;
+    if (t < tile1) {
+      const int tr = t % R, tc = t / R;
+      const int c = tc * 16 + (lane & 15);
+      const int pq = c / Mp;
+      const int k = c - pq * Mp;
+      const int pp = pq / P, p = pq - pp * P;
+      if (k < M) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int kp = tr * 16 + (lane >> 4) + 4 * e;
+          if (kp < M) {
+            double v = wgt * acc[i][e];
+            bad |= !isfinite(v);
+            Bb[(int64_t)(p * M + k) * K + (pp * M + kp)] = v;
+          }
+        }
+      }
+    }
+  }
+  if (bad) atomicOr(A.flags, FLAG_NONFINITE);
+}
+
+__global__ void k_gauss_legendre(int n, double *gl) {
+  int i = threadIdx.x;
+  if (i >= 32) return;
+  double x = 0.0, w = 0.0;
+  if (i < n) gauss_legendre_node(n, i, x, w);
+  gl[i] = x;
+  gl[32 + i] = w;
+}
+
+__global__ void k_fill_zero_words(unsigned *flags, unsigned long long *nodes) {
+  if (threadIdx.x == 0) {
+    *flags = 0u;
+    *nodes = 0ull;
+  }
+}
+
+__global__ void k_dest(const int32_t *nbr, int64_t nslot, int32_t *dest) {
+  int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (s >= nslot) return;
+  int32_t k = nbr[s];
+  dest[s] = (k >= 0) ? k : (int32_t)s;
+}
+
+template <int MAXT, int PQ>
+hipError_t launch_t(const AsmArgs &a, size_t lds, hipStream_t st) {
+  unsigned grid = (unsigned)(a.nblocks * a.nsplit);
+  hipLaunchKernelGGL((k_assemble<MAXT, PQ>), dim3(grid), dim3(NTHREADS), lds, st, a);
+  return hipGetLastError();
+}
+
+template <int PQ>
+hipError_t launch_p(int maxt, const AsmArgs &a, size_t lds, hipStream_t st) {
+  switch (maxt) {
+    case 1: return launch_t<1, PQ>(a, lds, st);
+    case 2: return launch_t<2, PQ>(a, lds, st);
+    case 4: return launch_t<4, PQ>(a, lds, st);
+    case 8: return launch_t<8, PQ>(a, lds, st);
+    case 12: return launch_t<12, PQ>(a, lds, st);
+    case 16: return launch_t<16, PQ>(a, lds, st);
+    default: return launch_t<24, PQ>(a, lds, st);
+  }
+}
+
+}  // namespace
+
+void free_op(dfm_op op) {
+  if (!op) return;
+  (void)hipFree(op->B);
+  (void)hipFree(op->dest);
+  delete op;
+}
+
+}  // namespace dfm
+
+using namespace dfm;
+
+extern "C" dfm_status dfm_assemble(dfm_mesh mesh, const dfm_basis *basis, const double *mu, void *stream_,
+                                   dfm_op *out) {
+  DFM_REQUIRE(mesh && basis && mu && out, DFM_E_INVALID, "null argument");
+  *out = nullptr;
+  const dfm_basis bs = *basis;
+  DFM_REQUIRE(bs.pos_order == 0 || bs.pos_order == 1, DFM_E_INVALID, "pos_order must be 0 or 1");
+  DFM_REQUIRE(bs.mom_family == 0 || bs.mom_family == 1, DFM_E_INVALID, "mom_family must be 0 or 1");
+  DFM_REQUIRE(bs.mom_degree >= 0 && bs.mom_degree <= DMAX, DFM_E_INVALID, "mom_degree must be in 0..16");
+  DFM_REQUIRE(bs.quad_n >= 1 && bs.quad_n <= 32, DFM_E_INVALID, "quad_n must be in 1..32");
+  DFM_REQUIRE(bs.rule == 0 || bs.rule == 1, DFM_E_INVALID, "rule must be 0 or 1");
+  DFM_REQUIRE(bs.dtype == 0, DFM_E_UNSUPPORTED, "only FP64 assembly (dtype 0) is implemented");
+  hipStream_t st = (hipStream_t)stream_;
+
+  const int P = bs.pos_order == 0 ? 1 : 3;
+  const int D = bs.mom_degree;
+  const int M = (D + 1) * (D + 2) / 2;
+  const int K = P * M;
+  const int Mp = (M + 15) / 16 * 16;
+  const int PQ = P * P;
+  const int R = Mp / 16;
+  const int total = R * (PQ * Mp / 16);
+  int per_wave = (total + 3) / 4;
+  int nsplit = 1;
+  while ((per_wave + nsplit - 1) / nsplit > 24) ++nsplit;
+  int per_split_wave = (per_wave + nsplit - 1) / nsplit;
+  int maxt = per_split_wave <= 1 ? 1 : per_split_wave <= 2 ? 2 : per_split_wave <= 4 ? 4
+           : per_split_wave <= 8 ? 8 : per_split_wave <= 12 ? 12 : per_split_wave <= 16 ? 16 : 24;
+  int chunk = Mp <= 48 ? 64 : (Mp <= 96 ? 32 : 16);
+  size_t lds_nodes = sizeof(double) * (size_t)(2 * chunk * Mp + chunk * PQ);
+  size_t lds_clip = sizeof(double) * 2 * PPOLY * VMAX * 3;
+  size_t lds = lds_nodes > lds_clip ? lds_nodes : lds_clip;
+
+  dfm_op op = new dfm_op_s();
+  op->mesh = mesh;
+  op->basis = bs;
+  op->P = P;
+  op->M = M;
+  op->K = K;
+  op->nt = mesh->nt;
+  op->ndof = 4 * mesh->nt * (int64_t)K;
+  const int64_t nblocks = 12 * mesh->nt;
+  double *gl = nullptr, *thom_d = nullptr;
+  unsigned *flags = nullptr;
+  unsigned long long *nodes = nullptr;
+  auto fail = [&](dfm_status code) {
+    (void)hipFree(gl);
+    (void)hipFree(thom_d);
+    (void)hipFree(flags);
+    (void)hipFree(nodes);
+    free_op(op);
+    return code;
+  };
+#define TRY(expr)                                                                            \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) {                                                                  \
+      set_error(std::string(#expr) + ": " + hipGetErrorString(e_));                          \
+      return fail(e_ == hipErrorOutOfMemory ? DFM_E_NOMEM : DFM_E_HIP);                      \
+    }                                                                                        \
+  } while (0)
+  TRY(hipMalloc(&op->B, sizeof(double) * (size_t)nblocks * K * K));
+  TRY(hipMalloc(&op->dest, sizeof(int32_t) * 4 * mesh->nt));
+  TRY(hipMalloc(&gl, sizeof(double) * 64));
+  TRY(hipMalloc(&thom_d, sizeof(double) * 3 * (DMAX + 1) * (DMAX + 1)));
+  TRY(hipMalloc(&flags, sizeof(unsigned)));
+  TRY(hipMalloc(&nodes, sizeof(unsigned long long)));
+
+  // Tridiagonal factors of I + J (Legendre Gram / pi): J_(a,a+1) = (a+1)/sqrt((2a+1)(2a+3)).
+  std::vector<double> th(3 * (DMAX + 1) * (DMAX + 1), 0.0);
+  double *jo = th.data(), *cp = jo + (DMAX + 1) * (DMAX + 1), *idn = cp + (DMAX + 1) * (DMAX + 1);
+  for (int a = 0; a < DMAX; ++a) jo[a] = (a + 1.0) / std::sqrt((2.0 * a + 1.0) * (2.0 * a + 3.0));
+  for (int b = 0; b <= D; ++b) {
+    int N = D - b;
+    double cprev = 0.0;
+    for (int a = 0; a <= N; ++a) {
+      double den = (a == 0) ? 1.0 : 1.0 - jo[a - 1] * cprev;
+      idn[b * (DMAX + 1) + a] = 1.0 / den;
+      double c = (a < N) ? jo[a] / den : 0.0;
+      cp[b * (DMAX + 1) + a] = c;
+      cprev = c;
+    }
+  }
+  TRY(hipMemcpyAsync(thom_d, th.data(), sizeof(double) * th.size(), hipMemcpyHostToDevice, st));
+  k_gauss_legendre<<<1, 32, 0, st>>>(bs.quad_n, gl);
+  TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_dest, dim3((unsigned)((4 * mesh->nt + 255) / 256)), dim3(256), 0, st, mesh->nbr,
+                     4 * mesh->nt, op->dest);
+  TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_fill_zero_words, dim3(1), dim3(64), 0, st, flags, nodes);
+  TRY(hipGetLastError());
+
+  AsmArgs a{};
+  a.verts = mesh->verts;
+  a.tets = mesh->tets;
+  a.nbr = mesh->nbr;
+  a.refl = mesh->refl;
+  a.face = mesh->face;
+  a.vol = mesh->vol;
+  a.mu = mu;
+  a.gl = gl;
+  a.thom = thom_d;
+  a.B = op->B;
+  a.flags = flags;
+  a.nodes = nodes;
+  a.nblocks = nblocks;
+  a.P = P;
+  a.D = D;
+  a.M = M;
+  a.Mp = Mp;
+  a.K = K;
+  a.n = bs.quad_n;
+  a.family = bs.mom_family;
+  a.rule = bs.rule;
+  a.chunk = chunk;
+  a.nsplit = nsplit;
+  a.total_tiles = total;
+  a.row_tiles = R;
+  a.tiles_per_split = (total + nsplit - 1) / nsplit;
+  hipError_t le = (PQ == 1) ? launch_p<1>(maxt, a, lds, st) : launch_p<9>(maxt, a, lds, st);
+  TRY(le);
+  unsigned hflags = 0;
+  unsigned long long hnodes = 0;
+  TRY(hipMemcpyAsync(&hflags, flags, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+  TRY(hipMemcpyAsync(&hnodes, nodes, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+  TRY(hipStreamSynchronize(st));
+#undef TRY
+  (void)hipFree(gl);
+  (void)hipFree(thom_d);
+  (void)hipFree(flags);
+  (void)hipFree(nodes);
+  gl = thom_d = nullptr;
+  flags = nullptr;
+  nodes = nullptr;
+  if (hflags & FLAG_CELL_OVERFLOW) {
+    set_error("a block needs more quadrature cells than the table holds");
+    return fail(DFM_E_NUMERIC);
+  }
+  if (hflags & FLAG_NONFINITE) {
+    set_error("non-finite value in B (check mu and the mesh)");
+    return fail(DFM_E_NUMERIC);
+  }
+  op->nodes = (int64_t)hnodes;
+  *out = op;
+  return DFM_OK;
+}
+
+extern "C" void dfm_op_destroy(dfm_op op) { free_op(op); }
+
+extern "C" dfm_status dfm_op_info(dfm_op op, int64_t *ndof, int64_t *K, int64_t *nblocks, int64_t *nodes,
+                                  int64_t *bytes) {
+  DFM_REQUIRE(op != nullptr, DFM_E_INVALID, "null operator");
+  if (ndof) *ndof = op->ndof;
+  if (K) *K = op->K;
+  if (nblocks) *nblocks = 12 * op->nt;
+  if (nodes) *nodes = op->nodes;
+  if (bytes) *bytes = (int64_t)sizeof(double) * 12 * op->nt * op->K * op->K;
+  return DFM_OK;
+}
+
+namespace {
+// blocks out [nt][4][3][K][K] row-major from the internal column-major blocks
+__global__ void k_export_blocks(const double *B, int64_t nblk, int K, double *out) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t kk = (int64_t)K * K;
+  if (i >= nblk * kk) return;
+  int64_t b = i / kk;
+  int64_t e = i - b * kk;
+  int row = (int)(e / K), col = (int)(e - (int64_t)row * K);
+  out[i] = B[b * kk + (int64_t)col * K + row];
+}
+}  // namespace
+
+extern "C" dfm_status dfm_op_export(dfm_op op, double *blocks, int32_t *dest, void *stream_) {
+  DFM_REQUIRE(op != nullptr, DFM_E_INVALID, "null operator");
+  hipStream_t st = (hipStream_t)stream_;
+  if (blocks) {
+    int64_t nblk = 12 * op->nt;
+    int64_t tot = nblk * op->K * op->K;
+    hipLaunchKernelGGL(k_export_blocks, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, op->B, nblk, op->K,
+                       blocks);
+    DFM_HIP(hipGetLastError());
+  }
+  if (dest) DFM_HIP(hipMemcpyAsync(dest, op->dest, sizeof(int32_t) * 4 * op->nt, hipMemcpyDeviceToDevice, st));
+  return DFM_OK;
+}

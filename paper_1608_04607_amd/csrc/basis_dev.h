@@ -1,0 +1,167 @@
+// Device-side basis functions shared by the assembly and source kernels.
+//
+// Momentum basis on the inward hemisphere of a face frame, total degree <= D:
+//   family 0: psi_(a,b) = p_a(2 cos(theta) - 1) p_b(phi/pi - 1), p_a = sqrt(2a+1) P_a,
+//             k = t(t+1)/2 + b for t = a + b;
+//   family 1: Zernike Z_n^m(sin(theta), phi) (Sec. 3.1), k = n(n+1)/2 + (m+n)/2.
+// The Galerkin inner product is ds cos(theta) dOmega (the measure of Eq. Bapprox).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace dfm {
+namespace {
+
+constexpr int DMAX = 16;
+constexpr double SEAM_SNAP = 1e-13;
+
+__device__ inline void legendre_table(double x, int D, double *p) {
+  // orthonormal p_a = sqrt(2a+1) P_a by the three-term recurrence
+  double pm1 = 1.0, pc = x;
+  p[0] = 1.0;
+#pragma unroll
+  for (int a = 1; a <= DMAX; ++a) {
+    if (a <= D) p[a] = sqrt(2.0 * a + 1.0) * pc;
+    double pn = ((2.0 * a + 1.0) * x * pc - a * pm1) / (a + 1.0);
+    pm1 = pc;
+    pc = pn;
+  }
+}
+
+// psi_k at a direction with frame components (dx, dy, dz) into out[0..M)
+__device__ void momentum_basis(double dx, double dy, double dz, int D, int family, double *out) {
+  if (family == 0) {
+    double phi = atan2(dy, dx);
+    if (phi < 0.0) phi += 2.0 * M_PI;
+    if (fabs(dy) <= SEAM_SNAP && dx > 0.0) phi = 0.0;
+    double px[DMAX + 1], py[DMAX + 1];
+    legendre_table(2.0 * dz - 1.0, D, px);
+    legendre_table(phi / M_PI - 1.0, D, py);
+#pragma unroll
+    for (int t = 0; t <= DMAX; ++t) {
+      if (t <= D) {
+#pragma unroll
+        for (int b = 0; b <= t; ++b) out[t * (t + 1) / 2 + b] = px[t - b] * py[b];
+      }
+    }
+  } else {
+    // Z_n^{+-m} = P_k^{(0,m)}(2 rho^2 - 1) * (Re, Im)(dx + i dy)^m, n = m + 2k, with the
+    // Jacobi polynomials P_k^{(0,m)} from their three-term recurrence
+    double r2 = dx * dx + dy * dy;
+    double tt = 2.0 * r2 - 1.0;
+    double cm = 1.0, sm = 0.0;
+#pragma unroll
+    for (int m = 0; m <= DMAX; ++m) {
+      if (m <= D) {
+        double pkm1 = 0.0, pk = 1.0;
+#pragma unroll
+        for (int k = 0; 2 * k + m <= DMAX; ++k) {
+          int n = m + 2 * k;
+          if (n <= D) {
+            if (k == 1) {
+              pkm1 = pk;
+              pk = 1.0 + (m + 2.0) * (tt - 1.0) * 0.5;
+            } else if (k >= 2) {
+              double kk = k, mm = m;
+              double a1 = 2.0 * kk * (kk + mm) * (2.0 * kk + mm - 2.0);
+              double a2 = (2.0 * kk + mm - 1.0) * ((2.0 * kk + mm) * (2.0 * kk + mm - 2.0) * tt - mm * mm);
+              double a3 = 2.0 * (kk + mm - 1.0) * (kk - 1.0) * (2.0 * kk + mm);
+              double pn = (a2 * pk - a3 * pkm1) / a1;
+              pkm1 = pk;
+              pk = pn;
+            }
+            int base = n * (n + 1) / 2;
+            out[base + (m + n) / 2] = pk * cm;
+            if (m > 0) out[base + (n - m) / 2] = pk * sm;
+          }
+        }
+      }
+      double cn = cm * dx - sm * dy;
+      double sn = cm * dy + sm * dx;
+      cm = cn;
+      sm = sn;
+    }
+  }
+}
+
+// psi' premultiplied by G^-1 (in place on out[0..M))
+__device__ void apply_gram_inverse(double *out, int D, int family, const double *thom) {
+  if (family == 1) {
+    for (int n = 0; n <= D; ++n) {
+      int base = n * (n + 1) / 2;
+      for (int i = 0; i <= n; ++i) {
+        int m = -n + 2 * i;
+        double eps = (m == 0) ? 2.0 : 1.0;
+        out[base + i] *= (2.0 * n + 2.0) / (eps * M_PI);
+      }
+    }
+    return;
+  }
+  // block b: unknowns a = 0..N (N = D-b) at k(a,b) = (a+b)(a+b+1)/2 + b; matrix pi (I + J)
+  const double *jo = thom;
+  const double *cp = thom + (DMAX + 1) * (DMAX + 1);
+  const double *id = thom + 2 * (DMAX + 1) * (DMAX + 1);
+  for (int b = 0; b <= D; ++b) {
+    int N = D - b;
+    const double *cpb = cp + b * (DMAX + 1);
+    const double *idb = id + b * (DMAX + 1);
+    double prev = 0.0;
+    for (int a = 0; a <= N; ++a) {
+      int t = a + b;
+      int k = t * (t + 1) / 2 + b;
+      double v = out[k] * (1.0 / M_PI);
+      double dpa = (a == 0) ? v * idb[0] : (v - jo[a - 1] * prev) * idb[a];
+      out[k] = dpa;
+      prev = dpa;
+    }
+    double next = 0.0;
+    for (int a = N; a >= 0; --a) {
+      int t = a + b;
+      int k = t * (t + 1) / 2 + b;
+      double xa = (a == N) ? out[k] : out[k] - cpb[a] * next;
+      out[k] = xa;
+      next = xa;
+    }
+  }
+}
+
+__device__ inline void pos_basis(const double *lam, double area, double *e) {
+  e[0] = 1.0 / sqrt(area);
+  e[1] = sqrt(6.0 / area) * (lam[1] - lam[0]);
+  e[2] = sqrt(2.0 / area) * (3.0 * lam[2] - 1.0);
+}
+
+
+// n-point Gauss-Legendre node i (ascending) and weight on [-1, 1], by Newton's
+// method on P_n from the usual cosine initial guess.
+__device__ inline void gauss_legendre_node(int n, int i, double &x_out, double &w_out) {
+  int ii = n - 1 - i;  // Newton iterate ii-th largest root
+  double x = cos(M_PI * (ii + 0.75) / (n + 0.5));
+  double dp = 1.0;
+  for (int it = 0; it < 100; ++it) {
+    double p0 = 1.0, p1 = x;
+    for (int k = 2; k <= n; ++k) {
+      double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    double pnm1 = (n == 1) ? 1.0 : p0;
+    dp = n * (x * p1 - pnm1) / (x * x - 1.0);
+    double dx = p1 / dp;
+    x -= dx;
+    if (fabs(dx) <= 1e-16) break;
+  }
+  double p0 = 1.0, p1 = x;
+  for (int k = 2; k <= n; ++k) {
+    double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+    p0 = p1;
+    p1 = p2;
+  }
+  double pnm1 = (n == 1) ? 1.0 : p0;
+  dp = n * (x * p1 - pnm1) / (x * x - 1.0);
+  x_out = x;
+  w_out = 2.0 / ((1.0 - x * x) * dp * dp);
+}
+
+}  // namespace
+}  // namespace dfm

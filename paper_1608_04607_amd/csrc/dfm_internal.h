@@ -1,0 +1,68 @@
+// Internal declarations of the DFM library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/dfm.h"
+
+namespace dfm {
+
+void set_error(const std::string &msg);
+
+#define DFM_HIP(expr)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) {                                                                  \
+      ::dfm::set_error(std::string(#expr) + ": " + hipGetErrorString(e_));                   \
+      return DFM_E_HIP;                                                                      \
+    }                                                                                        \
+  } while (0)
+
+#define DFM_REQUIRE(cond, code, msg)                                                         \
+  do {                                                                                       \
+    if (!(cond)) {                                                                           \
+      ::dfm::set_error(msg);                                                                 \
+      return (code);                                                                         \
+    }                                                                                        \
+  } while (0)
+
+// Per-face geometry record, 12 doubles: area, outward unit normal (3),
+// frame x (3), frame y (3), pad (2).  The frame z is minus the normal.
+constexpr int FACE_REC = 12;
+
+// Error flags raised by kernels (bit mask in a device word).
+enum : unsigned {
+  FLAG_NONMANIFOLD = 1u,
+  FLAG_BAD_ID = 2u,
+  FLAG_DEGENERATE = 4u,
+  FLAG_NONUNIFORM = 8u,
+  FLAG_CELL_OVERFLOW = 16u,
+  FLAG_NONFINITE = 32u,
+  FLAG_HASH_FULL = 64u,
+};
+
+}  // namespace dfm
+
+struct dfm_mesh_s {
+  int64_t nt = 0, nv = 0, n_boundary = 0;
+  double *verts = nullptr;    // [nv][3]
+  int32_t *tets = nullptr;    // [nt][4]
+  int32_t *nbr = nullptr;     // [nt][4]
+  double *refl = nullptr;     // [nt][4]
+  double *face = nullptr;     // [nt][4][FACE_REC]
+  double *vol = nullptr;      // [nt]
+  double bbox_diag = 1.0;
+};
+
+struct dfm_op_s {
+  dfm_mesh mesh = nullptr;
+  dfm_basis basis{};
+  int P = 1, M = 1, K = 1;
+  int64_t nt = 0, ndof = 0;
+  int64_t nodes = 0;
+  double *B = nullptr;        // [nt][4][3K][K]: block (j, l_out, s) column-major K x K
+  int32_t *dest = nullptr;    // [nt][4]
+};

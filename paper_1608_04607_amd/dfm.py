@@ -1,0 +1,149 @@
+"""Thin Python binding of the C ABI (include/dfm.h): argument marshalling only.
+
+Device memory and streams come from PyTorch; every computation runs in the HIP
+library.  Tensors passed in must be CUDA (HIP) tensors of the documented dtype;
+they are made contiguous here and their data pointers handed to the library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import torch
+
+from . import _lib
+from ._lib import Basis, SolveInfo, SolveOpts, check
+
+LEGENDRE, ZERNIKE = 0, 1
+PAPER_RULE, SEAM_RULE = 0, 1
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev(t, dtype):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"expected dtype {dtype}, got {t.dtype}")
+    return t.contiguous()
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Mesh:
+    """Face adjacency and geometry of a tetrahedral mesh (dfm_mesh_build)."""
+
+    def __init__(self, verts, tets, refl=None, c=None, rho_f=None, stream=None):
+        lib = _lib.load()
+        self.verts = _dev(verts, torch.float64)
+        self.tets = _dev(tets, torch.int64)
+        keep = [self.verts, self.tets]
+        args = []
+        for a in (refl, c, rho_f):
+            a = _dev(a, torch.float64) if a is not None else None
+            keep.append(a)
+            args.append(_ptr(a))
+        self._keep = keep
+        h = C.c_void_p()
+        check(lib.dfm_mesh_build(_ptr(self.verts), self.verts.shape[0], _ptr(self.tets), self.tets.shape[0],
+                                 args[0], args[1], args[2], _stream(stream), C.byref(h)))
+        self.handle = h
+        self.nt = int(self.tets.shape[0])
+
+    def info(self):
+        nt, nb = C.c_int64(), C.c_int64()
+        check(_lib.load().dfm_mesh_info(self.handle, C.byref(nt), C.byref(nb)))
+        return nt.value, nb.value
+
+    def export(self, stream=None):
+        dev = self.verts.device
+        nbr = torch.empty((self.nt, 4), dtype=torch.int32, device=dev)
+        area = torch.empty((self.nt, 4), dtype=torch.float64, device=dev)
+        frame = torch.empty((self.nt, 4, 3, 3), dtype=torch.float64, device=dev)
+        vol = torch.empty((self.nt,), dtype=torch.float64, device=dev)
+        check(_lib.load().dfm_mesh_export(self.handle, _ptr(nbr), _ptr(area), _ptr(frame), _ptr(vol),
+                                          _stream(stream)))
+        return nbr, area, frame, vol
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            _lib.load().dfm_mesh_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Operator:
+    """Assembled transfer operator B (dfm_assemble) and its solves."""
+
+    def __init__(self, mesh: Mesh, mu, pos_order=0, mom_family=LEGENDRE, mom_degree=4, quad_n=8,
+                 rule=SEAM_RULE, stream=None):
+        lib = _lib.load()
+        self.mesh = mesh
+        self.mu = _dev(mu, torch.float64)
+        self.basis = Basis(pos_order, mom_family, mom_degree, quad_n, rule, 0)
+        h = C.c_void_p()
+        check(lib.dfm_assemble(mesh.handle, C.byref(self.basis), _ptr(self.mu), _stream(stream), C.byref(h)))
+        self.handle = h
+        nd, K, nb, nodes, nbytes = (C.c_int64() for _ in range(5))
+        check(lib.dfm_op_info(h, C.byref(nd), C.byref(K), C.byref(nb), C.byref(nodes), C.byref(nbytes)))
+        self.ndof, self.K, self.nblocks, self.nodes, self.nbytes = nd.value, K.value, nb.value, nodes.value, nbytes.value
+        self.device = self.mu.device
+
+    def export(self, stream=None):
+        nt = self.mesh.nt
+        blocks = torch.empty((nt, 4, 3, self.K, self.K), dtype=torch.float64, device=self.device)
+        dest = torch.empty((nt, 4), dtype=torch.int32, device=self.device)
+        check(_lib.load().dfm_op_export(self.handle, _ptr(blocks), _ptr(dest), _stream(stream)))
+        return blocks, dest
+
+    def apply(self, x, transpose=False, stream=None):
+        x = _dev(x, torch.float64)
+        nrhs = 1 if x.dim() == 1 else x.shape[0]
+        y = torch.empty_like(x)
+        check(_lib.load().dfm_apply(self.handle, _ptr(x), _ptr(y), nrhs, int(bool(transpose)), _stream(stream)))
+        return y
+
+    def solve(self, rho0, method="gmres", rtol=1e-8, restart=50, max_iter=20000, stream=None, raise_nonconv=True):
+        rho0 = _dev(rho0, torch.float64)
+        nrhs = 1 if rho0.dim() == 1 else rho0.shape[0]
+        rho = torch.empty_like(rho0)
+        opts = SolveOpts(1 if method == "gmres" else 0, restart, max_iter, rtol, 0)
+        info = (SolveInfo * nrhs)()
+        code = _lib.load().dfm_solve(self.handle, _ptr(rho0), _ptr(rho), nrhs, C.byref(opts), info, _stream(stream))
+        if code != 0 and (raise_nonconv or code != -5):
+            check(code)
+        return rho, [(i.iters, i.restarts, i.relres) for i in info]
+
+    def source_points(self, xyz, flux=1.0, stream=None):
+        xyz = _dev(xyz, torch.float64)
+        ns = xyz.shape[0]
+        rho0 = torch.empty((ns, self.ndof), dtype=torch.float64, device=self.device)
+        check(_lib.load().dfm_source_points(self.handle, _ptr(xyz), ns, flux, _ptr(rho0), _stream(stream)))
+        return rho0
+
+    def source_plane(self, axis, value, profile=0, params=None, flux=1.0, stream=None):
+        rho0 = torch.empty((self.ndof,), dtype=torch.float64, device=self.device)
+        par = (C.c_double * 4)(*(params if params is not None else (0.0, 0.0, 0.0, 1.0)))
+        check(_lib.load().dfm_source_plane(self.handle, axis, float(value), profile, par, flux, _ptr(rho0),
+                                           _stream(stream)))
+        return rho0
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            _lib.load().dfm_op_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,248 @@
+"""GPU (HIP library, called through the C ABI) against the FP64 CPU oracle.
+
+Tolerance: 1e-10 relative for every FP64 result (B blocks, products, solutions,
+sources), measured as max |gpu - oracle| / max |oracle| over the compared array.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import synth  # noqa: E402
+from oracle import assemble as oa  # noqa: E402
+from oracle import mesh as om  # noqa: E402
+from oracle import quadrature as oq  # noqa: E402
+from oracle import solve as osv  # noqa: E402
+from oracle import sources as osrc  # noqa: E402
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+TOL = 1e-10
+DEV = "cuda:0"
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def gpu_mesh(verts, tets, refl=None, **kw):
+    from paper_1608_04607_amd import dfm
+    t = lambda x: None if x is None else torch.tensor(x, device=DEV)  # noqa: E731
+    return dfm.Mesh(t(verts), t(tets), refl=t(refl), **kw)
+
+
+def gpu_op(mesh, mu, bs: oa.Basis):
+    from paper_1608_04607_amd import dfm
+    return dfm.Operator(mesh, torch.tensor(np.asarray(mu, dtype=np.float64), device=DEV), bs.pos_order,
+                        bs.mom_family, bs.mom_degree, bs.quad_n, rule=bs.rule)
+
+
+def box(n, jitter, seed=0, wall=0.9):
+    v, t = synth.kuhn_box((n, n, n), (1.0, 1.0, 1.0), jitter, seed)
+    refl = np.full((t.shape[0], 4), wall)
+    return v, t, refl
+
+
+# ---------------------------------------------------------------------------- mesh
+
+
+@pytest.mark.parametrize("n,jit", [(1, 0.0), (3, 0.15)])
+def test_mesh_tables(n, jit):
+    say(f"[mesh] n={n} jitter={jit}")
+    v, t, refl = box(n, jit)
+    g = gpu_mesh(v, t, refl)
+    nbr, area, frame, vol = (x.cpu().numpy() for x in g.export())
+    torch.cuda.synchronize()
+    m = om.build_mesh(v, t, refl)
+    assert np.array_equal(nbr, m.nbr)
+    assert rel(area, m.area) < 1e-14
+    assert rel(frame, m.frame) < 1e-14
+    assert rel(vol, m.volume) < 1e-14
+    assert g.info() == (t.shape[0], int((m.nbr < 0).sum()))
+
+
+def test_mesh_errors():
+    from paper_1608_04607_amd._lib import DFMError
+    say("[mesh errors]")
+    v = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1], [0, 0, -1], [1, 1, 1]], dtype=np.float64)
+    # three tets on the face (0,1,2): non-manifold
+    with pytest.raises(DFMError, match="MESH"):
+        gpu_mesh(v, np.array([[0, 1, 2, 3], [0, 1, 2, 4], [0, 1, 2, 5]]))
+    # flat tet
+    vf = v.copy()
+    vf[3] = [0.5, 0.5, 0.0]
+    with pytest.raises(DFMError, match="MESH"):
+        gpu_mesh(vf, np.array([[0, 1, 2, 3]]))
+    # vertex id out of range
+    with pytest.raises(DFMError, match="MESH"):
+        gpu_mesh(v, np.array([[0, 1, 2, 9]]))
+    # impedance contrast is not implemented
+    with pytest.raises(DFMError, match="UNSUPPORTED"):
+        gpu_mesh(v, np.array([[0, 1, 2, 3], [0, 1, 2, 4]]), c=torch.tensor([1.0, 2.0], dtype=torch.float64, device=DEV))
+    # uniform c and rho_f are accepted
+    gpu_mesh(v, np.array([[0, 1, 2, 3], [0, 1, 2, 4]]), c=torch.tensor([2.0, 2.0], dtype=torch.float64, device=DEV),
+             rho_f=torch.tensor([1.5, 1.5], dtype=torch.float64, device=DEV))
+
+
+# ---------------------------------------------------------------------------- assembly
+
+CASES = [
+    # name, mesh (n, jitter), mu, basis
+    ("cube-p0-leg4-n8-paper", (1, 0.0), 0.0, oa.Basis(0, 0, 4, 8, oq.PAPER_RULE)),
+    ("cube-p0-leg4-n8-seam", (1, 0.0), 0.0, oa.Basis(0, 0, 4, 8, oq.SEAM_RULE)),
+    ("box2-p1-leg4-n5-seam", (2, 0.15), 0.3, oa.Basis(1, 0, 4, 5, oq.SEAM_RULE)),
+    ("box2-p0-zern5-n6-paper", (2, 0.2), 0.05, oa.Basis(0, 1, 5, 6, oq.PAPER_RULE)),
+    ("box2-p1-zern3-n4-seam-bigmu", (2, 0.1), 9.0, oa.Basis(1, 1, 3, 4, oq.SEAM_RULE)),
+    ("box1-p0-leg7-n3-paper-bigmu", (1, 0.1), 6.0, oa.Basis(0, 0, 7, 3, oq.PAPER_RULE)),
+]
+
+
+@pytest.mark.parametrize("name,meshspec,mu,bs", CASES, ids=[c[0] for c in CASES])
+def test_assembly_matches_oracle(name, meshspec, mu, bs):
+    say(f"[assemble] {name}")
+    n, jit = meshspec
+    if name.startswith("cube"):
+        p = synth.problem_c1()
+        v, t, refl = p.verts, p.tets, p.refl
+    else:
+        v, t, refl = box(n, jit, seed=7)
+    mu_arr = np.full(t.shape[0], mu) * np.linspace(0.5, 1.5, t.shape[0])
+    g = gpu_mesh(v, t, refl)
+    op = gpu_op(g, mu_arr, bs)
+    blocks, dest = (x.cpu().numpy() for x in op.export())
+    m = om.build_mesh(v, t, refl)
+    Bo, desto = oa.assemble(m, bs, mu_arr)
+    assert np.array_equal(dest, desto)
+    err = rel(blocks, Bo)
+    say(f"    rel err {err:.3e}  nodes {op.nodes}")
+    assert err < TOL
+
+
+def test_assembly_max_degree_p1_split():
+    """D = 16 with the linear position basis (K = 459): the largest supported
+    block, whose output tiles are spread over several workgroups."""
+    say("[assemble] single tet, P1, D=16, n=2")
+    v = np.array([[0.1, 0.0, 0.0], [1.0, 0.2, 0.0], [0.3, 1.1, 0.1], [0.2, 0.3, 0.9]])
+    t = np.array([[0, 1, 2, 3]])
+    refl = np.array([[0.9, 1.0, 0.7, 0.5]])
+    bs = oa.Basis(1, 0, 16, 2, oq.SEAM_RULE)
+    g = gpu_mesh(v, t, refl)
+    op = gpu_op(g, [0.2], bs)
+    blocks, _ = (x.cpu().numpy() for x in op.export())
+    Bo, _ = oa.assemble(om.build_mesh(v, t, refl), bs, [0.2])
+    assert rel(blocks, Bo) < TOL
+
+
+def test_full_size_box8_sampled():
+    """The 3072-tet box (P1, Legendre D = 8, n = 12, seam rule) assembled whole on
+    the GPU; sampled tets checked against the oracle block by block."""
+    say("[assemble] box8 P1 D8 n12 full size, sampled")
+    p = synth.problem_c2()
+    bs = oa.Basis(p.pos_order, 0, p.mom_degree, p.quad_n, oq.SEAM_RULE)
+    g = gpu_mesh(p.verts, p.tets, p.refl)
+    op = gpu_op(g, p.mu, bs)
+    blocks, dest = op.export()
+    m = om.build_mesh(p.verts, p.tets, p.refl)
+    sample = np.random.default_rng(11).choice(p.nt, 5, replace=False)
+    Bo, desto = oa.assemble(m, bs, p.mu, tets=sample)
+    got = blocks[torch.tensor(sample, device=DEV)].cpu().numpy()
+    assert np.array_equal(dest.cpu().numpy()[sample], desto)
+    err = rel(got, Bo)
+    say(f"    rel err {err:.3e}")
+    assert err < TOL
+    assert torch.isfinite(blocks).all()
+
+
+# ---------------------------------------------------------------------------- apply / solve
+
+
+@pytest.fixture(scope="module")
+def small():
+    v, t, refl = box(2, 0.15, seed=3)
+    mu = np.full(t.shape[0], 0.05)
+    bs = oa.Basis(1, 0, 3, 4, oq.SEAM_RULE)
+    g = gpu_mesh(v, t, refl)
+    op = gpu_op(g, mu, bs)
+    m = om.build_mesh(v, t, refl)
+    Bo, desto = oa.assemble(m, bs, mu)
+    return g, op, m, bs, Bo, desto, mu
+
+
+def test_apply_matches_oracle(small):
+    say("[apply]")
+    g, op, m, bs, Bo, desto, mu = small
+    A = osv.to_sparse(Bo, desto)
+    x = np.random.default_rng(5).standard_normal((3, A.shape[0]))
+    y = op.apply(torch.tensor(x, device=DEV)).cpu().numpy()
+    yt = op.apply(torch.tensor(x, device=DEV), transpose=True).cpu().numpy()
+    assert rel(y, (A @ x.T).T) < TOL
+    assert rel(yt, (A.T @ x.T).T) < TOL
+
+
+@pytest.mark.parametrize("method", ["neumann", "gmres"])
+def test_solve_matches_oracle(small, method):
+    say(f"[solve] {method}")
+    g, op, m, bs, Bo, desto, mu = small
+    A = osv.to_sparse(Bo, desto)
+    rhs = np.random.default_rng(8).standard_normal(A.shape[0])
+    ref = osv.solve_direct(A, rhs)
+    rho, info = op.solve(torch.tensor(rhs, device=DEV), method=method, rtol=1e-13, restart=30)
+    say(f"    info {info}")
+    assert info[0][2] <= 1e-13
+    assert rel(rho.cpu().numpy(), ref) < 1e-9
+
+
+def test_cube_neumann_matches_direct():
+    say("[solve] cube, Neumann to 1e-12")
+    p = synth.problem_c1()
+    bs = oa.Basis(0, 0, 4, 8, oq.SEAM_RULE)
+    g = gpu_mesh(p.verts, p.tets, p.refl)
+    op = gpu_op(g, p.mu, bs)
+    rho0 = op.source_plane(0, 0.0, profile=0)
+    rho, info = op.solve(rho0, method="neumann", rtol=1e-12)
+    m = om.build_mesh(p.verts, p.tets, p.refl)
+    Bo, desto = oa.assemble(m, bs, p.mu)
+    r0o = osrc.project(m, bs, p.source)[0]
+    assert rel(rho0.cpu().numpy(), r0o) < TOL
+    ref = osv.solve_direct(osv.to_sparse(Bo, desto), r0o)
+    assert info[0][2] <= 1e-12 and info[0][0] > 100
+    assert rel(rho.cpu().numpy(), ref) < 1e-9
+
+
+def test_solver_reports_nonconvergence(small):
+    from paper_1608_04607_amd._lib import DFMError
+    g, op, *_ = small
+    rhs = torch.ones(op.ndof, dtype=torch.float64, device=DEV)
+    with pytest.raises(DFMError, match="NOCONV"):
+        op.solve(rhs, method="neumann", rtol=1e-14, max_iter=3)
+
+
+# ---------------------------------------------------------------------------- sources
+
+
+@pytest.mark.parametrize("family", [0, 1])
+def test_sources_match_oracle(family):
+    say(f"[sources] family {family}")
+    v, t, refl = box(2, 0.15, seed=2)
+    bs = oa.Basis(1, family, 6, 2, oq.PAPER_RULE)
+    g = gpu_mesh(v, t, refl)
+    op = gpu_op(g, np.zeros(t.shape[0]), bs)
+    m = om.build_mesh(v, t, refl)
+    src = {"kind": "gauss_patch", "axis": 0, "value": 0.0, "center": (0.0, 0.5, 0.5), "sigma": 0.1, "flux": 1.0}
+    got = op.source_plane(0, 0.0, profile=1, params=(0.0, 0.5, 0.5, 0.1)).cpu().numpy()
+    assert rel(got, osrc.project(m, bs, src)[0]) < TOL
+    got = op.source_plane(0, 0.0, profile=0).cpu().numpy()
+    assert rel(got, osrc.project(m, bs, {"kind": "face_flux", "axis": 0, "value": 0.0})[0]) < TOL
+    pts = synth.uniform_points_on_box_surface((1, 1, 1), 7, np.random.default_rng(4))
+    got = op.source_points(torch.tensor(pts, device=DEV)).cpu().numpy()
+    assert rel(got, osrc.project(m, bs, {"kind": "points", "xyz": pts})) < TOL
