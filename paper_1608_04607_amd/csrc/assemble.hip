@@ -44,7 +44,7 @@ namespace {
 constexpr int CMAX = 80;       // quadrature cells per block
 constexpr int PPOLY = 32;      // polygons per region while cutting (2^5 cuts)
 constexpr int VMAX = 12;       // corners per polygon
-constexpr int NTHREADS = 256;  // 4 waves
+constexpr int NTHREADS = 512;  // 8 waves
 constexpr int NPLANES = 5;
 constexpr double TOL = 1e-12;
 
@@ -60,6 +60,7 @@ struct AsmArgs {
   const double *mu;
   const double *gl;     // [2][32]: nodes, weights (ascending)
   const double *thom;   // [3][DMAX+1][DMAX+1]: Jacobi off-diagonal, Thomas c', 1/denominator
+  const double *coef;   // [NMOM][NSERIES] power-series coefficients of the chord moments
   double *B;
   unsigned *flags;
   unsigned long long *nodes;
@@ -76,6 +77,7 @@ struct BlockGeo {
   double xin[3], yin[3], zin[3];
   double xd[3], yd[3], zd[3];
   double vol, mu, weight;
+  double en_in[3], en_out[3], sqrt_ratio;
   int gid[4];
   int l_in, l_out, xb;
   int base[3];
@@ -99,40 +101,45 @@ __device__ inline void unit3(double *v) {
 }
 
 // I_{i,m}(a) = int_0^1 u^i (1-u)^m exp(-a u) du.
-// Power series in a for a <= 2 (term ratio (-a)/(r+1) (i+r+1)/(i+r+m+2)); for
-// larger a the binomial expansion of (1-u)^m over J_n(a) = int_0^1 u^n e^{-au} du =
+// For a <= 2: the power series sum_r c_r a^r, c_r = (-1)^r (i+r)! m! / (r! (i+r+m+1)!),
+// by Horner with the coefficients tabulated once per launch (40 terms).
+// For a > 2: the binomial expansion of (1-u)^m over J_n(a) = int_0^1 u^n e^{-au} du =
 // n!/a^{n+1} (1 - e^{-a} sum_{k<=n} a^k/k!).
-__device__ double moment_I(int i, int m, double a) {
-  double fi = 1.0, fm = 1.0, fs = 1.0;
-  for (int k = 2; k <= i; ++k) fi *= k;
-  for (int k = 2; k <= m; ++k) fm *= k;
-  for (int k = 2; k <= i + m + 1; ++k) fs *= k;
-  if (a <= 2.0) {
-    double t = fi * fm / fs;
-    double sum = t;
-    for (int r = 0; r < 40; ++r) {
-      t *= (-a) / (r + 1) * (double)(i + r + 1) / (double)(i + r + m + 2);
-      sum += t;
-    }
-    return sum;
-  }
+constexpr int NSERIES = 40;
+constexpr int NMOM = 4;   // (i, m) = (0,1), (2,1), (1,2), (0,3)
+__device__ __constant__ const int MOM_I[NMOM] = {0, 2, 1, 0};
+__device__ __constant__ const int MOM_M[NMOM] = {1, 1, 2, 3};
+
+__device__ double moment_closed(int i, int m, double a) {
   double ea = exp(-a);
+  double inva = 1.0 / a;
   double sum = 0.0;
   double binom = 1.0;
   for (int j = 0; j <= m; ++j) {
     int nn = i + j;
-    double ek = 1.0, term = 1.0, fact = 1.0;
+    double ek = 1.0, term = 1.0, fact = 1.0, ipow = inva;
     for (int k = 1; k <= nn; ++k) {
       term *= a / k;
       ek += term;
       fact *= k;
+      ipow *= inva;
     }
-    double Jn = fact / pow(a, (double)(nn + 1)) * (1.0 - ea * ek);
+    double Jn = fact * ipow * (1.0 - ea * ek);
     sum += ((j & 1) ? -binom : binom) * Jn;
     binom = binom * (m - j) / (j + 1);
   }
   return sum;
 }
+
+__device__ inline double moment(const double *coef, int which, double a) {
+  if (a > 2.0) return moment_closed(MOM_I[which], MOM_M[which], a);
+  const double *c = coef + which * NSERIES;
+  double s = c[NSERIES - 1];
+#pragma unroll 8
+  for (int r = NSERIES - 2; r >= 0; --r) s = fma(s, a, c[r]);
+  return s;
+}
+
 
 // ---------------------------------------------------------------------------
 // Cells (lane 0 of the workgroup)
@@ -424,74 +431,90 @@ __device__ inline void node_direction(const double (*cells)[4][3], const double 
   cross3(fx, fe, cr);
   double det = dot3(f, cr);
   double nf2 = dot3(f, f);
-  double nf = sqrt(nf2);
-  W = w * dot3(f, zin) * fabs(det) / (nf2 * nf2);
-  d[0] = f[0] / nf;
-  d[1] = f[1] / nf;
-  d[2] = f[2] / nf;
+  double inv = 1.0 / sqrt(nf2);
+  double inv2 = inv * inv;
+  W = w * dot3(f, zin) * fabs(det) * (inv2 * inv2);
+  d[0] = f[0] * inv;
+  d[1] = f[1] * inv;
+  d[2] = f[2] * inv;
+}
+
+// orthonormal linear position basis from barycentrics, scale factors pre-computed
+__device__ inline void pos_basis_n(const double *lam, const double *en, double *e) {
+  e[0] = en[0];
+  e[1] = en[1] * (lam[1] - lam[0]);
+  e[2] = en[2] * (3.0 * lam[2] - 1.0);
 }
 
 // W * S[p'][p] for one direction (P = 1 or 3) into sw[0..P*P)
-__device__ void spatial_weights(const BlockGeo &G, const double *d, double W, int P, double *sw) {
+template <int P>
+__device__ void spatial_weights(const BlockGeo &G, const double *coef, const double *d, double W, double *sw) {
   const int li = G.l_in, lo = G.l_out;
   double c[4];
   double A = 0.0;
+#pragma unroll
   for (int g = 0; g < 4; ++g) {
     c[g] = (g == li) ? 0.0 : G.area[g] * dot3(d, G.nrm[g]);
     if (g != li) A += fmax(c[g], 0.0);
   }
-  double om = fmax(c[lo], 0.0) / A;
-  double L = 3.0 * G.vol / A;
-  double a = G.mu * L;
-  double Ain = G.area[li], Aout = G.area[lo];
+  const double iA = 1.0 / A;
+  const double om = fmax(c[lo], 0.0) * iA;
+  const double a = G.mu * (3.0 * G.vol) * iA;
   if (P == 1) {
-    sw[0] = (om > 0.0) ? W * 2.0 * om * moment_I(0, 1, a) * sqrt(Ain / Aout) : 0.0;
+    sw[0] = (om > 0.0) ? W * 2.0 * om * moment(coef, 0, a) * G.sqrt_ratio : 0.0;
     return;
   }
   if (!(om > 0.0)) {
-    for (int i = 0; i < 9; ++i) sw[i] = 0.0;
+#pragma unroll
+    for (int i = 0; i < P * P; ++i) sw[i] = 0.0;
     return;
   }
   const int xb = G.xb, y = (xb + 1) % 3, z = (xb + 2) % 3;
-  double lamO[3] = {fmax(c[G.base[0]], 0.0) / A, fmax(c[G.base[1]], 0.0) / A, fmax(c[G.base[2]], 0.0) / A};
+  double lamO[3] = {fmax(c[G.base[0]], 0.0) * iA, fmax(c[G.base[1]], 0.0) * iA, fmax(c[G.base[2]], 0.0) * iA};
   double lamY[3] = {0.0, 0.0, 0.0}, lamZ[3] = {0.0, 0.0, 0.0};
   lamY[y] = 1.0;
   lamZ[z] = 1.0;
   double bin[3][3];
-  pos_basis(lamO, Ain, bin[0]);
-  pos_basis(lamY, Ain, bin[1]);
-  pos_basis(lamZ, Ain, bin[2]);
-  double cos_in = dot3(d, G.zin);
+  pos_basis_n(lamO, G.en_in, bin[0]);
+  pos_basis_n(lamY, G.en_in, bin[1]);
+  pos_basis_n(lamZ, G.en_in, bin[2]);
+  const double cos_in = dot3(d, G.zin);
   double lamE[3], lamYo[3], lamZo[3];
+#pragma unroll
   for (int t = 0; t < 3; ++t) {
     int v = G.oface[t];
-    lamE[t] = (v == li) ? Ain * cos_in / A : fmax(-c[v], 0.0) / A;
+    lamE[t] = (v == li) ? G.area[li] * cos_in * iA : fmax(-c[v], 0.0) * iA;
     lamYo[t] = (v == G.base[y]) ? 1.0 : 0.0;
     lamZo[t] = (v == G.base[z]) ? 1.0 : 0.0;
   }
   double bout[3][3];
-  pos_basis(lamE, Aout, bout[0]);
-  pos_basis(lamYo, Aout, bout[1]);
-  pos_basis(lamZo, Aout, bout[2]);
-  double T = om * Ain;
-  double I21 = moment_I(2, 1, a), I12 = moment_I(1, 2, a), I03 = moment_I(0, 3, a);
+  pos_basis_n(lamE, G.en_out, bout[0]);
+  pos_basis_n(lamYo, G.en_out, bout[1]);
+  pos_basis_n(lamZo, G.en_out, bout[2]);
+  const double T = om * G.area[li];
+  const double I21 = moment(coef, 1, a), I12 = moment(coef, 2, a), I03 = moment(coef, 3, a);
   double Gm[3][3];
   Gm[0][0] = 2.0 * T * I21;
   Gm[0][1] = Gm[1][0] = Gm[0][2] = Gm[2][0] = T * I12;
-  Gm[1][1] = Gm[2][2] = 2.0 * T / 3.0 * I03;
-  Gm[1][2] = Gm[2][1] = T / 3.0 * I03;
-  for (int pp = 0; pp < 3; ++pp) {
-    for (int p = 0; p < 3; ++p) {
-      double s = 0.0;
-      for (int al = 0; al < 3; ++al)
-        for (int be = 0; be < 3; ++be) s += bout[al][pp] * Gm[al][be] * bin[be][p];
-      sw[pp * 3 + p] = W * s;
-    }
-  }
+  Gm[1][1] = Gm[2][2] = (2.0 / 3.0) * T * I03;
+  Gm[1][2] = Gm[2][1] = (1.0 / 3.0) * T * I03;
+  // S = bout^T Gm bin
+  double tmp[3][3];
+#pragma unroll
+  for (int al = 0; al < 3; ++al)
+#pragma unroll
+    for (int p = 0; p < 3; ++p) tmp[al][p] = Gm[al][0] * bin[0][p] + Gm[al][1] * bin[1][p] + Gm[al][2] * bin[2][p];
+#pragma unroll
+  for (int pp = 0; pp < 3; ++pp)
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+      sw[pp * 3 + p] = W * (bout[0][pp] * tmp[0][p] + bout[1][pp] * tmp[1][p] + bout[2][pp] * tmp[2][p]);
 }
 
 // ---------------------------------------------------------------------------
-// The kernel
+// The kernel: 8 waves.  Node phase: wave w takes role w % 4 (0 geometry and S,
+// 1 psi, 2 G^-1 psi', 3 idle) for the nodes of half w / 4 of the chunk.
+// Contraction: wave w owns output tiles t = tile0 + w + 8 i.
 // ---------------------------------------------------------------------------
 
 template <int MAXT, int PQ>
@@ -500,6 +523,7 @@ __global__ __launch_bounds__(NTHREADS) void k_assemble(AsmArgs A) {
   __shared__ double cells[CMAX][4][3];
   __shared__ double glx[32], glw[32];
   __shared__ double thom[3 * (DMAX + 1) * (DMAX + 1)];
+  __shared__ double coef[NMOM * NSERIES];
   extern __shared__ double dyn[];
 
   const int tid = threadIdx.x;
@@ -512,7 +536,7 @@ __global__ __launch_bounds__(NTHREADS) void k_assemble(AsmArgs A) {
   const int l_out = r / 3;
   const int sidx = r % 3;
   const int l_in = (sidx < l_out) ? sidx : sidx + 1;
-  const int P = PQ == 1 ? 1 : 3;
+  constexpr int P = PQ == 1 ? 1 : 3;
   const int Mp = A.Mp, M = A.M, K = A.K, n = A.n, D = A.D;
 
   if (tid < 32) {
@@ -520,6 +544,7 @@ __global__ __launch_bounds__(NTHREADS) void k_assemble(AsmArgs A) {
     glw[tid] = A.gl[32 + tid];
   }
   for (int i = tid; i < 3 * (DMAX + 1) * (DMAX + 1); i += NTHREADS) thom[i] = A.thom[i];
+  for (int i = tid; i < NMOM * NSERIES; i += NTHREADS) coef[i] = A.coef[i];
   if (tid == 0) {
     const int32_t *t = A.tets + 4 * (int64_t)j;
     for (int m = 0; m < 4; ++m) {
@@ -579,6 +604,14 @@ __global__ __launch_bounds__(NTHREADS) void k_assemble(AsmArgs A) {
         G.zd[i] = -fo[1 + i];
       }
     }
+    const double Ain = G.area[l_in], Aout = G.area[l_out];
+    G.en_in[0] = 1.0 / sqrt(Ain);
+    G.en_in[1] = sqrt(6.0 / Ain);
+    G.en_in[2] = sqrt(2.0 / Ain);
+    G.en_out[0] = 1.0 / sqrt(Aout);
+    G.en_out[1] = sqrt(6.0 / Aout);
+    G.en_out[2] = sqrt(2.0 / Aout);
+    G.sqrt_ratio = sqrt(Ain / Aout);
     G.vol = A.vol[j];
     G.mu = A.mu[j];
     build_cells(G, cells, dyn, A.rule);
@@ -596,65 +629,85 @@ __global__ __launch_bounds__(NTHREADS) void k_assemble(AsmArgs A) {
   int tile1 = tile0 + A.tiles_per_split;
   if (tile1 > A.total_tiles) tile1 = A.total_tiles;
   const int R = A.row_tiles;
+  const int role = wave & 3;
+  const int half = wave >> 2;
+  const int col = lane & 15;
+  const int qrow = lane >> 4;
+
+  // tile coordinates of this wave's tiles (clamped into range; inactive tiles
+  // still load valid LDS addresses but skip the MFMA)
+  int aoff[MAXT], boff[MAXT], spq[MAXT];
+  bool act[MAXT];
+#pragma unroll
+  for (int i = 0; i < MAXT; ++i) {
+    int t = tile0 + wave + 8 * i;
+    act[i] = t < tile1;
+    if (!act[i]) t = tile1 - 1;
+    const int tr = t % R, tc = t / R;
+    const int c = tc * 16 + col;
+    const int pq = c / Mp;
+    aoff[i] = tr * 16 + col;
+    boff[i] = c - pq * Mp;
+    spq[i] = pq;
+  }
 
   v4d acc[MAXT];
 #pragma unroll
   for (int i = 0; i < MAXT; ++i) acc[i] = v4d{0.0, 0.0, 0.0, 0.0};
 
   for (int q0 = 0; q0 < Q; q0 += chunk) {
-    const int q = q0 + lane;
-    if (lane < chunk && wave < 3) {
+    const int ql = half * 64 + lane;   // node within the chunk
+    const int q = q0 + ql;
+    if (role < 3 && ql < chunk) {
       if (q < Q) {
         double d[3], W;
         node_direction(cells, glx, glw, n, G.zin, q, d, W);
-        if (wave == 0) {
+        if (role == 0) {
           double sw[PQ];
-          spatial_weights(G, d, W, P, sw);
+          spatial_weights<P>(G, coef, d, W, sw);
 #pragma unroll
-          for (int i = 0; i < PQ; ++i) Sw[lane * PQ + i] = sw[i];
-        } else if (wave == 1) {
-          double *o = Bpsi + lane * Mp;
+          for (int i = 0; i < PQ; ++i) Sw[ql * PQ + i] = sw[i];
+        } else if (role == 1) {
+          double *o = Bpsi + ql * Mp;
           momentum_basis(dot3(d, G.xin), dot3(d, G.yin), dot3(d, G.zin), D, A.family, o);
           for (int k = M; k < Mp; ++k) o[k] = 0.0;
-        } else if (wave == 2) {
+        } else {
           double dd[3] = {d[0], d[1], d[2]};
           if (!G.transmit) {
             double dn = dot3(d, G.nrm[l_out]);
             for (int i = 0; i < 3; ++i) dd[i] = d[i] - 2.0 * dn * G.nrm[l_out][i];
           }
-          double *o = Apsi + lane * Mp;
+          double *o = Apsi + ql * Mp;
           momentum_basis(dot3(dd, G.xd), dot3(dd, G.yd), dot3(dd, G.zd), D, A.family, o);
           apply_gram_inverse(o, D, A.family, thom);
           for (int k = M; k < Mp; ++k) o[k] = 0.0;
         }
       } else {
-        if (wave == 0) {
-          for (int i = 0; i < PQ; ++i) Sw[lane * PQ + i] = 0.0;
-        } else if (wave == 1) {
-          for (int k = 0; k < Mp; ++k) Bpsi[lane * Mp + k] = 0.0;
-        } else if (wave == 2) {
-          for (int k = 0; k < Mp; ++k) Apsi[lane * Mp + k] = 0.0;
+        if (role == 0) {
+          for (int i = 0; i < PQ; ++i) Sw[ql * PQ + i] = 0.0;
+        } else if (role == 1) {
+          for (int k = 0; k < Mp; ++k) Bpsi[ql * Mp + k] = 0.0;
+        } else {
+          for (int k = 0; k < Mp; ++k) Apsi[ql * Mp + k] = 0.0;
         }
       }
     }
     __syncthreads();
     const int steps = (Q - q0 >= chunk) ? chunk / 4 : (Q - q0 + 3) / 4;
     for (int s = 0; s < steps; ++s) {
-      const int qq = 4 * s + (lane >> 4);
-      const int col = lane & 15;
+      const int qq = 4 * s + qrow;
+      const double *arow = Apsi + qq * Mp;
+      const double *brow = Bpsi + qq * Mp;
+      const double *srow = Sw + qq * PQ;
+      double av[MAXT], bv[MAXT];
 #pragma unroll
       for (int i = 0; i < MAXT; ++i) {
-        const int t = tile0 + wave + 4 * i;
-        if (t < tile1) {
-          const int tr = t % R, tc = t / R;
-          double a = Apsi[qq * Mp + tr * 16 + col];
-          const int c = tc * 16 + col;
-          const int pq = c / Mp;
-          const int kk = c - pq * Mp;
-          double b = Bpsi[qq * Mp + kk] * Sw[qq * PQ + pq];
-          acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[i], 0, 0, 0);
-        }
+        av[i] = arow[aoff[i]];
+        bv[i] = brow[boff[i]] * srow[spq[i]];
       }
+#pragma unroll
+      for (int i = 0; i < MAXT; ++i)
+        if (act[i]) acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[i], acc[i], 0, 0, 0);
     }
     __syncthreads();
   }
@@ -665,17 +718,17 @@ __global__ __launch_bounds__(NTHREADS) void k_assemble(AsmArgs A) {
   bool bad = false;
 #pragma unroll
   for (int i = 0; i < MAXT; ++i) {
-    const int t = tile0 + wave + 4 * i;
+    const int t = tile0 + wave + 8 * i;
     if (t < tile1) {
       const int tr = t % R, tc = t / R;
-      const int c = tc * 16 + (lane & 15);
+      const int c = tc * 16 + col;
       const int pq = c / Mp;
       const int k = c - pq * Mp;
       const int pp = pq / P, p = pq - pp * P;
       if (k < M) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const int kp = tr * 16 + (lane >> 4) + 4 * e;
+          const int kp = tr * 16 + qrow + 4 * e;
           if (kp < M) {
             double v = wgt * acc[i][e];
             bad |= !isfinite(v);
@@ -713,8 +766,11 @@ __global__ void k_dest(const int32_t *nbr, int64_t nslot, int32_t *dest) {
 
 template <int MAXT, int PQ>
 hipError_t launch_t(const AsmArgs &a, size_t lds, hipStream_t st) {
+  auto kern = k_assemble<MAXT, PQ>;
+  hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
   unsigned grid = (unsigned)(a.nblocks * a.nsplit);
-  hipLaunchKernelGGL((k_assemble<MAXT, PQ>), dim3(grid), dim3(NTHREADS), lds, st, a);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(NTHREADS), lds, st, a);
   return hipGetLastError();
 }
 
@@ -723,11 +779,12 @@ hipError_t launch_p(int maxt, const AsmArgs &a, size_t lds, hipStream_t st) {
   switch (maxt) {
     case 1: return launch_t<1, PQ>(a, lds, st);
     case 2: return launch_t<2, PQ>(a, lds, st);
+    case 3: return launch_t<3, PQ>(a, lds, st);
     case 4: return launch_t<4, PQ>(a, lds, st);
+    case 6: return launch_t<6, PQ>(a, lds, st);
     case 8: return launch_t<8, PQ>(a, lds, st);
     case 12: return launch_t<12, PQ>(a, lds, st);
-    case 16: return launch_t<16, PQ>(a, lds, st);
-    default: return launch_t<24, PQ>(a, lds, st);
+    default: return launch_t<16, PQ>(a, lds, st);
   }
 }
 
@@ -765,13 +822,14 @@ extern "C" dfm_status dfm_assemble(dfm_mesh mesh, const dfm_basis *basis, const 
   const int PQ = P * P;
   const int R = Mp / 16;
   const int total = R * (PQ * Mp / 16);
-  int per_wave = (total + 3) / 4;
-  int nsplit = 1;
-  while ((per_wave + nsplit - 1) / nsplit > 24) ++nsplit;
+  const int NW = NTHREADS / 64;
+  int per_wave = (total + NW - 1) / NW;
+  int nsplit = (per_wave + 15) / 16;
   int per_split_wave = (per_wave + nsplit - 1) / nsplit;
-  int maxt = per_split_wave <= 1 ? 1 : per_split_wave <= 2 ? 2 : per_split_wave <= 4 ? 4
-           : per_split_wave <= 8 ? 8 : per_split_wave <= 12 ? 12 : per_split_wave <= 16 ? 16 : 24;
-  int chunk = Mp <= 48 ? 64 : (Mp <= 96 ? 32 : 16);
+  int maxt = per_split_wave <= 1 ? 1 : per_split_wave <= 2 ? 2 : per_split_wave <= 3 ? 3 : per_split_wave <= 4 ? 4
+           : per_split_wave <= 6 ? 6 : per_split_wave <= 8 ? 8 : per_split_wave <= 12 ? 12 : 16;
+  // nodes per chunk: two halves of 64 when the LDS allows
+  int chunk = Mp <= 48 ? 128 : (Mp <= 96 ? 64 : 32);
   size_t lds_nodes = sizeof(double) * (size_t)(2 * chunk * Mp + chunk * PQ);
   size_t lds_clip = sizeof(double) * 2 * PPOLY * VMAX * 3;
   size_t lds = lds_nodes > lds_clip ? lds_nodes : lds_clip;
@@ -785,12 +843,13 @@ extern "C" dfm_status dfm_assemble(dfm_mesh mesh, const dfm_basis *basis, const 
   op->nt = mesh->nt;
   op->ndof = 4 * mesh->nt * (int64_t)K;
   const int64_t nblocks = 12 * mesh->nt;
-  double *gl = nullptr, *thom_d = nullptr;
+  double *gl = nullptr, *thom_d = nullptr, *coef_d = nullptr;
   unsigned *flags = nullptr;
   unsigned long long *nodes = nullptr;
   auto fail = [&](dfm_status code) {
     (void)hipFree(gl);
     (void)hipFree(thom_d);
+    (void)hipFree(coef_d);
     (void)hipFree(flags);
     (void)hipFree(nodes);
     free_op(op);
@@ -808,6 +867,7 @@ extern "C" dfm_status dfm_assemble(dfm_mesh mesh, const dfm_basis *basis, const 
   TRY(hipMalloc(&op->dest, sizeof(int32_t) * 4 * mesh->nt));
   TRY(hipMalloc(&gl, sizeof(double) * 64));
   TRY(hipMalloc(&thom_d, sizeof(double) * 3 * (DMAX + 1) * (DMAX + 1)));
+  TRY(hipMalloc(&coef_d, sizeof(double) * NMOM * NSERIES));
   TRY(hipMalloc(&flags, sizeof(unsigned)));
   TRY(hipMalloc(&nodes, sizeof(unsigned long long)));
 
@@ -826,7 +886,24 @@ extern "C" dfm_status dfm_assemble(dfm_mesh mesh, const dfm_basis *basis, const 
       cprev = c;
     }
   }
-  TRY(hipMemcpyAsync(thom_d, th.data(), sizeof(double) * th.size(), hipMemcpyHostToDevice, st));
+  TRY(hipMemcpy(thom_d, th.data(), sizeof(double) * th.size(), hipMemcpyHostToDevice));
+  // c_r = (-1)^r (i+r)! m! / (r! (i+r+m+1)!) for the moments (i, m) used by the kernel
+  {
+    const int mi[NMOM] = {0, 2, 1, 0}, mm[NMOM] = {1, 1, 2, 3};
+    std::vector<double> cf(NMOM * NSERIES);
+    for (int w = 0; w < NMOM; ++w) {
+      int i = mi[w], m = mm[w];
+      double c = 1.0;  // r = 0: i! m! / (i+m+1)!
+      for (int k = 1; k <= i; ++k) c *= k;
+      for (int k = 1; k <= m; ++k) c *= k;
+      for (int k = 1; k <= i + m + 1; ++k) c /= k;
+      for (int r = 0; r < NSERIES; ++r) {
+        cf[w * NSERIES + r] = c;
+        c *= -1.0 / (r + 1) * (double)(i + r + 1) / (double)(i + r + m + 2);
+      }
+    }
+    TRY(hipMemcpy(coef_d, cf.data(), sizeof(double) * cf.size(), hipMemcpyHostToDevice));
+  }
   k_gauss_legendre<<<1, 32, 0, st>>>(bs.quad_n, gl);
   TRY(hipGetLastError());
   hipLaunchKernelGGL(k_dest, dim3((unsigned)((4 * mesh->nt + 255) / 256)), dim3(256), 0, st, mesh->nbr,
@@ -845,6 +922,7 @@ extern "C" dfm_status dfm_assemble(dfm_mesh mesh, const dfm_basis *basis, const 
   a.mu = mu;
   a.gl = gl;
   a.thom = thom_d;
+  a.coef = coef_d;
   a.B = op->B;
   a.flags = flags;
   a.nodes = nodes;
@@ -872,9 +950,10 @@ extern "C" dfm_status dfm_assemble(dfm_mesh mesh, const dfm_basis *basis, const 
 #undef TRY
   (void)hipFree(gl);
   (void)hipFree(thom_d);
+  (void)hipFree(coef_d);
   (void)hipFree(flags);
   (void)hipFree(nodes);
-  gl = thom_d = nullptr;
+  gl = thom_d = coef_d = nullptr;
   flags = nullptr;
   nodes = nullptr;
   if (hflags & FLAG_CELL_OVERFLOW) {

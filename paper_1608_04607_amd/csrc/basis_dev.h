@@ -17,12 +17,15 @@ constexpr double SEAM_SNAP = 1e-13;
 
 __device__ inline void legendre_table(double x, int D, double *p) {
   // orthonormal p_a = sqrt(2a+1) P_a by the three-term recurrence
+  // (a+1) P_{a+1} = (2a+1) x P_a - a P_{a-1}; with a a compile-time constant in the
+  // unrolled loop the coefficient quotients fold to constants (no division per node)
   double pm1 = 1.0, pc = x;
   p[0] = 1.0;
 #pragma unroll
   for (int a = 1; a <= DMAX; ++a) {
-    if (a <= D) p[a] = sqrt(2.0 * a + 1.0) * pc;
-    double pn = ((2.0 * a + 1.0) * x * pc - a * pm1) / (a + 1.0);
+    if (a > D) break;
+    p[a] = sqrt(2.0 * a + 1.0) * pc;
+    double pn = ((2.0 * a + 1.0) / (a + 1.0)) * x * pc - (a / (a + 1.0)) * pm1;
     pm1 = pc;
     pc = pn;
   }
@@ -36,7 +39,7 @@ __device__ void momentum_basis(double dx, double dy, double dz, int D, int famil
     if (fabs(dy) <= SEAM_SNAP && dx > 0.0) phi = 0.0;
     double px[DMAX + 1], py[DMAX + 1];
     legendre_table(2.0 * dz - 1.0, D, px);
-    legendre_table(phi / M_PI - 1.0, D, py);
+    legendre_table(phi * (1.0 / M_PI) - 1.0, D, py);
 #pragma unroll
     for (int t = 0; t <= DMAX; ++t) {
       if (t <= D) {
