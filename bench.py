@@ -127,7 +127,7 @@ def main():
         return torch.cuda.Event(enable_timing=True)
 
     def step(record):
-        e = [ev() for _ in range(5)]
+        e = [ev() for _ in range(6)]
         e[0].record(stream)
         mesh = dfm.Mesh(verts, tets, refl=refl)
         e[1].record(stream)
@@ -135,10 +135,15 @@ def main():
         e[2].record(stream)
         rho0 = op.source_plane(0, 0.0, profile=1, params=src)
         e[3].record(stream)
+        # plain FP64 GMRES, then FP32 GMRES corrections inside FP64 iterative refinement
         rho, info = op.solve(rho0, method="gmres", rtol=1e-8, restart=args.restart, max_iter=20000)
         e[4].record(stream)
+        rho_m, info_m = op.solve(rho0, method="gmres", rtol=1e-8, restart=args.restart, max_iter=20000,
+                                 precision=1)
+        e[5].record(stream)
         if record is not None:
-            record.append((e, info, op.nodes, op.nblocks, op.K, op.ndof))
+            diff = float(((rho_m - rho).norm() / rho.norm()).item())
+            record.append((e, info + info_m, op.nodes, op.nblocks, op.K, op.ndof, diff))
         op.close()
         mesh.close()
         return rho
@@ -153,10 +158,10 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 
-    phase = np.array([[r[0][i].elapsed_time(r[0][i + 1]) for i in range(4)] for r in recs])  # ms
-    t_mesh, t_asm, t_src, t_solve = phase.mean(axis=0)
-    info = recs[-1][1][0]
-    nodes, nblocks, K, ndof = recs[-1][2:]
+    phase = np.array([[r[0][i].elapsed_time(r[0][i + 1]) for i in range(5)] for r in recs])  # ms
+    t_mesh, t_asm, t_src, t_solve, t_mixed = phase.mean(axis=0)
+    info, info_m = recs[-1][1]
+    nodes, nblocks, K, ndof, diff = recs[-1][2:]
     blocks_per_s = nblocks * args.steps / (phase[:, 1].sum() / 1e3)
 
     # SpMV kernel: one dfm_apply launch per call, timed with events on the same stream
@@ -180,7 +185,7 @@ def main():
     asm_tflops = flops_asm / (t_asm / 1e3) / 1e12
     spmv_bytes = 8.0 * (12 * (ndof // (4 * K)) * K * K + 2 * ndof)
     spmv_gbs = spmv_bytes / (t_spmv / 1e3) / 1e9
-    t_spmv_step = t_spmv * info[0]
+    t_spmv_step = t_spmv * info[0]  # FP64 solve's operator applications
     roof_asm = {"kernel": "k_assemble", "bound": "mfma", "achieved": asm_tflops, "peak": FP64_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": asm_tflops / FP64_PEAK_TFLOPS, "traffic": None,
                 "algorithmic": f"2*Q*K^2 flop per block, Q summed over blocks = {nodes}, K = {K}"}
@@ -205,12 +210,17 @@ def main():
                                "_mu0.05_R0.9_gauss-patch_gmres1e-8",
                    "tets": int(prob.nt), "blocks": int(nblocks), "K": int(K), "ndof": int(ndof),
                    "quadrature_directions": int(nodes)},
-        "phase_ms": {"mesh_build": t_mesh, "assemble": t_asm, "source": t_src, "solve": t_solve},
-        "solve_ms_per_rhs": t_solve,
-        "solve_iters": info[0],
-        "solve_restarts": info[1],
-        "solve_relres": info[2],
-        "solve_precision": "fp64",
+        "phase_ms": {"mesh_build": t_mesh, "assemble": t_asm, "source": t_src, "solve_fp64": t_solve,
+                     "solve_fp32_refined": t_mixed},
+        "solve_ms_per_rhs": t_mixed,
+        "solve_precision": "fp32 GMRES corrections, fp64 refinement residuals",
+        "solve_relres": info_m[2],
+        "solve_iters": info_m[0],
+        "solve_fp64_ms_per_rhs": t_solve,
+        "solve_fp64_iters": info[0],
+        "solve_fp64_relres": info[2],
+        "solve_speedup_vs_fp64": t_solve / t_mixed,
+        "solve_rel_diff_vs_fp64": diff,
         "spmv_ms": t_spmv,
         "roofline": dominant,
         "roofline_other": other,

@@ -78,7 +78,11 @@ typedef struct {
   int restart;    /* GMRES restart length (Krylov vectors kept), 1..200                 */
   int max_iter;   /* total iteration cap (operator applications)                        */
   double rtol;    /* stop when ||rho0 - (I-B) rho||_2 <= rtol ||rho0||_2                */
-  int precision;  /* 0: FP64 throughout (the only value implemented)                   */
+  int precision;  /* 0: FP64 throughout; 1 (GMRES only): iterative refinement with FP64
+                        residuals of the FP64 operator around FP32 GMRES corrections on an
+                        FP32 copy of B (made on first use, kept with the operator) with FP32
+                        Krylov vectors and FP64 accumulation.  The stop test is the FP64
+                        residual in both cases.                                          */
 } dfm_solve_opts;
 
 typedef struct {

@@ -17,10 +17,12 @@ namespace {
 __device__ inline int in_face(int l_out, int s) { return s < l_out ? s : s + 1; }
 
 // y[dest(br)][row] = alpha * v[dest(br)][row] + beta * sum_{s,col} B[br,s][col][row] x[4j+l_in(s)][col]
-// (v may be null when alpha == 0).
-__global__ void k_spmv(const double *__restrict__ B, const int32_t *__restrict__ dest, int64_t nrows, int K,
-                       const double *__restrict__ x, const double *__restrict__ v, double *__restrict__ y,
-                       double alpha, double beta) {
+// (v may be null when alpha == 0); TB / TX are the storage types of B and of the
+// vectors, the sum is accumulated in FP64.
+template <typename TB, typename TX>
+__global__ void k_spmv(const TB *__restrict__ B, const int32_t *__restrict__ dest, int64_t nrows, int K,
+                       const TX *__restrict__ x, const TX *__restrict__ v, TX *__restrict__ y, double alpha,
+                       double beta) {
   int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (g >= nrows) return;
   int64_t br = g / K;
@@ -30,15 +32,20 @@ __global__ void k_spmv(const double *__restrict__ B, const int32_t *__restrict__
   const int64_t KK = (int64_t)K * K;
   double acc = 0.0;
   for (int s = 0; s < 3; ++s) {
-    const double *Bb = B + (br * 3 + s) * KK + row;
-    const double *xs = x + (4 * j + in_face(l_out, s)) * (int64_t)K;
+    const TB *Bb = B + (br * 3 + s) * KK + row;
+    const TX *xs = x + (4 * j + in_face(l_out, s)) * (int64_t)K;
 #pragma unroll 8
-    for (int col = 0; col < K; ++col) acc = fma(Bb[(int64_t)col * K], xs[col], acc);
+    for (int col = 0; col < K; ++col) acc = fma((double)Bb[(int64_t)col * K], (double)xs[col], acc);
   }
   int64_t o = (int64_t)dest[br] * K + row;
   double r = beta * acc;
-  if (v) r = fma(alpha, v[o], r);
-  y[o] = r;
+  if (v) r = fma(alpha, (double)v[o], r);
+  y[o] = (TX)r;
+}
+
+__global__ void k_to_fp32(const double *__restrict__ a, float *__restrict__ b, int64_t n) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (float)a[i];
 }
 
 // y[4j + l_in][col] = sum_{l_out != l_in} sum_row B[j,l_out,s(l_in)][col][row] x[dest(j,l_out)][row]
@@ -68,7 +75,29 @@ __global__ void k_spmv_t(const double *__restrict__ B, const int32_t *__restrict
 hipError_t spmv(dfm_op op, const double *x, const double *v, double *y, double alpha, double beta, hipStream_t st) {
   int64_t nrows = op->ndof;
   unsigned grid = (unsigned)((nrows + 255) / 256);
-  hipLaunchKernelGGL(k_spmv, dim3(grid), dim3(256), 0, st, op->B, op->dest, nrows, op->K, x, v, y, alpha, beta);
+  hipLaunchKernelGGL((k_spmv<double, double>), dim3(grid), dim3(256), 0, st, op->B, op->dest, nrows, op->K, x, v, y,
+                     alpha, beta);
+  return hipGetLastError();
+}
+
+hipError_t spmv32(dfm_op op, const float *x, const float *v, float *y, float alpha, float beta, hipStream_t st) {
+  int64_t nrows = op->ndof;
+  unsigned grid = (unsigned)((nrows + 255) / 256);
+  hipLaunchKernelGGL((k_spmv<float, float>), dim3(grid), dim3(256), 0, st, op->B32, op->dest, nrows, op->K, x, v, y,
+                     (double)alpha, (double)beta);
+  return hipGetLastError();
+}
+
+// FP32 copy of B for the mixed-precision solver (made once, kept with the operator)
+hipError_t ensure_fp32(dfm_op op, hipStream_t st) {
+  if (op->B32) return hipSuccess;
+  int64_t nel = 12 * op->nt * (int64_t)op->K * op->K;
+  hipError_t e = hipMalloc(&op->B32, sizeof(float) * nel);
+  if (e != hipSuccess) {
+    op->B32 = nullptr;
+    return e;
+  }
+  hipLaunchKernelGGL(k_to_fp32, dim3((unsigned)((nel + 255) / 256)), dim3(256), 0, st, op->B, op->B32, nel);
   return hipGetLastError();
 }
 

@@ -793,6 +793,7 @@ hipError_t launch_p(int maxt, const AsmArgs &a, size_t lds, hipStream_t st) {
 void free_op(dfm_op op) {
   if (!op) return;
   (void)hipFree(op->B);
+  (void)hipFree(op->B32);
   (void)hipFree(op->dest);
   delete op;
 }

@@ -64,5 +64,6 @@ struct dfm_op_s {
   int64_t nt = 0, ndof = 0;
   int64_t nodes = 0;
   double *B = nullptr;        // [nt][4][3K][K]: block (j, l_out, s) column-major K x K
+  float *B32 = nullptr;       // same layout in FP32, made on first mixed-precision solve
   int32_t *dest = nullptr;    // [nt][4]
 };

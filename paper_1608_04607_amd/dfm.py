@@ -112,11 +112,12 @@ class Operator:
         check(_lib.load().dfm_apply(self.handle, _ptr(x), _ptr(y), nrhs, int(bool(transpose)), _stream(stream)))
         return y
 
-    def solve(self, rho0, method="gmres", rtol=1e-8, restart=50, max_iter=20000, stream=None, raise_nonconv=True):
+    def solve(self, rho0, method="gmres", rtol=1e-8, restart=50, max_iter=20000, precision=0, stream=None,
+              raise_nonconv=True):
         rho0 = _dev(rho0, torch.float64)
         nrhs = 1 if rho0.dim() == 1 else rho0.shape[0]
         rho = torch.empty_like(rho0)
-        opts = SolveOpts(1 if method == "gmres" else 0, restart, max_iter, rtol, 0)
+        opts = SolveOpts(1 if method == "gmres" else 0, restart, max_iter, rtol, int(precision))
         info = (SolveInfo * nrhs)()
         code = _lib.load().dfm_solve(self.handle, _ptr(rho0), _ptr(rho), nrhs, C.byref(opts), info, _stream(stream))
         if code != 0 and (raise_nonconv or code != -5):

@@ -202,6 +202,20 @@ def test_solve_matches_oracle(small, method):
     assert rel(rho.cpu().numpy(), ref) < 1e-9
 
 
+def test_mixed_precision_solve_matches_oracle(small):
+    """FP32 GMRES corrections refined with FP64 residuals reach the FP64 tolerance."""
+    say("[solve] gmres, FP32 + FP64 refinement")
+    g, op, m, bs, Bo, desto, mu = small
+    A = osv.to_sparse(Bo, desto)
+    rhs = np.random.default_rng(9).standard_normal(A.shape[0])
+    ref = osv.solve_direct(A, rhs)
+    rho, info = op.solve(torch.tensor(rhs, device=DEV), method="gmres", rtol=1e-11, restart=30, precision=1)
+    say(f"    info {info}")
+    assert info[0][2] <= 1e-11
+    assert osv.relres(A, rhs, rho.cpu().numpy()) <= 2e-11
+    assert rel(rho.cpu().numpy(), ref) < 1e-8
+
+
 def test_cube_neumann_matches_direct():
     say("[solve] cube, Neumann to 1e-12")
     p = synth.problem_c1()
