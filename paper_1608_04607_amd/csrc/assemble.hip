@@ -65,7 +65,7 @@ struct AsmArgs {
   unsigned *flags;
   unsigned long long *nodes;
   int64_t nblocks;
-  int P, D, M, Mp, K, n, family, rule;
+  int P, D, M, Mp, K, Kp, n, family, rule;
   int chunk;
   int nsplit, tiles_per_split, total_tiles, row_tiles;
 };
@@ -713,7 +713,8 @@ __global__ __launch_bounds__(NTHREADS) void k_assemble(AsmArgs A) {
   }
 
   // write out: lane holds rows lane/16 + 4e (e = 0..3), column lane%16 of each tile
-  double *Bb = A.B + (int64_t)blk * K * K;
+  const int Kp = A.Kp;
+  double *Bb = A.B + (int64_t)blk * K * Kp;
   const double wgt = G.weight;
   bool bad = false;
 #pragma unroll
@@ -732,12 +733,18 @@ __global__ __launch_bounds__(NTHREADS) void k_assemble(AsmArgs A) {
           if (kp < M) {
             double v = wgt * acc[i][e];
             bad |= !isfinite(v);
-            Bb[(int64_t)(p * M + k) * K + (pp * M + kp)] = v;
+            Bb[(int64_t)(p * M + k) * Kp + (pp * M + kp)] = v;
           }
         }
       }
     }
   }
+  // zero the padding rows K..Kp-1 of every column
+  if (split == 0)
+    for (int i = tid; i < K * (Kp - K); i += NTHREADS) {
+      int c = i / (Kp - K), rr = K + (i - c * (Kp - K));
+      Bb[(int64_t)c * Kp + rr] = 0.0;
+    }
   if (bad) atomicOr(A.flags, FLAG_NONFINITE);
 }
 
@@ -841,6 +848,7 @@ extern "C" dfm_status dfm_assemble(dfm_mesh mesh, const dfm_basis *basis, const 
   op->P = P;
   op->M = M;
   op->K = K;
+  op->Kp = (K + 3) / 4 * 4;
   op->nt = mesh->nt;
   op->ndof = 4 * mesh->nt * (int64_t)K;
   const int64_t nblocks = 12 * mesh->nt;
@@ -864,7 +872,7 @@ extern "C" dfm_status dfm_assemble(dfm_mesh mesh, const dfm_basis *basis, const 
       return fail(e_ == hipErrorOutOfMemory ? DFM_E_NOMEM : DFM_E_HIP);                      \
     }                                                                                        \
   } while (0)
-  TRY(hipMalloc(&op->B, sizeof(double) * (size_t)nblocks * K * K));
+  TRY(hipMalloc(&op->B, sizeof(double) * (size_t)nblocks * K * op->Kp));
   TRY(hipMalloc(&op->dest, sizeof(int32_t) * 4 * mesh->nt));
   TRY(hipMalloc(&gl, sizeof(double) * 64));
   TRY(hipMalloc(&thom_d, sizeof(double) * 3 * (DMAX + 1) * (DMAX + 1)));
@@ -933,6 +941,7 @@ extern "C" dfm_status dfm_assemble(dfm_mesh mesh, const dfm_basis *basis, const 
   a.M = M;
   a.Mp = Mp;
   a.K = K;
+  a.Kp = op->Kp;
   a.n = bs.quad_n;
   a.family = bs.mom_family;
   a.rule = bs.rule;
@@ -979,20 +988,20 @@ extern "C" dfm_status dfm_op_info(dfm_op op, int64_t *ndof, int64_t *K, int64_t 
   if (K) *K = op->K;
   if (nblocks) *nblocks = 12 * op->nt;
   if (nodes) *nodes = op->nodes;
-  if (bytes) *bytes = (int64_t)sizeof(double) * 12 * op->nt * op->K * op->K;
+  if (bytes) *bytes = (int64_t)sizeof(double) * 12 * op->nt * op->K * op->Kp;
   return DFM_OK;
 }
 
 namespace {
 // blocks out [nt][4][3][K][K] row-major from the internal column-major blocks
-__global__ void k_export_blocks(const double *B, int64_t nblk, int K, double *out) {
+__global__ void k_export_blocks(const double *B, int64_t nblk, int K, int Kp, double *out) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   int64_t kk = (int64_t)K * K;
   if (i >= nblk * kk) return;
   int64_t b = i / kk;
   int64_t e = i - b * kk;
   int row = (int)(e / K), col = (int)(e - (int64_t)row * K);
-  out[i] = B[b * kk + (int64_t)col * K + row];
+  out[i] = B[b * (int64_t)K * Kp + (int64_t)col * Kp + row];
 }
 }  // namespace
 
@@ -1003,7 +1012,7 @@ extern "C" dfm_status dfm_op_export(dfm_op op, double *blocks, int32_t *dest, vo
     int64_t nblk = 12 * op->nt;
     int64_t tot = nblk * op->K * op->K;
     hipLaunchKernelGGL(k_export_blocks, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, op->B, nblk, op->K,
-                       blocks);
+                       op->Kp, blocks);
     DFM_HIP(hipGetLastError());
   }
   if (dest) DFM_HIP(hipMemcpyAsync(dest, op->dest, sizeof(int32_t) * 4 * op->nt, hipMemcpyDeviceToDevice, st));

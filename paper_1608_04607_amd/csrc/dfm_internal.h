@@ -60,10 +60,10 @@ struct dfm_mesh_s {
 struct dfm_op_s {
   dfm_mesh mesh = nullptr;
   dfm_basis basis{};
-  int P = 1, M = 1, K = 1;
+  int P = 1, M = 1, K = 1, Kp = 4;  // Kp: padded column length of the stored blocks
   int64_t nt = 0, ndof = 0;
   int64_t nodes = 0;
-  double *B = nullptr;        // [nt][4][3K][K]: block (j, l_out, s) column-major K x K
+  double *B = nullptr;        // [nt][4][3K][Kp]: block (j, l_out, s) column-major, K columns of length Kp
   float *B32 = nullptr;       // same layout in FP32, made on first mixed-precision solve
   int32_t *dest = nullptr;    // [nt][4]
 };

@@ -24,7 +24,7 @@ hipError_t ensure_fp32(dfm_op op, hipStream_t st);
 
 namespace {
 
-constexpr int RED_BLOCKS = 512;
+constexpr int RED_BLOCKS = 2048;
 constexpr int RED_THREADS = 256;
 constexpr int NWAVE = RED_THREADS / 64;
 constexpr int MAXV = 201;
@@ -33,9 +33,11 @@ constexpr int MAXV = 201;
 // Each thread keeps a slice of w in registers, so V is read exactly once.
 template <typename T>
 __global__ __launch_bounds__(RED_THREADS) void k_multidot(const T *__restrict__ V, int64_t ldv, int nvec,
-                                                        const T *__restrict__ w, int64_t n,
-                                                        double *__restrict__ partial) {
-  constexpr int RPT = 16;  // rows per thread kept in registers per sweep
+                                                        const T *__restrict__ extra, const T *__restrict__ w,
+                                                        int64_t n, double *__restrict__ partial) {
+  // vectors 0..nvec-1 are V[i], vector nvec (when extra != null) is `extra`
+  if (extra) ++nvec;
+  constexpr int RPT = 8;  // rows per thread kept in registers per sweep
   __shared__ double red[NWAVE][64];
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t r0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -51,7 +53,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_multidot(const T *__restrict__ 
         wr[u] = r < n ? (double)w[r] : 0.0;
       }
       for (int i = 0; i < ni; ++i) {
-        const T *vi = V + (int64_t)(i0 + i) * ldv;
+        const T *vi = (extra && i0 + i == nvec - 1) ? extra : V + (int64_t)(i0 + i) * ldv;
         double a = 0.0;
 #pragma unroll
         for (int u = 0; u < RPT; ++u) {
@@ -89,18 +91,33 @@ __global__ void k_reduce_partials(const double *__restrict__ partial, int nb, do
   }
 }
 
-// w[row] += sign * sum_i V[i][row] * h[i]
+// w[row] += sign * sum_i V[i][row] * h[i]; when partial != null also the block
+// partial sums of ||w_new||^2 (grid-stride, RED_BLOCKS blocks)
 template <typename T>
-__global__ void k_combine(const T *__restrict__ V, int64_t ldv, int nvec, const double *__restrict__ h, double sign,
-                          T *__restrict__ w, int64_t n) {
+__global__ __launch_bounds__(RED_THREADS) void k_combine(const T *__restrict__ V, int64_t ldv, int nvec,
+                                                       const double *__restrict__ h, double sign, T *__restrict__ w,
+                                                       int64_t n, double *__restrict__ partial) {
   __shared__ double hs[MAXV];
+  __shared__ double red[NWAVE];
   for (int i = threadIdx.x; i < nvec; i += blockDim.x) hs[i] = h[i];
   __syncthreads();
-  int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (r >= n) return;
-  double acc = 0.0;
-  for (int i = 0; i < nvec; ++i) acc = fma((double)V[(int64_t)i * ldv + r], hs[i], acc);
-  w[r] = (T)fma(sign, acc, (double)w[r]);
+  double nrm = 0.0;
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int i = 0; i < nvec; ++i) acc = fma((double)V[(int64_t)i * ldv + r], hs[i], acc);
+    T nw = (T)fma(sign, acc, (double)w[r]);
+    w[r] = nw;
+    nrm = fma((double)nw, (double)nw, nrm);
+  }
+  if (!partial) return;
+  for (int off = 32; off > 0; off >>= 1) nrm += __shfl_down(nrm, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nrm;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int k = 0; k < NWAVE; ++k) t += red[k];
+    partial[blockIdx.x] = t;
+  }
 }
 
 template <typename T>
@@ -139,10 +156,25 @@ struct Ctx {
   double *partial = nullptr;  // [MAXV][RED_BLOCKS]
   double *dsc = nullptr;      // device scalars
   unsigned grid() const { return (unsigned)((n + 255) / 256); }
+  // out[0..nvec) = V^T w, and out[nvec] = extra . w when extra != null (device)
   template <typename T>
-  hipError_t dots(const T *V, int64_t ldv, int nvec, const T *w, double *out) {
-    hipLaunchKernelGGL(k_multidot<T>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, st, V, ldv, nvec, w, n, partial);
-    hipLaunchKernelGGL(k_reduce_partials, dim3(nvec), dim3(RED_THREADS), 0, st, partial, RED_BLOCKS, out);
+  hipError_t dots(const T *V, int64_t ldv, int nvec, const T *w, double *out, const T *extra = nullptr) {
+    int nout = nvec + (extra ? 1 : 0);
+    hipLaunchKernelGGL(k_multidot<T>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, st, V, ldv, nvec, extra, w, n, partial);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(nout), dim3(RED_THREADS), 0, st, partial, RED_BLOCKS, out);
+    return hipGetLastError();
+  }
+  // w += sign V h; *nrm2_out = ||w||^2 (device) when nrm2_out != null
+  template <typename T>
+  hipError_t combine(const T *V, int64_t ldv, int nvec, const double *h, double sign, T *w, double *nrm2_out) {
+    if (nrm2_out) {
+      hipLaunchKernelGGL(k_combine<T>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, st, V, ldv, nvec, h, sign, w, n,
+                         partial);
+      hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(RED_THREADS), 0, st, partial, RED_BLOCKS, nrm2_out);
+    } else {
+      hipLaunchKernelGGL(k_combine<T>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, st, V, ldv, nvec, h, sign, w, n,
+                         (double *)nullptr);
+    }
     return hipGetLastError();
   }
   template <typename T>
@@ -194,20 +226,18 @@ hipError_t gmres(Ctx &c, const T *b, T *x, T *V, T *w, T *t, int m, double rtol,
       T *vk = V + (int64_t)k * n;
       if ((e = c.apply_ImB(vk, w)) != hipSuccess) return e;
       its++;
-      // classical Gram-Schmidt; a second pass when the first lost > 30 % of ||w||
-      if ((e = c.dots<T>(w, 0, 1, w, c.dsc)) != hipSuccess) return e;
-      if ((e = c.dots<T>(V, n, k + 1, w, h1)) != hipSuccess) return e;
-      hipLaunchKernelGGL(k_combine<T>, dim3(G), dim3(256), 0, c.st, V, n, k + 1, h1, -1.0, w, n);
-      if ((e = c.dots<T>(w, 0, 1, w, c.dsc + 1)) != hipSuccess) return e;
+      // classical Gram-Schmidt: one pass for V^T w and ||w||^2, one for w -= V h
+      // and ||w||^2; a second pass when the first lost > 30 % of ||w||
+      if ((e = c.dots<T>(V, n, k + 1, w, h1, w)) != hipSuccess) return e;  // h1[k+1] = ||w||^2
+      if ((e = c.combine<T>(V, n, k + 1, h1, -1.0, w, c.dsc + 1)) != hipSuccess) return e;
       if ((e = hipMemcpyAsync(hh.data(), c.dsc, sizeof(double) * (8 + nvmax), hipMemcpyDeviceToHost, c.st)))
         return e;
       if ((e = hipStreamSynchronize(c.st)) != hipSuccess) return e;
-      double before = std::sqrt(hh[0]), hn = std::sqrt(hh[1]);
+      double before = std::sqrt(hh[8 + k + 1]), hn = std::sqrt(hh[1]);
       for (int i = 0; i <= k; ++i) H[(size_t)i * m + k] = hh[8 + i];
       if (hn < 0.7 * before) {
         if ((e = c.dots<T>(V, n, k + 1, w, h2)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_combine<T>, dim3(G), dim3(256), 0, c.st, V, n, k + 1, h2, -1.0, w, n);
-        if ((e = c.dots<T>(w, 0, 1, w, c.dsc + 1)) != hipSuccess) return e;
+        if ((e = c.combine<T>(V, n, k + 1, h2, -1.0, w, c.dsc + 1)) != hipSuccess) return e;
         if ((e = hipMemcpyAsync(hh.data() + 1, c.dsc + 1, sizeof(double), hipMemcpyDeviceToHost, c.st))) return e;
         if ((e = hipMemcpyAsync(hh.data() + 8 + nvmax, h2, sizeof(double) * (k + 1), hipMemcpyDeviceToHost, c.st)))
           return e;
@@ -243,7 +273,7 @@ hipError_t gmres(Ctx &c, const T *b, T *x, T *V, T *w, T *t, int m, double rtol,
       y[i] = s / H[(size_t)i * m + i];
     }
     if ((e = hipMemcpyAsync(h1, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, c.st))) return e;
-    hipLaunchKernelGGL(k_combine<T>, dim3(G), dim3(256), 0, c.st, V, n, k, h1, 1.0, x, n);
+    if ((e = c.combine<T>(V, n, k, h1, 1.0, x, nullptr)) != hipSuccess) return e;
     if (!check_true && rel <= rtol) {
       if ((e = hipStreamSynchronize(c.st)) != hipSuccess) return e;
       done = true;
