@@ -175,6 +175,32 @@ dfm_status dfm_source_points(dfm_op op, const double *xyz, int64_t ns, double fl
 dfm_status dfm_source_plane(dfm_op op, int axis, double value, int profile, const double *params,
                             double flux, double *rho0, void *stream);
 
+/* Receiver energy (Sec. 4.1, Eq. IntDens integrated over a tet): the energy in
+ * tet j carried by a density rho is E_j = sum_l int rho (1 - exp(-mu_j L))/mu_j ds dp
+ * (L the chord from the start point; L itself when mu_j = 0), which equals the
+ * interior density of Eq. IntDens integrated over the tet.  J = sum of E_j over
+ * the tets whose centroid lies in the closed box = g . rho.
+ *   mu   device f64 [nt] the damping the operator was assembled with
+ *   box  host f64 [6] xmin, xmax, ymin, ymax, zmin, zmax
+ *   g    device f64 [ndof] (overwritten)
+ * The directions are those of the operator's blocks.  Synchronises `stream`. */
+dfm_status dfm_receiver_functional(dfm_op op, const double *mu, const double *box, double *g, void *stream);
+
+/* Gradients of J = g . rho by the adjoint of (I - B) rho = rho0 (Sec. 2, Eq. GovIE):
+ * solves (I - B)^T lambda = g (FP64 GMRES or Neumann per opts, precision 0 only),
+ * then dJ/dmu_j = lambda^T dB/dmu_j rho + rho . dg/dmu_j for every tet and, for the
+ * source weights w of rho0 = sum_s w_s rho0_s, dJ/dw_s = lambda . rho0_s.
+ *   mu, box as for dfm_receiver_functional; rho device f64 [ndof] the forward
+ *   solution; src device f64 [nsrc][ndof] the unit sources (may be NULL when
+ *   nsrc = 0); lambda device f64 [ndof] out; d_mu device f64 [nt] out; d_w device
+ *   f64 [nsrc] out; info host [1] or NULL.
+ * dB/dmu_j is exact for the assembled B (same directions; the spatial integral is
+ * differentiated analytically).  Returns DFM_E_NOCONV (gradients still written)
+ * if the adjoint solve stops above opts->rtol.  Synchronises `stream`. */
+dfm_status dfm_adjoint(dfm_op op, const double *mu, const double *box, const double *rho, const double *src,
+                       int nsrc, const dfm_solve_opts *opts, double *lambda, double *d_mu, double *d_w,
+                       dfm_solve_info *info, void *stream);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *dfm_last_error(void);
 

@@ -104,9 +104,10 @@ __global__ void k_to_fp32(const double *__restrict__ a, float *__restrict__ b, i
   if (i < n) b[i] = (float)a[i];
 }
 
-// y[4j + l_in][col] = sum_{l_out != l_in} sum_row B[j,l_out,s(l_in)][col][row] x[dest(j,l_out)][row]
+// y[4j + l_in][col] = alpha v[...] + beta sum_{l_out != l_in} sum_row B[j,l_out,s(l_in)][col][row] x[dest(j,l_out)][row]
 __global__ void k_spmv_t(const double *__restrict__ B, const int32_t *__restrict__ dest, int64_t nrows, int K, int Kp,
-                         const double *__restrict__ x, double *__restrict__ y) {
+                         const double *__restrict__ x, const double *__restrict__ v, double *__restrict__ y,
+                         double alpha, double beta) {
   int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (g >= nrows) return;
   int64_t slot = g / K;
@@ -123,7 +124,9 @@ __global__ void k_spmv_t(const double *__restrict__ B, const int32_t *__restrict
     const double *xs = x + (int64_t)dest[br] * K;
     for (int row = 0; row < K; ++row) acc = fma(Bb[row], xs[row], acc);
   }
-  y[g] = acc;
+  double r = beta * acc;
+  if (v) r = fma(alpha, v[g], r);
+  y[g] = r;
 }
 
 }  // namespace
@@ -157,10 +160,11 @@ hipError_t ensure_fp32(dfm_op op, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t spmv_t(dfm_op op, const double *x, double *y, hipStream_t st) {
+hipError_t spmv_t(dfm_op op, const double *x, const double *v, double *y, double alpha, double beta, hipStream_t st) {
   int64_t nrows = op->ndof;
   unsigned grid = (unsigned)((nrows + 255) / 256);
-  hipLaunchKernelGGL(k_spmv_t, dim3(grid), dim3(256), 0, st, op->B, op->dest, nrows, op->K, op->Kp, x, y);
+  hipLaunchKernelGGL(k_spmv_t, dim3(grid), dim3(256), 0, st, op->B, op->dest, nrows, op->K, op->Kp, x, v, y, alpha,
+                     beta);
   return hipGetLastError();
 }
 
@@ -176,7 +180,7 @@ extern "C" dfm_status dfm_apply(dfm_op op, const double *x, double *y, int nrhs,
   for (int r = 0; r < nrhs; ++r) {
     const double *xr = x + (int64_t)r * op->ndof;
     double *yr = y + (int64_t)r * op->ndof;
-    DFM_HIP(transpose ? spmv_t(op, xr, yr, st) : spmv(op, xr, nullptr, yr, 0.0, 1.0, st));
+    DFM_HIP(transpose ? spmv_t(op, xr, nullptr, yr, 0.0, 1.0, st) : spmv(op, xr, nullptr, yr, 0.0, 1.0, st));
   }
   return DFM_OK;
 }

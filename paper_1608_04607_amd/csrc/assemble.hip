@@ -62,6 +62,11 @@ struct AsmArgs {
   const double *thom;   // [3][DMAX+1][DMAX+1]: Jacobi off-diagonal, Thomas c', 1/denominator
   const double *coef;   // [NMOM][NSERIES] power-series coefficients of the chord moments
   double *B;
+  const double *rho;    // adjoint: forward solution [ndof]
+  const double *lam;    // adjoint: adjoint solution [ndof]
+  double *out_vec;      // energy: per-block contribution to g [nblocks][K]
+  double *out_scal;     // per-block scalar [nblocks]
+  double box[6];        // receiver box xmin, xmax, ymin, ymax, zmin, zmax
   unsigned *flags;
   unsigned long long *nodes;
   int64_t nblocks;
@@ -100,15 +105,22 @@ __device__ inline void unit3(double *v) {
   v[2] /= n;
 }
 
-// I_{i,m}(a) = int_0^1 u^i (1-u)^m exp(-a u) du.
-// For a <= 2: the power series sum_r c_r a^r, c_r = (-1)^r (i+r)! m! / (r! (i+r+m+1)!),
-// by Horner with the coefficients tabulated once per launch (40 terms).
-// For a > 2: the binomial expansion of (1-u)^m over J_n(a) = int_0^1 u^n e^{-au} du =
-// n!/a^{n+1} (1 - e^{-a} sum_{k<=n} a^k/k!).
+// Chord moments, tabulated as power series in a = mu L_max (40 terms, a <= 2):
+//   kind 0: I_{i,m}(a) = int_0^1 u^i (1-u)^m exp(-a u) du,
+//           c_r = (-1)^r (i+r)! m! / (r! (i+r+m+1)!);
+//   kind 1: H_{i,m}(a) = int_0^1 u^i (1-u)^m (1 - exp(-a u))/a du,
+//           c_r = (-1)^r (i+r+1)! m! / ((r+1)! (i+r+m+2)!);
+//   kind 2: d/da H_{i,m}(a), c_r = (r+1) c^H_{r+1}.
+// For a > 2 the closed forms: the binomial expansion of (1-u)^m over
+// J_n(a) = int_0^1 u^n e^{-au} du = n!/a^{n+1} (1 - e^{-a} sum_{k<=n} a^k/k!) for I,
+// H = (B - I_{i,m})/a and H' = (a I_{i+1,m} - (B - I_{i,m}))/a^2 with B = i! m!/(i+m+1)!.
 constexpr int NSERIES = 40;
-constexpr int NMOM = 4;   // (i, m) = (0,1), (2,1), (1,2), (0,3)
-__device__ __constant__ const int MOM_I[NMOM] = {0, 2, 1, 0};
-__device__ __constant__ const int MOM_M[NMOM] = {1, 1, 2, 3};
+constexpr int NMOM = 12;
+// 0..3: I for S (0,1)(2,1)(1,2)(0,3); 4..7: I for dS/da (1,1)(3,1)(2,2)(1,3);
+// 8, 9: H (1,1)(0,2) for the chord energy; 10, 11: their derivatives
+__device__ __constant__ const int MOM_KIND[NMOM] = {0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 2, 2};
+__device__ __constant__ const int MOM_I[NMOM] = {0, 2, 1, 0, 1, 3, 2, 1, 1, 0, 1, 0};
+__device__ __constant__ const int MOM_M[NMOM] = {1, 1, 2, 3, 1, 1, 2, 3, 1, 2, 1, 2};
 
 __device__ double moment_closed(int i, int m, double a) {
   double ea = exp(-a);
@@ -131,15 +143,26 @@ __device__ double moment_closed(int i, int m, double a) {
   return sum;
 }
 
+__device__ double moment_large(int which, double a) {
+  const int kind = MOM_KIND[which], i = MOM_I[which], m = MOM_M[which];
+  if (kind == 0) return moment_closed(i, m, a);
+  double B = 1.0;
+  for (int k = 1; k <= i; ++k) B *= k;
+  for (int k = 1; k <= m; ++k) B *= k;
+  for (int k = 1; k <= i + m + 1; ++k) B /= k;
+  const double Iim = moment_closed(i, m, a);
+  if (kind == 1) return (B - Iim) / a;
+  return (a * moment_closed(i + 1, m, a) - (B - Iim)) / (a * a);
+}
+
 __device__ inline double moment(const double *coef, int which, double a) {
-  if (a > 2.0) return moment_closed(MOM_I[which], MOM_M[which], a);
+  if (a > 2.0) return moment_large(which, a);
   const double *c = coef + which * NSERIES;
   double s = c[NSERIES - 1];
 #pragma unroll 8
   for (int r = NSERIES - 2; r >= 0; --r) s = fma(s, a, c[r]);
   return s;
 }
-
 
 // ---------------------------------------------------------------------------
 // Cells (lane 0 of the workgroup)
@@ -511,6 +534,193 @@ __device__ void spatial_weights(const BlockGeo &G, const double *coef, const dou
       sw[pp * 3 + p] = W * (bout[0][pp] * tmp[0][p] + bout[1][pp] * tmp[1][p] + bout[2][pp] * tmp[2][p]);
 }
 
+// W * dS[p'][p]/dmu for one direction: the spatial integral differentiated in mu
+// through a = mu L_max, d/da I_{i,m} = -I_{i+1,m}.
+template <int P>
+__device__ void dspatial_weights(const BlockGeo &G, const double *coef, const double *d, double W, double *sw) {
+  const int li = G.l_in, lo = G.l_out;
+  double c[4];
+  double A = 0.0;
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    c[g] = (g == li) ? 0.0 : G.area[g] * dot3(d, G.nrm[g]);
+    if (g != li) A += fmax(c[g], 0.0);
+  }
+  const double iA = 1.0 / A;
+  const double om = fmax(c[lo], 0.0) * iA;
+  const double L = (3.0 * G.vol) * iA;
+  const double a = G.mu * L;
+  if (P == 1) {
+    sw[0] = (om > 0.0) ? -W * 2.0 * om * moment(coef, 4, a) * G.sqrt_ratio * L : 0.0;
+    return;
+  }
+  if (!(om > 0.0)) {
+#pragma unroll
+    for (int i = 0; i < P * P; ++i) sw[i] = 0.0;
+    return;
+  }
+  const int xb = G.xb, y = (xb + 1) % 3, z = (xb + 2) % 3;
+  double lamO[3] = {fmax(c[G.base[0]], 0.0) * iA, fmax(c[G.base[1]], 0.0) * iA, fmax(c[G.base[2]], 0.0) * iA};
+  double lamY[3] = {0.0, 0.0, 0.0}, lamZ[3] = {0.0, 0.0, 0.0};
+  lamY[y] = 1.0;
+  lamZ[z] = 1.0;
+  double bin[3][3];
+  pos_basis_n(lamO, G.en_in, bin[0]);
+  pos_basis_n(lamY, G.en_in, bin[1]);
+  pos_basis_n(lamZ, G.en_in, bin[2]);
+  const double cos_in = dot3(d, G.zin);
+  double lamE[3], lamYo[3], lamZo[3];
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    int v = G.oface[t];
+    lamE[t] = (v == li) ? G.area[li] * cos_in * iA : fmax(-c[v], 0.0) * iA;
+    lamYo[t] = (v == G.base[y]) ? 1.0 : 0.0;
+    lamZo[t] = (v == G.base[z]) ? 1.0 : 0.0;
+  }
+  double bout[3][3];
+  pos_basis_n(lamE, G.en_out, bout[0]);
+  pos_basis_n(lamYo, G.en_out, bout[1]);
+  pos_basis_n(lamZo, G.en_out, bout[2]);
+  const double T = -om * G.area[li] * L;
+  const double I31 = moment(coef, 5, a), I22 = moment(coef, 6, a), I13 = moment(coef, 7, a);
+  double Gm[3][3];
+  Gm[0][0] = 2.0 * T * I31;
+  Gm[0][1] = Gm[1][0] = Gm[0][2] = Gm[2][0] = T * I22;
+  Gm[1][1] = Gm[2][2] = (2.0 / 3.0) * T * I13;
+  Gm[1][2] = Gm[2][1] = (1.0 / 3.0) * T * I13;
+  double tmp[3][3];
+#pragma unroll
+  for (int al = 0; al < 3; ++al)
+#pragma unroll
+    for (int p = 0; p < 3; ++p) tmp[al][p] = Gm[al][0] * bin[0][p] + Gm[al][1] * bin[1][p] + Gm[al][2] * bin[2][p];
+#pragma unroll
+  for (int pp = 0; pp < 3; ++pp)
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+      sw[pp * 3 + p] = W * (bout[0][pp] * tmp[0][p] + bout[1][pp] * tmp[1][p] + bout[2][pp] * tmp[2][p]);
+}
+
+// Chord energy of the start set of face l_out: W * int b_p(s) (1 - exp(-mu L))/mu ds
+// into e[p], and its mu-derivative into de[p].  L = L_max b_O on the start set,
+// so with h(a, u) = (1 - exp(-a u))/a the corner moments are
+// int_T b_O h = 2|T| H_{1,1}(a) L_max and int_T b_Y h = |T| H_{0,2}(a) L_max.
+template <int P>
+__device__ void energy_weights(const BlockGeo &G, const double *coef, const double *d, double W, double *e,
+                               double *de) {
+  const int li = G.l_in, lo = G.l_out;
+  double c[4];
+  double A = 0.0;
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    c[g] = (g == li) ? 0.0 : G.area[g] * dot3(d, G.nrm[g]);
+    if (g != li) A += fmax(c[g], 0.0);
+  }
+  const double iA = 1.0 / A;
+  const double om = fmax(c[lo], 0.0) * iA;
+  if (!(om > 0.0)) {
+#pragma unroll
+    for (int p = 0; p < P; ++p) e[p] = de[p] = 0.0;
+    return;
+  }
+  const double L = (3.0 * G.vol) * iA;
+  const double a = G.mu * L;
+  const double T = om * G.area[li];
+  const double fO = 2.0 * T * moment(coef, 8, a) * L, fYZ = T * moment(coef, 9, a) * L;
+  const double dO = 2.0 * T * moment(coef, 10, a) * L * L, dYZ = T * moment(coef, 11, a) * L * L;
+  if (P == 1) {
+    e[0] = W * G.en_in[0] * (fO + 2.0 * fYZ);
+    de[0] = W * G.en_in[0] * (dO + 2.0 * dYZ);
+    return;
+  }
+  const int xb = G.xb, y = (xb + 1) % 3, z = (xb + 2) % 3;
+  double lamO[3] = {fmax(c[G.base[0]], 0.0) * iA, fmax(c[G.base[1]], 0.0) * iA, fmax(c[G.base[2]], 0.0) * iA};
+  double lamY[3] = {0.0, 0.0, 0.0}, lamZ[3] = {0.0, 0.0, 0.0};
+  lamY[y] = 1.0;
+  lamZ[z] = 1.0;
+  double bO[3], bY[3], bZ[3];
+  pos_basis_n(lamO, G.en_in, bO);
+  pos_basis_n(lamY, G.en_in, bY);
+  pos_basis_n(lamZ, G.en_in, bZ);
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    e[p] = W * (fO * bO[p] + fYZ * (bY[p] + bZ[p]));
+    de[p] = W * (dO * bO[p] + dYZ * (bY[p] + bZ[p]));
+  }
+}
+
+// Tet geometry, face frames, destination frame and weight of block (j, l_in ->
+// l_out) into G (called by one thread).
+__device__ void block_setup(const AsmArgs &A, int j, int l_in, int l_out, BlockGeo &G) {
+  const int32_t *t = A.tets + 4 * (int64_t)j;
+  for (int m = 0; m < 4; ++m) {
+    G.gid[m] = t[m];
+    for (int i = 0; i < 3; ++i) G.P[m][i] = A.verts[3 * (int64_t)t[m] + i];
+    const double *f = A.face + FACE_REC * (4 * (int64_t)j + m);
+    G.area[m] = f[0];
+    for (int i = 0; i < 3; ++i) G.nrm[m][i] = f[1 + i];
+  }
+  const double *fi = A.face + FACE_REC * (4 * (int64_t)j + l_in);
+  for (int i = 0; i < 3; ++i) {
+    G.xin[i] = fi[4 + i];
+    G.yin[i] = fi[7 + i];
+    G.zin[i] = -fi[1 + i];
+  }
+  G.l_in = l_in;
+  G.l_out = l_out;
+  // base vertices of the inbound face in increasing global id
+  int b3[3], nb = 0;
+  for (int m = 0; m < 4; ++m)
+    if (m != l_in) b3[nb++] = m;
+  for (int a = 0; a < 3; ++a)
+    for (int b = a + 1; b < 3; ++b)
+      if (G.gid[b3[b]] < G.gid[b3[a]]) {
+        int tmp = b3[a]; b3[a] = b3[b]; b3[b] = tmp;
+      }
+  for (int a = 0; a < 3; ++a) {
+    G.base[a] = b3[a];
+    if (b3[a] == l_out) G.xb = a;
+  }
+  int o3[3], no = 0;
+  for (int m = 0; m < 4; ++m)
+    if (m != l_out) o3[no++] = m;
+  for (int a = 0; a < 3; ++a)
+    for (int b = a + 1; b < 3; ++b)
+      if (G.gid[o3[b]] < G.gid[o3[a]]) {
+        int tmp = o3[a]; o3[a] = o3[b]; o3[b] = tmp;
+      }
+  for (int a = 0; a < 3; ++a) G.oface[a] = o3[a];
+  int nb_slot = A.nbr[4 * (int64_t)j + l_out];
+  const double *fo = A.face + FACE_REC * (4 * (int64_t)j + l_out);
+  if (nb_slot >= 0) {
+    const double *fn = A.face + FACE_REC * (int64_t)nb_slot;
+    G.transmit = 1;
+    G.weight = 1.0;
+    for (int i = 0; i < 3; ++i) {
+      G.xd[i] = fn[4 + i];
+      G.yd[i] = fn[7 + i];
+      G.zd[i] = -fn[1 + i];
+    }
+  } else {
+    G.transmit = 0;
+    G.weight = A.refl[4 * (int64_t)j + l_out];
+    for (int i = 0; i < 3; ++i) {
+      G.xd[i] = fo[4 + i];
+      G.yd[i] = fo[7 + i];
+      G.zd[i] = -fo[1 + i];
+    }
+  }
+  const double Ain = G.area[l_in], Aout = G.area[l_out];
+  G.en_in[0] = 1.0 / sqrt(Ain);
+  G.en_in[1] = sqrt(6.0 / Ain);
+  G.en_in[2] = sqrt(2.0 / Ain);
+  G.en_out[0] = 1.0 / sqrt(Aout);
+  G.en_out[1] = sqrt(6.0 / Aout);
+  G.en_out[2] = sqrt(2.0 / Aout);
+  G.sqrt_ratio = sqrt(Ain / Aout);
+  G.vol = A.vol[j];
+  G.mu = A.mu[j];
+}
+
 // ---------------------------------------------------------------------------
 // The kernel: 8 waves.  Node phase: wave w takes role w % 4 (0 geometry and S,
 // 1 psi, 2 G^-1 psi', 3 idle) for the nodes of half w / 4 of the chunk.
@@ -546,74 +756,7 @@ __global__ __launch_bounds__(NTHREADS) void k_assemble(AsmArgs A) {
   for (int i = tid; i < 3 * (DMAX + 1) * (DMAX + 1); i += NTHREADS) thom[i] = A.thom[i];
   for (int i = tid; i < NMOM * NSERIES; i += NTHREADS) coef[i] = A.coef[i];
   if (tid == 0) {
-    const int32_t *t = A.tets + 4 * (int64_t)j;
-    for (int m = 0; m < 4; ++m) {
-      G.gid[m] = t[m];
-      for (int i = 0; i < 3; ++i) G.P[m][i] = A.verts[3 * (int64_t)t[m] + i];
-      const double *f = A.face + FACE_REC * (4 * (int64_t)j + m);
-      G.area[m] = f[0];
-      for (int i = 0; i < 3; ++i) G.nrm[m][i] = f[1 + i];
-    }
-    const double *fi = A.face + FACE_REC * (4 * (int64_t)j + l_in);
-    for (int i = 0; i < 3; ++i) {
-      G.xin[i] = fi[4 + i];
-      G.yin[i] = fi[7 + i];
-      G.zin[i] = -fi[1 + i];
-    }
-    G.l_in = l_in;
-    G.l_out = l_out;
-    // base vertices of the inbound face in increasing global id
-    int b3[3], nb = 0;
-    for (int m = 0; m < 4; ++m)
-      if (m != l_in) b3[nb++] = m;
-    for (int a = 0; a < 3; ++a)
-      for (int b = a + 1; b < 3; ++b)
-        if (G.gid[b3[b]] < G.gid[b3[a]]) {
-          int tmp = b3[a]; b3[a] = b3[b]; b3[b] = tmp;
-        }
-    for (int a = 0; a < 3; ++a) {
-      G.base[a] = b3[a];
-      if (b3[a] == l_out) G.xb = a;
-    }
-    int o3[3], no = 0;
-    for (int m = 0; m < 4; ++m)
-      if (m != l_out) o3[no++] = m;
-    for (int a = 0; a < 3; ++a)
-      for (int b = a + 1; b < 3; ++b)
-        if (G.gid[o3[b]] < G.gid[o3[a]]) {
-          int tmp = o3[a]; o3[a] = o3[b]; o3[b] = tmp;
-        }
-    for (int a = 0; a < 3; ++a) G.oface[a] = o3[a];
-    int nb_slot = A.nbr[4 * (int64_t)j + l_out];
-    const double *fo = A.face + FACE_REC * (4 * (int64_t)j + l_out);
-    if (nb_slot >= 0) {
-      const double *fn = A.face + FACE_REC * (int64_t)nb_slot;
-      G.transmit = 1;
-      G.weight = 1.0;
-      for (int i = 0; i < 3; ++i) {
-        G.xd[i] = fn[4 + i];
-        G.yd[i] = fn[7 + i];
-        G.zd[i] = -fn[1 + i];
-      }
-    } else {
-      G.transmit = 0;
-      G.weight = A.refl[4 * (int64_t)j + l_out];
-      for (int i = 0; i < 3; ++i) {
-        G.xd[i] = fo[4 + i];
-        G.yd[i] = fo[7 + i];
-        G.zd[i] = -fo[1 + i];
-      }
-    }
-    const double Ain = G.area[l_in], Aout = G.area[l_out];
-    G.en_in[0] = 1.0 / sqrt(Ain);
-    G.en_in[1] = sqrt(6.0 / Ain);
-    G.en_in[2] = sqrt(2.0 / Ain);
-    G.en_out[0] = 1.0 / sqrt(Aout);
-    G.en_out[1] = sqrt(6.0 / Aout);
-    G.en_out[2] = sqrt(2.0 / Aout);
-    G.sqrt_ratio = sqrt(Ain / Aout);
-    G.vol = A.vol[j];
-    G.mu = A.mu[j];
+    block_setup(A, j, l_in, l_out, G);
     build_cells(G, cells, dyn, A.rule);
     if (G.overflow) atomicOr(A.flags, FLAG_CELL_OVERFLOW);
     if (split == 0) atomicAdd(A.nodes, (unsigned long long)G.ncells * (unsigned long long)(n * n));
@@ -748,6 +891,239 @@ __global__ __launch_bounds__(NTHREADS) void k_assemble(AsmArgs A) {
   if (bad) atomicOr(A.flags, FLAG_NONFINITE);
 }
 
+// ---------------------------------------------------------------------------
+// Adjoint kernels (same cells and directions as k_assemble, one block each)
+// ---------------------------------------------------------------------------
+
+__device__ inline void load_tables(const AsmArgs &A, double *glx, double *glw, double *thom, double *coef) {
+  const int tid = threadIdx.x;
+  if (tid < 32) {
+    glx[tid] = A.gl[tid];
+    glw[tid] = A.gl[32 + tid];
+  }
+  for (int i = tid; i < 3 * (DMAX + 1) * (DMAX + 1); i += NTHREADS) thom[i] = A.thom[i];
+  for (int i = tid; i < NMOM * NSERIES; i += NTHREADS) coef[i] = A.coef[i];
+}
+
+__device__ inline double block_sum(double v, double *red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < NTHREADS / 64; ++w) t += red[w];
+  return t;
+}
+
+// Receiver energy: out_vec[blk][(p,k)] = sum_q W E_p psi_k over the block's
+// directions (E = chord energy of the start set of l_out), zero outside the box;
+// out_scal[blk] = rho[slot] . (the same with dE/dmu) when rho != null.
+template <int PQ>
+__global__ __launch_bounds__(NTHREADS) void k_energy(AsmArgs A) {
+  __shared__ BlockGeo G;
+  __shared__ double cells[CMAX][4][3];
+  __shared__ double glx[32], glw[32];
+  __shared__ double thom[3 * (DMAX + 1) * (DMAX + 1)];
+  __shared__ double coef[NMOM * NSERIES];
+  __shared__ double red[NTHREADS / 64];
+  __shared__ int inside;
+  extern __shared__ double dyn[];
+  constexpr int P = PQ == 1 ? 1 : 3;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t blk = blockIdx.x;
+  const int j = (int)(blk / 12), r = (int)(blk % 12), l_out = r / 3, sidx = r % 3;
+  const int l_in = (sidx < l_out) ? sidx : sidx + 1;
+  const int Mp = A.Mp, M = A.M, K = A.K, n = A.n, D = A.D;
+  if (tid == 0) {
+    double cx[3] = {0.0, 0.0, 0.0};
+    for (int m = 0; m < 4; ++m)
+      for (int i = 0; i < 3; ++i) cx[i] += 0.25 * A.verts[3 * (int64_t)A.tets[4 * (int64_t)j + m] + i];
+    inside = 1;
+    for (int i = 0; i < 3; ++i) inside &= (cx[i] >= A.box[2 * i] && cx[i] <= A.box[2 * i + 1]) ? 1 : 0;
+  }
+  __syncthreads();
+  if (!inside) {
+    for (int t = tid; t < K; t += NTHREADS) A.out_vec[blk * K + t] = 0.0;
+    if (tid == 0 && A.out_scal) A.out_scal[blk] = 0.0;
+    return;
+  }
+  load_tables(A, glx, glw, thom, coef);
+  if (tid == 0) {
+    block_setup(A, j, l_in, l_out, G);
+    build_cells(G, cells, dyn, A.rule);
+    if (G.overflow) atomicOr(A.flags, FLAG_CELL_OVERFLOW);
+  }
+  __syncthreads();
+  const int chunk = A.chunk;
+  double *Bpsi = dyn;                   // [chunk][Mp]
+  double *Ew = dyn + chunk * Mp;        // [chunk][2P]: W E_p, W dE_p
+  const int Q = G.ncells * n * n;
+  const int role = wave & 3, half = wave >> 2;
+  double acc = 0.0, dacc = 0.0;
+  const int tp = tid < K ? tid / M : 0, tk = tid < K ? tid - tp * M : 0;
+  for (int q0 = 0; q0 < Q; q0 += chunk) {
+    const int ql = half * 64 + lane;
+    const int q = q0 + ql;
+    if (role < 2 && ql < chunk) {
+      if (q < Q) {
+        double d[3], W;
+        node_direction(cells, glx, glw, n, G.zin, q, d, W);
+        if (role == 0) {
+          double e[P], de[P];
+          energy_weights<P>(G, coef, d, W, e, de);
+#pragma unroll
+          for (int p = 0; p < P; ++p) {
+            Ew[ql * 2 * P + p] = e[p];
+            Ew[ql * 2 * P + P + p] = de[p];
+          }
+        } else {
+          double *o = Bpsi + ql * Mp;
+          momentum_basis(dot3(d, G.xin), dot3(d, G.yin), dot3(d, G.zin), D, A.family, o);
+        }
+      } else {
+        if (role == 0)
+          for (int i = 0; i < 2 * P; ++i) Ew[ql * 2 * P + i] = 0.0;
+        else
+          for (int k = 0; k < M; ++k) Bpsi[ql * Mp + k] = 0.0;
+      }
+    }
+    __syncthreads();
+    if (tid < K) {
+      const int nq = min(chunk, Q - q0);
+      for (int qq = 0; qq < nq; ++qq) {
+        const double bk = Bpsi[qq * Mp + tk];
+        acc = fma(Ew[qq * 2 * P + tp], bk, acc);
+        dacc = fma(Ew[qq * 2 * P + P + tp], bk, dacc);
+      }
+    }
+    __syncthreads();
+  }
+  if (tid < K) A.out_vec[blk * K + tid] = acc;
+  if (A.out_scal) {
+    double v = (tid < K) ? dacc * A.rho[(4 * (int64_t)j + l_in) * K + tid] : 0.0;
+    double t = block_sum(v, red);
+    if (tid == 0) A.out_scal[blk] = t;
+  }
+}
+
+// lambda^T (dB/dmu_j) rho for one block: sum_q W sum_{p',p} dS_p'p (G^-1 psi'(d') . lambda_dest,p')
+// (psi(d) . rho_src,p), times the transmission / reflection weight.
+template <int PQ>
+__global__ __launch_bounds__(NTHREADS) void k_dmu(AsmArgs A) {
+  __shared__ BlockGeo G;
+  __shared__ double cells[CMAX][4][3];
+  __shared__ double glx[32], glw[32];
+  __shared__ double thom[3 * (DMAX + 1) * (DMAX + 1)];
+  __shared__ double coef[NMOM * NSERIES];
+  __shared__ double red[NTHREADS / 64];
+  __shared__ double rs[3 * (DMAX + 1) * (DMAX + 2) / 2], ls[3 * (DMAX + 1) * (DMAX + 2) / 2];
+  extern __shared__ double dyn[];
+  constexpr int P = PQ == 1 ? 1 : 3;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t blk = blockIdx.x;
+  const int j = (int)(blk / 12), r = (int)(blk % 12), l_out = r / 3, sidx = r % 3;
+  const int l_in = (sidx < l_out) ? sidx : sidx + 1;
+  const int Mp = A.Mp, M = A.M, K = A.K, n = A.n, D = A.D;
+  load_tables(A, glx, glw, thom, coef);
+  if (tid == 0) {
+    block_setup(A, j, l_in, l_out, G);
+    build_cells(G, cells, dyn, A.rule);
+    if (G.overflow) atomicOr(A.flags, FLAG_CELL_OVERFLOW);
+  }
+  __syncthreads();
+  {
+    const int32_t nbs = A.nbr[4 * (int64_t)j + l_out];
+    const int64_t dslot = nbs >= 0 ? nbs : 4 * (int64_t)j + l_out;
+    for (int t = tid; t < K; t += NTHREADS) {
+      rs[t] = A.rho[(4 * (int64_t)j + l_in) * K + t];
+      ls[t] = A.lam[dslot * K + t];
+    }
+  }
+  const int chunk = A.chunk;
+  double *Apsi = dyn;
+  double *Bpsi = dyn + chunk * Mp;
+  double *Sw = dyn + 2 * chunk * Mp;
+  const int Q = G.ncells * n * n;
+  const int role = wave & 3, half = wave >> 2;
+  double acc = 0.0;
+  for (int q0 = 0; q0 < Q; q0 += chunk) {
+    const int ql = half * 64 + lane;
+    const int q = q0 + ql;
+    if (role < 3 && ql < chunk) {
+      if (q < Q) {
+        double d[3], W;
+        node_direction(cells, glx, glw, n, G.zin, q, d, W);
+        if (role == 0) {
+          double sw[PQ];
+          dspatial_weights<P>(G, coef, d, W, sw);
+#pragma unroll
+          for (int i = 0; i < PQ; ++i) Sw[ql * PQ + i] = sw[i];
+        } else if (role == 1) {
+          momentum_basis(dot3(d, G.xin), dot3(d, G.yin), dot3(d, G.zin), D, A.family, Bpsi + ql * Mp);
+        } else {
+          double dd[3] = {d[0], d[1], d[2]};
+          if (!G.transmit) {
+            double dn = dot3(d, G.nrm[l_out]);
+            for (int i = 0; i < 3; ++i) dd[i] = d[i] - 2.0 * dn * G.nrm[l_out][i];
+          }
+          double *o = Apsi + ql * Mp;
+          momentum_basis(dot3(dd, G.xd), dot3(dd, G.yd), dot3(dd, G.zd), D, A.family, o);
+          apply_gram_inverse(o, D, A.family, thom);
+        }
+      } else if (role == 0) {
+        for (int i = 0; i < PQ; ++i) Sw[ql * PQ + i] = 0.0;
+      }
+    }
+    __syncthreads();
+    if (tid < chunk && q0 + tid < Q) {
+      const double *bp = Bpsi + tid * Mp, *ap = Apsi + tid * Mp;
+      double av[P], bv[P];
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        double sa = 0.0, sb = 0.0;
+        for (int k = 0; k < M; ++k) {
+          sa = fma(bp[k], rs[p * M + k], sa);
+          sb = fma(ap[k], ls[p * M + k], sb);
+        }
+        av[p] = sa;
+        bv[p] = sb;
+      }
+#pragma unroll
+      for (int pp = 0; pp < P; ++pp)
+#pragma unroll
+        for (int p = 0; p < P; ++p) acc = fma(Sw[tid * PQ + pp * P + p] * bv[pp], av[p], acc);
+    }
+    __syncthreads();
+  }
+  double t = block_sum(acc, red);
+  if (tid == 0) A.out_scal[blk] = G.weight * t;
+}
+
+// g[slot (j, l_in)] = sum over the three blocks (j, l_out != l_in) of out_vec
+__global__ void k_energy_gather(const double *out_vec, int64_t nt, int K, double *g) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= 4 * nt * K) return;
+  int64_t slot = i / K;
+  int t = (int)(i - slot * K);
+  int64_t j = slot >> 2;
+  int l_in = (int)(slot & 3);
+  double s = 0.0;
+  for (int l_out = 0; l_out < 4; ++l_out) {
+    if (l_out == l_in) continue;
+    int sidx = l_in < l_out ? l_in : l_in - 1;
+    s += out_vec[((4 * j + l_out) * 3 + sidx) * K + t];
+  }
+  g[i] = s;
+}
+
+// dmu[j] = sum of the per-block scalars of tet j (two arrays, the second optional)
+__global__ void k_block_gather(const double *a, const double *b, int64_t nt, double *out) {
+  int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= nt) return;
+  double s = 0.0;
+  for (int q = 0; q < 12; ++q) s += a[12 * j + q] + (b ? b[12 * j + q] : 0.0);
+  out[j] = s;
+}
+
 __global__ void k_gauss_legendre(int n, double *gl) {
   int i = threadIdx.x;
   if (i >= 32) return;
@@ -795,6 +1171,94 @@ hipError_t launch_p(int maxt, const AsmArgs &a, size_t lds, hipStream_t st) {
   }
 }
 
+// node-chunk length and dynamic LDS bytes of the block kernels for an operator
+inline void block_layout(int Mp, int PQ, int &chunk, size_t &lds) {
+  chunk = Mp <= 48 ? 128 : (Mp <= 96 ? 64 : 32);
+  size_t lds_nodes = sizeof(double) * (size_t)(2 * chunk * Mp + chunk * PQ);
+  size_t lds_clip = sizeof(double) * 2 * PPOLY * VMAX * 3;
+  lds = lds_nodes > lds_clip ? lds_nodes : lds_clip;
+}
+
+AsmArgs op_args(dfm_op op, const double *mu, unsigned *flags) {
+  dfm_mesh mesh = op->mesh;
+  AsmArgs a{};
+  a.verts = mesh->verts;
+  a.tets = mesh->tets;
+  a.nbr = mesh->nbr;
+  a.refl = mesh->refl;
+  a.face = mesh->face;
+  a.vol = mesh->vol;
+  a.mu = mu;
+  a.gl = op->gl;
+  a.thom = op->thom;
+  a.coef = op->coef;
+  a.B = op->B;
+  a.flags = flags;
+  a.nblocks = 12 * op->nt;
+  a.P = op->P;
+  a.D = op->basis.mom_degree;
+  a.M = op->M;
+  a.Mp = (op->M + 15) / 16 * 16;
+  a.K = op->K;
+  a.Kp = op->Kp;
+  a.n = op->basis.quad_n;
+  a.family = op->basis.mom_family;
+  a.rule = op->basis.rule;
+  size_t lds;
+  block_layout(a.Mp, op->P * op->P, a.chunk, lds);
+  a.nsplit = 1;
+  return a;
+}
+
+template <typename KERN>
+hipError_t launch_block_kernel(KERN kern, const AsmArgs &a, size_t lds, hipStream_t st) {
+  hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3((unsigned)a.nblocks), dim3(NTHREADS), lds, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+// Receiver energy per block (and rho . dE/dmu when rho != null), gathered into g.
+hipError_t energy_functional(dfm_op op, const double *mu, const double *box, const double *rho, double *g,
+                             double *blk_vec, double *blk_scal, unsigned *flags, hipStream_t st) {
+  AsmArgs a = op_args(op, mu, flags);
+  for (int i = 0; i < 6; ++i) a.box[i] = box[i];
+  a.rho = rho;
+  a.out_vec = blk_vec;
+  a.out_scal = rho ? blk_scal : nullptr;
+  int chunk;
+  size_t lds;
+  block_layout(a.Mp, op->P * op->P, chunk, lds);
+  size_t lds_e = sizeof(double) * (size_t)(chunk * a.Mp + chunk * 2 * op->P);
+  if (lds_e > lds) lds = lds_e;
+  hipError_t e = op->P == 1 ? launch_block_kernel(k_energy<1>, a, lds, st) : launch_block_kernel(k_energy<9>, a, lds, st);
+  if (e != hipSuccess) return e;
+  int64_t tot = op->ndof;
+  hipLaunchKernelGGL(k_energy_gather, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, blk_vec, op->nt, op->K, g);
+  return hipGetLastError();
+}
+
+// lambda^T dB/dmu_j rho per block into blk_scal; dmu[j] = sum over the tet's
+// blocks of blk_scal (+ extra_scal when given).
+hipError_t dmu_contraction(dfm_op op, const double *mu, const double *rho, const double *lam, double *blk_scal,
+                           const double *extra_scal, double *dmu, unsigned *flags, hipStream_t st) {
+  AsmArgs a = op_args(op, mu, flags);
+  a.rho = rho;
+  a.lam = lam;
+  a.out_scal = blk_scal;
+  int chunk;
+  size_t lds;
+  block_layout(a.Mp, op->P * op->P, chunk, lds);
+  hipError_t e = op->P == 1 ? launch_block_kernel(k_dmu<1>, a, lds, st) : launch_block_kernel(k_dmu<9>, a, lds, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_block_gather, dim3((unsigned)((op->nt + 255) / 256)), dim3(256), 0, st, blk_scal, extra_scal,
+                     op->nt, dmu);
+  return hipGetLastError();
+}
+
+namespace {
 }  // namespace
 
 void free_op(dfm_op op) {
@@ -802,6 +1266,9 @@ void free_op(dfm_op op) {
   (void)hipFree(op->B);
   (void)hipFree(op->B32);
   (void)hipFree(op->dest);
+  (void)hipFree(op->gl);
+  (void)hipFree(op->thom);
+  (void)hipFree(op->coef);
   delete op;
 }
 
@@ -896,19 +1363,29 @@ extern "C" dfm_status dfm_assemble(dfm_mesh mesh, const dfm_basis *basis, const 
     }
   }
   TRY(hipMemcpy(thom_d, th.data(), sizeof(double) * th.size(), hipMemcpyHostToDevice));
-  // c_r = (-1)^r (i+r)! m! / (r! (i+r+m+1)!) for the moments (i, m) used by the kernel
+  // power-series coefficients of the chord moments (see moment())
   {
-    const int mi[NMOM] = {0, 2, 1, 0}, mm[NMOM] = {1, 1, 2, 3};
+    const int kind[NMOM] = {0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 2, 2};
+    const int mi[NMOM] = {0, 2, 1, 0, 1, 3, 2, 1, 1, 0, 1, 0}, mm[NMOM] = {1, 1, 2, 3, 1, 1, 2, 3, 1, 2, 1, 2};
+    auto fact = [](int k) {
+      double f = 1.0;
+      for (int t = 2; t <= k; ++t) f *= t;
+      return f;
+    };
     std::vector<double> cf(NMOM * NSERIES);
     for (int w = 0; w < NMOM; ++w) {
       int i = mi[w], m = mm[w];
-      double c = 1.0;  // r = 0: i! m! / (i+m+1)!
-      for (int k = 1; k <= i; ++k) c *= k;
-      for (int k = 1; k <= m; ++k) c *= k;
-      for (int k = 1; k <= i + m + 1; ++k) c /= k;
       for (int r = 0; r < NSERIES; ++r) {
-        cf[w * NSERIES + r] = c;
-        c *= -1.0 / (r + 1) * (double)(i + r + 1) / (double)(i + r + m + 2);
+        double c;
+        if (kind[w] == 0) {
+          c = fact(i + r) * fact(m) / (fact(r) * fact(i + r + m + 1));
+        } else {
+          int rr = kind[w] == 1 ? r : r + 1;
+          c = fact(i + rr + 1) * fact(m) / (fact(rr + 1) * fact(i + rr + m + 2));
+          if (kind[w] == 2) c *= rr;
+        }
+        int sgn = kind[w] == 2 ? r + 1 : r;
+        cf[w * NSERIES + r] = (sgn & 1) ? -c : c;
       }
     }
     TRY(hipMemcpy(coef_d, cf.data(), sizeof(double) * cf.size(), hipMemcpyHostToDevice));
@@ -958,9 +1435,9 @@ extern "C" dfm_status dfm_assemble(dfm_mesh mesh, const dfm_basis *basis, const 
   TRY(hipMemcpyAsync(&hnodes, nodes, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
   TRY(hipStreamSynchronize(st));
 #undef TRY
-  (void)hipFree(gl);
-  (void)hipFree(thom_d);
-  (void)hipFree(coef_d);
+  op->gl = gl;
+  op->thom = thom_d;
+  op->coef = coef_d;
   (void)hipFree(flags);
   (void)hipFree(nodes);
   gl = thom_d = coef_d = nullptr;

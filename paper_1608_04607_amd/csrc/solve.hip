@@ -20,6 +20,7 @@ namespace dfm {
 
 hipError_t spmv(dfm_op op, const double *x, const double *v, double *y, double alpha, double beta, hipStream_t st);
 hipError_t spmv32(dfm_op op, const float *x, const float *v, float *y, float alpha, float beta, hipStream_t st);
+hipError_t spmv_t(dfm_op op, const double *x, const double *v, double *y, double alpha, double beta, hipStream_t st);
 hipError_t ensure_fp32(dfm_op op, hipStream_t st);
 
 namespace {
@@ -152,6 +153,7 @@ __global__ void k_zero(T *__restrict__ y, int64_t n) {
 struct Ctx {
   dfm_op op;
   hipStream_t st;
+  bool transpose = false;  // solve (I - B)^T x = b (FP64 only)
   int64_t n;
   double *partial = nullptr;  // [MAXV][RED_BLOCKS]
   double *dsc = nullptr;      // device scalars
@@ -188,7 +190,12 @@ struct Ctx {
     return e;
   }
   // y = (I - B) x, with the FP32 copy of B for FP32 vectors
-  hipError_t apply_ImB(const double *x, double *y) { return spmv(op, x, x, y, 1.0, -1.0, st); }
+  hipError_t apply_ImB(const double *x, double *y) {
+    return transpose ? spmv_t(op, x, x, y, 1.0, -1.0, st) : spmv(op, x, x, y, 1.0, -1.0, st);
+  }
+  hipError_t apply_B(const double *x, double *y) {
+    return transpose ? spmv_t(op, x, nullptr, y, 0.0, 1.0, st) : spmv(op, x, nullptr, y, 0.0, 1.0, st);
+  }
   hipError_t apply_ImB(const float *x, float *y) { return spmv32(op, x, x, y, 1.0f, -1.0f, st); }
 };
 
@@ -299,8 +306,9 @@ hipError_t gmres(Ctx &c, const T *b, T *x, T *V, T *w, T *t, int m, double rtol,
 
 using namespace dfm;
 
-extern "C" dfm_status dfm_solve(dfm_op op, const double *rho0, double *rho, int nrhs, const dfm_solve_opts *opts,
-                                dfm_solve_info *info, void *stream_) {
+namespace dfm {
+dfm_status solve_impl(dfm_op op, const double *rho0, double *rho, int nrhs, const dfm_solve_opts *opts,
+                      dfm_solve_info *info, bool transpose, void *stream_) {
   DFM_REQUIRE(op && rho0 && rho && opts, DFM_E_INVALID, "null argument");
   DFM_REQUIRE(nrhs >= 1, DFM_E_INVALID, "nrhs must be >= 1");
   DFM_REQUIRE(opts->method == 0 || opts->method == 1, DFM_E_INVALID, "method must be 0 (Neumann) or 1 (GMRES)");
@@ -310,12 +318,15 @@ extern "C" dfm_status dfm_solve(dfm_op op, const double *rho0, double *rho, int 
   DFM_REQUIRE(opts->max_iter >= 1 && opts->rtol > 0.0, DFM_E_INVALID, "need max_iter >= 1 and rtol > 0");
   const int m = opts->method == 1 ? opts->restart : 1;
   DFM_REQUIRE(m >= 1 && m <= MAXV - 1, DFM_E_INVALID, "restart must be in 1..200");
+  DFM_REQUIRE(!(transpose && opts->precision == 1), DFM_E_UNSUPPORTED,
+              "transposed solves are implemented in FP64 only");
   hipStream_t st = (hipStream_t)stream_;
   const int64_t n = op->ndof;
   Ctx c;
   c.op = op;
   c.st = st;
   c.n = n;
+  c.transpose = transpose;
   double *V = nullptr, *w = nullptr, *t = nullptr;
   float *V32 = nullptr, *w32 = nullptr, *t32 = nullptr, *b32 = nullptr, *e32 = nullptr;
   dfm_status status = DFM_OK;
@@ -378,7 +389,7 @@ extern "C" dfm_status dfm_solve(dfm_op op, const double *rho0, double *rho, int 
       hipLaunchKernelGGL((k_copy<double, double>), dim3(G), dim3(256), 0, st, b, cur, n);
       TRY(hipGetLastError());
       while (inf.iters < opts->max_iter) {
-        TRY(spmv(op, cur, nullptr, nxt, 0.0, 1.0, st));
+        TRY(c.apply_B(cur, nxt));
         inf.iters++;
         double tn;
         TRY(c.norm2<double>(nxt, tn));
@@ -436,4 +447,10 @@ extern "C" dfm_status dfm_solve(dfm_op op, const double *rho0, double *rho, int 
   if (status == DFM_E_NOCONV) set_error("solver stopped at max_iter above the tolerance");
   if (status == DFM_E_NUMERIC) set_error("non-finite residual in the solver");
   return status;
+}
+}  // namespace dfm
+
+extern "C" dfm_status dfm_solve(dfm_op op, const double *rho0, double *rho, int nrhs, const dfm_solve_opts *opts,
+                                dfm_solve_info *info, void *stream_) {
+  return solve_impl(op, rho0, rho, nrhs, opts, info, false, stream_);
 }

@@ -138,6 +138,27 @@ class Operator:
                                            _stream(stream)))
         return rho0
 
+    def receiver_functional(self, box, stream=None):
+        g = torch.empty((self.ndof,), dtype=torch.float64, device=self.device)
+        bx = (C.c_double * 6)(*box)
+        check(_lib.load().dfm_receiver_functional(self.handle, _ptr(self.mu), bx, _ptr(g), _stream(stream)))
+        return g
+
+    def adjoint(self, rho, box, src=None, method="gmres", rtol=1e-10, restart=50, max_iter=20000, stream=None):
+        """(lambda, dJ/dmu, dJ/dw, info) for J = receiver energy in `box`."""
+        rho = _dev(rho, torch.float64)
+        nsrc = 0 if src is None else src.shape[0]
+        src = _dev(src, torch.float64) if src is not None else None
+        lam = torch.empty((self.ndof,), dtype=torch.float64, device=self.device)
+        dmu = torch.empty((self.mesh.nt,), dtype=torch.float64, device=self.device)
+        dw = torch.empty((max(nsrc, 1),), dtype=torch.float64, device=self.device)
+        bx = (C.c_double * 6)(*box)
+        opts = SolveOpts(1 if method == "gmres" else 0, restart, max_iter, rtol, 0)
+        info = SolveInfo()
+        check(_lib.load().dfm_adjoint(self.handle, _ptr(self.mu), bx, _ptr(rho), _ptr(src), nsrc, C.byref(opts),
+                                      _ptr(lam), _ptr(dmu), _ptr(dw), C.byref(info), _stream(stream)))
+        return lam, dmu, dw[:nsrc], (info.iters, info.restarts, info.relres)
+
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
             _lib.load().dfm_op_destroy(self.handle)

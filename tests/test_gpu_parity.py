@@ -260,3 +260,80 @@ def test_sources_match_oracle(family):
     pts = synth.uniform_points_on_box_surface((1, 1, 1), 7, np.random.default_rng(4))
     got = op.source_points(torch.tensor(pts, device=DEV)).cpu().numpy()
     assert rel(got, osrc.project(m, bs, {"kind": "points", "xyz": pts})) < TOL
+
+
+# ---------------------------------------------------------------------------- adjoint
+
+from oracle import adjoint as oj  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def adj():
+    v, t = synth.kuhn_box((2, 1, 1), (1.0, 1.0, 1.0), 0.15, 3)
+    refl = np.full((t.shape[0], 4), 0.8)
+    mu = np.random.default_rng(1).uniform(0.1, 0.6, t.shape[0])
+    box = (0.5, 1.0, 0.0, 1.0, 0.0, 0.7)
+    pts = synth.uniform_points_on_box_surface((1, 1, 1), 3, np.random.default_rng(2))
+    return v, t, refl, mu, box, pts
+
+
+@pytest.mark.parametrize("order,family", [(0, 0), (1, 0), (1, 1)])
+def test_receiver_functional_matches_oracle(adj, order, family):
+    say(f"[adjoint] receiver functional P{order} family {family}")
+    v, t, refl, mu, box, pts = adj
+    bs = oa.Basis(order, family, 3, 4, oq.SEAM_RULE)
+    g_gpu = gpu_op(gpu_mesh(v, t, refl), mu, bs).receiver_functional(box).cpu().numpy()
+    g_or = oj.receiver_functional(om.build_mesh(v, t, refl), bs, mu, box)
+    assert rel(g_gpu, g_or) < TOL
+
+
+@pytest.mark.parametrize("order", [0, 1])
+def test_adjoint_gradients_match_oracle(adj, order):
+    say(f"[adjoint] gradients P{order}")
+    v, t, refl, mu, box, pts = adj
+    bs = oa.Basis(order, 0, 2, 4, oq.SEAM_RULE)
+    m = om.build_mesh(v, t, refl)
+    op = gpu_op(gpu_mesh(v, t, refl), mu, bs)
+    w = np.array([0.7, 1.3, 0.4])
+    src = op.source_points(torch.tensor(pts, device=DEV))
+    rho0 = torch.tensor(w, device=DEV) @ src
+    rho, _ = op.solve(rho0, rtol=1e-13, restart=40)
+    lam, dmu, dw, info = op.adjoint(rho, box, src=src, rtol=1e-13, restart=40)
+    say(f"    adjoint info {info}")
+    B, dest = oa.assemble(m, bs, mu)
+    A = osv.to_sparse(B, dest)
+    rho0s = osrc.project(m, bs, {"kind": "points", "xyz": pts})
+    rho_o = osv.solve_direct(A, w @ rho0s)
+    g = oj.receiver_functional(m, bs, mu, box)
+    lam_o = osv.solve_direct(A.T.tocsr(), g)
+    dmu_o = oj.gradient_mu(m, bs, mu, lam_o, rho_o, box)
+    assert rel(lam.cpu().numpy(), lam_o) < 1e-9
+    assert rel(dmu.cpu().numpy(), dmu_o) < 1e-9
+    assert rel(dw.cpu().numpy(), rho0s @ lam_o) < 1e-9
+
+
+def test_adjoint_gradient_vs_central_differences(adj):
+    """GPU gradient against central differences of GPU forward solves (step 1e-6)."""
+    say("[adjoint] central differences")
+    v, t, refl, mu, box, pts = adj
+    bs = oa.Basis(0, 0, 2, 4, oq.SEAM_RULE)
+    mesh = gpu_mesh(v, t, refl)
+    xyz = torch.tensor(pts, device=DEV)
+
+    def J(mu_arr):
+        op = gpu_op(mesh, mu_arr, bs)
+        rho, _ = op.solve(op.source_points(xyz).sum(0), rtol=1e-14, restart=60)
+        return float(op.receiver_functional(box) @ rho)
+
+    op = gpu_op(mesh, mu, bs)
+    src = op.source_points(xyz)
+    rho, _ = op.solve(src.sum(0), rtol=1e-14, restart=60)
+    _, dmu, dw, _ = op.adjoint(rho, box, src=src, rtol=1e-14, restart=60)
+    dmu = dmu.cpu().numpy()
+    h = 1e-6
+    for e in (1, 6, 11):
+        mp, mm = mu.copy(), mu.copy()
+        mp[e] += h
+        mm[e] -= h
+        fd = (J(mp) - J(mm)) / (2 * h)
+        assert dmu[e] == pytest.approx(fd, rel=1e-5, abs=1e-8 * np.abs(dmu).max())
