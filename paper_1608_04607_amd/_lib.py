@@ -61,10 +61,15 @@ _lib = None
 
 
 def load(path=LIB_PATH):
-    """Load libdfm.so and declare every entry point (raises if it is missing)."""
+    """Load libdfm.so and declare every entry point (raises if it is missing).
+
+    torch is imported first: it brings its own HIP runtime, and the library must
+    bind to that same runtime (one process, one HIP runtime) instead of loading
+    a second copy from the system."""
     global _lib
     if _lib is not None:
         return _lib
+    import torch  # noqa: F401
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with `python -m paper_1608_04607_amd.build` "
                           "(or __graft_entry__.build())")

@@ -72,7 +72,9 @@ struct AsmArgs {
   int64_t nblocks;
   int P, D, M, Mp, K, Kp, n, family, rule;
   int chunk;
-  int nsplit, tiles_per_split, total_tiles, row_tiles;
+  // contraction layout: nsplit workgroups per block share the column tiles;
+  // inside one, the 8 waves form a wr_waves x (8 / wr_waves) grid of rectangles
+  int nsplit, row_tiles, col_tiles, wr_waves, slab_tiles;
 };
 
 struct BlockGeo {
@@ -723,11 +725,79 @@ __device__ void block_setup(const AsmArgs &A, int j, int l_in, int l_out, BlockG
 
 // ---------------------------------------------------------------------------
 // The kernel: 8 waves.  Node phase: wave w takes role w % 4 (0 geometry and S,
-// 1 psi, 2 G^-1 psi', 3 idle) for the nodes of half w / 4 of the chunk.
-// Contraction: wave w owns output tiles t = tile0 + w + 8 i.
+// 1 psi, 2 psi', 3 idle) for the nodes of half w / 4 of the chunk.
+// Contraction: the output T (Mp rows x PQ Mp columns, 16 x 16 tiles) is cut into
+// nsplit column ranges, one per workgroup; wave w owns the rectangle of row
+// range w / WC and column range w % WC of its workgroup's range (balanced
+// partitions, WC = 8 / wr_waves, so a wave's rectangle is RB or RB - 1 rows by
+// CB or CB - 1 columns).  Per 4 nodes a wave loads each of its row fragments and
+// column fragments once and issues rows x cols MFMAs.
+// Epilogue: T goes through LDS in slabs of column tiles, where one thread per
+// column applies the weight and G^-1 (the Galerkin solve of Eq. Bapprox), and
+// leaves as contiguous column segments of the block.
 // ---------------------------------------------------------------------------
 
-template <int MAXT, int PQ>
+// The MFMAs of one chunk for an R x C rectangle (compile-time); the fragments of
+// step s + 1 are loaded while the MFMAs of step s run.  ap, bp, sp point at the
+// lane's entries of step 0; steps >= 1.
+template <int R, int C, int RB, int CB, int PQ>
+__device__ __forceinline__ void contract_chunk(v4d (&acc)[CB][RB], const double *__restrict__ ap,
+                                               const double *__restrict__ bp, const double *__restrict__ sp,
+                                               const int (&boff)[CB], const int (&spq)[CB], int steps, int Ml) {
+  if constexpr (R > 0 && C > 0) {
+    double a0[R], b0[C];
+#pragma unroll
+    for (int i = 0; i < R; ++i) a0[i] = ap[i * 16];
+#pragma unroll
+    for (int c = 0; c < C; ++c) b0[c] = bp[boff[c]] * sp[spq[c]];
+    const int sa = 4 * Ml;
+    for (int s = 1; s < steps; ++s) {
+      ap += sa;
+      bp += sa;
+      sp += 4 * PQ;
+      double a1[R], b1[C], s1[C];
+#pragma unroll
+      for (int i = 0; i < R; ++i) a1[i] = ap[i * 16];
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        b1[c] = bp[boff[c]];
+        s1[c] = sp[spq[c]];
+      }
+#pragma unroll
+      for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int i = 0; i < R; ++i) acc[c][i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[i], b0[c], acc[c][i], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < R; ++i) a0[i] = a1[i];
+#pragma unroll
+      for (int c = 0; c < C; ++c) b0[c] = b1[c] * s1[c];
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+      for (int i = 0; i < R; ++i) acc[c][i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[i], b0[c], acc[c][i], 0, 0, 0);
+  }
+}
+
+// Tiles of the rectangle that fall in column tiles [t0, t1) into the LDS slab
+// Ts[(ct - t0) * 16 + column][row] (row stride Ml).
+template <int R, int C, int RB, int CB>
+__device__ __forceinline__ void stage_tiles(const v4d (&acc)[CB][RB], double *Ts, int c0, int r0, int t0, int t1,
+                                            int Ml, int col, int qrow) {
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int ct = c0 + c;
+    if (ct >= t0 && ct < t1) {
+      double *dst = Ts + ((ct - t0) * 16 + col) * Ml + r0 * 16 + qrow;
+#pragma unroll
+      for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) dst[i * 16 + 4 * e] = acc[c][i][e];
+    }
+  }
+}
+
+template <int RB, int CB, int PQ, int DM>
 __global__ __launch_bounds__(NTHREADS) void k_assemble(AsmArgs A) {
   __shared__ BlockGeo G;
   __shared__ double cells[CMAX][4][3];
@@ -738,7 +808,7 @@ __global__ __launch_bounds__(NTHREADS) void k_assemble(AsmArgs A) {
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int64_t blk = blockIdx.x / A.nsplit;
   const int split = blockIdx.x % A.nsplit;
   const int j = (int)(blk / 12);
@@ -748,6 +818,7 @@ __global__ __launch_bounds__(NTHREADS) void k_assemble(AsmArgs A) {
   const int l_in = (sidx < l_out) ? sidx : sidx + 1;
   constexpr int P = PQ == 1 ? 1 : 3;
   const int Mp = A.Mp, M = A.M, K = A.K, n = A.n, D = A.D;
+  const int Ml = Mp + 1;  // LDS row stride of the per-node basis rows: odd, so lanes hit distinct banks
 
   if (tid < 32) {
     glx[tid] = A.gl[tid];
@@ -764,39 +835,35 @@ __global__ __launch_bounds__(NTHREADS) void k_assemble(AsmArgs A) {
   __syncthreads();
 
   const int chunk = A.chunk;
-  double *Apsi = dyn;                    // [chunk][Mp]  G^-1 psi'(d')
-  double *Bpsi = dyn + chunk * Mp;       // [chunk][Mp]  psi(d)
-  double *Sw = dyn + 2 * chunk * Mp;     // [chunk][PQ]  W S
-  const int Q = G.ncells * n * n;
-  const int tile0 = split * A.tiles_per_split;
-  int tile1 = tile0 + A.tiles_per_split;
-  if (tile1 > A.total_tiles) tile1 = A.total_tiles;
-  const int R = A.row_tiles;
+  double *Apsi = dyn;                    // [chunk][Mp + 1]  psi'(d')
+  double *Bpsi = dyn + chunk * Ml;       // [chunk][Mp + 1]  psi(d)
+  double *Sw = dyn + 2 * chunk * Ml;     // [chunk][PQ]  W S
+  const int Q = __builtin_amdgcn_readfirstlane(G.ncells * n * n);
+  const int WR = A.wr_waves, WC = 8 / WR;
+  const int wr = wave / WC, wc = wave - (wave / WC) * WC;
+  const int cs0 = (split * A.col_tiles) / A.nsplit, cs1 = ((split + 1) * A.col_tiles) / A.nsplit;
+  const int ncs = cs1 - cs0;
+  const int r0 = (wr * A.row_tiles) / WR, rb = ((wr + 1) * A.row_tiles) / WR - r0;
+  const int c0 = cs0 + (wc * ncs) / WC, cb = cs0 + ((wc + 1) * ncs) / WC - c0;
   const int role = wave & 3;
   const int half = wave >> 2;
   const int col = lane & 15;
   const int qrow = lane >> 4;
 
-  // tile coordinates of this wave's tiles (clamped into range; inactive tiles
-  // still load valid LDS addresses but skip the MFMA)
-  int aoff[MAXT], boff[MAXT], spq[MAXT];
-  bool act[MAXT];
+  // column tile c0 + c lies inside one position pair pq (Mp is a multiple of 16)
+  int boff[CB], spq[CB];
 #pragma unroll
-  for (int i = 0; i < MAXT; ++i) {
-    int t = tile0 + wave + 8 * i;
-    act[i] = t < tile1;
-    if (!act[i]) t = tile1 - 1;
-    const int tr = t % R, tc = t / R;
-    const int c = tc * 16 + col;
-    const int pq = c / Mp;
-    aoff[i] = tr * 16 + col;
-    boff[i] = c - pq * Mp;
-    spq[i] = pq;
+  for (int c = 0; c < CB; ++c) {
+    const int ct = (c < cb) ? c0 + c : c0;
+    spq[c] = (ct * 16) / Mp;
+    boff[c] = ct * 16 - spq[c] * Mp + col;
   }
 
-  v4d acc[MAXT];
+  v4d acc[CB][RB];
 #pragma unroll
-  for (int i = 0; i < MAXT; ++i) acc[i] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int c = 0; c < CB; ++c)
+#pragma unroll
+    for (int i = 0; i < RB; ++i) acc[c][i] = v4d{0.0, 0.0, 0.0, 0.0};
 
   for (int q0 = 0; q0 < Q; q0 += chunk) {
     const int ql = half * 64 + lane;   // node within the chunk
@@ -811,8 +878,8 @@ __global__ __launch_bounds__(NTHREADS) void k_assemble(AsmArgs A) {
 #pragma unroll
           for (int i = 0; i < PQ; ++i) Sw[ql * PQ + i] = sw[i];
         } else if (role == 1) {
-          double *o = Bpsi + ql * Mp;
-          momentum_basis(dot3(d, G.xin), dot3(d, G.yin), dot3(d, G.zin), D, A.family, o);
+          double *o = Bpsi + ql * Ml;
+          momentum_row<DM, false>(dot3(d, G.xin), dot3(d, G.yin), dot3(d, G.zin), D, A.family, thom, o);
           for (int k = M; k < Mp; ++k) o[k] = 0.0;
         } else {
           double dd[3] = {d[0], d[1], d[2]};
@@ -820,67 +887,72 @@ __global__ __launch_bounds__(NTHREADS) void k_assemble(AsmArgs A) {
             double dn = dot3(d, G.nrm[l_out]);
             for (int i = 0; i < 3; ++i) dd[i] = d[i] - 2.0 * dn * G.nrm[l_out][i];
           }
-          double *o = Apsi + ql * Mp;
-          momentum_basis(dot3(dd, G.xd), dot3(dd, G.yd), dot3(dd, G.zd), D, A.family, o);
-          apply_gram_inverse(o, D, A.family, thom);
+          double *o = Apsi + ql * Ml;
+          momentum_row<DM, false>(dot3(dd, G.xd), dot3(dd, G.yd), dot3(dd, G.zd), D, A.family, thom, o);
           for (int k = M; k < Mp; ++k) o[k] = 0.0;
         }
       } else {
         if (role == 0) {
           for (int i = 0; i < PQ; ++i) Sw[ql * PQ + i] = 0.0;
         } else if (role == 1) {
-          for (int k = 0; k < Mp; ++k) Bpsi[ql * Mp + k] = 0.0;
+          for (int k = 0; k < Mp; ++k) Bpsi[ql * Ml + k] = 0.0;
         } else {
-          for (int k = 0; k < Mp; ++k) Apsi[ql * Mp + k] = 0.0;
+          for (int k = 0; k < Mp; ++k) Apsi[ql * Ml + k] = 0.0;
         }
       }
     }
     __syncthreads();
     const int steps = (Q - q0 >= chunk) ? chunk / 4 : (Q - q0 + 3) / 4;
-    for (int s = 0; s < steps; ++s) {
-      const int qq = 4 * s + qrow;
-      const double *arow = Apsi + qq * Mp;
-      const double *brow = Bpsi + qq * Mp;
-      const double *srow = Sw + qq * PQ;
-      double av[MAXT], bv[MAXT];
-#pragma unroll
-      for (int i = 0; i < MAXT; ++i) {
-        av[i] = arow[aoff[i]];
-        bv[i] = brow[boff[i]] * srow[spq[i]];
-      }
-#pragma unroll
-      for (int i = 0; i < MAXT; ++i)
-        if (act[i]) acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[i], acc[i], 0, 0, 0);
+    const double *ap = Apsi + qrow * Ml + r0 * 16 + col;
+    const double *bp = Bpsi + qrow * Ml;
+    const double *sp = Sw + qrow * PQ;
+    if (rb == RB) {
+      if (cb == CB) contract_chunk<RB, CB, RB, CB, PQ>(acc, ap, bp, sp, boff, spq, steps, Ml);
+      else contract_chunk<RB, CB - 1, RB, CB, PQ>(acc, ap, bp, sp, boff, spq, steps, Ml);
+    } else {
+      if (cb == CB) contract_chunk<RB - 1, CB, RB, CB, PQ>(acc, ap, bp, sp, boff, spq, steps, Ml);
+      else contract_chunk<RB - 1, CB - 1, RB, CB, PQ>(acc, ap, bp, sp, boff, spq, steps, Ml);
     }
     __syncthreads();
   }
 
-  // write out: lane holds rows lane/16 + 4e (e = 0..3), column lane%16 of each tile
+  // epilogue, one slab of column tiles [t0, t1) at a time
   const int Kp = A.Kp;
   double *Bb = A.B + (int64_t)blk * K * Kp;
   const double wgt = G.weight;
+  double *Ts = dyn;
   bool bad = false;
-#pragma unroll
-  for (int i = 0; i < MAXT; ++i) {
-    const int t = tile0 + wave + 8 * i;
-    if (t < tile1) {
-      const int tr = t % R, tc = t / R;
-      const int c = tc * 16 + col;
+  for (int t0 = cs0; t0 < cs1; t0 += A.slab_tiles) {
+    const int t1 = min(cs1, t0 + A.slab_tiles);
+    if (rb == RB) {
+      if (cb == CB) stage_tiles<RB, CB, RB, CB>(acc, Ts, c0, r0, t0, t1, Ml, col, qrow);
+      else stage_tiles<RB, CB - 1, RB, CB>(acc, Ts, c0, r0, t0, t1, Ml, col, qrow);
+    } else {
+      if (cb == CB) stage_tiles<RB - 1, CB, RB, CB>(acc, Ts, c0, r0, t0, t1, Ml, col, qrow);
+      else stage_tiles<RB - 1, CB - 1, RB, CB>(acc, Ts, c0, r0, t0, t1, Ml, col, qrow);
+    }
+    __syncthreads();
+    const int ncol = (t1 - t0) * 16;
+    if (tid < ncol) {
+      const int c = t0 * 16 + tid;
+      if (c - (c / Mp) * Mp < M) gram_solve_column<DM>(Ts + tid * Ml, D, A.family, thom, wgt);
+    }
+    __syncthreads();
+    for (int cs = wave; cs < ncol; cs += NTHREADS / 64) {
+      const int c = t0 * 16 + cs;
       const int pq = c / Mp;
       const int k = c - pq * Mp;
-      const int pp = pq / P, p = pq - pp * P;
       if (k < M) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int kp = tr * 16 + qrow + 4 * e;
-          if (kp < M) {
-            double v = wgt * acc[i][e];
-            bad |= !isfinite(v);
-            Bb[(int64_t)(p * M + k) * Kp + (pp * M + kp)] = v;
-          }
+        const int pp = pq / P, p = pq - (pq / P) * P;
+        double *dst = Bb + (int64_t)(p * M + k) * Kp + pp * M;
+        for (int kp = lane; kp < M; kp += 64) {
+          const double v = Ts[cs * Ml + kp];
+          bad |= !isfinite(v);
+          dst[kp] = v;
         }
       }
     }
+    __syncthreads();
   }
   // zero the padding rows K..Kp-1 of every column
   if (split == 0)
@@ -933,6 +1005,7 @@ __global__ __launch_bounds__(NTHREADS) void k_energy(AsmArgs A) {
   const int j = (int)(blk / 12), r = (int)(blk % 12), l_out = r / 3, sidx = r % 3;
   const int l_in = (sidx < l_out) ? sidx : sidx + 1;
   const int Mp = A.Mp, M = A.M, K = A.K, n = A.n, D = A.D;
+  const int Ml = Mp + 1;  // LDS row stride of the per-node basis rows: odd, so lanes hit distinct banks
   if (tid == 0) {
     double cx[3] = {0.0, 0.0, 0.0};
     for (int m = 0; m < 4; ++m)
@@ -954,8 +1027,8 @@ __global__ __launch_bounds__(NTHREADS) void k_energy(AsmArgs A) {
   }
   __syncthreads();
   const int chunk = A.chunk;
-  double *Bpsi = dyn;                   // [chunk][Mp]
-  double *Ew = dyn + chunk * Mp;        // [chunk][2P]: W E_p, W dE_p
+  double *Bpsi = dyn;                   // [chunk][Mp + 1]
+  double *Ew = dyn + chunk * Ml;        // [chunk][2P]: W E_p, W dE_p
   const int Q = G.ncells * n * n;
   const int role = wave & 3, half = wave >> 2;
   double acc = 0.0, dacc = 0.0;
@@ -976,21 +1049,21 @@ __global__ __launch_bounds__(NTHREADS) void k_energy(AsmArgs A) {
             Ew[ql * 2 * P + P + p] = de[p];
           }
         } else {
-          double *o = Bpsi + ql * Mp;
-          momentum_basis(dot3(d, G.xin), dot3(d, G.yin), dot3(d, G.zin), D, A.family, o);
+          double *o = Bpsi + ql * Ml;
+          momentum_row<DMAX, false>(dot3(d, G.xin), dot3(d, G.yin), dot3(d, G.zin), D, A.family, thom, o);
         }
       } else {
         if (role == 0)
           for (int i = 0; i < 2 * P; ++i) Ew[ql * 2 * P + i] = 0.0;
         else
-          for (int k = 0; k < M; ++k) Bpsi[ql * Mp + k] = 0.0;
+          for (int k = 0; k < M; ++k) Bpsi[ql * Ml + k] = 0.0;
       }
     }
     __syncthreads();
     if (tid < K) {
       const int nq = min(chunk, Q - q0);
       for (int qq = 0; qq < nq; ++qq) {
-        const double bk = Bpsi[qq * Mp + tk];
+        const double bk = Bpsi[qq * Ml + tk];
         acc = fma(Ew[qq * 2 * P + tp], bk, acc);
         dacc = fma(Ew[qq * 2 * P + P + tp], bk, dacc);
       }
@@ -1023,6 +1096,7 @@ __global__ __launch_bounds__(NTHREADS) void k_dmu(AsmArgs A) {
   const int j = (int)(blk / 12), r = (int)(blk % 12), l_out = r / 3, sidx = r % 3;
   const int l_in = (sidx < l_out) ? sidx : sidx + 1;
   const int Mp = A.Mp, M = A.M, K = A.K, n = A.n, D = A.D;
+  const int Ml = Mp + 1;  // LDS row stride of the per-node basis rows: odd, so lanes hit distinct banks
   load_tables(A, glx, glw, thom, coef);
   if (tid == 0) {
     block_setup(A, j, l_in, l_out, G);
@@ -1040,8 +1114,8 @@ __global__ __launch_bounds__(NTHREADS) void k_dmu(AsmArgs A) {
   }
   const int chunk = A.chunk;
   double *Apsi = dyn;
-  double *Bpsi = dyn + chunk * Mp;
-  double *Sw = dyn + 2 * chunk * Mp;
+  double *Bpsi = dyn + chunk * Ml;
+  double *Sw = dyn + 2 * chunk * Ml;
   const int Q = G.ncells * n * n;
   const int role = wave & 3, half = wave >> 2;
   double acc = 0.0;
@@ -1058,16 +1132,16 @@ __global__ __launch_bounds__(NTHREADS) void k_dmu(AsmArgs A) {
 #pragma unroll
           for (int i = 0; i < PQ; ++i) Sw[ql * PQ + i] = sw[i];
         } else if (role == 1) {
-          momentum_basis(dot3(d, G.xin), dot3(d, G.yin), dot3(d, G.zin), D, A.family, Bpsi + ql * Mp);
+          momentum_row<DMAX, false>(dot3(d, G.xin), dot3(d, G.yin), dot3(d, G.zin), D, A.family, thom,
+                                    Bpsi + ql * Ml);
         } else {
           double dd[3] = {d[0], d[1], d[2]};
           if (!G.transmit) {
             double dn = dot3(d, G.nrm[l_out]);
             for (int i = 0; i < 3; ++i) dd[i] = d[i] - 2.0 * dn * G.nrm[l_out][i];
           }
-          double *o = Apsi + ql * Mp;
-          momentum_basis(dot3(dd, G.xd), dot3(dd, G.yd), dot3(dd, G.zd), D, A.family, o);
-          apply_gram_inverse(o, D, A.family, thom);
+          double *o = Apsi + ql * Ml;
+          momentum_row<DMAX, true>(dot3(dd, G.xd), dot3(dd, G.yd), dot3(dd, G.zd), D, A.family, thom, o);
         }
       } else if (role == 0) {
         for (int i = 0; i < PQ; ++i) Sw[ql * PQ + i] = 0.0;
@@ -1075,7 +1149,7 @@ __global__ __launch_bounds__(NTHREADS) void k_dmu(AsmArgs A) {
     }
     __syncthreads();
     if (tid < chunk && q0 + tid < Q) {
-      const double *bp = Bpsi + tid * Mp, *ap = Apsi + tid * Mp;
+      const double *bp = Bpsi + tid * Ml, *ap = Apsi + tid * Ml;
       double av[P], bv[P];
 #pragma unroll
       for (int p = 0; p < P; ++p) {
@@ -1147,9 +1221,9 @@ __global__ void k_dest(const int32_t *nbr, int64_t nslot, int32_t *dest) {
   dest[s] = (k >= 0) ? k : (int32_t)s;
 }
 
-template <int MAXT, int PQ>
+template <int RB, int CB, int PQ, int DM>
 hipError_t launch_t(const AsmArgs &a, size_t lds, hipStream_t st) {
-  auto kern = k_assemble<MAXT, PQ>;
+  auto kern = k_assemble<RB, CB, PQ, DM>;
   hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   unsigned grid = (unsigned)(a.nblocks * a.nsplit);
@@ -1157,24 +1231,86 @@ hipError_t launch_t(const AsmArgs &a, size_t lds, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <int PQ>
-hipError_t launch_p(int maxt, const AsmArgs &a, size_t lds, hipStream_t st) {
-  switch (maxt) {
-    case 1: return launch_t<1, PQ>(a, lds, st);
-    case 2: return launch_t<2, PQ>(a, lds, st);
-    case 3: return launch_t<3, PQ>(a, lds, st);
-    case 4: return launch_t<4, PQ>(a, lds, st);
-    case 6: return launch_t<6, PQ>(a, lds, st);
-    case 8: return launch_t<8, PQ>(a, lds, st);
-    case 12: return launch_t<12, PQ>(a, lds, st);
-    default: return launch_t<16, PQ>(a, lds, st);
+// Instantiated kernels: (rows, cols) rectangle per wave, position pairs PQ and
+// the momentum-degree bound of the node code -- the rectangles that the layout
+// search below picks for every degree D <= 16 of both position bases.
+#define DFM_SHAPES(X)                                                                              \
+  X(1, 1, 1, 8) X(3, 1, 1, 8) X(2, 1, 1, 16) X(3, 2, 1, 16) X(4, 2, 1, 16) X(3, 5, 1, 16) X(5, 3, 1, 16) \
+  X(1, 3, 9, 8) X(1, 5, 9, 8) X(3, 4, 9, 8) X(2, 5, 9, 16) X(5, 3, 9, 16) X(3, 5, 9, 16) X(4, 4, 9, 16)
+#define DFM_SHAPE_ROW(r, c, pq, d) {r, c, pq, d},
+constexpr int SHAPES[][4] = {DFM_SHAPES(DFM_SHAPE_ROW)};
+constexpr int NSHAPES = sizeof(SHAPES) / sizeof(SHAPES[0]);
+
+hipError_t launch_shape(int shape, const AsmArgs &a, size_t lds, hipStream_t st) {
+  int idx = 0;
+#define DFM_SHAPE_CASE(r, c, pq, d) \
+  if (shape == idx++) return launch_t<r, c, pq, d>(a, lds, st);
+  DFM_SHAPES(DFM_SHAPE_CASE)
+#undef DFM_SHAPE_CASE
+  return hipErrorInvalidValue;
+}
+
+// Contraction layout for R row tiles and C column tiles: the fewest column
+// splits (each split recomputes the nodes), then the least MFMA work on the
+// busiest SIMD (waves w and w + 4 share one), then the fewest fragment loads.
+// The rectangle of every wave is exactly (RB or RB - 1) x (CB or CB - 1) for an
+// instantiated (RB, CB) of the degree bound.
+struct TileLayout {
+  int nsplit, wr_waves, shape;
+};
+
+TileLayout choose_layout(int R, int C, int pq, int dm) {
+  TileLayout best{0, 0, -1};
+  int best_mm = 0, best_ml = 0;
+  for (int nsplit = 1; nsplit <= C && best.shape < 0; ++nsplit) {
+    for (int WR : {1, 2, 4, 8}) {
+      const int WC = 8 / WR;
+      int rbmax = 0, cbmax = 0, rbmin = 1 << 30, cbmin = 1 << 30;
+      int simd_mfma[4] = {0, 0, 0, 0}, simd_load[4] = {0, 0, 0, 0};
+      for (int split = 0; split < nsplit; ++split) {
+        const int cs0 = (split * C) / nsplit, ncs = ((split + 1) * C) / nsplit - cs0;
+        int sm[4] = {0, 0, 0, 0}, sl[4] = {0, 0, 0, 0};
+        for (int w = 0; w < 8; ++w) {
+          const int wr = w / WC, wc = w % WC;
+          const int rb = ((wr + 1) * R) / WR - (wr * R) / WR;
+          const int cb = ((wc + 1) * ncs) / WC - (wc * ncs) / WC;
+          rbmax = rb > rbmax ? rb : rbmax;
+          cbmax = cb > cbmax ? cb : cbmax;
+          rbmin = rb < rbmin ? rb : rbmin;
+          cbmin = cb < cbmin ? cb : cbmin;
+          sm[w % 4] += rb * cb;
+          sl[w % 4] += (rb > 0 && cb > 0) ? rb + 2 * cb : 0;
+        }
+        for (int s = 0; s < 4; ++s) {
+          simd_mfma[s] = sm[s] > simd_mfma[s] ? sm[s] : simd_mfma[s];
+          simd_load[s] = sl[s] > simd_load[s] ? sl[s] : simd_load[s];
+        }
+      }
+      if (rbmin < rbmax - 1 || cbmin < cbmax - 1) continue;
+      int shape = -1;
+      for (int k = 0; k < NSHAPES; ++k)
+        if (SHAPES[k][0] == rbmax && SHAPES[k][1] == cbmax && SHAPES[k][2] == pq && SHAPES[k][3] == dm)
+          shape = k;
+      if (shape < 0) continue;
+      int mm = 0, ml = 0;
+      for (int s = 0; s < 4; ++s) {
+        mm = simd_mfma[s] > mm ? simd_mfma[s] : mm;
+        ml = simd_load[s] > ml ? simd_load[s] : ml;
+      }
+      if (best.shape < 0 || mm < best_mm || (mm == best_mm && ml < best_ml)) {
+        best = TileLayout{nsplit, WR, shape};
+        best_mm = mm;
+        best_ml = ml;
+      }
+    }
   }
+  return best;
 }
 
 // node-chunk length and dynamic LDS bytes of the block kernels for an operator
 inline void block_layout(int Mp, int PQ, int &chunk, size_t &lds) {
   chunk = Mp <= 48 ? 128 : (Mp <= 96 ? 64 : 32);
-  size_t lds_nodes = sizeof(double) * (size_t)(2 * chunk * Mp + chunk * PQ);
+  size_t lds_nodes = sizeof(double) * (size_t)(2 * chunk * (Mp + 1) + chunk * PQ);
   size_t lds_clip = sizeof(double) * 2 * PPOLY * VMAX * 3;
   lds = lds_nodes > lds_clip ? lds_nodes : lds_clip;
 }
@@ -1231,7 +1367,7 @@ hipError_t energy_functional(dfm_op op, const double *mu, const double *box, con
   int chunk;
   size_t lds;
   block_layout(a.Mp, op->P * op->P, chunk, lds);
-  size_t lds_e = sizeof(double) * (size_t)(chunk * a.Mp + chunk * 2 * op->P);
+  size_t lds_e = sizeof(double) * (size_t)(chunk * (a.Mp + 1) + chunk * 2 * op->P);
   if (lds_e > lds) lds = lds_e;
   hipError_t e = op->P == 1 ? launch_block_kernel(k_energy<1>, a, lds, st) : launch_block_kernel(k_energy<9>, a, lds, st);
   if (e != hipSuccess) return e;
@@ -1296,18 +1432,12 @@ extern "C" dfm_status dfm_assemble(dfm_mesh mesh, const dfm_basis *basis, const 
   const int Mp = (M + 15) / 16 * 16;
   const int PQ = P * P;
   const int R = Mp / 16;
-  const int total = R * (PQ * Mp / 16);
-  const int NW = NTHREADS / 64;
-  int per_wave = (total + NW - 1) / NW;
-  int nsplit = (per_wave + 15) / 16;
-  int per_split_wave = (per_wave + nsplit - 1) / nsplit;
-  int maxt = per_split_wave <= 1 ? 1 : per_split_wave <= 2 ? 2 : per_split_wave <= 3 ? 3 : per_split_wave <= 4 ? 4
-           : per_split_wave <= 6 ? 6 : per_split_wave <= 8 ? 8 : per_split_wave <= 12 ? 12 : 16;
+  const TileLayout lay = choose_layout(R, PQ * Mp / 16, PQ, D <= 8 ? 8 : 16);
+  DFM_REQUIRE(lay.shape >= 0, DFM_E_UNSUPPORTED, "no contraction layout for this basis size");
   // nodes per chunk: two halves of 64 when the LDS allows
-  int chunk = Mp <= 48 ? 128 : (Mp <= 96 ? 64 : 32);
-  size_t lds_nodes = sizeof(double) * (size_t)(2 * chunk * Mp + chunk * PQ);
-  size_t lds_clip = sizeof(double) * 2 * PPOLY * VMAX * 3;
-  size_t lds = lds_nodes > lds_clip ? lds_nodes : lds_clip;
+  int chunk;
+  size_t lds;
+  block_layout(Mp, PQ, chunk, lds);
 
   dfm_op op = new dfm_op_s();
   op->mesh = mesh;
@@ -1423,11 +1553,17 @@ extern "C" dfm_status dfm_assemble(dfm_mesh mesh, const dfm_basis *basis, const 
   a.family = bs.mom_family;
   a.rule = bs.rule;
   a.chunk = chunk;
-  a.nsplit = nsplit;
-  a.total_tiles = total;
+  a.nsplit = lay.nsplit;
   a.row_tiles = R;
-  a.tiles_per_split = (total + nsplit - 1) / nsplit;
-  hipError_t le = (PQ == 1) ? launch_p<1>(maxt, a, lds, st) : launch_p<9>(maxt, a, lds, st);
+  a.col_tiles = PQ * Mp / 16;
+  a.wr_waves = lay.wr_waves;
+  a.slab_tiles = (int)(lds / (sizeof(double) * 16 * (size_t)(Mp + 1)));
+  if (a.slab_tiles > NTHREADS / 16) a.slab_tiles = NTHREADS / 16;
+  if (a.slab_tiles < 1) {
+    set_error("dynamic LDS too small for one column tile of the block");
+    TRY(hipErrorInvalidValue);
+  }
+  hipError_t le = launch_shape(lay.shape, a, lds, st);
   TRY(le);
   unsigned hflags = 0;
   unsigned long long hnodes = 0;

@@ -15,14 +15,15 @@ namespace {
 constexpr int DMAX = 16;
 constexpr double SEAM_SNAP = 1e-13;
 
-__device__ inline void legendre_table(double x, int D, double *p) {
+template <int DM>
+__device__ __forceinline__ void legendre_table(double x, int D, double *p) {
   // orthonormal p_a = sqrt(2a+1) P_a by the three-term recurrence
   // (a+1) P_{a+1} = (2a+1) x P_a - a P_{a-1}; with a a compile-time constant in the
   // unrolled loop the coefficient quotients fold to constants (no division per node)
   double pm1 = 1.0, pc = x;
   p[0] = 1.0;
 #pragma unroll
-  for (int a = 1; a <= DMAX; ++a) {
+  for (int a = 1; a <= DM; ++a) {
     if (a > D) break;
     p[a] = sqrt(2.0 * a + 1.0) * pc;
     double pn = ((2.0 * a + 1.0) / (a + 1.0)) * x * pc - (a / (a + 1.0)) * pm1;
@@ -31,34 +32,75 @@ __device__ inline void legendre_table(double x, int D, double *p) {
   }
 }
 
-// psi_k at a direction with frame components (dx, dy, dz) into out[0..M)
-__device__ void momentum_basis(double dx, double dy, double dz, int D, int family, double *out) {
+// One row of the momentum basis at a direction with frame components (dx, dy, dz):
+// out[k] = psi_k, or (G^-1 psi)_k when GINV, for k < M = (D+1)(D+2)/2, D <= DM.
+// Every loop is unrolled to the compile-time bound DM, so the basis values stay
+// in registers and out is written once per entry.  The Legendre family's Gram
+// matrix is pi (I + J) per block of fixed b (unknowns a = 0..D-b), solved by the
+// Thomas algorithm with the elimination tables thom = [J off-diagonal | c' | 1/den];
+// the Zernike family's is diagonal.
+template <int DM, bool GINV>
+__device__ __forceinline__ void momentum_row(double dx, double dy, double dz, int D, int family,
+                                             const double *__restrict__ thom, double *__restrict__ out) {
   if (family == 0) {
     double phi = atan2(dy, dx);
     if (phi < 0.0) phi += 2.0 * M_PI;
     if (fabs(dy) <= SEAM_SNAP && dx > 0.0) phi = 0.0;
-    double px[DMAX + 1], py[DMAX + 1];
-    legendre_table(2.0 * dz - 1.0, D, px);
-    legendre_table(phi * (1.0 / M_PI) - 1.0, D, py);
+    double px[DM + 1];
+    legendre_table<DM>(2.0 * dz - 1.0, D, px);
+    const double y = phi * (1.0 / M_PI) - 1.0;
+    double Pb = 1.0, Pbm1 = 0.0;  // P_b(y), P_{b-1}(y)
 #pragma unroll
-    for (int t = 0; t <= DMAX; ++t) {
-      if (t <= D) {
+    for (int b = 0; b <= DM; ++b) {
+      if (b > D) break;
+      const int N = D - b;
+      const double qb = sqrt(2.0 * b + 1.0) * Pb;
+      if (!GINV) {
 #pragma unroll
-        for (int b = 0; b <= t; ++b) out[t * (t + 1) / 2 + b] = px[t - b] * py[b];
+        for (int a = 0; a <= DM - b; ++a)
+          if (a <= N) out[(a + b) * (a + b + 1) / 2 + b] = px[a] * qb;
+      } else {
+        const double *jo = thom;
+        const double *cpb = thom + (DMAX + 1) * (DMAX + 1) + b * (DMAX + 1);
+        const double *idb = thom + 2 * (DMAX + 1) * (DMAX + 1) + b * (DMAX + 1);
+        double dp[DM + 1];
+        double prev = 0.0;
+#pragma unroll
+        for (int a = 0; a <= DM - b; ++a) {
+          if (a <= N) {
+            const double v = px[a] * qb * (1.0 / M_PI);
+            const double dpa = (a == 0) ? v * idb[0] : (v - jo[a - 1] * prev) * idb[a];
+            dp[a] = dpa;
+            prev = dpa;
+          }
+        }
+        double next = 0.0;
+#pragma unroll
+        for (int a = DM - b; a >= 0; --a) {
+          if (a <= N) {
+            const double xa = (a == N) ? dp[a] : dp[a] - cpb[a] * next;
+            out[(a + b) * (a + b + 1) / 2 + b] = xa;
+            next = xa;
+          }
+        }
       }
+      const double Pn = ((2.0 * b + 1.0) / (b + 1.0)) * y * Pb - (b / (b + 1.0)) * Pbm1;
+      Pbm1 = Pb;
+      Pb = Pn;
     }
   } else {
     // Z_n^{+-m} = P_k^{(0,m)}(2 rho^2 - 1) * (Re, Im)(dx + i dy)^m, n = m + 2k, with the
-    // Jacobi polynomials P_k^{(0,m)} from their three-term recurrence
+    // Jacobi polynomials P_k^{(0,m)} from their three-term recurrence; the Gram
+    // matrix is diag(eps_m pi / (2n + 2)), eps_0 = 2, else 1
     double r2 = dx * dx + dy * dy;
     double tt = 2.0 * r2 - 1.0;
     double cm = 1.0, sm = 0.0;
 #pragma unroll
-    for (int m = 0; m <= DMAX; ++m) {
+    for (int m = 0; m <= DM; ++m) {
       if (m <= D) {
         double pkm1 = 0.0, pk = 1.0;
 #pragma unroll
-        for (int k = 0; 2 * k + m <= DMAX; ++k) {
+        for (int k = 0; 2 * k + m <= DM; ++k) {
           int n = m + 2 * k;
           if (n <= D) {
             if (k == 1) {
@@ -73,9 +115,11 @@ __device__ void momentum_basis(double dx, double dy, double dz, int D, int famil
               pkm1 = pk;
               pk = pn;
             }
-            int base = n * (n + 1) / 2;
-            out[base + (m + n) / 2] = pk * cm;
-            if (m > 0) out[base + (n - m) / 2] = pk * sm;
+            const int base = n * (n + 1) / 2;
+            const double gp = GINV ? (2.0 * n + 2.0) / ((m == 0 ? 2.0 : 1.0) * M_PI) : 1.0;
+            const double gm = GINV ? (2.0 * n + 2.0) / M_PI : 1.0;
+            out[base + (m + n) / 2] = (pk * cm) * gp;
+            if (m > 0) out[base + (n - m) / 2] = (pk * sm) * gm;
           }
         }
       }
@@ -124,6 +168,55 @@ __device__ void apply_gram_inverse(double *out, int D, int family, const double 
       double xa = (a == N) ? out[k] : out[k] - cpb[a] * next;
       out[k] = xa;
       next = xa;
+    }
+  }
+}
+
+// In place on a contiguous column c[0..M): c <- scale * G^-1 c, loops unrolled to
+// the compile-time degree bound DM >= D so each Thomas block sits in registers.
+template <int DM>
+__device__ __forceinline__ void gram_solve_column(double *__restrict__ c, int D, int family,
+                                                  const double *__restrict__ thom, double scale) {
+  if (family == 1) {
+#pragma unroll
+    for (int n = 0; n <= DM; ++n) {
+      if (n <= D) {
+#pragma unroll
+        for (int i = 0; i <= n; ++i) {
+          const int m = -n + 2 * i;
+          c[n * (n + 1) / 2 + i] *= scale * ((2.0 * n + 2.0) / ((m == 0 ? 2.0 : 1.0) * M_PI));
+        }
+      }
+    }
+    return;
+  }
+#pragma unroll
+  for (int b = 0; b <= DM; ++b) {
+    if (b > D) break;
+    const int N = D - b;
+    const double *jo = thom;
+    const double *cpb = thom + (DMAX + 1) * (DMAX + 1) + b * (DMAX + 1);
+    const double *idb = thom + 2 * (DMAX + 1) * (DMAX + 1) + b * (DMAX + 1);
+    double v[DM + 1];
+#pragma unroll
+    for (int a = 0; a <= DM - b; ++a)
+      if (a <= N) v[a] = c[(a + b) * (a + b + 1) / 2 + b];
+    double prev = 0.0;
+#pragma unroll
+    for (int a = 0; a <= DM - b; ++a) {
+      if (a <= N) {
+        const double w = v[a] * (1.0 / M_PI);
+        prev = (a == 0) ? w * idb[0] : (w - jo[a - 1] * prev) * idb[a];
+        v[a] = prev;
+      }
+    }
+    double next = 0.0;
+#pragma unroll
+    for (int a = DM - b; a >= 0; --a) {
+      if (a <= N) {
+        next = (a == N) ? v[a] : v[a] - cpb[a] * next;
+        c[(a + b) * (a + b + 1) / 2 + b] = scale * next;
+      }
     }
   }
 }
