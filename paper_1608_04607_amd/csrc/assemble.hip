@@ -42,13 +42,14 @@ void free_op(dfm_op op);
 namespace {
 
 constexpr int CMAX = 80;       // quadrature cells per block
-constexpr int PPOLY = 32;      // polygons per region while cutting (2^5 cuts)
 constexpr int VMAX = 12;       // corners per polygon
 constexpr int NTHREADS = 512;  // 8 waves
 constexpr int NPLANES = 5;
 constexpr double TOL = 1e-12;
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+
+struct BlockGeo;
 
 struct AsmArgs {
   const double *verts;
@@ -69,6 +70,8 @@ struct AsmArgs {
   double box[6];        // receiver box xmin, xmax, ymin, ymax, zmin, zmax
   unsigned *flags;
   unsigned long long *nodes;
+  BlockGeo *geo;        // per block: frames and cell count (from k_cells)
+  double *cellbuf;      // per block: [CMAX][4][3] cell corners (from k_cells)
   int64_t nblocks;
   int P, D, M, Mp, K, Kp, n, family, rule;
   int chunk;
@@ -364,6 +367,14 @@ __device__ void region_patch(const BlockGeo &G, int r, double (*out)[3]) {
   }
 }
 
+// Cells of one block.  Rule 0: the four direction regions of Sec. 3.4 as they are.
+// Rule 1: every region cut by the five seam planes, depth first (positive side
+// first, so the pieces come out in the same order as cutting all pieces by one
+// plane after the other), each final piece fanned from a pole it touches.
+// work holds (NPLANES + 2) * VMAX * 3 doubles: a stack of one polygon per level
+// and one temporary.
+constexpr int CELL_WORK = (NPLANES + 2) * VMAX * 3;
+
 __device__ void build_cells(BlockGeo &G, double (*cells)[4][3], double *work, int rule) {
   int xb = G.xb;
   int qa = 1 + xb, qb = 1 + (xb + 2) % 3;
@@ -384,47 +395,43 @@ __device__ void build_cells(BlockGeo &G, double (*cells)[4][3], double *work, in
     planes[4][i] = G.zin[i] - G.nrm[G.l_out][i];
   }
   double pole_d[3] = {G.nrm[G.l_out][0], G.nrm[G.l_out][1], G.nrm[G.l_out][2]};
-  double(*bufA)[VMAX][3] = (double(*)[VMAX][3])work;
-  double(*bufB)[VMAX][3] = (double(*)[VMAX][3])(work + PPOLY * VMAX * 3);
-  int cntA[PPOLY], cntB[PPOLY];
+  double(*stk)[VMAX][3] = (double(*)[VMAX][3])work;                    // [NPLANES + 1]
+  double(*tmp)[3] = (double(*)[3])(work + (NPLANES + 1) * VMAX * 3);   // [VMAX]
+  int cnt[NPLANES + 1], lvl[NPLANES + 1];
   for (int r = 0; r < 4; ++r) {
     double patch[4][3];
     region_patch(G, regions[r], patch);
-    int na = 1;
-    cntA[0] = patch_polygon(patch, bufA[0]);
-    for (int pl = 0; pl < NPLANES; ++pl) {
-      int nb = 0;
-      for (int pi = 0; pi < na; ++pi) {
-        int mp, mn;
-        if (nb + 2 > PPOLY) {
-          G.overflow = 1;
-          break;
-        }
-        clip_poly(bufA[pi], cntA[pi], planes[pl], bufB[nb], mp, bufB[nb + 1], mn);
-        if (mp > 0) {
-          cntB[nb] = mp;
-          ++nb;
-          if (mn > 0) {
-            // the negative part was written one slot further; move it down
-            cntB[nb] = mn;
-            ++nb;
-          }
-        } else if (mn > 0) {
-          for (int k = 0; k < mn; ++k)
-            for (int i = 0; i < 3; ++i) bufB[nb][k][i] = bufB[nb + 1][k][i];
-          cntB[nb] = mn;
-          ++nb;
-        }
+    cnt[0] = patch_polygon(patch, stk[0]);
+    lvl[0] = 0;
+    int sp = 0;
+    // an entry at stack index i has level >= i, so clipping writes at most index NPLANES
+    while (sp >= 0) {
+      const int pl = lvl[sp];
+      if (pl == NPLANES) {
+        fan_polygon(G, cells, stk[sp], cnt[sp], G.zin, pole_d);
+        --sp;
+        continue;
       }
-      // swap
-      for (int pi = 0; pi < nb; ++pi) {
-        for (int k = 0; k < cntB[pi]; ++k)
-          for (int i = 0; i < 3; ++i) bufA[pi][k][i] = bufB[pi][k][i];
-        cntA[pi] = cntB[pi];
+      int mp, mn;
+      clip_poly(stk[sp], cnt[sp], planes[pl], stk[sp + 1], mp, tmp, mn);
+      int top = sp - 1;
+      if (mn > 0) {
+        ++top;  // == sp: the negative part replaces the clipped polygon
+        for (int k = 0; k < mn; ++k)
+          for (int i = 0; i < 3; ++i) stk[top][k][i] = tmp[k][i];
+        cnt[top] = mn;
+        lvl[top] = pl + 1;
       }
-      na = nb;
+      if (mp > 0) {
+        ++top;  // the positive part goes on top and is cut first
+        if (top != sp + 1)
+          for (int k = 0; k < mp; ++k)
+            for (int i = 0; i < 3; ++i) stk[top][k][i] = stk[sp + 1][k][i];
+        cnt[top] = mp;
+        lvl[top] = pl + 1;
+      }
+      sp = top;
     }
-    for (int pi = 0; pi < na; ++pi) fan_polygon(G, cells, bufA[pi], cntA[pi], G.zin, pole_d);
   }
 }
 
@@ -724,6 +731,28 @@ __device__ void block_setup(const AsmArgs &A, int j, int l_in, int l_out, BlockG
 }
 
 // ---------------------------------------------------------------------------
+// Frames and quadrature cells of every block, one thread per block, each with its
+// cutting stack in LDS; the assembly kernel reads them back.
+// ---------------------------------------------------------------------------
+constexpr int CELL_THREADS = 32;
+
+__global__ __launch_bounds__(CELL_THREADS) void k_cells(AsmArgs A) {
+  __shared__ double work[CELL_THREADS][CELL_WORK];
+  const int64_t b = (int64_t)blockIdx.x * CELL_THREADS + threadIdx.x;
+  if (b >= A.nblocks) return;
+  const int j = (int)(b / 12);
+  const int r = (int)(b % 12);
+  const int l_out = r / 3;
+  const int sidx = r % 3;
+  const int l_in = (sidx < l_out) ? sidx : sidx + 1;
+  BlockGeo G;
+  block_setup(A, j, l_in, l_out, G);
+  build_cells(G, (double(*)[4][3])(A.cellbuf + b * (CMAX * 12)), work[threadIdx.x], A.rule);
+  if (G.overflow) atomicOr(A.flags, FLAG_CELL_OVERFLOW);
+  A.geo[b] = G;
+}
+
+// ---------------------------------------------------------------------------
 // The kernel: 8 waves.  Node phase: wave w takes role w % 4 (0 geometry and S,
 // 1 psi, 2 psi', 3 idle) for the nodes of half w / 4 of the chunk.
 // Contraction: the output T (Mp rows x PQ Mp columns, 16 x 16 tiles) is cut into
@@ -826,11 +855,18 @@ __global__ __launch_bounds__(NTHREADS) void k_assemble(AsmArgs A) {
   }
   for (int i = tid; i < 3 * (DMAX + 1) * (DMAX + 1); i += NTHREADS) thom[i] = A.thom[i];
   for (int i = tid; i < NMOM * NSERIES; i += NTHREADS) coef[i] = A.coef[i];
-  if (tid == 0) {
-    block_setup(A, j, l_in, l_out, G);
-    build_cells(G, cells, dyn, A.rule);
-    if (G.overflow) atomicOr(A.flags, FLAG_CELL_OVERFLOW);
-    if (split == 0) atomicAdd(A.nodes, (unsigned long long)G.ncells * (unsigned long long)(n * n));
+  {
+    // frames and cells of the block, prepared by k_cells
+    const unsigned *src = (const unsigned *)(A.geo + blk);
+    unsigned *dst = (unsigned *)&G;
+    for (int i = tid; i < (int)(sizeof(BlockGeo) / 4); i += NTHREADS) dst[i] = src[i];
+  }
+  __syncthreads();
+  {
+    const double *src = A.cellbuf + blk * (CMAX * 12);
+    double *dst = &cells[0][0][0];
+    for (int i = tid; i < G.ncells * 12; i += NTHREADS) dst[i] = src[i];
+    if (tid == 0 && split == 0) atomicAdd(A.nodes, (unsigned long long)G.ncells * (unsigned long long)(n * n));
   }
   __syncthreads();
 
@@ -1311,7 +1347,7 @@ TileLayout choose_layout(int R, int C, int pq, int dm) {
 inline void block_layout(int Mp, int PQ, int &chunk, size_t &lds) {
   chunk = Mp <= 48 ? 128 : (Mp <= 96 ? 64 : 32);
   size_t lds_nodes = sizeof(double) * (size_t)(2 * chunk * (Mp + 1) + chunk * PQ);
-  size_t lds_clip = sizeof(double) * 2 * PPOLY * VMAX * 3;
+  size_t lds_clip = sizeof(double) * CELL_WORK;
   lds = lds_nodes > lds_clip ? lds_nodes : lds_clip;
 }
 
@@ -1452,7 +1488,11 @@ extern "C" dfm_status dfm_assemble(dfm_mesh mesh, const dfm_basis *basis, const 
   double *gl = nullptr, *thom_d = nullptr, *coef_d = nullptr;
   unsigned *flags = nullptr;
   unsigned long long *nodes = nullptr;
+  BlockGeo *geo = nullptr;
+  double *cellbuf = nullptr;
   auto fail = [&](dfm_status code) {
+    (void)hipFree(geo);
+    (void)hipFree(cellbuf);
     (void)hipFree(gl);
     (void)hipFree(thom_d);
     (void)hipFree(coef_d);
@@ -1476,6 +1516,8 @@ extern "C" dfm_status dfm_assemble(dfm_mesh mesh, const dfm_basis *basis, const 
   TRY(hipMalloc(&coef_d, sizeof(double) * NMOM * NSERIES));
   TRY(hipMalloc(&flags, sizeof(unsigned)));
   TRY(hipMalloc(&nodes, sizeof(unsigned long long)));
+  TRY(hipMalloc(&geo, sizeof(BlockGeo) * (size_t)nblocks));
+  TRY(hipMalloc(&cellbuf, sizeof(double) * CMAX * 12 * (size_t)nblocks));
 
   // Tridiagonal factors of I + J (Legendre Gram / pi): J_(a,a+1) = (a+1)/sqrt((2a+1)(2a+3)).
   std::vector<double> th(3 * (DMAX + 1) * (DMAX + 1), 0.0);
@@ -1563,6 +1605,11 @@ extern "C" dfm_status dfm_assemble(dfm_mesh mesh, const dfm_basis *basis, const 
     set_error("dynamic LDS too small for one column tile of the block");
     TRY(hipErrorInvalidValue);
   }
+  a.geo = geo;
+  a.cellbuf = cellbuf;
+  hipLaunchKernelGGL(k_cells, dim3((unsigned)((nblocks + CELL_THREADS - 1) / CELL_THREADS)), dim3(CELL_THREADS), 0,
+                     st, a);
+  TRY(hipGetLastError());
   hipError_t le = launch_shape(lay.shape, a, lds, st);
   TRY(le);
   unsigned hflags = 0;
@@ -1571,6 +1618,10 @@ extern "C" dfm_status dfm_assemble(dfm_mesh mesh, const dfm_basis *basis, const 
   TRY(hipMemcpyAsync(&hnodes, nodes, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
   TRY(hipStreamSynchronize(st));
 #undef TRY
+  (void)hipFree(geo);
+  (void)hipFree(cellbuf);
+  geo = nullptr;
+  cellbuf = nullptr;
   op->gl = gl;
   op->thom = thom_d;
   op->coef = coef_d;
