@@ -83,6 +83,31 @@ def cpu_baseline(prob, rule, ntets):
                       f"FP64 NumPy oracle, {cores} worker processes, {dt:.1f} s"}
 
 
+# --------------------------------------------------------------------------- HBM byte counters
+
+COUNTERS = os.path.join(ROOT, "profiles", "counters_box8x8x8_P1_D8_n12.txt")
+
+
+def measured_traffic(label):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 byte counters
+    (FETCH_SIZE / WRITE_SIZE scaled by a plain-copy calibration), or None when the
+    kernel's source file changed since the counters were taken."""
+    import hashlib
+    if not os.path.exists(COUNTERS):
+        return None
+    for line in open(COUNTERS):
+        if not line.startswith("kernel="):
+            continue
+        kv = dict(tok.split("=", 1) for tok in line.split())
+        if kv["kernel"] != label:
+            continue
+        src = os.path.join(ROOT, kv["source"])
+        if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != kv["sha256"]:
+            return None
+        return float(kv["bytes"])
+    return None
+
+
 # --------------------------------------------------------------------------- GPU path
 
 
@@ -201,10 +226,10 @@ def main():
     spmv_gbs = spmv_bytes / (t_spmv / 1e3) / 1e9
     t_spmv_step = t_spmv * info[0]  # FP64 solve's operator applications
     roof_asm = {"kernel": "k_assemble", "bound": "mfma", "achieved": asm_tflops, "peak": FP64_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": asm_tflops / FP64_PEAK_TFLOPS, "traffic": None,
+                "unit": "TFLOP/s", "frac": asm_tflops / FP64_PEAK_TFLOPS, "traffic": measured_traffic("k_assemble"),
                 "algorithmic": f"2*Q*K^2 flop per block, Q summed over blocks = {nodes}, K = {K}"}
     roof_spmv = {"kernel": "k_spmv", "bound": "hbm", "achieved": spmv_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                 "frac": spmv_gbs / HBM_PEAK_GBS, "traffic": None,
+                 "frac": spmv_gbs / HBM_PEAK_GBS, "traffic": measured_traffic("k_spmv_f64"),
                  "algorithmic": "8*(12*N*K^2 + 2*ndof) bytes per launch (B once, x and y once)"}
     dominant, other = (roof_asm, roof_spmv) if t_asm >= t_spmv_step else (roof_spmv, roof_asm)
     out = {
