@@ -78,11 +78,16 @@ typedef struct {
   int restart;    /* GMRES restart length (Krylov vectors kept), 1..200                 */
   int max_iter;   /* total iteration cap (operator applications)                        */
   double rtol;    /* stop when ||rho0 - (I-B) rho||_2 <= rtol ||rho0||_2                */
-  int precision;  /* 0: FP64 throughout; 1 (GMRES only): iterative refinement with FP64
-                        residuals of the FP64 operator around FP32 GMRES corrections on an
-                        FP32 copy of B (made on first use, kept with the operator) with FP32
-                        Krylov vectors and FP64 accumulation.  The stop test is the FP64
-                        residual in both cases.                                          */
+  int precision;  /* 0: FP64 throughout.  1: iterative refinement with FP64 residuals of
+                        the FP64 operator around FP32 corrections on an FP32 copy of B
+                        (made on first use, kept with the operator):
+                        GMRES  -- FP32 GMRES with FP32 Krylov vectors and FP64
+                                  accumulation, one right-hand side after the other;
+                        Neumann -- FP32 Neumann partial sums for all nrhs right-hand
+                                  sides together, one product per term on the FP32
+                                  matrix cores (dfm_apply_f32), until the estimated
+                                  tail of every active series is below 1e-4.
+                        The stop test is the FP64 residual in every case.               */
 } dfm_solve_opts;
 
 typedef struct {
@@ -150,7 +155,16 @@ dfm_status dfm_op_export(dfm_op op, double *blocks, int32_t *dest, void *stream)
  * x and y device f64 [nrhs][ndof], not aliased. */
 dfm_status dfm_apply(dfm_op op, const double *x, double *y, int nrhs, int transpose, void *stream);
 
-/* Solve (I - B) rho = rho0 for nrhs right-hand sides, one after the other.
+/* y = B32 x for nrhs right-hand sides on the FP32 matrix cores, with B32 the FP32
+ * copy of B (made on first use, kept with the operator).  x and y device f32
+ * [nrhs][ndof], not aliased.  Each block row (12 per tet: 3 blocks of K x K) is
+ * read once per 128 right-hand sides; products accumulate in FP32.
+ * Errors: DFM_E_INVALID, DFM_E_NOMEM (the FP32 copy). */
+dfm_status dfm_apply_f32(dfm_op op, const float *x, float *y, int nrhs, void *stream);
+
+/* Solve (I - B) rho = rho0 for nrhs right-hand sides: one after the other, except
+ * method 0 with precision 1, which iterates all of them together (see
+ * dfm_solve_opts).
  *   rho0, rho  device f64 [nrhs][ndof]; info host [nrhs] or NULL.
  * Returns DFM_E_NOCONV (rho holds the last iterate) if any right-hand side did
  * not reach opts->rtol within opts->max_iter.  Synchronises `stream`. */

@@ -100,8 +100,8 @@ inline size_t spmv_lds(int K, int Kp) {
 }
 
 __global__ void k_to_fp32(const double *__restrict__ a, float *__restrict__ b, int64_t n) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < n) b[i] = (float)a[i];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    b[i] = (float)a[i];
 }
 
 // y[4j + l_in][col] = alpha v[...] + beta sum_{l_out != l_in} sum_row B[j,l_out,s(l_in)][col][row] x[dest(j,l_out)][row]
@@ -129,6 +129,143 @@ __global__ void k_spmv_t(const double *__restrict__ B, const int32_t *__restrict
   y[g] = r;
 }
 
+// Batched product for R right-hand sides on the FP32 matrix cores
+// (v_mfma_f32_16x16x4f32): for every block row br = (j, l_out) and rhs r,
+//   y[r][dest(br)][row] = sum_{s, col} B32[br, s][col][row] x[r][4j + l_in(s)][col],
+// and, when e != null, e[r][dest(br)][row] += that value.  Vectors are f32
+// [R][ndof].  Workgroup = (block row, tile of SPMM_RT right-hand sides, group of
+// SPMM_ROWS output rows); its 8 waves form 2 row halves (3 row tiles of 16) x 4
+// rhs quarters (2 rhs tiles of 16).  The contraction runs over the 3K columns of
+// the block row in chunks of SPMM_KC: the chunk of B (rows x columns) and of x
+// (rhs x columns) is loaded coalesced into registers one chunk ahead, stored to
+// LDS and read back as MFMA fragments.  The result tile goes through LDS so that
+// each rhs's output rows are written as one contiguous segment.
+constexpr int SPMM_THREADS = 512;
+constexpr int SPMM_RT = 128;                  // right-hand sides per workgroup
+constexpr int SPMM_ROWS = 96;                 // output rows per workgroup
+constexpr int SPMM_KC = 32;                   // contraction chunk (columns)
+constexpr int SPMM_BLD = SPMM_ROWS + 4;       // LDS row stride of the B chunk [col][row]
+constexpr int SPMM_XLD = SPMM_RT + 4;         // LDS row stride of the x chunk [col][rhs]
+constexpr int SPMM_YLD = SPMM_ROWS + 1;       // LDS row stride of the result [rhs][row]
+constexpr int SPMM_NB = SPMM_KC * SPMM_ROWS / SPMM_THREADS;   // B chunk values per thread
+constexpr int SPMM_NX = SPMM_KC * SPMM_RT / SPMM_THREADS;     // x chunk values per thread
+constexpr int SPMM_LDS_CHUNK = SPMM_KC * (SPMM_BLD + SPMM_XLD), SPMM_LDS_OUT = SPMM_RT * SPMM_YLD;
+constexpr size_t SPMM_LDS = sizeof(float) * (size_t)(SPMM_LDS_CHUNK > SPMM_LDS_OUT ? SPMM_LDS_CHUNK : SPMM_LDS_OUT);
+static_assert(SPMM_NB * SPMM_THREADS == SPMM_KC * SPMM_ROWS && SPMM_NX * SPMM_THREADS == SPMM_KC * SPMM_RT, "");
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(SPMM_THREADS, 4) void k_spmm32(const float *__restrict__ B,
+                                                           const int32_t *__restrict__ dest, int64_t nt, int K, int Kp,
+                                                           int64_t ndof, int R, const float *__restrict__ x,
+                                                           float *__restrict__ y, float *__restrict__ e) {
+  extern __shared__ float lds[];
+  float *bs = lds;                              // [SPMM_KC][SPMM_BLD]
+  float *xs = lds + SPMM_KC * SPMM_BLD;         // [SPMM_KC][SPMM_XLD]
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  // workgroups are dealt to the 8 XCDs in turn (blockIdx.x % 8): the four block
+  // rows of a tet go to one XCD back to back, so the x panels they share (each
+  // source slot feeds three of them) are read from HBM once and then from its L2
+  const int64_t bid = blockIdx.x;
+  int64_t br = bid;
+  if ((nt & 7) == 0) {
+    const int64_t slot = bid >> 3, xcd = bid & 7;
+    br = 4 * (8 * (slot >> 2) + xcd) + (slot & 3);
+  }
+  const int r0 = blockIdx.y * SPMM_RT;          // first rhs of the tile
+  const int m0 = blockIdx.z * SPMM_ROWS;        // first output row of the group
+  const int64_t j = br >> 2;
+  const int l_out = (int)(br & 3);
+  const int ncol = 3 * K;                       // contraction length of the block row
+  const int nchunk = (ncol + SPMM_KC - 1) / SPMM_KC;
+  const float *Bbr = B + br * 3 * (int64_t)K * Kp;   // 3K columns of length Kp
+
+  // coalesced chunk loads.  B chunk value i = tid + u * SPMM_THREADS -> (column
+  // i / SPMM_ROWS, row i % SPMM_ROWS), offsets fixed per thread; x chunk value i ->
+  // (rhs i / SPMM_KC, column i % SPMM_KC), the column the same for every u.
+  int bcol[SPMM_NB], brow[SPMM_NB];
+#pragma unroll
+  for (int u = 0; u < SPMM_NB; ++u) {
+    const int i = tid + u * SPMM_THREADS;
+    bcol[u] = i / SPMM_ROWS;
+    brow[u] = m0 + i % SPMM_ROWS;
+  }
+  const int xc = tid % SPMM_KC, xr = r0 + tid / SPMM_KC;   // rhs xr + u * (SPMM_THREADS / SPMM_KC)
+  constexpr int XRS = SPMM_THREADS / SPMM_KC;
+  float pb[SPMM_NB], px[SPMM_NX];
+  auto load_chunk = [&](int ch) {
+    const int c0 = ch * SPMM_KC;
+#pragma unroll
+    for (int u = 0; u < SPMM_NB; ++u) {
+      const int c = c0 + bcol[u];
+      pb[u] = (c < ncol && brow[u] < Kp) ? __builtin_nontemporal_load(Bbr + (int64_t)c * Kp + brow[u]) : 0.0f;
+    }
+    const int c = c0 + xc;
+    const int s = c / K;
+    const float *xp = x + (int64_t)xr * ndof + (4 * j + in_face(l_out, s < 3 ? s : 2)) * (int64_t)K + (c - s * K);
+#pragma unroll
+    for (int u = 0; u < SPMM_NX; ++u)
+      px[u] = (c < ncol && xr + u * XRS < R) ? xp[(int64_t)u * XRS * ndof] : 0.0f;
+  };
+  auto store_chunk = [&]() {
+#pragma unroll
+    for (int u = 0; u < SPMM_NB; ++u) bs[bcol[u] * SPMM_BLD + brow[u] - m0] = pb[u];
+#pragma unroll
+    for (int u = 0; u < SPMM_NX; ++u) xs[xc * SPMM_XLD + (xr - r0) + u * XRS] = px[u];
+  };
+
+  const int wr = wave >> 2, wc = wave & 3;      // row half, rhs quarter
+  const int col = lane & 15, kq = lane >> 4;
+  v4f acc[3][2];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+
+  load_chunk(0);
+  for (int ch = 0; ch < nchunk; ++ch) {
+    store_chunk();
+    __syncthreads();
+    if (ch + 1 < nchunk) load_chunk(ch + 1);   // in flight while this chunk is contracted
+#pragma unroll
+    for (int ks = 0; ks < SPMM_KC / 4; ++ks) {
+      const int c = ks * 4 + kq;
+      float av[3], bv[2];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) av[a] = bs[c * SPMM_BLD + (wr * 3 + a) * 16 + col];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) bv[b] = xs[c * SPMM_XLD + (wc * 2 + b) * 16 + col];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // result tile: lane holds rows 4 (lane / 16) + q of each 16-row tile, rhs lane % 16
+  float *ys = lds;                              // [SPMM_RT][SPMM_YLD]
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        ys[((wc * 2 + b) * 16 + col) * SPMM_YLD + (wr * 3 + a) * 16 + 4 * kq + q] = acc[a][b][q];
+  __syncthreads();
+  const int nrows = min(SPMM_ROWS, K - m0);
+  const int64_t ob = (int64_t)dest[br] * K + m0;
+  for (int i = tid; i < SPMM_RT * nrows; i += SPMM_THREADS) {
+    const int r = i / nrows, m = i - r * nrows;
+    if (r0 + r < R) {
+      const float v = ys[r * SPMM_YLD + m];
+      const int64_t o = (int64_t)(r0 + r) * ndof + ob + m;
+      y[o] = v;
+      if (e) e[o] += v;
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t spmv(dfm_op op, const double *x, const double *v, double *y, double alpha, double beta, hipStream_t st) {
@@ -147,6 +284,18 @@ hipError_t spmv32(dfm_op op, const float *x, const float *v, float *y, float alp
   return hipGetLastError();
 }
 
+// y = B32 x for R right-hand sides on the matrix cores (and e += y when e != null)
+hipError_t spmm32(dfm_op op, const float *x, float *y, float *e, int R, hipStream_t st) {
+  dim3 grid((unsigned)(4 * op->nt), (unsigned)((R + SPMM_RT - 1) / SPMM_RT),
+            (unsigned)((op->K + SPMM_ROWS - 1) / SPMM_ROWS));
+  hipError_t err = hipFuncSetAttribute((const void *)k_spmm32, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)SPMM_LDS);
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(k_spmm32, grid, dim3(SPMM_THREADS), SPMM_LDS, st, op->B32, op->dest, op->nt, op->K, op->Kp,
+                     op->ndof, R, x, y, e);
+  return hipGetLastError();
+}
+
 // FP32 copy of B for the mixed-precision solver (made once, kept with the operator)
 hipError_t ensure_fp32(dfm_op op, hipStream_t st) {
   if (op->B32) return hipSuccess;
@@ -156,7 +305,7 @@ hipError_t ensure_fp32(dfm_op op, hipStream_t st) {
     op->B32 = nullptr;
     return e;
   }
-  hipLaunchKernelGGL(k_to_fp32, dim3((unsigned)((nel + 255) / 256)), dim3(256), 0, st, op->B, op->B32, nel);
+  hipLaunchKernelGGL(k_to_fp32, dim3(ew_grid(nel)), dim3(256), 0, st, op->B, op->B32, nel);
   return hipGetLastError();
 }
 
@@ -184,3 +333,19 @@ extern "C" dfm_status dfm_apply(dfm_op op, const double *x, double *y, int nrhs,
   }
   return DFM_OK;
 }
+
+extern "C" dfm_status dfm_apply_f32(dfm_op op, const float *x, float *y, int nrhs, void *stream_) {
+  DFM_REQUIRE(op && x && y, DFM_E_INVALID, "null argument");
+  DFM_REQUIRE(nrhs >= 1 && nrhs <= 65535, DFM_E_INVALID, "nrhs must be in 1..65535");
+  DFM_REQUIRE(x != y, DFM_E_INVALID, "x and y must not alias");
+  hipStream_t st = (hipStream_t)stream_;
+  hipError_t e = ensure_fp32(op, st);
+  if (e == hipErrorOutOfMemory) {
+    set_error("no device memory for the FP32 copy of B");
+    return DFM_E_NOMEM;
+  }
+  DFM_HIP(e);
+  DFM_HIP(spmm32(op, x, y, nullptr, nrhs, st));
+  return DFM_OK;
+}
+

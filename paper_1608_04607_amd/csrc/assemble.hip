@@ -1659,13 +1659,13 @@ extern "C" dfm_status dfm_op_info(dfm_op op, int64_t *ndof, int64_t *K, int64_t 
 namespace {
 // blocks out [nt][4][3][K][K] row-major from the internal column-major blocks
 __global__ void k_export_blocks(const double *B, int64_t nblk, int K, int Kp, double *out) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  int64_t kk = (int64_t)K * K;
-  if (i >= nblk * kk) return;
-  int64_t b = i / kk;
-  int64_t e = i - b * kk;
-  int row = (int)(e / K), col = (int)(e - (int64_t)row * K);
-  out[i] = B[b * (int64_t)K * Kp + (int64_t)col * Kp + row];
+  const int64_t kk = (int64_t)K * K;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nblk * kk; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = i / kk;
+    const int64_t e = i - b * kk;
+    const int row = (int)(e / K), col = (int)(e - (int64_t)row * K);
+    out[i] = B[b * (int64_t)K * Kp + (int64_t)col * Kp + row];
+  }
 }
 }  // namespace
 
@@ -1675,7 +1675,7 @@ extern "C" dfm_status dfm_op_export(dfm_op op, double *blocks, int32_t *dest, vo
   if (blocks) {
     int64_t nblk = 12 * op->nt;
     int64_t tot = nblk * op->K * op->K;
-    hipLaunchKernelGGL(k_export_blocks, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, op->B, nblk, op->K,
+    hipLaunchKernelGGL(k_export_blocks, dim3(ew_grid(tot)), dim3(256), 0, st, op->B, nblk, op->K,
                        op->Kp, blocks);
     DFM_HIP(hipGetLastError());
   }

@@ -29,6 +29,14 @@ void set_error(const std::string &msg);
     }                                                                                        \
   } while (0)
 
+// Grid for the element-wise kernels: they loop with a grid stride, so the launch
+// stays far below the 2^32 work items a dispatch can describe however long the
+// array is.
+inline unsigned ew_grid(int64_t n) {
+  const int64_t g = (n + 255) / 256;
+  return (unsigned)(g < 65536 ? (g > 0 ? g : 1) : 65536);
+}
+
 // Per-face geometry record, 12 doubles: area, outward unit normal (3),
 // frame x (3), frame y (3), pad (2).  The frame z is minus the normal.
 constexpr int FACE_REC = 12;

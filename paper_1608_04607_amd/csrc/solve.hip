@@ -5,6 +5,10 @@
 // with FP32 Krylov vectors (FP64 accumulation in every dot product and product
 // with B) and refines the solution with FP64 residuals of the FP64 operator:
 //   r = rho0 - (I - B) rho (FP64),  (I - B32) e ~= r (FP32 GMRES),  rho += e.
+// Method 0 with precision 1 solves many right-hand sides together: the
+// corrections are FP32 Neumann partial sums e = sum_k B32^k (r/|r|), one batched
+// product for all right-hand sides per term on the FP32 matrix cores, refined
+// with FP64 residuals of the FP64 operator.
 // The host drives the iterations; every vector operation and every product with
 // B runs on the GPU.
 #include <hip/hip_runtime.h>
@@ -22,6 +26,7 @@ hipError_t spmv(dfm_op op, const double *x, const double *v, double *y, double a
 hipError_t spmv32(dfm_op op, const float *x, const float *v, float *y, float alpha, float beta, hipStream_t st);
 hipError_t spmv_t(dfm_op op, const double *x, const double *v, double *y, double alpha, double beta, hipStream_t st);
 hipError_t ensure_fp32(dfm_op op, hipStream_t st);
+hipError_t spmm32(dfm_op op, const float *x, float *y, float *e, int R, hipStream_t st);
 
 namespace {
 
@@ -123,31 +128,27 @@ __global__ __launch_bounds__(RED_THREADS) void k_combine(const T *__restrict__ V
 
 template <typename T>
 __global__ void k_scale_by(const T *__restrict__ x, double s, T *__restrict__ y, int64_t n) {
-  int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (r >= n) return;
-  y[r] = (T)((double)x[r] / s);
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
+    y[r] = (T)((double)x[r] / s);
 }
 
 // y = a * x + b * y
 template <typename TX, typename TY>
 __global__ void k_axpby(double a, const TX *__restrict__ x, double b, TY *__restrict__ y, int64_t n) {
-  int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (r >= n) return;
-  y[r] = (TY)fma(a, (double)x[r], b * (double)y[r]);
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
+    y[r] = (TY)fma(a, (double)x[r], b * (double)y[r]);
 }
 
 template <typename TX, typename TY>
 __global__ void k_copy(const TX *__restrict__ x, TY *__restrict__ y, int64_t n) {
-  int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (r >= n) return;
-  y[r] = (TY)x[r];
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
+    y[r] = (TY)x[r];
 }
 
 template <typename T>
 __global__ void k_zero(T *__restrict__ y, int64_t n) {
-  int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (r >= n) return;
-  y[r] = (T)0;
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
+    y[r] = (T)0;
 }
 
 struct Ctx {
@@ -157,7 +158,7 @@ struct Ctx {
   int64_t n;
   double *partial = nullptr;  // [MAXV][RED_BLOCKS]
   double *dsc = nullptr;      // device scalars
-  unsigned grid() const { return (unsigned)((n + 255) / 256); }
+  unsigned grid() const { return ew_grid(n); }
   // out[0..nvec) = V^T w, and out[nvec] = extra . w when extra != null (device)
   template <typename T>
   hipError_t dots(const T *V, int64_t ldv, int nvec, const T *w, double *out, const T *extra = nullptr) {
@@ -202,6 +203,51 @@ struct Ctx {
 // GMRES(m) on (I - B) x = b with x0 = 0, vectors of type T.  Stops when the
 // relative residual is <= rtol: the true residual when check_true (FP64 solves),
 // the Arnoldi estimate otherwise (inner solves of the refinement).
+// out[r] += sum_i v[r][i]^2 for the rows r of a [R][n] block (grid.y = R)
+template <typename T>
+__global__ __launch_bounds__(RED_THREADS) void k_row_norms2(const T *__restrict__ v, int64_t n, double *__restrict__ out) {
+  __shared__ double red[NWAVE];
+  const T *row = v + blockIdx.y * n;
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)RED_THREADS + threadIdx.x; i < n; i += (int64_t)gridDim.x * RED_THREADS) {
+    const double a = (double)row[i];
+    acc = fma(a, a, acc);
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < NWAVE; ++w) t += red[w];
+    atomicAdd(out + blockIdx.y, t);
+  }
+}
+
+// t[r][i] = e[r][i] = (float)(s[r] * v[r][i])
+__global__ void k_rows_to_f32(const double *__restrict__ v, const double *__restrict__ s, float *__restrict__ t,
+                              float *__restrict__ e, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t o = blockIdx.y * n + i;
+  const float a = (float)(s[blockIdx.y] * v[o]);
+  t[o] = a;
+  e[o] = a;
+}
+
+// x[r][i] += a[r] * e[r][i]
+__global__ void k_rows_axpy(const double *__restrict__ a, const float *__restrict__ e, double *__restrict__ x,
+                            int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t o = blockIdx.y * n + i;
+  x[o] = fma(a[blockIdx.y], (double)e[o], x[o]);
+}
+
+__global__ void k_zero_f64(double *__restrict__ y, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = 0.0;
+}
+
 template <typename T>
 hipError_t gmres(Ctx &c, const T *b, T *x, T *V, T *w, T *t, int m, double rtol, int max_iter, bool check_true,
                  int &its, int &restarts, double &rel, bool &done) {
@@ -307,19 +353,160 @@ hipError_t gmres(Ctx &c, const T *b, T *x, T *V, T *w, T *t, int m, double rtol,
 using namespace dfm;
 
 namespace dfm {
+// Batched mixed-precision Neumann refinement (method 0, precision 1), all R
+// right-hand sides at once:
+//   r = rho0 - (I - B) rho in FP64;  e = sum_{k >= 0} B32^k (r / |r|) in FP32
+//   until the estimated tail |t_k| q / (1 - q) of the series (q the observed
+//   contraction of |t| over the last terms) is below INNER_TOL for every active
+//   right-hand side;  rho += |r| e.
+// Iterations count the batched products with B32 (the same for every rhs).
+static dfm_status solve_neumann_batched(dfm_op op, const double *rho0, double *rho, int R, const dfm_solve_opts *opts,
+                                        dfm_solve_info *info, hipStream_t st) {
+  const int64_t n = op->ndof;
+  constexpr double INNER_TOL = 1e-4;
+  constexpr int CHECK = 8;            // norms of the series term every CHECK products
+  float *t0 = nullptr, *t1 = nullptr, *e32 = nullptr;
+  double *res = nullptr, *tmp = nullptr, *sc = nullptr;
+  auto cleanup = [&]() {
+    (void)hipFree(t0);
+    (void)hipFree(t1);
+    (void)hipFree(e32);
+    (void)hipFree(res);
+    (void)hipFree(tmp);
+    (void)hipFree(sc);
+  };
+#define TRYB(expr)                                                                           \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) {                                                                  \
+      set_error(std::string(#expr) + ": " + hipGetErrorString(e_));                          \
+      cleanup();                                                                             \
+      return e_ == hipErrorOutOfMemory ? DFM_E_NOMEM : DFM_E_HIP;                            \
+    }                                                                                        \
+  } while (0)
+  TRYB(ensure_fp32(op, st));
+  TRYB(hipMalloc(&t0, sizeof(float) * (size_t)R * n));
+  TRYB(hipMalloc(&t1, sizeof(float) * (size_t)R * n));
+  TRYB(hipMalloc(&e32, sizeof(float) * (size_t)R * n));
+  TRYB(hipMalloc(&res, sizeof(double) * (size_t)R * n));
+  TRYB(hipMalloc(&tmp, sizeof(double) * n));
+  TRYB(hipMalloc(&sc, sizeof(double) * 2 * (size_t)R));
+  const dim3 eg((unsigned)((n + 255) / 256), (unsigned)R);
+  const dim3 rg((unsigned)std::min<int64_t>(256, (n + RED_THREADS - 1) / RED_THREADS), (unsigned)R);
+  std::vector<double> h(2 * (size_t)R);
+  // per-rhs squared norms of a [R][n] block into sc[0..R) (host copy in h)
+  auto norms2_f64 = [&](const double *v) -> hipError_t {
+    hipLaunchKernelGGL(k_zero_f64, dim3((R + 255) / 256), dim3(256), 0, st, sc, R);
+    hipLaunchKernelGGL(k_row_norms2<double>, rg, dim3(RED_THREADS), 0, st, v, n, sc);
+    hipError_t e = hipMemcpyAsync(h.data(), sc, sizeof(double) * R, hipMemcpyDeviceToHost, st);
+    return e != hipSuccess ? e : hipStreamSynchronize(st);
+  };
+  auto norms2_f32 = [&](const float *v) -> hipError_t {
+    hipLaunchKernelGGL(k_zero_f64, dim3((R + 255) / 256), dim3(256), 0, st, sc, R);
+    hipLaunchKernelGGL(k_row_norms2<float>, rg, dim3(RED_THREADS), 0, st, v, n, sc);
+    hipError_t e = hipMemcpyAsync(h.data(), sc, sizeof(double) * R, hipMemcpyDeviceToHost, st);
+    return e != hipSuccess ? e : hipStreamSynchronize(st);
+  };
+  std::vector<double> bn(R), rn(R), rel(R, 1.0), tprev(R);
+  std::vector<char> done(R, 0);
+  TRYB(norms2_f64(rho0));
+  for (int r = 0; r < R; ++r) {
+    bn[r] = std::sqrt(h[r]);
+    if (!(bn[r] > 0.0)) {
+      done[r] = 1;
+      rel[r] = 0.0;
+    }
+  }
+  {
+    const int64_t tot = (int64_t)R * n;
+    const unsigned gb = ew_grid(tot);
+    hipLaunchKernelGGL(k_zero<double>, dim3(gb), dim3(256), 0, st, rho, tot);
+    hipLaunchKernelGGL((k_copy<double, double>), dim3(gb), dim3(256), 0, st, rho0, res, tot);
+    TRYB(hipGetLastError());
+  }
+  rn = bn;
+  int iters = 0;
+  bool finite = true;
+  for (int outer = 0; outer < 40 && iters < opts->max_iter; ++outer) {
+    // t = e = r / |r| for the active right-hand sides (zero for the others)
+    for (int r = 0; r < R; ++r) h[r] = (!done[r] && rn[r] > 0.0) ? 1.0 / rn[r] : 0.0;
+    TRYB(hipMemcpyAsync(sc + R, h.data(), sizeof(double) * R, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_rows_to_f32, eg, dim3(256), 0, st, res, sc + R, t0, e32, n);
+    TRYB(hipGetLastError());
+    std::fill(tprev.begin(), tprev.end(), 1.0);
+    while (iters < opts->max_iter) {
+      TRYB(spmm32(op, t0, t1, e32, R, st));
+      std::swap(t0, t1);
+      ++iters;
+      if (iters % CHECK) continue;
+      TRYB(norms2_f32(t0));
+      bool inner_done = true;
+      for (int r = 0; r < R; ++r) {
+        if (done[r]) continue;
+        const double tn = std::sqrt(h[r]);
+        if (!std::isfinite(tn)) finite = false;
+        const double q = std::pow(tn / tprev[r], 1.0 / CHECK);
+        tprev[r] = tn;
+        const double tail = q < 1.0 ? tn * q / (1.0 - q) : HUGE_VAL;
+        if (!(tail <= INNER_TOL)) inner_done = false;
+      }
+      if (inner_done || !finite) break;
+    }
+    if (!finite) break;
+    // rho += |r| e;  r = rho0 - (I - B) rho  (FP64, one product per rhs)
+    for (int r = 0; r < R; ++r) h[r] = done[r] ? 0.0 : rn[r];
+    TRYB(hipMemcpyAsync(sc + R, h.data(), sizeof(double) * R, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_rows_axpy, eg, dim3(256), 0, st, sc + R, e32, rho, n);
+    TRYB(hipGetLastError());
+    for (int r = 0; r < R; ++r) {
+      if (done[r]) continue;
+      double *x = rho + (int64_t)r * n, *rr = res + (int64_t)r * n;
+      TRYB(spmv(op, x, x, tmp, -1.0, 1.0, st));   // tmp = B x - x
+      hipLaunchKernelGGL((k_copy<double, double>), dim3(ew_grid(n)), dim3(256), 0, st, rho0 + (int64_t)r * n, rr, n);
+      hipLaunchKernelGGL((k_axpby<double, double>), dim3(ew_grid(n)), dim3(256), 0, st, 1.0, tmp, 1.0, rr, n);
+      TRYB(hipGetLastError());
+    }
+    TRYB(norms2_f64(res));
+    bool all = true;
+    for (int r = 0; r < R; ++r) {
+      if (done[r]) continue;
+      rn[r] = std::sqrt(h[r]);
+      rel[r] = rn[r] / bn[r];
+      if (!std::isfinite(rel[r])) finite = false;
+      if (rel[r] <= opts->rtol) done[r] = 1;
+      else all = false;
+    }
+    if (all || !finite) break;
+  }
+#undef TRYB
+  cleanup();
+  dfm_status status = DFM_OK;
+  for (int r = 0; r < R; ++r) {
+    if (info) info[r] = dfm_solve_info{iters, 0, rel[r]};
+    if (!std::isfinite(rel[r])) status = DFM_E_NUMERIC;
+    else if (!done[r] && status == DFM_OK) status = DFM_E_NOCONV;
+  }
+  if (!finite) status = DFM_E_NUMERIC;
+  if (status == DFM_E_NOCONV) set_error("solver stopped at max_iter above the tolerance");
+  if (status == DFM_E_NUMERIC) set_error("non-finite residual in the solver");
+  return status;
+}
+}  // namespace dfm
+
+namespace dfm {
 dfm_status solve_impl(dfm_op op, const double *rho0, double *rho, int nrhs, const dfm_solve_opts *opts,
                       dfm_solve_info *info, bool transpose, void *stream_) {
   DFM_REQUIRE(op && rho0 && rho && opts, DFM_E_INVALID, "null argument");
   DFM_REQUIRE(nrhs >= 1, DFM_E_INVALID, "nrhs must be >= 1");
   DFM_REQUIRE(opts->method == 0 || opts->method == 1, DFM_E_INVALID, "method must be 0 (Neumann) or 1 (GMRES)");
   DFM_REQUIRE(opts->precision == 0 || opts->precision == 1, DFM_E_INVALID, "precision must be 0 or 1");
-  DFM_REQUIRE(!(opts->precision == 1 && opts->method == 0), DFM_E_UNSUPPORTED,
-              "mixed precision is implemented for GMRES only");
   DFM_REQUIRE(opts->max_iter >= 1 && opts->rtol > 0.0, DFM_E_INVALID, "need max_iter >= 1 and rtol > 0");
   const int m = opts->method == 1 ? opts->restart : 1;
   DFM_REQUIRE(m >= 1 && m <= MAXV - 1, DFM_E_INVALID, "restart must be in 1..200");
   DFM_REQUIRE(!(transpose && opts->precision == 1), DFM_E_UNSUPPORTED,
               "transposed solves are implemented in FP64 only");
+  if (opts->method == 0 && opts->precision == 1)
+    return solve_neumann_batched(op, rho0, rho, nrhs, opts, info, (hipStream_t)stream_);
   hipStream_t st = (hipStream_t)stream_;
   const int64_t n = op->ndof;
   Ctx c;
@@ -418,7 +605,7 @@ dfm_status solve_impl(dfm_op op, const double *rho0, double *rho, int nrhs, cons
         int its = 0, rs = 0;
         double irel;
         bool idone;
-        TRY(gmres<float>(c, b32, e32, V32, w32, t32, m, inner_tol, opts->max_iter - inf.iters, false, its, rs, irel,
+        TRY(gmres<float>(c, b32, e32, V32, w32, t32, m, inner_tol, opts->max_iter - inf.iters, true, its, rs, irel,
                          idone));
         inf.iters += its;
         inf.restarts += rs;

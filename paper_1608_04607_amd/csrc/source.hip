@@ -23,8 +23,8 @@ namespace {
 constexpr double PLANE_TOL = 1e-12;
 
 __global__ void k_zero_f64(double *y, int64_t n) {
-  int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (r < n) y[r] = 0.0;
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
+    y[r] = 0.0;
 }
 
 __global__ void k_init_found(int *found, int64_t ns, double *total, unsigned *flags) {
@@ -303,7 +303,7 @@ extern "C" dfm_status dfm_source_points(dfm_op op, const double *xyz, int64_t ns
   TRY_SC(hipMalloc(&sc.idx, sizeof(int) * ns));
   TRY_SC(hipMalloc(&sc.flags, sizeof(unsigned)));
   int64_t tot = ns * op->ndof;
-  hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, rho0, tot);
+  hipLaunchKernelGGL(k_zero_f64, dim3(ew_grid(tot)), dim3(256), 0, st, rho0, tot);
   hipLaunchKernelGGL(k_init_found, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st, sc.idx, ns, sc.total,
                      sc.flags);
   TRY_SC(hipGetLastError());
@@ -339,7 +339,7 @@ extern "C" dfm_status dfm_source_plane(dfm_op op, int axis, double value, int pr
   TRY_SC(hipMalloc(&sc.total, sizeof(double)));
   TRY_SC(hipMalloc(&sc.idx, sizeof(int) * nslot));
   TRY_SC(hipMalloc(&sc.flags, sizeof(unsigned)));
-  hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)((op->ndof + 255) / 256)), dim3(256), 0, st, rho0, op->ndof);
+  hipLaunchKernelGGL(k_zero_f64, dim3(ew_grid(op->ndof)), dim3(256), 0, st, rho0, op->ndof);
   hipLaunchKernelGGL(k_init_found, dim3(1), dim3(1), 0, st, sc.idx, 0, sc.total, sc.flags);
   TRY_SC(hipGetLastError());
   TRY_SC(angular(op, 0.0, 1.5 / M_PI, sc, st));

@@ -112,6 +112,14 @@ class Operator:
         check(_lib.load().dfm_apply(self.handle, _ptr(x), _ptr(y), nrhs, int(bool(transpose)), _stream(stream)))
         return y
 
+    def apply_f32(self, x, stream=None):
+        """y = B32 x for a [nrhs][ndof] FP32 block on the FP32 matrix cores."""
+        x = _dev(x, torch.float32)
+        nrhs = 1 if x.dim() == 1 else x.shape[0]
+        y = torch.empty_like(x)
+        check(_lib.load().dfm_apply_f32(self.handle, _ptr(x), _ptr(y), nrhs, _stream(stream)))
+        return y
+
     def solve(self, rho0, method="gmres", rtol=1e-8, restart=50, max_iter=20000, precision=0, stream=None,
               raise_nonconv=True):
         rho0 = _dev(rho0, torch.float64)

@@ -216,6 +216,47 @@ def test_mixed_precision_solve_matches_oracle(small):
     assert rel(rho.cpu().numpy(), ref) < 1e-8
 
 
+@pytest.mark.parametrize("order,degree,nrhs", [(1, 8, 130), (0, 4, 3)])
+def test_batched_fp32_product_matches_oracle(order, degree, nrhs):
+    """dfm_apply_f32 (all right-hand sides at once on the FP32 matrix cores) vs the
+    oracle's B applied in FP64 to the same FP32 inputs: 1e-5 relative per rhs.
+    K = 135 spans two 96-row groups; 130 right-hand sides span two rhs tiles."""
+    say(f"[apply f32] P{order} D{degree} nrhs {nrhs}")
+    v, t, refl = box(2, 0.15, seed=4)
+    mu = np.full(t.shape[0], 0.05)
+    bs = oa.Basis(order, 0, degree, 4, oq.SEAM_RULE)
+    op = gpu_op(gpu_mesh(v, t, refl), mu, bs)
+    m = om.build_mesh(v, t, refl)
+    A = osv.to_sparse(*oa.assemble(m, bs, mu))
+    x = np.random.default_rng(6).standard_normal((nrhs, A.shape[0])).astype(np.float32)
+    y = op.apply_f32(torch.tensor(x, device=DEV)).cpu().numpy().astype(np.float64)
+    ref = (A @ x.astype(np.float64).T).T
+    err = np.abs(y - ref).max(axis=1) / np.abs(ref).max(axis=1)
+    say(f"    worst rhs {err.max():.2e}")
+    assert err.max() < 1e-5
+
+
+def test_batched_mixed_neumann_matches_oracle(small):
+    """Method 0 with precision 1: all right-hand sides together, FP32 Neumann
+    corrections on the matrix cores refined by FP64 residuals, against sparse LU of
+    the oracle's B."""
+    say("[solve] batched FP32 Neumann + FP64 refinement")
+    g, op, m, bs, Bo, desto, mu = small
+    A = osv.to_sparse(Bo, desto)
+    rhs = np.random.default_rng(10).standard_normal((5, A.shape[0]))
+    rhs[3] = 0.0                                   # a zero right-hand side stays zero
+    rho, info = op.solve(torch.tensor(rhs, device=DEV), method="neumann", rtol=1e-10, precision=1)
+    rho = rho.cpu().numpy()
+    say(f"    info {info}")
+    for r in range(5):
+        assert info[r][2] <= 1e-10
+        if r == 3:
+            assert not rho[r].any()
+            continue
+        assert osv.relres(A, rhs[r], rho[r]) <= 2e-10
+        assert rel(rho[r], osv.solve_direct(A, rhs[r])) < 1e-7
+
+
 def test_cube_neumann_matches_direct():
     say("[solve] cube, Neumann to 1e-12")
     p = synth.problem_c1()

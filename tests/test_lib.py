@@ -14,7 +14,7 @@ LIB = os.path.join(ROOT, "paper_1608_04607_amd", "libdfm.so")
 def declared_symbols():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(dfm_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(dfm_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_header_declares_the_entry_points():
