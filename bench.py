@@ -28,6 +28,7 @@ if ROOT not in sys.path:
 METRIC = "B-assembly face-pair blocks/s; (I-B)rho solve ms/RHS at 1e-8 residual vs plain FP64"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
 
 
 def parse():
@@ -36,6 +37,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--rule", choices=["seam", "paper"], default="seam")
+    ap.add_argument("--workload", choices=["box8", "box32-batched"], default="box8",
+                    help="box8: the 3072-tet single-rhs case (default); box32-batched: 49152 tets, 128 sources")
     ap.add_argument("--restart", type=int, default=50)
     ap.add_argument("--cpu-tets", type=int, default=24, help="tets in the oracle's timed sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -50,12 +53,12 @@ def parse():
 _ORACLE = {}
 
 
-def _oracle_init(verts, tets, refl, rule):
+def _oracle_init(verts, tets, refl, rule, pos_order=1, degree=8, quad_n=12):
     os.environ["OMP_NUM_THREADS"] = "1"
     from oracle import assemble as oa
     from oracle import mesh as om
     _ORACLE["mesh"] = om.build_mesh(verts, tets, refl)
-    _ORACLE["bs"] = oa.Basis(1, 0, 8, 12, rule)
+    _ORACLE["bs"] = oa.Basis(pos_order, 0, degree, quad_n, rule)
 
 
 def _oracle_tet(args):
@@ -65,7 +68,7 @@ def _oracle_tet(args):
     return 12
 
 
-def cpu_baseline(prob, rule, ntets):
+def cpu_baseline(prob, rule, ntets, label="3072-tet box"):
     """Blocks/s of the unmodified oracle on `ntets` sampled tets, one process per core."""
     import multiprocessing as mp
 
@@ -73,13 +76,14 @@ def cpu_baseline(prob, rule, ntets):
     cores = min(16, len(os.sched_getaffinity(0)))
     sample = np.random.default_rng(6).choice(prob.nt, ntets, replace=False)
     ctx = mp.get_context("fork")
-    with ctx.Pool(cores, initializer=_oracle_init, initargs=(prob.verts, prob.tets, prob.refl, rule)) as pool:
+    init = (prob.verts, prob.tets, prob.refl, rule, prob.pos_order, prob.mom_degree, prob.quad_n)
+    with ctx.Pool(cores, initializer=_oracle_init, initargs=init) as pool:
         pool.map(_oracle_tet, [(int(sample[0]), prob.mu)] * cores)      # warm every worker
         t0 = time.perf_counter()
         blocks = sum(pool.map(_oracle_tet, [(int(j), prob.mu) for j in sample], chunksize=1))
         dt = time.perf_counter() - t0
     return {"value": blocks / dt, "unit": "blocks/s", "cores": cores, "kind": "oracle",
-            "sample": f"{ntets} tets ({blocks} blocks) drawn with seed 6 from the same 3072-tet box, "
+            "sample": f"{ntets} tets ({blocks} blocks) drawn with seed 6 from the same {label}, "
                       f"FP64 NumPy oracle, {cores} worker processes, {dt:.1f} s"}
 
 
@@ -117,6 +121,9 @@ def main():
         print(f"bench.py: this build runs on one GPU only (--gpus {args.gpus} requested); "
               "the multi-GPU sharding of the path is described in DESIGN.md, not implemented.", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "box32-batched":
+        return main_box32(args)
 
     import numpy as np
 
@@ -265,6 +272,166 @@ def main():
         "roofline_other": other,
         "cpu_baseline": base,
     }
+    print(json.dumps(out))
+
+
+def main_box32(args):
+    """49152-tet box (32x16x16 cells), P0 x Legendre D=12, n=16, lognormal mu, 128
+    isotropic boundary point sources.  One step = mesh build -> assembly -> 128
+    sources -> batched solve of all 128 (FP32 Neumann corrections on the matrix
+    cores inside FP64 refinement) to relative residual 1e-8.  The plain FP64
+    reference is one single-rhs FP64 Neumann solve of the first source, timed
+    after the steps.  `value` is assembly blocks/s."""
+    import numpy as np
+
+    import synth
+    prob = synth.problem_c3(nsrc=128)
+    base = None
+    if not args.no_cpu_baseline:
+        base = cpu_baseline(prob, 1 if args.rule == "seam" else 0, min(args.cpu_tets, 8), "49152-tet box")
+        print(f"bench: cpu baseline {base['value']:.2f} blocks/s", file=sys.stderr, flush=True)
+
+    import torch
+
+    from paper_1608_04607_amd import dfm
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    T = lambda a: torch.tensor(a, device=dev)  # noqa: E731
+    verts, tets, refl, mu, xyz = T(prob.verts), T(prob.tets), T(prob.refl), T(prob.mu), T(prob.source["xyz"])
+    rule = 1 if args.rule == "seam" else 0
+    R = xyz.shape[0]
+    if args.kernels_only:
+        mesh = dfm.Mesh(verts, tets, refl=refl)
+        op = dfm.Operator(mesh, mu, prob.pos_order, dfm.LEGENDRE, prob.mom_degree, prob.quad_n, rule=rule)
+        rho0 = op.source_points(xyz)
+        x32 = rho0.float()
+        for _ in range(5):
+            op.apply_f32(x32)
+        for _ in range(5):
+            op.apply(rho0[0])
+        torch.cuda.synchronize()
+        print(json.dumps({"kernels_only": True, "workload": "box32", "nodes": op.nodes, "K": op.K, "ndof": op.ndof,
+                          "B_bytes": op.nbytes, "nrhs": R}))
+        return
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    def step(record):
+        e = [ev() for _ in range(5)]
+        e[0].record(stream)
+        mesh = dfm.Mesh(verts, tets, refl=refl)
+        e[1].record(stream)
+        op = dfm.Operator(mesh, mu, prob.pos_order, dfm.LEGENDRE, prob.mom_degree, prob.quad_n, rule=rule)
+        e[2].record(stream)
+        rho0 = op.source_points(xyz)
+        e[3].record(stream)
+        # in segments of at most SEG batched products, each continuing from the last
+        # iterate (warm start), so that progress is reported while it runs
+        SEG = 2500
+        rho, total = None, 0
+        while True:
+            rho, info = op.solve(rho0, method="neumann", rtol=1e-8, precision=1, max_iter=SEG, rho=rho,
+                                 raise_nonconv=False)
+            total += info[0][0]
+            worst = max(i[2] for i in info)
+            print(f"bench: {total} batched products, worst relres {worst:.2e}", file=sys.stderr, flush=True)
+            if worst <= 1e-8 or total >= 40000:
+                break
+        info = [(total, 0, i[2]) for i in info]
+        e[4].record(stream)
+        torch.cuda.synchronize()
+        if record is not None:
+            record.append((e, info, op.nodes, op.nblocks, op.K, op.ndof))
+            return op, mesh, rho0, rho
+        op.close()
+        mesh.close()
+        return None
+
+    for _ in range(args.warmup):
+        step(None)
+    torch.cuda.synchronize()
+    recs = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        out = step(recs)
+        if i < args.steps - 1:
+            out[0].close()
+            out[1].close()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    op, mesh, rho0, rho = out
+    phase = np.array([[r[0][i].elapsed_time(r[0][i + 1]) for i in range(4)] for r in recs])
+    t_mesh, t_asm, t_src, t_solve = phase.mean(axis=0)
+    info = recs[-1][1]
+    nodes, nblocks, K, ndof = recs[-1][2:]
+    # true FP64 residuals of a few right-hand sides
+    worst = 0.0
+    for r in (0, R // 2, R - 1):
+        res = rho0[r] - (rho[r] - op.apply(rho[r]))
+        worst = max(worst, float((res.norm() / rho0[r].norm()).item()))
+    del rho
+    # the batched product alone (HIP events on the library's stream)
+    x32 = rho0.float()
+    for _ in range(2):
+        op.apply_f32(x32)
+    e0, e1 = ev(), ev()
+    e0.record(stream)
+    for _ in range(5):
+        op.apply_f32(x32)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_spmm = e0.elapsed_time(e1) / 5
+    del x32
+    print("bench: plain FP64 single-rhs Neumann reference", file=sys.stderr, flush=True)
+    e0, e1 = ev(), ev()
+    e0.record(stream)
+    _, info64 = op.solve(rho0[0], method="neumann", rtol=1e-8, max_iter=40000)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t64 = e0.elapsed_time(e1)
+    nt = prob.nt
+    Kp = (K + 3) // 4 * 4
+    flops = 2.0 * 12 * nt * K * K * R
+    spmm_tf = flops / (t_spmm / 1e3) / 1e12
+    spmm_bytes = 4.0 * (12 * nt * K * Kp + 2 * R * ndof)
+    out = {
+        "metric": METRIC,
+        "value": nblocks * args.steps / (phase[:, 1].sum() / 1e3),
+        "unit": "blocks/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 assembly; f32 batched corrections, f64 residuals",
+        "data": "synthetic",
+        "config": {"workload": f"box32x16x16-kuhn-49152tets-jitter0.1_P0xLegendreD12_n16_{args.rule}-rule"
+                               "_mu-lognormal(ln0.02,0.5)_R0.9_128-point-sources_batched-1e-8",
+                   "tets": int(nt), "blocks": int(nblocks), "K": int(K), "ndof": int(ndof), "nrhs": int(R),
+                   "quadrature_directions": int(nodes)},
+        "phase_ms": {"mesh_build": t_mesh, "assemble": t_asm, "sources": t_src, "solve_batched": t_solve},
+        "solve_ms_per_rhs": t_solve / R,
+        "solve_precision": "fp32 Neumann corrections (batched products on the fp32 matrix cores), fp64 refinement",
+        "solve_iters": info[0][0],
+        "solve_relres_worst": max(i[2] for i in info),
+        "solve_true_relres_sampled": worst,
+        "solve_fp64_ms_per_rhs": t64,
+        "solve_fp64_method": "plain fp64 Neumann, one rhs",
+        "solve_fp64_iters": info64[0][0],
+        "solve_speedup_per_rhs_vs_fp64": t64 / (t_solve / R),
+        "roofline": {"kernel": "k_spmm32", "bound": "mfma", "achieved": spmm_tf, "peak": FP32_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": spmm_tf / FP32_PEAK_TFLOPS, "traffic": None,
+                     "algorithmic": f"2*12*nt*K^2*R flop per launch, R = {R}; bytes 4*(12*nt*K*Kp + 2*R*ndof) = "
+                                    f"{spmm_bytes:.3e} ({spmm_bytes / (t_spmm / 1e3) / 1e9:.0f} GB/s)",
+                     "ms_per_launch": t_spmm},
+        "cpu_baseline": base,
+    }
+    op.close()
+    mesh.close()
     print(json.dumps(out))
 
 

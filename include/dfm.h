@@ -88,6 +88,9 @@ typedef struct {
                                   matrix cores (dfm_apply_f32), until the estimated
                                   tail of every active series is below 1e-4.
                         The stop test is the FP64 residual in every case.               */
+  int warm_start; /* 0: start from rho = 0; 1 (method 0 with precision 1 only): rho holds
+                     the starting iterate on entry, so a solve stopped at max_iter can
+                     be continued by calling again                                     */
 } dfm_solve_opts;
 
 typedef struct {

@@ -25,7 +25,7 @@ class Basis(C.Structure):
 
 class SolveOpts(C.Structure):
     _fields_ = [("method", C.c_int), ("restart", C.c_int), ("max_iter", C.c_int),
-                ("rtol", C.c_double), ("precision", C.c_int)]
+                ("rtol", C.c_double), ("precision", C.c_int), ("warm_start", C.c_int)]
 
 
 class SolveInfo(C.Structure):

@@ -417,14 +417,30 @@ static dfm_status solve_neumann_batched(dfm_op op, const double *rho0, double *r
       rel[r] = 0.0;
     }
   }
-  {
+  if (!opts->warm_start) {
     const int64_t tot = (int64_t)R * n;
     const unsigned gb = ew_grid(tot);
     hipLaunchKernelGGL(k_zero<double>, dim3(gb), dim3(256), 0, st, rho, tot);
     hipLaunchKernelGGL((k_copy<double, double>), dim3(gb), dim3(256), 0, st, rho0, res, tot);
     TRYB(hipGetLastError());
+    rn = bn;
+  } else {
+    // r = rho0 - (I - B) rho for the given iterate
+    for (int r = 0; r < R; ++r) {
+      double *x = rho + (int64_t)r * n, *rr = res + (int64_t)r * n;
+      TRYB(spmv(op, x, x, tmp, -1.0, 1.0, st));
+      hipLaunchKernelGGL((k_copy<double, double>), dim3(ew_grid(n)), dim3(256), 0, st, rho0 + (int64_t)r * n, rr, n);
+      hipLaunchKernelGGL((k_axpby<double, double>), dim3(ew_grid(n)), dim3(256), 0, st, 1.0, tmp, 1.0, rr, n);
+      TRYB(hipGetLastError());
+    }
+    TRYB(norms2_f64(res));
+    for (int r = 0; r < R; ++r) {
+      rn[r] = std::sqrt(h[r]);
+      if (done[r]) continue;
+      rel[r] = rn[r] / bn[r];
+      if (rel[r] <= opts->rtol) done[r] = 1;
+    }
   }
-  rn = bn;
   int iters = 0;
   bool finite = true;
   for (int outer = 0; outer < 40 && iters < opts->max_iter; ++outer) {
@@ -505,6 +521,9 @@ dfm_status solve_impl(dfm_op op, const double *rho0, double *rho, int nrhs, cons
   DFM_REQUIRE(m >= 1 && m <= MAXV - 1, DFM_E_INVALID, "restart must be in 1..200");
   DFM_REQUIRE(!(transpose && opts->precision == 1), DFM_E_UNSUPPORTED,
               "transposed solves are implemented in FP64 only");
+  DFM_REQUIRE(opts->warm_start == 0 || opts->warm_start == 1, DFM_E_INVALID, "warm_start must be 0 or 1");
+  DFM_REQUIRE(!(opts->warm_start && !(opts->method == 0 && opts->precision == 1)), DFM_E_UNSUPPORTED,
+              "warm_start is implemented for method 0 with precision 1 only");
   if (opts->method == 0 && opts->precision == 1)
     return solve_neumann_batched(op, rho0, rho, nrhs, opts, info, (hipStream_t)stream_);
   hipStream_t st = (hipStream_t)stream_;

@@ -121,11 +121,18 @@ class Operator:
         return y
 
     def solve(self, rho0, method="gmres", rtol=1e-8, restart=50, max_iter=20000, precision=0, stream=None,
-              raise_nonconv=True):
+              raise_nonconv=True, rho=None):
+        """Solve (I - B) rho = rho0; `rho` given: start from it (method "neumann" with
+        precision 1 only) and write the result into it."""
         rho0 = _dev(rho0, torch.float64)
         nrhs = 1 if rho0.dim() == 1 else rho0.shape[0]
-        rho = torch.empty_like(rho0)
-        opts = SolveOpts(1 if method == "gmres" else 0, restart, max_iter, rtol, int(precision))
+        warm = rho is not None
+        if warm:
+            if rho.shape != rho0.shape or rho.dtype != torch.float64 or not rho.is_cuda or not rho.is_contiguous():
+                raise TypeError("rho must be a contiguous CUDA float64 tensor shaped like rho0")
+        else:
+            rho = torch.empty_like(rho0)
+        opts = SolveOpts(1 if method == "gmres" else 0, restart, max_iter, rtol, int(precision), int(warm))
         info = (SolveInfo * nrhs)()
         code = _lib.load().dfm_solve(self.handle, _ptr(rho0), _ptr(rho), nrhs, C.byref(opts), info, _stream(stream))
         if code != 0 and (raise_nonconv or code != -5):
@@ -161,7 +168,7 @@ class Operator:
         dmu = torch.empty((self.mesh.nt,), dtype=torch.float64, device=self.device)
         dw = torch.empty((max(nsrc, 1),), dtype=torch.float64, device=self.device)
         bx = (C.c_double * 6)(*box)
-        opts = SolveOpts(1 if method == "gmres" else 0, restart, max_iter, rtol, 0)
+        opts = SolveOpts(1 if method == "gmres" else 0, restart, max_iter, rtol, 0, 0)
         info = SolveInfo()
         check(_lib.load().dfm_adjoint(self.handle, _ptr(self.mu), bx, _ptr(rho), _ptr(src), nsrc, C.byref(opts),
                                       _ptr(lam), _ptr(dmu), _ptr(dw), C.byref(info), _stream(stream)))

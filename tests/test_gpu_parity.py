@@ -257,6 +257,23 @@ def test_batched_mixed_neumann_matches_oracle(small):
         assert rel(rho[r], osv.solve_direct(A, rhs[r])) < 1e-7
 
 
+def test_batched_mixed_neumann_warm_start(small):
+    """A batched solve stopped at max_iter continues from its iterate (warm start)
+    to the same solution."""
+    say("[solve] batched, warm start")
+    g, op, m, bs, Bo, desto, mu = small
+    A = osv.to_sparse(Bo, desto)
+    rhs = np.random.default_rng(11).standard_normal((2, A.shape[0]))
+    b = torch.tensor(rhs, device=DEV)
+    rho, info = op.solve(b, method="neumann", rtol=1e-10, precision=1, max_iter=20, raise_nonconv=False)
+    assert info[0][2] > 1e-10
+    rho, info2 = op.solve(b, method="neumann", rtol=1e-10, precision=1, rho=rho)
+    say(f"    {info} -> {info2}")
+    for r in range(2):
+        assert info2[r][2] <= 1e-10
+        assert rel(rho[r].cpu().numpy(), osv.solve_direct(A, rhs[r])) < 1e-7
+
+
 def test_cube_neumann_matches_direct():
     say("[solve] cube, Neumann to 1e-12")
     p = synth.problem_c1()
