@@ -183,9 +183,14 @@ dfm_status dfm_solve(dfm_op op, const double *rho0, double *rho, int nrhs, const
  *     rho0 device f64 [ns][ndof] (overwritten)
  *   DFM_E_INVALID if a point lies on no boundary face.
  * dfm_source_plane: one right-hand side on the boundary faces lying in the plane
- *   x[axis] == value: rho0 = flux * sigma(s) * (3/(2 pi)) cos(theta), with
- *   sigma = 1/(total area of those faces) (profile 0) or the unit Gaussian
- *   exp(-|s-c|^2/(2 s^2))/(2 pi s^2), params (host) = {cx, cy, cz, s} (profile 1).
+ *   x[axis] == value: rho0 = flux * sigma(s) * alpha(p), with
+ *   profile 0: sigma = 1/(total area of those faces), alpha = (3/(2 pi)) cos(theta);
+ *   profile 1: sigma = the unit Gaussian exp(-|s-c|^2/(2 s^2))/(2 pi s^2), params
+ *              (host) = {cx, cy, cz, s}, alpha as for profile 0;
+ *   profile 2: sigma as for profile 0, direction fixed along the inward normal:
+ *              alpha = delta(rho)/(2 pi rho), rho = sin(theta) (the normal-incidence
+ *              density of Eq. RhoNeumann, Sec. 4.1), projected through the phi
+ *              average of the momentum functions at theta = 0.
  *     rho0 device f64 [ndof] (overwritten) */
 dfm_status dfm_source_points(dfm_op op, const double *xyz, int64_t ns, double flux, double *rho0,
                              void *stream);

@@ -11,7 +11,11 @@ Source kinds (all scaled to a total flux int f ds dp = ``flux``):
   gauss_patch sigma = exp(-|s-c|^2/(2 s^2))/(2 pi s^2) on the faces of that plane,
               alpha as above;
   points      sigma = delta(s - s0) on the boundary face containing s0, alpha = 1/pi
-              (isotropic in p, unit flux).
+              (isotropic in p, unit flux);
+  face_normal sigma as for face_flux, direction fixed along the inward normal: the
+              normal-incidence density of Eq. RhoNeumann (Sec. 4.1), alpha =
+              delta(rho)/(2 pi rho) in the polar coordinates rho = sin(theta), phi of
+              the tangential momentum (unit flux per area).
 """
 from __future__ import annotations
 
@@ -34,6 +38,17 @@ def project_angular(alpha, D, family, nu=64, nphi=128):
     psi = basis.momentum(U.ravel(), PHI.ravel(), D, family)
     rhs = psi.T @ (W.ravel() * alpha(U.ravel(), PHI.ravel()))
     return np.linalg.solve(basis.gram(D, family), rhs)
+
+
+def project_pole(D, family, nphi=128):
+    """G^{-1} int delta(rho)/(2 pi rho) psi_k rho drho dphi: the momentum functions at
+    the pole (theta = 0) averaged over phi (Gauss-Legendre in phi, exact for both
+    families), then the Gram solve."""
+    xp, wp = np.polynomial.legendre.leggauss(nphi)
+    phi = np.pi * (xp + 1.0)
+    psi = basis.momentum(np.ones_like(phi), phi, D, family)      # cos(theta) = 1
+    avg = (0.5 * wp) @ psi
+    return np.linalg.solve(basis.gram(D, family), avg)
 
 
 def _plane_slots(mesh, axis, value):
@@ -72,6 +87,14 @@ def project(mesh, bs: Basis, src):
     nt = mesh.nt
     kind = src["kind"]
     flux = float(src.get("flux", 1.0))
+    if kind == "face_normal":
+        ang = project_pole(bs.mom_degree, bs.mom_family)
+        slots = _plane_slots(mesh, src["axis"], src["value"])
+        total = sum(mesh.area[j, l] for (j, l) in slots)
+        rho0 = np.zeros((1, 4 * nt, P, M))
+        for (j, l) in slots:
+            rho0[0, 4 * j + l, 0, :] = flux / total * np.sqrt(mesh.area[j, l]) * ang
+        return rho0.reshape(1, -1)
     if kind in ("face_flux", "gauss_patch"):
         ang = project_angular(_flux_alpha, bs.mom_degree, bs.mom_family)
         slots = _plane_slots(mesh, src["axis"], src["value"])

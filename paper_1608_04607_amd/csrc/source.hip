@@ -39,7 +39,10 @@ __global__ void k_init_found(int *found, int64_t ns, double *total, unsigned *fl
 // Angular coefficients ang[0..M) of alpha(u) = a0 + a1 u (u = cos(theta)).
 // Thread i computes r_i = 2 pi int_0^1 alpha(u) f_i(u) u du for the i-th
 // phi-independent function f_i; thread 0 then applies G^-1.
-__global__ void k_axisym_profile(double a0, double a1, int D, int family, const double *thom, double *ang) {
+// pole != 0: the functions' values at the pole (theta = 0) instead, i.e. the
+// projection of delta(rho)/(2 pi rho) (normal incidence, Sec. 4.1 Eq. RhoNeumann).
+__global__ void k_axisym_profile(double a0, double a1, int pole, int D, int family, const double *thom,
+                                 double *ang) {
   __shared__ double r[DMAX + 1];
   __shared__ double glx[32], glw[32];
   int t = threadIdx.x;
@@ -88,6 +91,8 @@ __global__ void k_axisym_profile(double a0, double a1, int D, int family, const 
       acc += wq * (a0 + a1 * u) * f * u;
     }
     r[t] = 2.0 * M_PI * acc;
+    // at the pole: p_t(1) = sqrt(2t+1) (Legendre, b = 0); R_{2t}^0(0) = P_t(-1) = (-1)^t (Zernike)
+    if (pole) r[t] = (family == 0) ? sqrt(2.0 * t + 1.0) : ((t & 1) ? -1.0 : 1.0);
   }
   __syncthreads();
   if (t == 0) {
@@ -192,7 +197,7 @@ __global__ void k_plane_mark(const int32_t *tets, const double *verts, const int
   mark[s] = on;
 }
 
-// profile 0: sigma = 1 / total area; profile 1: unit Gaussian (c, sg) integrated by
+// profiles 0 and 2: sigma = 1 / total area; profile 1: unit Gaussian (c, sg) integrated by
 // a collapsed 32 x 32 Gauss rule on the triangle.
 __global__ void k_plane_coeffs(const int32_t *tets, const double *verts, const double *face, const int *mark,
                                int64_t nslot, int profile, double cx, double cy, double cz, double sg,
@@ -210,7 +215,7 @@ __global__ void k_plane_coeffs(const int32_t *tets, const double *verts, const d
   if (s >= nslot || !mark[s]) return;
   double A = face[FACE_REC * s];
   double mom[3] = {0.0, 0.0, 0.0};
-  if (profile == 0) {
+  if (profile != 1) {
     mom[0] = sqrt(A) / *total;
   } else {
     double v[3][3];
@@ -252,7 +257,7 @@ struct Scratch {
   }
 };
 
-hipError_t angular(dfm_op op, double a0, double a1, Scratch &sc, hipStream_t st) {
+hipError_t angular(dfm_op op, double a0, double a1, int pole, Scratch &sc, hipStream_t st) {
   const int D = op->basis.mom_degree;
   std::vector<double> th(3 * (DMAX + 1) * (DMAX + 1), 0.0);
   double *jo = th.data(), *cp = jo + (DMAX + 1) * (DMAX + 1), *idn = cp + (DMAX + 1) * (DMAX + 1);
@@ -270,7 +275,8 @@ hipError_t angular(dfm_op op, double a0, double a1, Scratch &sc, hipStream_t st)
   }
   hipError_t e = hipMemcpy(sc.thom, th.data(), sizeof(double) * th.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_axisym_profile, dim3(1), dim3(64), 0, st, a0, a1, D, op->basis.mom_family, sc.thom, sc.ang);
+  hipLaunchKernelGGL(k_axisym_profile, dim3(1), dim3(64), 0, st, a0, a1, pole, D, op->basis.mom_family, sc.thom,
+                     sc.ang);
   return hipGetLastError();
 }
 
@@ -307,7 +313,7 @@ extern "C" dfm_status dfm_source_points(dfm_op op, const double *xyz, int64_t ns
   hipLaunchKernelGGL(k_init_found, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st, sc.idx, ns, sc.total,
                      sc.flags);
   TRY_SC(hipGetLastError());
-  TRY_SC(angular(op, 1.0 / M_PI, 0.0, sc, st));
+  TRY_SC(angular(op, 1.0 / M_PI, 0.0, 0, sc, st));
   int64_t nslot = 4 * m->nt;
   unsigned gx = (unsigned)std::min<int64_t>((nslot + 255) / 256, 1024);
   hipLaunchKernelGGL(k_locate, dim3(gx, (unsigned)ns), dim3(256), 0, st, m->tets, m->verts, m->nbr, nslot, xyz,
@@ -327,8 +333,8 @@ extern "C" dfm_status dfm_source_plane(dfm_op op, int axis, double value, int pr
                                        double flux, double *rho0, void *stream_) {
   DFM_REQUIRE(op && rho0, DFM_E_INVALID, "null argument");
   DFM_REQUIRE(axis >= 0 && axis <= 2, DFM_E_INVALID, "axis must be 0, 1 or 2");
-  DFM_REQUIRE(profile == 0 || (profile == 1 && params != nullptr && params[3] > 0.0), DFM_E_INVALID,
-              "profile 0 (uniform) or 1 (Gaussian, params = cx, cy, cz, sigma > 0)");
+  DFM_REQUIRE(profile == 0 || profile == 2 || (profile == 1 && params != nullptr && params[3] > 0.0), DFM_E_INVALID,
+              "profile 0 (uniform), 1 (Gaussian, params = cx, cy, cz, sigma > 0) or 2 (uniform, normal incidence)");
   hipStream_t st = (hipStream_t)stream_;
   dfm_mesh m = op->mesh;
   Scratch sc;
@@ -342,7 +348,7 @@ extern "C" dfm_status dfm_source_plane(dfm_op op, int axis, double value, int pr
   hipLaunchKernelGGL(k_zero_f64, dim3(ew_grid(op->ndof)), dim3(256), 0, st, rho0, op->ndof);
   hipLaunchKernelGGL(k_init_found, dim3(1), dim3(1), 0, st, sc.idx, 0, sc.total, sc.flags);
   TRY_SC(hipGetLastError());
-  TRY_SC(angular(op, 0.0, 1.5 / M_PI, sc, st));
+  TRY_SC(angular(op, 0.0, 1.5 / M_PI, profile == 2, sc, st));
   unsigned g = (unsigned)((nslot + 255) / 256);
   hipLaunchKernelGGL(k_plane_mark, dim3(g), dim3(256), 0, st, m->tets, m->verts, m->nbr, m->face, nslot, axis, value,
                      sc.idx, sc.total);

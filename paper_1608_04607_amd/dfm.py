@@ -184,3 +184,37 @@ class Operator:
             self.close()
         except Exception:
             pass
+
+
+class ReceiverEnergy(torch.autograd.Function):
+    """J(mu, w) = receiver energy in `box` of the stationary density for the source
+    rho0 = sum_s w_s src_s, differentiable in the damping mu [nt] and the source
+    weights w [nsrc].  Forward: dfm_assemble (for this mu), dfm_solve,
+    dfm_receiver_functional; backward: dfm_adjoint (transposed solve and the dB/dmu
+    contraction).  The weighted source sum and J = g . rho are tensor glue."""
+
+    @staticmethod
+    def forward(ctx, mu, w, mesh, src, box, basis, rtol=1e-12, restart=50):
+        pos_order, family, degree, quad_n, rule = basis
+        op = Operator(mesh, mu.detach(), pos_order, family, degree, quad_n, rule=rule)
+        rho0 = (w.detach().to(src.dtype)[:, None] * src).sum(0)
+        rho, _ = op.solve(rho0, method="gmres", rtol=rtol, restart=restart)
+        g = op.receiver_functional(box)
+        ctx.save_for_backward(rho)
+        ctx.op, ctx.src, ctx.box, ctx.rtol, ctx.restart = op, src, box, rtol, restart
+        return (g * rho).sum()
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (rho,) = ctx.saved_tensors
+        op = ctx.op
+        _, dmu, dw, _ = op.adjoint(rho, ctx.box, src=ctx.src, rtol=ctx.rtol, restart=ctx.restart)
+        op.close()
+        return grad_out * dmu, grad_out * dw, None, None, None, None, None, None
+
+
+def receiver_energy(mesh, mu, w, src, box, basis, rtol=1e-12, restart=50):
+    """Differentiable receiver energy (see ReceiverEnergy); basis = (pos_order,
+    mom_family, mom_degree, quad_n, rule)."""
+    return ReceiverEnergy.apply(mu, w, mesh, src, tuple(box), tuple(basis), rtol, restart)
+

@@ -89,3 +89,36 @@ def test_sources_have_unit_flux(family):
     pts = synth.uniform_points_on_box_surface((1, 1, 1), 5, np.random.default_rng(0))
     r = osrc.project(m, bs, {"kind": "points", "xyz": pts})
     assert np.allclose(r @ mv, 1.0, atol=1e-13)
+
+
+@pytest.mark.parametrize("family", [ob.LEGENDRE, ob.ZERNIKE])
+def test_normal_incidence_source_pins(family):
+    """Eq. RhoNeumann projected: G times the coefficients is the phi-average of the
+    basis at the pole -- sqrt(2a+1) for b = 0 (Legendre), (-1)^(n/2) for m = 0
+    (Zernike), zero otherwise -- and the projected density carries unit flux per
+    area (checked by brute-force quadrature of the reconstructed function)."""
+    D = 6
+    ang = osrc.project_pole(D, family)
+    G = ob.gram(D, family)
+    ref = np.zeros(ang.size)
+    for t in range(D + 1):
+        for i in range(t + 1):
+            k = t * (t + 1) // 2 + i
+            if family == ob.LEGENDRE and i == 0:        # (a, b) = (t, 0)
+                ref[k] = math.sqrt(2 * t + 1)
+            if family == ob.ZERNIKE and t % 2 == 0 and -t + 2 * i == 0:
+                ref[k] = (-1) ** (t // 2)
+    assert np.abs(G @ ang - ref).max() < 1e-12
+    xu, wu = np.polynomial.legendre.leggauss(40)
+    xp, wp = np.polynomial.legendre.leggauss(40)
+    U, PHI = np.meshgrid(0.5 * (xu + 1), np.pi * (xp + 1), indexing="ij")
+    W = np.outer(0.5 * wu, np.pi * wp) * U
+    f = ob.momentum(U.ravel(), PHI.ravel(), D, family) @ ang
+    assert (W.ravel() @ f) == pytest.approx(1.0, abs=1e-12)
+    # on a mesh: unit flux per area of the plane
+    p = synth.problem_c1()
+    m = om.build_mesh(p.verts, p.tets, p.refl)
+    bs = oa.Basis(0, family, D, 4)
+    r0 = osrc.project(m, bs, {"kind": "face_normal", "axis": 0, "value": 0.0, "flux": 1.0})[0]
+    assert mass_vector(m, bs) @ r0 == pytest.approx(1.0, abs=1e-12)
+
