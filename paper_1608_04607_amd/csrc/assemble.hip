@@ -915,7 +915,10 @@ __global__ __launch_bounds__(NTHREADS) void k_assemble(AsmArgs A) {
           for (int i = 0; i < PQ; ++i) Sw[ql * PQ + i] = sw[i];
         } else if (role == 1) {
           double *o = Bpsi + ql * Ml;
-          momentum_row<DM, false>(dot3(d, G.xin), dot3(d, G.yin), dot3(d, G.zin), D, A.family, thom, o);
+          if (D == DM)
+            momentum_row<DM, false, true>(dot3(d, G.xin), dot3(d, G.yin), dot3(d, G.zin), D, A.family, thom, o);
+          else
+            momentum_row<DM, false>(dot3(d, G.xin), dot3(d, G.yin), dot3(d, G.zin), D, A.family, thom, o);
           for (int k = M; k < Mp; ++k) o[k] = 0.0;
         } else {
           double dd[3] = {d[0], d[1], d[2]};
@@ -924,7 +927,10 @@ __global__ __launch_bounds__(NTHREADS) void k_assemble(AsmArgs A) {
             for (int i = 0; i < 3; ++i) dd[i] = d[i] - 2.0 * dn * G.nrm[l_out][i];
           }
           double *o = Apsi + ql * Ml;
-          momentum_row<DM, false>(dot3(dd, G.xd), dot3(dd, G.yd), dot3(dd, G.zd), D, A.family, thom, o);
+          if (D == DM)
+            momentum_row<DM, false, true>(dot3(dd, G.xd), dot3(dd, G.yd), dot3(dd, G.zd), D, A.family, thom, o);
+          else
+            momentum_row<DM, false>(dot3(dd, G.xd), dot3(dd, G.yd), dot3(dd, G.zd), D, A.family, thom, o);
           for (int k = M; k < Mp; ++k) o[k] = 0.0;
         }
       } else {
@@ -971,7 +977,10 @@ __global__ __launch_bounds__(NTHREADS) void k_assemble(AsmArgs A) {
     const int ncol = (t1 - t0) * 16;
     if (tid < ncol) {
       const int c = t0 * 16 + tid;
-      if (c - (c / Mp) * Mp < M) gram_solve_column<DM>(Ts + tid * Ml, D, A.family, thom, wgt);
+      if (c - (c / Mp) * Mp < M) {
+        if (D == DM) gram_solve_column<DM, true>(Ts + tid * Ml, D, A.family, thom, wgt);
+        else gram_solve_column<DM>(Ts + tid * Ml, D, A.family, thom, wgt);
+      }
     }
     __syncthreads();
     for (int cs = wave; cs < ncol; cs += NTHREADS / 64) {
@@ -1270,9 +1279,10 @@ hipError_t launch_t(const AsmArgs &a, size_t lds, hipStream_t st) {
 // Instantiated kernels: (rows, cols) rectangle per wave, position pairs PQ and
 // the momentum-degree bound of the node code -- the rectangles that the layout
 // search below picks for every degree D <= 16 of both position bases.
-#define DFM_SHAPES(X)                                                                              \
-  X(1, 1, 1, 8) X(3, 1, 1, 8) X(2, 1, 1, 16) X(3, 2, 1, 16) X(4, 2, 1, 16) X(3, 5, 1, 16) X(5, 3, 1, 16) \
-  X(1, 3, 9, 8) X(1, 5, 9, 8) X(3, 4, 9, 8) X(2, 5, 9, 16) X(5, 3, 9, 16) X(3, 5, 9, 16) X(4, 4, 9, 16)
+#define DFM_SHAPES(X)                                                                                \
+  X(1, 1, 1, 8) X(3, 1, 1, 8) X(1, 3, 9, 8) X(1, 5, 9, 8) X(3, 4, 9, 8)                                 \
+  X(2, 1, 1, 12) X(3, 2, 1, 12) X(2, 5, 9, 12) X(5, 3, 9, 12) X(3, 5, 9, 12)                           \
+  X(4, 2, 1, 16) X(3, 5, 1, 16) X(5, 3, 1, 16) X(4, 4, 9, 16) X(5, 3, 9, 16)
 #define DFM_SHAPE_ROW(r, c, pq, d) {r, c, pq, d},
 constexpr int SHAPES[][4] = {DFM_SHAPES(DFM_SHAPE_ROW)};
 constexpr int NSHAPES = sizeof(SHAPES) / sizeof(SHAPES[0]);
@@ -1468,7 +1478,8 @@ extern "C" dfm_status dfm_assemble(dfm_mesh mesh, const dfm_basis *basis, const 
   const int Mp = (M + 15) / 16 * 16;
   const int PQ = P * P;
   const int R = Mp / 16;
-  const TileLayout lay = choose_layout(R, PQ * Mp / 16, PQ, D <= 8 ? 8 : 16);
+  // degree bound of the node code: 8, 12 or 16 (the degree itself when it is one of them)
+  const TileLayout lay = choose_layout(R, PQ * Mp / 16, PQ, D <= 8 ? 8 : (D <= 12 ? 12 : 16));
   DFM_REQUIRE(lay.shape >= 0, DFM_E_UNSUPPORTED, "no contraction layout for this basis size");
   // nodes per chunk: two halves of 64 when the LDS allows
   int chunk;

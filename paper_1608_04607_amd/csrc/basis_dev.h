@@ -39,9 +39,11 @@ __device__ __forceinline__ void legendre_table(double x, int D, double *p) {
 // matrix is pi (I + J) per block of fixed b (unknowns a = 0..D-b), solved by the
 // Thomas algorithm with the elimination tables thom = [J off-diagonal | c' | 1/den];
 // the Zernike family's is diagonal.
-template <int DM, bool GINV>
-__device__ __forceinline__ void momentum_row(double dx, double dy, double dz, int D, int family,
+// EXACT: D == DM, so every degree guard folds at compile time.
+template <int DM, bool GINV, bool EXACT = false>
+__device__ __forceinline__ void momentum_row(double dx, double dy, double dz, int D_, int family,
                                              const double *__restrict__ thom, double *__restrict__ out) {
+  const int D = EXACT ? DM : D_;
   if (family == 0) {
     double phi = atan2(dy, dx);
     if (phi < 0.0) phi += 2.0 * M_PI;
@@ -174,9 +176,10 @@ __device__ void apply_gram_inverse(double *out, int D, int family, const double 
 
 // In place on a contiguous column c[0..M): c <- scale * G^-1 c, loops unrolled to
 // the compile-time degree bound DM >= D so each Thomas block sits in registers.
-template <int DM>
-__device__ __forceinline__ void gram_solve_column(double *__restrict__ c, int D, int family,
+template <int DM, bool EXACT = false>
+__device__ __forceinline__ void gram_solve_column(double *__restrict__ c, int D_, int family,
                                                   const double *__restrict__ thom, double scale) {
+  const int D = EXACT ? DM : D_;
   if (family == 1) {
 #pragma unroll
     for (int n = 0; n <= DM; ++n) {
