@@ -69,7 +69,12 @@ typedef struct {
   int rule;       /* 0: the seven direction regions of Sec. 3.4 (four reach each face);
                      1: those regions cut at the momentum-basis seams and around both
                         poles, each cell touching a pole fanned from it                 */
-  int dtype;      /* 0: FP64 assembly and storage of B (the only value implemented)     */
+  int dtype;      /* 0: B assembled and stored in FP64;
+                     1: node geometry, basis values and the Gram solve in FP64, the
+                        contraction over the directions on the FP32 matrix cores and
+                        B stored in FP32 only (half the memory).  Products and
+                        residuals still accumulate in FP64; transposed products
+                        (and so dfm_adjoint) need dtype 0 (DFM_E_UNSUPPORTED).        */
 } dfm_basis;
 
 /* Solver options for (I - B) rho = rho0 (Sec. 2, Eq. NSum / GovIE). */

@@ -268,7 +268,16 @@ __global__ __launch_bounds__(SPMM_THREADS, 4) void k_spmm32(const float *__restr
 
 }  // namespace
 
+// FP64 vectors; the operator in FP64, or in FP32 when it was assembled in FP32
+// (accumulation in FP64 either way)
 hipError_t spmv(dfm_op op, const double *x, const double *v, double *y, double alpha, double beta, hipStream_t st) {
+  if (!op->B) {
+    int64_t nthreads = 4 * op->nt * (int64_t)(op->Kp / Vec<float>::W);
+    unsigned grid = (unsigned)((nthreads + SPMV_THREADS - 1) / SPMV_THREADS);
+    hipLaunchKernelGGL((k_spmv<float, double>), dim3(grid), dim3(SPMV_THREADS), spmv_lds<float>(op->K, op->Kp), st,
+                       op->B32, op->dest, nthreads, op->K, op->Kp, x, v, y, alpha, beta);
+    return hipGetLastError();
+  }
   int64_t nthreads = 4 * op->nt * (int64_t)(op->Kp / Vec<double>::W);
   unsigned grid = (unsigned)((nthreads + SPMV_THREADS - 1) / SPMV_THREADS);
   hipLaunchKernelGGL((k_spmv<double, double>), dim3(grid), dim3(SPMV_THREADS), spmv_lds<double>(op->K, op->Kp), st,
@@ -310,6 +319,7 @@ hipError_t ensure_fp32(dfm_op op, hipStream_t st) {
 }
 
 hipError_t spmv_t(dfm_op op, const double *x, const double *v, double *y, double alpha, double beta, hipStream_t st) {
+  if (!op->B) return hipErrorNotSupported;   // transposed products need the FP64 operator
   int64_t nrows = op->ndof;
   unsigned grid = (unsigned)((nrows + 255) / 256);
   hipLaunchKernelGGL(k_spmv_t, dim3(grid), dim3(256), 0, st, op->B, op->dest, nrows, op->K, op->Kp, x, v, y, alpha,
@@ -323,6 +333,7 @@ using namespace dfm;
 
 extern "C" dfm_status dfm_apply(dfm_op op, const double *x, double *y, int nrhs, int transpose, void *stream_) {
   DFM_REQUIRE(op && x && y, DFM_E_INVALID, "null argument");
+  DFM_REQUIRE(!(transpose && !op->B), DFM_E_UNSUPPORTED, "transposed products need an operator assembled in FP64");
   DFM_REQUIRE(nrhs >= 1, DFM_E_INVALID, "nrhs must be >= 1");
   DFM_REQUIRE(x != y, DFM_E_INVALID, "x and y must not alias");
   hipStream_t st = (hipStream_t)stream_;

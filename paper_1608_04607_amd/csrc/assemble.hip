@@ -48,6 +48,29 @@ constexpr int NPLANES = 5;
 constexpr double TOL = 1e-12;
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// The contraction's matrix-core step in the precision of B: FP64 v_mfma_f64_16x16x4
+// (result row of lane l, register e: l/16 + 4e) or FP32 v_mfma_f32_16x16x4 (row
+// 4 (l/16) + e); the column is l % 16 in both.
+template <typename TA>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  typedef v4d acc_t;
+  static __device__ __forceinline__ acc_t step(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int qrow, int e) { return qrow + 4 * e; }
+};
+template <>
+struct Mfma<float> {
+  typedef v4f acc_t;
+  static __device__ __forceinline__ acc_t step(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int qrow, int e) { return 4 * qrow + e; }
+};
 
 struct BlockGeo;
 
@@ -63,6 +86,7 @@ struct AsmArgs {
   const double *thom;   // [3][DMAX+1][DMAX+1]: Jacobi off-diagonal, Thomas c', 1/denominator
   const double *coef;   // [NMOM][NSERIES] power-series coefficients of the chord moments
   double *B;
+  float *B32;           // output when B is assembled in FP32
   const double *rho;    // adjoint: forward solution [ndof]
   const double *lam;    // adjoint: adjoint solution [ndof]
   double *out_vec;      // energy: per-block contribution to g [nblocks][K]
@@ -768,13 +792,25 @@ __global__ __launch_bounds__(CELL_THREADS) void k_cells(AsmArgs A) {
 
 // The MFMAs of one chunk for an R x C rectangle (compile-time); the fragments of
 // step s + 1 are loaded while the MFMAs of step s run.  ap, bp, sp point at the
-// lane's entries of step 0; steps >= 1.
-template <int R, int C, int RB, int CB, int PQ>
-__device__ __forceinline__ void contract_chunk(v4d (&acc)[CB][RB], const double *__restrict__ ap,
-                                               const double *__restrict__ bp, const double *__restrict__ sp,
+// lane's entries of step 0; steps >= 1.  The running sums are FP64 in both
+// precisions: in FP32 the chunk (at most 128 directions) is summed on the FP32
+// matrix cores and then added in FP64, so rounding grows with the chunk length,
+// not with the block's whole quadrature.
+template <int R, int C, int RB, int CB, int PQ, typename TA>
+__device__ __forceinline__ void contract_chunk(v4d (&acc)[CB][RB], const TA *__restrict__ ap,
+                                               const TA *__restrict__ bp, const TA *__restrict__ sp,
                                                const int (&boff)[CB], const int (&spq)[CB], int steps, int Ml) {
   if constexpr (R > 0 && C > 0) {
-    double a0[R], b0[C];
+    typedef typename Mfma<TA>::acc_t acc_t;
+    acc_t cacc[C][R];
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        if constexpr (sizeof(TA) == 8) cacc[c][i] = acc[c][i];
+        else cacc[c][i] = acc_t{0, 0, 0, 0};
+      }
+    TA a0[R], b0[C];
 #pragma unroll
     for (int i = 0; i < R; ++i) a0[i] = ap[i * 16];
 #pragma unroll
@@ -784,7 +820,7 @@ __device__ __forceinline__ void contract_chunk(v4d (&acc)[CB][RB], const double 
       ap += sa;
       bp += sa;
       sp += 4 * PQ;
-      double a1[R], b1[C], s1[C];
+      TA a1[R], b1[C], s1[C];
 #pragma unroll
       for (int i = 0; i < R; ++i) a1[i] = ap[i * 16];
 #pragma unroll
@@ -795,7 +831,7 @@ __device__ __forceinline__ void contract_chunk(v4d (&acc)[CB][RB], const double 
 #pragma unroll
       for (int c = 0; c < C; ++c)
 #pragma unroll
-        for (int i = 0; i < R; ++i) acc[c][i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[i], b0[c], acc[c][i], 0, 0, 0);
+        for (int i = 0; i < R; ++i) cacc[c][i] = Mfma<TA>::step(a0[i], b0[c], cacc[c][i]);
 #pragma unroll
       for (int i = 0; i < R; ++i) a0[i] = a1[i];
 #pragma unroll
@@ -804,29 +840,48 @@ __device__ __forceinline__ void contract_chunk(v4d (&acc)[CB][RB], const double 
 #pragma unroll
     for (int c = 0; c < C; ++c)
 #pragma unroll
-      for (int i = 0; i < R; ++i) acc[c][i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[i], b0[c], acc[c][i], 0, 0, 0);
+      for (int i = 0; i < R; ++i) {
+        cacc[c][i] = Mfma<TA>::step(a0[i], b0[c], cacc[c][i]);
+        if constexpr (sizeof(TA) == 8) {
+          acc[c][i] = cacc[c][i];
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc[c][i][e] += (double)cacc[c][i][e];
+        }
+      }
   }
 }
 
 // Tiles of the rectangle that fall in column tiles [t0, t1) into the LDS slab
-// Ts[(ct - t0) * 16 + column][row] (row stride Ml).
-template <int R, int C, int RB, int CB>
+// Ts[(ct - t0) * 16 + column][row] (row stride Ml), in FP64.
+template <int R, int C, int RB, int CB, typename TA>
 __device__ __forceinline__ void stage_tiles(const v4d (&acc)[CB][RB], double *Ts, int c0, int r0, int t0, int t1,
                                             int Ml, int col, int qrow) {
 #pragma unroll
   for (int c = 0; c < C; ++c) {
     const int ct = c0 + c;
     if (ct >= t0 && ct < t1) {
-      double *dst = Ts + ((ct - t0) * 16 + col) * Ml + r0 * 16 + qrow;
+      double *dst = Ts + ((ct - t0) * 16 + col) * Ml + r0 * 16;
 #pragma unroll
       for (int i = 0; i < R; ++i)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) dst[i * 16 + 4 * e] = acc[c][i][e];
+        for (int e = 0; e < 4; ++e) dst[i * 16 + Mfma<TA>::row(qrow, e)] = acc[c][i][e];
     }
   }
 }
 
-template <int RB, int CB, int PQ, int DM>
+template <typename TA>
+__device__ __forceinline__ TA *out_blocks(const AsmArgs &A);
+template <>
+__device__ __forceinline__ double *out_blocks<double>(const AsmArgs &A) {
+  return A.B;
+}
+template <>
+__device__ __forceinline__ float *out_blocks<float>(const AsmArgs &A) {
+  return A.B32;
+}
+
+template <int RB, int CB, int PQ, int DM, typename TA>
 __global__ __launch_bounds__(NTHREADS) void k_assemble(AsmArgs A) {
   __shared__ BlockGeo G;
   __shared__ double cells[CMAX][4][3];
@@ -871,9 +926,9 @@ __global__ __launch_bounds__(NTHREADS) void k_assemble(AsmArgs A) {
   __syncthreads();
 
   const int chunk = A.chunk;
-  double *Apsi = dyn;                    // [chunk][Mp + 1]  psi'(d')
-  double *Bpsi = dyn + chunk * Ml;       // [chunk][Mp + 1]  psi(d)
-  double *Sw = dyn + 2 * chunk * Ml;     // [chunk][PQ]  W S
+  TA *Apsi = reinterpret_cast<TA *>(dyn);   // [chunk][Mp + 1]  psi'(d')
+  TA *Bpsi = Apsi + chunk * Ml;              // [chunk][Mp + 1]  psi(d)
+  TA *Sw = Apsi + 2 * chunk * Ml;            // [chunk][PQ]  W S
   const int Q = __builtin_amdgcn_readfirstlane(G.ncells * n * n);
   const int WR = A.wr_waves, WC = 8 / WR;
   const int wr = wave / WC, wc = wave - (wave / WC) * WC;
@@ -895,7 +950,7 @@ __global__ __launch_bounds__(NTHREADS) void k_assemble(AsmArgs A) {
     boff[c] = ct * 16 - spq[c] * Mp + col;
   }
 
-  v4d acc[CB][RB];
+  v4d acc[CB][RB];   // FP64 running sums (see contract_chunk)
 #pragma unroll
   for (int c = 0; c < CB; ++c)
 #pragma unroll
@@ -912,66 +967,66 @@ __global__ __launch_bounds__(NTHREADS) void k_assemble(AsmArgs A) {
           double sw[PQ];
           spatial_weights<P>(G, coef, d, W, sw);
 #pragma unroll
-          for (int i = 0; i < PQ; ++i) Sw[ql * PQ + i] = sw[i];
+          for (int i = 0; i < PQ; ++i) Sw[ql * PQ + i] = (TA)sw[i];
         } else if (role == 1) {
-          double *o = Bpsi + ql * Ml;
+          TA *o = Bpsi + ql * Ml;
           if (D == DM)
-            momentum_row<DM, false, true>(dot3(d, G.xin), dot3(d, G.yin), dot3(d, G.zin), D, A.family, thom, o);
+            momentum_row<DM, false, true, TA>(dot3(d, G.xin), dot3(d, G.yin), dot3(d, G.zin), D, A.family, thom, o);
           else
-            momentum_row<DM, false>(dot3(d, G.xin), dot3(d, G.yin), dot3(d, G.zin), D, A.family, thom, o);
-          for (int k = M; k < Mp; ++k) o[k] = 0.0;
+            momentum_row<DM, false, false, TA>(dot3(d, G.xin), dot3(d, G.yin), dot3(d, G.zin), D, A.family, thom, o);
+          for (int k = M; k < Mp; ++k) o[k] = (TA)0;
         } else {
           double dd[3] = {d[0], d[1], d[2]};
           if (!G.transmit) {
             double dn = dot3(d, G.nrm[l_out]);
             for (int i = 0; i < 3; ++i) dd[i] = d[i] - 2.0 * dn * G.nrm[l_out][i];
           }
-          double *o = Apsi + ql * Ml;
+          TA *o = Apsi + ql * Ml;
           if (D == DM)
-            momentum_row<DM, false, true>(dot3(dd, G.xd), dot3(dd, G.yd), dot3(dd, G.zd), D, A.family, thom, o);
+            momentum_row<DM, false, true, TA>(dot3(dd, G.xd), dot3(dd, G.yd), dot3(dd, G.zd), D, A.family, thom, o);
           else
-            momentum_row<DM, false>(dot3(dd, G.xd), dot3(dd, G.yd), dot3(dd, G.zd), D, A.family, thom, o);
-          for (int k = M; k < Mp; ++k) o[k] = 0.0;
+            momentum_row<DM, false, false, TA>(dot3(dd, G.xd), dot3(dd, G.yd), dot3(dd, G.zd), D, A.family, thom, o);
+          for (int k = M; k < Mp; ++k) o[k] = (TA)0;
         }
       } else {
         if (role == 0) {
-          for (int i = 0; i < PQ; ++i) Sw[ql * PQ + i] = 0.0;
+          for (int i = 0; i < PQ; ++i) Sw[ql * PQ + i] = (TA)0;
         } else if (role == 1) {
-          for (int k = 0; k < Mp; ++k) Bpsi[ql * Ml + k] = 0.0;
+          for (int k = 0; k < Mp; ++k) Bpsi[ql * Ml + k] = (TA)0;
         } else {
-          for (int k = 0; k < Mp; ++k) Apsi[ql * Ml + k] = 0.0;
+          for (int k = 0; k < Mp; ++k) Apsi[ql * Ml + k] = (TA)0;
         }
       }
     }
     __syncthreads();
     const int steps = (Q - q0 >= chunk) ? chunk / 4 : (Q - q0 + 3) / 4;
-    const double *ap = Apsi + qrow * Ml + r0 * 16 + col;
-    const double *bp = Bpsi + qrow * Ml;
-    const double *sp = Sw + qrow * PQ;
+    const TA *ap = Apsi + qrow * Ml + r0 * 16 + col;
+    const TA *bp = Bpsi + qrow * Ml;
+    const TA *sp = Sw + qrow * PQ;
     if (rb == RB) {
-      if (cb == CB) contract_chunk<RB, CB, RB, CB, PQ>(acc, ap, bp, sp, boff, spq, steps, Ml);
-      else contract_chunk<RB, CB - 1, RB, CB, PQ>(acc, ap, bp, sp, boff, spq, steps, Ml);
+      if (cb == CB) contract_chunk<RB, CB, RB, CB, PQ, TA>(acc, ap, bp, sp, boff, spq, steps, Ml);
+      else contract_chunk<RB, CB - 1, RB, CB, PQ, TA>(acc, ap, bp, sp, boff, spq, steps, Ml);
     } else {
-      if (cb == CB) contract_chunk<RB - 1, CB, RB, CB, PQ>(acc, ap, bp, sp, boff, spq, steps, Ml);
-      else contract_chunk<RB - 1, CB - 1, RB, CB, PQ>(acc, ap, bp, sp, boff, spq, steps, Ml);
+      if (cb == CB) contract_chunk<RB - 1, CB, RB, CB, PQ, TA>(acc, ap, bp, sp, boff, spq, steps, Ml);
+      else contract_chunk<RB - 1, CB - 1, RB, CB, PQ, TA>(acc, ap, bp, sp, boff, spq, steps, Ml);
     }
     __syncthreads();
   }
 
   // epilogue, one slab of column tiles [t0, t1) at a time
   const int Kp = A.Kp;
-  double *Bb = A.B + (int64_t)blk * K * Kp;
+  TA *Bb = out_blocks<TA>(A) + (int64_t)blk * K * Kp;
   const double wgt = G.weight;
   double *Ts = dyn;
   bool bad = false;
   for (int t0 = cs0; t0 < cs1; t0 += A.slab_tiles) {
     const int t1 = min(cs1, t0 + A.slab_tiles);
     if (rb == RB) {
-      if (cb == CB) stage_tiles<RB, CB, RB, CB>(acc, Ts, c0, r0, t0, t1, Ml, col, qrow);
-      else stage_tiles<RB, CB - 1, RB, CB>(acc, Ts, c0, r0, t0, t1, Ml, col, qrow);
+      if (cb == CB) stage_tiles<RB, CB, RB, CB, TA>(acc, Ts, c0, r0, t0, t1, Ml, col, qrow);
+      else stage_tiles<RB, CB - 1, RB, CB, TA>(acc, Ts, c0, r0, t0, t1, Ml, col, qrow);
     } else {
-      if (cb == CB) stage_tiles<RB - 1, CB, RB, CB>(acc, Ts, c0, r0, t0, t1, Ml, col, qrow);
-      else stage_tiles<RB - 1, CB - 1, RB, CB>(acc, Ts, c0, r0, t0, t1, Ml, col, qrow);
+      if (cb == CB) stage_tiles<RB - 1, CB, RB, CB, TA>(acc, Ts, c0, r0, t0, t1, Ml, col, qrow);
+      else stage_tiles<RB - 1, CB - 1, RB, CB, TA>(acc, Ts, c0, r0, t0, t1, Ml, col, qrow);
     }
     __syncthreads();
     const int ncol = (t1 - t0) * 16;
@@ -989,11 +1044,11 @@ __global__ __launch_bounds__(NTHREADS) void k_assemble(AsmArgs A) {
       const int k = c - pq * Mp;
       if (k < M) {
         const int pp = pq / P, p = pq - (pq / P) * P;
-        double *dst = Bb + (int64_t)(p * M + k) * Kp + pp * M;
+        TA *dst = Bb + (int64_t)(p * M + k) * Kp + pp * M;
         for (int kp = lane; kp < M; kp += 64) {
           const double v = Ts[cs * Ml + kp];
           bad |= !isfinite(v);
-          dst[kp] = v;
+          dst[kp] = (TA)v;
         }
       }
     }
@@ -1003,7 +1058,7 @@ __global__ __launch_bounds__(NTHREADS) void k_assemble(AsmArgs A) {
   if (split == 0)
     for (int i = tid; i < K * (Kp - K); i += NTHREADS) {
       int c = i / (Kp - K), rr = K + (i - c * (Kp - K));
-      Bb[(int64_t)c * Kp + rr] = 0.0;
+      Bb[(int64_t)c * Kp + rr] = (TA)0;
     }
   if (bad) atomicOr(A.flags, FLAG_NONFINITE);
 }
@@ -1266,9 +1321,9 @@ __global__ void k_dest(const int32_t *nbr, int64_t nslot, int32_t *dest) {
   dest[s] = (k >= 0) ? k : (int32_t)s;
 }
 
-template <int RB, int CB, int PQ, int DM>
+template <int RB, int CB, int PQ, int DM, typename TA>
 hipError_t launch_t(const AsmArgs &a, size_t lds, hipStream_t st) {
-  auto kern = k_assemble<RB, CB, PQ, DM>;
+  auto kern = k_assemble<RB, CB, PQ, DM, TA>;
   hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   unsigned grid = (unsigned)(a.nblocks * a.nsplit);
@@ -1287,10 +1342,10 @@ hipError_t launch_t(const AsmArgs &a, size_t lds, hipStream_t st) {
 constexpr int SHAPES[][4] = {DFM_SHAPES(DFM_SHAPE_ROW)};
 constexpr int NSHAPES = sizeof(SHAPES) / sizeof(SHAPES[0]);
 
-hipError_t launch_shape(int shape, const AsmArgs &a, size_t lds, hipStream_t st) {
+hipError_t launch_shape(int shape, bool fp32, const AsmArgs &a, size_t lds, hipStream_t st) {
   int idx = 0;
 #define DFM_SHAPE_CASE(r, c, pq, d) \
-  if (shape == idx++) return launch_t<r, c, pq, d>(a, lds, st);
+  if (shape == idx++) return fp32 ? launch_t<r, c, pq, d, float>(a, lds, st) : launch_t<r, c, pq, d, double>(a, lds, st);
   DFM_SHAPES(DFM_SHAPE_CASE)
 #undef DFM_SHAPE_CASE
   return hipErrorInvalidValue;
@@ -1468,7 +1523,7 @@ extern "C" dfm_status dfm_assemble(dfm_mesh mesh, const dfm_basis *basis, const 
   DFM_REQUIRE(bs.mom_degree >= 0 && bs.mom_degree <= DMAX, DFM_E_INVALID, "mom_degree must be in 0..16");
   DFM_REQUIRE(bs.quad_n >= 1 && bs.quad_n <= 32, DFM_E_INVALID, "quad_n must be in 1..32");
   DFM_REQUIRE(bs.rule == 0 || bs.rule == 1, DFM_E_INVALID, "rule must be 0 or 1");
-  DFM_REQUIRE(bs.dtype == 0, DFM_E_UNSUPPORTED, "only FP64 assembly (dtype 0) is implemented");
+  DFM_REQUIRE(bs.dtype == 0 || bs.dtype == 1, DFM_E_INVALID, "dtype must be 0 (FP64) or 1 (FP32)");
   hipStream_t st = (hipStream_t)stream_;
 
   const int P = bs.pos_order == 0 ? 1 : 3;
@@ -1520,7 +1575,10 @@ extern "C" dfm_status dfm_assemble(dfm_mesh mesh, const dfm_basis *basis, const 
       return fail(e_ == hipErrorOutOfMemory ? DFM_E_NOMEM : DFM_E_HIP);                      \
     }                                                                                        \
   } while (0)
-  TRY(hipMalloc(&op->B, sizeof(double) * (size_t)nblocks * K * op->Kp));
+  if (bs.dtype == 0)
+    TRY(hipMalloc(&op->B, sizeof(double) * (size_t)nblocks * K * op->Kp));
+  else
+    TRY(hipMalloc(&op->B32, sizeof(float) * (size_t)nblocks * K * op->Kp));
   TRY(hipMalloc(&op->dest, sizeof(int32_t) * 4 * mesh->nt));
   TRY(hipMalloc(&gl, sizeof(double) * 64));
   TRY(hipMalloc(&thom_d, sizeof(double) * 3 * (DMAX + 1) * (DMAX + 1)));
@@ -1593,6 +1651,7 @@ extern "C" dfm_status dfm_assemble(dfm_mesh mesh, const dfm_basis *basis, const 
   a.thom = thom_d;
   a.coef = coef_d;
   a.B = op->B;
+  a.B32 = op->B32;
   a.flags = flags;
   a.nodes = nodes;
   a.nblocks = nblocks;
@@ -1621,7 +1680,7 @@ extern "C" dfm_status dfm_assemble(dfm_mesh mesh, const dfm_basis *basis, const 
   hipLaunchKernelGGL(k_cells, dim3((unsigned)((nblocks + CELL_THREADS - 1) / CELL_THREADS)), dim3(CELL_THREADS), 0,
                      st, a);
   TRY(hipGetLastError());
-  hipError_t le = launch_shape(lay.shape, a, lds, st);
+  hipError_t le = launch_shape(lay.shape, bs.dtype == 1, a, lds, st);
   TRY(le);
   unsigned hflags = 0;
   unsigned long long hnodes = 0;
@@ -1663,19 +1722,20 @@ extern "C" dfm_status dfm_op_info(dfm_op op, int64_t *ndof, int64_t *K, int64_t 
   if (K) *K = op->K;
   if (nblocks) *nblocks = 12 * op->nt;
   if (nodes) *nodes = op->nodes;
-  if (bytes) *bytes = (int64_t)sizeof(double) * 12 * op->nt * op->K * op->Kp;
+  if (bytes) *bytes = (int64_t)(op->B ? sizeof(double) : sizeof(float)) * 12 * op->nt * op->K * op->Kp;
   return DFM_OK;
 }
 
 namespace {
 // blocks out [nt][4][3][K][K] row-major from the internal column-major blocks
-__global__ void k_export_blocks(const double *B, int64_t nblk, int K, int Kp, double *out) {
+template <typename TB>
+__global__ void k_export_blocks(const TB *B, int64_t nblk, int K, int Kp, double *out) {
   const int64_t kk = (int64_t)K * K;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nblk * kk; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t b = i / kk;
     const int64_t e = i - b * kk;
     const int row = (int)(e / K), col = (int)(e - (int64_t)row * K);
-    out[i] = B[b * (int64_t)K * Kp + (int64_t)col * Kp + row];
+    out[i] = (double)B[b * (int64_t)K * Kp + (int64_t)col * Kp + row];
   }
 }
 }  // namespace
@@ -1686,8 +1746,12 @@ extern "C" dfm_status dfm_op_export(dfm_op op, double *blocks, int32_t *dest, vo
   if (blocks) {
     int64_t nblk = 12 * op->nt;
     int64_t tot = nblk * op->K * op->K;
-    hipLaunchKernelGGL(k_export_blocks, dim3(ew_grid(tot)), dim3(256), 0, st, op->B, nblk, op->K,
-                       op->Kp, blocks);
+    if (op->B)
+      hipLaunchKernelGGL(k_export_blocks<double>, dim3(ew_grid(tot)), dim3(256), 0, st, op->B, nblk, op->K, op->Kp,
+                         blocks);
+    else
+      hipLaunchKernelGGL(k_export_blocks<float>, dim3(ew_grid(tot)), dim3(256), 0, st, op->B32, nblk, op->K, op->Kp,
+                         blocks);
     DFM_HIP(hipGetLastError());
   }
   if (dest) DFM_HIP(hipMemcpyAsync(dest, op->dest, sizeof(int32_t) * 4 * op->nt, hipMemcpyDeviceToDevice, st));

@@ -40,9 +40,9 @@ __device__ __forceinline__ void legendre_table(double x, int D, double *p) {
 // Thomas algorithm with the elimination tables thom = [J off-diagonal | c' | 1/den];
 // the Zernike family's is diagonal.
 // EXACT: D == DM, so every degree guard folds at compile time.
-template <int DM, bool GINV, bool EXACT = false>
+template <int DM, bool GINV, bool EXACT = false, typename TO = double>
 __device__ __forceinline__ void momentum_row(double dx, double dy, double dz, int D_, int family,
-                                             const double *__restrict__ thom, double *__restrict__ out) {
+                                             const double *__restrict__ thom, TO *__restrict__ out) {
   const int D = EXACT ? DM : D_;
   if (family == 0) {
     double phi = atan2(dy, dx);
@@ -60,7 +60,7 @@ __device__ __forceinline__ void momentum_row(double dx, double dy, double dz, in
       if (!GINV) {
 #pragma unroll
         for (int a = 0; a <= DM - b; ++a)
-          if (a <= N) out[(a + b) * (a + b + 1) / 2 + b] = px[a] * qb;
+          if (a <= N) out[(a + b) * (a + b + 1) / 2 + b] = (TO)(px[a] * qb);
       } else {
         const double *jo = thom;
         const double *cpb = thom + (DMAX + 1) * (DMAX + 1) + b * (DMAX + 1);
@@ -81,7 +81,7 @@ __device__ __forceinline__ void momentum_row(double dx, double dy, double dz, in
         for (int a = DM - b; a >= 0; --a) {
           if (a <= N) {
             const double xa = (a == N) ? dp[a] : dp[a] - cpb[a] * next;
-            out[(a + b) * (a + b + 1) / 2 + b] = xa;
+            out[(a + b) * (a + b + 1) / 2 + b] = (TO)xa;
             next = xa;
           }
         }
@@ -120,8 +120,8 @@ __device__ __forceinline__ void momentum_row(double dx, double dy, double dz, in
             const int base = n * (n + 1) / 2;
             const double gp = GINV ? (2.0 * n + 2.0) / ((m == 0 ? 2.0 : 1.0) * M_PI) : 1.0;
             const double gm = GINV ? (2.0 * n + 2.0) / M_PI : 1.0;
-            out[base + (m + n) / 2] = (pk * cm) * gp;
-            if (m > 0) out[base + (n - m) / 2] = (pk * sm) * gm;
+            out[base + (m + n) / 2] = (TO)((pk * cm) * gp);
+            if (m > 0) out[base + (n - m) / 2] = (TO)((pk * sm) * gm);
           }
         }
       }

@@ -521,6 +521,7 @@ dfm_status solve_impl(dfm_op op, const double *rho0, double *rho, int nrhs, cons
   DFM_REQUIRE(m >= 1 && m <= MAXV - 1, DFM_E_INVALID, "restart must be in 1..200");
   DFM_REQUIRE(!(transpose && opts->precision == 1), DFM_E_UNSUPPORTED,
               "transposed solves are implemented in FP64 only");
+  DFM_REQUIRE(!(transpose && !op->B), DFM_E_UNSUPPORTED, "transposed solves need an operator assembled in FP64");
   DFM_REQUIRE(opts->warm_start == 0 || opts->warm_start == 1, DFM_E_INVALID, "warm_start must be 0 or 1");
   DFM_REQUIRE(!(opts->warm_start && !(opts->method == 0 && opts->precision == 1)), DFM_E_UNSUPPORTED,
               "warm_start is implemented for method 0 with precision 1 only");

@@ -85,11 +85,11 @@ class Operator:
     """Assembled transfer operator B (dfm_assemble) and its solves."""
 
     def __init__(self, mesh: Mesh, mu, pos_order=0, mom_family=LEGENDRE, mom_degree=4, quad_n=8,
-                 rule=SEAM_RULE, stream=None):
+                 rule=SEAM_RULE, stream=None, dtype=0):
         lib = _lib.load()
         self.mesh = mesh
         self.mu = _dev(mu, torch.float64)
-        self.basis = Basis(pos_order, mom_family, mom_degree, quad_n, rule, 0)
+        self.basis = Basis(pos_order, mom_family, mom_degree, quad_n, rule, int(dtype))
         h = C.c_void_p()
         check(lib.dfm_assemble(mesh.handle, C.byref(self.basis), _ptr(self.mu), _stream(stream), C.byref(h)))
         self.handle = h

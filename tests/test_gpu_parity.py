@@ -274,6 +274,34 @@ def test_batched_mixed_neumann_warm_start(small):
         assert rel(rho[r].cpu().numpy(), osv.solve_direct(A, rhs[r])) < 1e-7
 
 
+@pytest.mark.parametrize("order,family,degree", [(1, 0, 8), (0, 1, 6)])
+def test_fp32_assembly_matches_oracle(order, family, degree):
+    """dtype 1: contraction on the FP32 matrix cores, B stored in FP32 -- blocks within
+    1e-5 of the oracle (relative to the largest entry), and the mixed solves refine
+    to the FP64 tolerance of that operator."""
+    from paper_1608_04607_amd import dfm
+    say(f"[assembly fp32] P{order} family {family} D{degree}")
+    v, t, refl = box(2, 0.15, seed=5)
+    mu = np.full(t.shape[0], 0.3)
+    bs = oa.Basis(order, family, degree, 6, oq.SEAM_RULE)
+    mesh = gpu_mesh(v, t, refl)
+    op = dfm.Operator(mesh, torch.tensor(mu, device=DEV), order, family, degree, 6, rule=oq.SEAM_RULE, dtype=1)
+    blocks, dest = op.export()
+    m = om.build_mesh(v, t, refl)
+    Bo, desto = oa.assemble(m, bs, mu)
+    err = rel(blocks.cpu().numpy(), np.asarray(Bo))
+    say(f"    blocks rel err {err:.2e}")
+    assert err < 1e-5
+    assert (dest.cpu().numpy() == desto).all()
+    A32 = osv.to_sparse(blocks.cpu().numpy(), desto)           # the operator as stored
+    rhs = np.random.default_rng(12).standard_normal(A32.shape[0])
+    for method in ("gmres", "neumann"):
+        rho, info = op.solve(torch.tensor(rhs, device=DEV), method=method, rtol=1e-10, precision=1)
+        assert osv.relres(A32, rhs, rho.cpu().numpy()) <= 2e-10
+    with pytest.raises(Exception, match="UNSUPPORTED"):
+        op.apply(torch.tensor(rhs, device=DEV), transpose=True)
+
+
 def test_cube_neumann_matches_direct():
     say("[solve] cube, Neumann to 1e-12")
     p = synth.problem_c1()
