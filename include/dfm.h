@@ -199,6 +199,13 @@ dfm_status dfm_solve(dfm_op op, const double *rho0, double *rho, int nrhs, const
  *     rho0 device f64 [ndof] (overwritten) */
 dfm_status dfm_source_points(dfm_op op, const double *xyz, int64_t ns, double flux, double *rho0,
                              void *stream);
+/* dfm_source_points_sum: the same point sources summed into nrhs right-hand sides,
+ *   rho0[which[i]] += projection of point i (independent instances sharing one mesh
+ *   take one right-hand side per source index).
+ *     which device i32 [ns] in 0..nrhs-1 (not checked on the device)
+ *     rho0  device f64 [nrhs][ndof] (overwritten) */
+dfm_status dfm_source_points_sum(dfm_op op, const double *xyz, int64_t ns, const int32_t *which, int nrhs,
+                                 double flux, double *rho0, void *stream);
 dfm_status dfm_source_plane(dfm_op op, int axis, double value, int profile, const double *params,
                             double flux, double *rho0, void *stream);
 

@@ -1,0 +1,135 @@
+"""Uneven batches of independent instances: meshes of different sizes, with their own
+damping, wall coefficients, momentum degree and point sources, solved together.
+
+Instances that share a discretisation (position order, momentum family and degree,
+Gauss points) are concatenated into one mesh.  Its components are disjoint, so B is
+block diagonal and one dfm_assemble launch assembles every instance of the group;
+right-hand side s of the group carries the s-th source of every instance
+(dfm_source_points_sum), and one batched solve (dfm_solve, Neumann with FP32
+corrections and FP64 refinement) solves all of them.  The global stopping test is
+tightened until every instance meets the tolerance on its own part of the residual.
+This module only arranges arrays and calls the library; every step of the method
+runs in its kernels.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import torch
+
+from . import dfm
+
+
+@dataclass
+class Group:
+    key: tuple                       # (pos_order, mom_family, mom_degree, quad_n)
+    members: list                    # instance indices
+    tet_offsets: list                # first tet of every member in the group mesh (+ total)
+    nsrc: int
+    mesh: dfm.Mesh = None
+    op: dfm.Operator = None
+    rho0: torch.Tensor = None
+    rho: torch.Tensor = None
+    products: int = 0
+    relres: list = field(default_factory=list)   # [member][rhs] on the member's own residual
+
+
+class UnevenBatch:
+    """problems: objects with verts, tets, mu, refl, pos_order, mom_degree, quad_n and
+    source = {"kind": "points", "xyz": ...} (e.g. synth.problem_c5())."""
+
+    def __init__(self, problems, mom_family=dfm.LEGENDRE, rule=dfm.SEAM_RULE, dtype=1, device="cuda:0"):
+        self.problems = list(problems)
+        self.family, self.rule, self.dtype, self.device = mom_family, rule, dtype, torch.device(device)
+        ext = [p.verts.max(axis=0) - p.verts.min(axis=0) for p in self.problems]
+        self._gap = 1.5 * max(float(e[0]) for e in ext) + 0.5    # x spacing of the instance grid
+        self._row = 1.5 * max(float(e[1]) for e in ext) + 0.5    # y spacing of its rows
+        groups = {}
+        for i, p in enumerate(self.problems):
+            groups.setdefault((p.pos_order, mom_family, p.mom_degree, p.quad_n), []).append(i)
+        self.groups = []
+        for key in sorted(groups):
+            mem = groups[key]
+            offs = [0]
+            for i in mem:
+                offs.append(offs[-1] + self.problems[i].nt)
+            nsrc = max(len(self.problems[i].source["xyz"]) for i in mem)
+            self.groups.append(Group(key, mem, offs, nsrc))
+
+    def _concat(self, g):
+        T = lambda a, dt: torch.as_tensor(a, dtype=dt).to(self.device)  # noqa: E731
+        verts, tets, mu, refl, xyz, which = [], [], [], [], [], []
+        voff = 0
+        for m, i in enumerate(g.members):
+            p = self.problems[i]
+            # instances are moved apart (the transport is translation invariant) so
+            # that a source point is found on its own instance's boundary
+            lo, hi = p.verts.min(axis=0), p.verts.max(axis=0)
+            shift = torch.tensor([self._gap * (m % 16) - lo[0], self._row * (m // 16) - lo[1], -lo[2]],
+                                 dtype=torch.float64, device=self.device)
+            verts.append(T(p.verts, torch.float64) + shift)
+            tets.append(T(p.tets, torch.int64) + voff)
+            mu.append(T(p.mu, torch.float64))
+            refl.append(T(p.refl, torch.float64))
+            pts = T(p.source["xyz"], torch.float64) + shift
+            xyz.append(pts)
+            which.append(torch.arange(pts.shape[0], dtype=torch.int32, device=self.device))
+            voff += p.verts.shape[0]
+        cat = torch.cat
+        return cat(verts), cat(tets), cat(mu), cat(refl), cat(xyz), cat(which)
+
+    def assemble(self, g, stream=None):
+        verts, tets, mu, refl, xyz, which = self._concat(g)
+        pos_order, family, degree, quad_n = g.key
+        g.mesh = dfm.Mesh(verts, tets, refl=refl, stream=stream)
+        g.op = dfm.Operator(g.mesh, mu, pos_order, family, degree, quad_n, rule=self.rule, stream=stream,
+                            dtype=self.dtype)
+        g.rho0 = g.op.source_points_sum(xyz, which, g.nsrc, stream=stream)
+
+    def member_relres(self, g, stream=None):
+        """[member][rhs] relative residual of every instance on its own unknowns."""
+        r = g.rho0 - (g.rho - g.op.apply(g.rho, stream=stream))
+        K = g.op.K
+        out = []
+        for m in range(len(g.members)):
+            a, b = 4 * K * g.tet_offsets[m], 4 * K * g.tet_offsets[m + 1]
+            rn = r[:, a:b].norm(dim=1)
+            bn = g.rho0[:, a:b].norm(dim=1)
+            out.append([float(x) for x in torch.where(bn > 0, rn / bn, torch.zeros_like(rn)).cpu()])
+        return out
+
+    def solve(self, g, rtol=1e-8, segment=2500, max_products=100000, progress=None, stream=None):
+        tol = rtol
+        while True:
+            g.rho, info = g.op.solve(g.rho0, method="neumann", rtol=tol, precision=1, max_iter=segment,
+                                     rho=g.rho, raise_nonconv=False, stream=stream)
+            g.products += info[0][0]
+            worst_global = max(i[2] for i in info)
+            if progress:
+                progress(g, worst_global)
+            if worst_global <= tol:
+                g.relres = self.member_relres(g, stream=stream)
+                worst = max(max(x) for x in g.relres)
+                if worst <= rtol:
+                    return
+                tol = max(tol * rtol / worst / 2.0, 1e-15)    # tighten the union's test and continue
+            if g.products >= max_products:
+                g.relres = self.member_relres(g, stream=stream)
+                return
+
+    def solution(self, i):
+        """rho of instance i: [nsrc][4 nt K] (the group's rhs s is the instance's source s)."""
+        for g in self.groups:
+            if i in g.members:
+                m = g.members.index(i)
+                K = g.op.K
+                return g.rho[:, 4 * K * g.tet_offsets[m]:4 * K * g.tet_offsets[m + 1]]
+        raise KeyError(i)
+
+    def release(self, g):
+        if g.op is not None:
+            g.op.close()
+        if g.mesh is not None:
+            g.mesh.close()
+        g.op = g.mesh = None

@@ -92,6 +92,69 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv(const TB *__restrict__ B,
   }
 }
 
+// A few right-hand sides at once from one stream of the FP32 operator: as k_spmv,
+// but each thread keeps NR accumulators, the x panels of all NR right-hand sides
+// are staged in LDS, and the running Neumann sum is updated in the same pass:
+// y[r] = B32 x[r], e[r] += y[r] (x, y, e f32 [NR][ndof] at stride ndof).
+template <int NR>
+__global__ __launch_bounds__(SPMV_THREADS) void k_spmv_rhs(const float *__restrict__ B, const int32_t *__restrict__ dest,
+                                                          int64_t nthreads, int K, int Kp, int64_t ndof,
+                                                          const float *__restrict__ x, float *__restrict__ y,
+                                                          float *__restrict__ e) {
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  extern __shared__ float xs_rhs[];
+  const int GPB = Kp / 4;
+  const int64_t g0 = blockIdx.x * (int64_t)SPMV_THREADS;
+  const int64_t br0 = g0 / GPB;
+  int64_t glast = g0 + SPMV_THREADS - 1;
+  if (glast >= nthreads) glast = nthreads - 1;
+  const int nrows_b = (int)(glast / GPB - br0 + 1);
+  const int panel = 3 * K;
+  const int per_rhs = nrows_b * panel;
+  for (int i = threadIdx.x; i < NR * per_rhs; i += SPMV_THREADS) {
+    const int r = i / per_rhs, q = i - r * per_rhs;
+    const int b = q / panel, c = q - b * panel;
+    const int s = c / K, col = c - s * K;
+    const int64_t br = br0 + b;
+    xs_rhs[i] = x[r * ndof + (4 * (br >> 2) + in_face((int)(br & 3), s)) * (int64_t)K + col];
+  }
+  __syncthreads();
+  const int64_t g = g0 + threadIdx.x;
+  if (g >= nthreads) return;
+  const int64_t br = g / GPB;
+  const int row0 = (int)(g - br * GPB) * 4;
+  const float *xp = xs_rhs + (br - br0) * panel;
+  const f4 *Bv = reinterpret_cast<const f4 *>(B + br * 3 * (int64_t)K * Kp + row0);
+  const int cstride = Kp / 4;
+  double acc[NR][4];
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[r][u] = 0.0;
+#pragma unroll 4
+  for (int c = 0; c < panel; ++c) {
+    const f4 bv = __builtin_nontemporal_load(Bv + (int64_t)c * cstride);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const double xc = xp[r * per_rhs + c];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[r][u] = fma((double)bv[u], xc, acc[r][u]);
+    }
+  }
+  const int64_t ob = (int64_t)dest[br] * K;
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int row = row0 + u;
+      if (row < K) {
+        const float v = (float)acc[r][u];
+        y[r * ndof + ob + row] = v;
+        if (e) e[r * ndof + ob + row] += v;
+      }
+    }
+}
+
 template <typename TB>
 inline size_t spmv_lds(int K, int Kp) {
   int gpb = Kp / Vec<TB>::W;
@@ -291,6 +354,38 @@ hipError_t spmv32(dfm_op op, const float *x, const float *v, float *y, float alp
   hipLaunchKernelGGL((k_spmv<float, float>), dim3(grid), dim3(SPMV_THREADS), spmv_lds<float>(op->K, op->Kp), st,
                      op->B32, op->dest, nthreads, op->K, op->Kp, x, v, y, (double)alpha, (double)beta);
   return hipGetLastError();
+}
+
+// y = B32 x (and e += y when e != null) for R right-hand sides, up to four per
+// stream of the operator
+hipError_t spmv32_rhs(dfm_op op, const float *x, float *y, float *e, int R, hipStream_t st) {
+  const int64_t nthreads = 4 * op->nt * (int64_t)(op->Kp / 4);
+  const unsigned grid = (unsigned)((nthreads + SPMV_THREADS - 1) / SPMV_THREADS);
+  const int gpb = op->Kp / 4;
+  const int64_t rows = (SPMV_THREADS + gpb - 1) / gpb + 1;
+  for (int r0 = 0; r0 < R; r0 += 4) {
+    const int nr = R - r0 < 4 ? R - r0 : 4;
+    const size_t lds = sizeof(float) * (size_t)(nr * rows * 3 * op->K);
+    const float *xr = x + (int64_t)r0 * op->ndof;
+    float *yr = y + (int64_t)r0 * op->ndof;
+    float *er = e ? e + (int64_t)r0 * op->ndof : nullptr;
+#define DFM_RHS_CASE(NRV)                                                                                  \
+  case NRV:                                                                                                \
+    hipLaunchKernelGGL(k_spmv_rhs<NRV>, dim3(grid), dim3(SPMV_THREADS), lds, st, op->B32, op->dest, nthreads, \
+                       op->K, op->Kp, op->ndof, xr, yr, er);                                               \
+    break;
+    switch (nr) {
+      DFM_RHS_CASE(1)
+      DFM_RHS_CASE(2)
+      DFM_RHS_CASE(3)
+      default:
+        DFM_RHS_CASE(4)
+    }
+#undef DFM_RHS_CASE
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+  }
+  return hipSuccess;
 }
 
 // y = B32 x for R right-hand sides on the matrix cores (and e += y when e != null)

@@ -163,9 +163,11 @@ __global__ void k_locate(const int32_t *tets, const double *verts, const int32_t
   }
 }
 
+// which == null: point r writes right-hand side r; else it adds into right-hand
+// side which[r] (atomically: points of one right-hand side may share a face)
 __global__ void k_point_coeffs(const int32_t *tets, const double *verts, const double *face, const double *xyz,
                                const int *found, int64_t ns, int P, int M, int K, int64_t ndof, double flux,
-                               const double *ang, double *rho0, unsigned *flags) {
+                               const double *ang, const int32_t *which, double *rho0, unsigned *flags) {
   int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (r >= ns) return;
   int s = found[r];
@@ -178,9 +180,12 @@ __global__ void k_point_coeffs(const int32_t *tets, const double *verts, const d
   bary3(v, xyz + 3 * r, lam);
   double e[3];
   pos_basis(lam, face[FACE_REC * (int64_t)s], e);
-  double *o = rho0 + r * ndof + (int64_t)s * K;
+  double *o = rho0 + (which ? (int64_t)which[r] : r) * ndof + (int64_t)s * K;
   for (int p = 0; p < P; ++p)
-    for (int k = 0; k < M; ++k) o[p * M + k] = flux * e[p] * ang[k];
+    for (int k = 0; k < M; ++k) {
+      if (which) atomicAdd(o + p * M + k, flux * e[p] * ang[k]);
+      else o[p * M + k] = flux * e[p] * ang[k];
+    }
 }
 
 __global__ void k_plane_mark(const int32_t *tets, const double *verts, const int32_t *nbr, const double *face,
@@ -295,11 +300,8 @@ using namespace dfm;
     }                                                                                        \
   } while (0)
 
-extern "C" dfm_status dfm_source_points(dfm_op op, const double *xyz, int64_t ns, double flux, double *rho0,
-                                        void *stream_) {
-  DFM_REQUIRE(op && xyz && rho0, DFM_E_INVALID, "null argument");
-  DFM_REQUIRE(ns >= 1 && ns <= 65535, DFM_E_INVALID, "ns must be in 1..65535");
-  hipStream_t st = (hipStream_t)stream_;
+static dfm_status source_points_impl(dfm_op op, const double *xyz, int64_t ns, const int32_t *which, int nrhs,
+                                     double flux, double *rho0, hipStream_t st) {
   dfm_mesh m = op->mesh;
   Scratch sc;
   const int M = op->M;
@@ -308,7 +310,7 @@ extern "C" dfm_status dfm_source_points(dfm_op op, const double *xyz, int64_t ns
   TRY_SC(hipMalloc(&sc.total, sizeof(double)));
   TRY_SC(hipMalloc(&sc.idx, sizeof(int) * ns));
   TRY_SC(hipMalloc(&sc.flags, sizeof(unsigned)));
-  int64_t tot = ns * op->ndof;
+  int64_t tot = (int64_t)nrhs * op->ndof;
   hipLaunchKernelGGL(k_zero_f64, dim3(ew_grid(tot)), dim3(256), 0, st, rho0, tot);
   hipLaunchKernelGGL(k_init_found, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st, sc.idx, ns, sc.total,
                      sc.flags);
@@ -319,7 +321,7 @@ extern "C" dfm_status dfm_source_points(dfm_op op, const double *xyz, int64_t ns
   hipLaunchKernelGGL(k_locate, dim3(gx, (unsigned)ns), dim3(256), 0, st, m->tets, m->verts, m->nbr, nslot, xyz,
                      sc.idx);
   hipLaunchKernelGGL(k_point_coeffs, dim3((unsigned)((ns + 63) / 64)), dim3(64), 0, st, m->tets, m->verts, m->face,
-                     xyz, sc.idx, ns, op->P, M, op->K, op->ndof, flux, sc.ang, rho0, sc.flags);
+                     xyz, sc.idx, ns, op->P, M, op->K, op->ndof, flux, sc.ang, which, rho0, sc.flags);
   TRY_SC(hipGetLastError());
   unsigned hflags = 0;
   TRY_SC(hipMemcpyAsync(&hflags, sc.flags, sizeof(unsigned), hipMemcpyDeviceToHost, st));
@@ -327,6 +329,20 @@ extern "C" dfm_status dfm_source_points(dfm_op op, const double *xyz, int64_t ns
   sc.release();
   DFM_REQUIRE(hflags == 0u, DFM_E_INVALID, "a source point lies on no boundary face");
   return DFM_OK;
+}
+
+extern "C" dfm_status dfm_source_points(dfm_op op, const double *xyz, int64_t ns, double flux, double *rho0,
+                                        void *stream_) {
+  DFM_REQUIRE(op && xyz && rho0, DFM_E_INVALID, "null argument");
+  DFM_REQUIRE(ns >= 1 && ns <= 65535, DFM_E_INVALID, "ns must be in 1..65535");
+  return source_points_impl(op, xyz, ns, nullptr, (int)ns, flux, rho0, (hipStream_t)stream_);
+}
+
+extern "C" dfm_status dfm_source_points_sum(dfm_op op, const double *xyz, int64_t ns, const int32_t *which, int nrhs,
+                                            double flux, double *rho0, void *stream_) {
+  DFM_REQUIRE(op && xyz && which && rho0, DFM_E_INVALID, "null argument");
+  DFM_REQUIRE(ns >= 1 && ns <= 65535 && nrhs >= 1, DFM_E_INVALID, "need 1 <= ns <= 65535 and nrhs >= 1");
+  return source_points_impl(op, xyz, ns, which, nrhs, flux, rho0, (hipStream_t)stream_);
 }
 
 extern "C" dfm_status dfm_source_plane(dfm_op op, int axis, double value, int profile, const double *params,

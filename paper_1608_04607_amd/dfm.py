@@ -146,6 +146,15 @@ class Operator:
         check(_lib.load().dfm_source_points(self.handle, _ptr(xyz), ns, flux, _ptr(rho0), _stream(stream)))
         return rho0
 
+    def source_points_sum(self, xyz, which, nrhs, flux=1.0, stream=None):
+        """Point sources summed into nrhs right-hand sides: rho0[which[i]] += point i."""
+        xyz = _dev(xyz, torch.float64)
+        which = _dev(which, torch.int32)
+        rho0 = torch.empty((nrhs, self.ndof), dtype=torch.float64, device=self.device)
+        check(_lib.load().dfm_source_points_sum(self.handle, _ptr(xyz), xyz.shape[0], _ptr(which), int(nrhs), flux,
+                                                _ptr(rho0), _stream(stream)))
+        return rho0
+
     def source_plane(self, axis, value, profile=0, params=None, flux=1.0, stream=None):
         rho0 = torch.empty((self.ndof,), dtype=torch.float64, device=self.device)
         par = (C.c_double * 4)(*(params if params is not None else (0.0, 0.0, 0.0, 1.0)))

@@ -23,6 +23,7 @@ __all__ = [
     "problem_c1",
     "problem_c2",
     "problem_c3",
+    "problem_c5",
     "uniform_points_on_box_surface",
 ]
 
@@ -210,3 +211,37 @@ def problem_c3(cells=(32, 16, 16), nsrc=128, seeds=(1, 2, 3)):
         source={"kind": "points", "xyz": pts, "flux": 1.0},
         size=size,
     )
+
+
+def problem_c5(n_instances=256, seed=5, tets_range=(500, 20000)):
+    """Uneven batch: ``n_instances`` independent boxes (1, U[1,4], U[1,4]) with a
+    log-uniform target tet count T in ``tets_range``, cells n_i = max(1, round(L_i
+    (T / (6 L_x L_y L_z))^(1/3))), jitter 0.2h; per box mu ~ U[0, 0.1] (uniform
+    over the box), walls R = 0.9, P0 x Legendre of degree uniform in {4, 6, 8, 10}
+    with n = D + 4 Gauss points, 4 isotropic point sources uniform by area on its
+    boundary.  Each box is its own Problem; seeds derive from ``seed``."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n_instances):
+        size = (1.0, float(rng.uniform(1.0, 4.0)), float(rng.uniform(1.0, 4.0)))
+        T = float(np.exp(rng.uniform(np.log(tets_range[0]), np.log(tets_range[1]))))
+        h = (T / (6.0 * size[0] * size[1] * size[2])) ** (1.0 / 3.0)
+        cells = tuple(max(1, int(round(L * h))) for L in size)
+        D = int(rng.choice([4, 6, 8, 10]))
+        mu_i = float(rng.uniform(0.0, 0.1))
+        verts, tets = kuhn_box(cells, size, jitter=0.2, seed=int(rng.integers(1 << 31)))
+        pts = uniform_points_on_box_surface(size, 4, np.random.default_rng(int(rng.integers(1 << 31))))
+        out.append(Problem(
+            name=f"uneven{i}_{cells[0]}x{cells[1]}x{cells[2]}_p0_d{D}",
+            verts=verts,
+            tets=tets,
+            mu=np.full(tets.shape[0], mu_i),
+            refl=_refl_field(verts, tets, 0.9),
+            pos_order=0,
+            mom_degree=D,
+            quad_n=D + 4,
+            source={"kind": "points", "xyz": pts, "flux": 1.0},
+            size=size,
+        ))
+    return out
+
