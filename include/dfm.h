@@ -84,13 +84,14 @@ typedef struct {
   int max_iter;   /* total iteration cap (operator applications)                        */
   double rtol;    /* stop when ||rho0 - (I-B) rho||_2 <= rtol ||rho0||_2                */
   int precision;  /* 0: FP64 throughout.  1: iterative refinement with FP64 residuals of
-                        the FP64 operator around FP32 corrections on an FP32 copy of B
-                        (made on first use, kept with the operator):
+                        the stored operator (the FP32 B itself when dtype = 1) around
+                        FP32 corrections on an FP32 copy of B (made on first use, kept
+                        with the operator):
                         GMRES  -- FP32 GMRES with FP32 Krylov vectors and FP64
                                   accumulation, one right-hand side after the other;
                         Neumann -- FP32 Neumann partial sums for all nrhs right-hand
-                                  sides together, one product per term on the FP32
-                                  matrix cores (dfm_apply_f32), until the estimated
+                                  sides together, one FP32 product per term (the
+                                  kernels of dfm_apply_f32), until the estimated
                                   tail of every active series is below 1e-4.
                         The stop test is the FP64 residual in every case.               */
   int warm_start; /* 0: start from rho = 0; 1 (method 0 with precision 1 only): rho holds
@@ -163,10 +164,13 @@ dfm_status dfm_op_export(dfm_op op, double *blocks, int32_t *dest, void *stream)
  * x and y device f64 [nrhs][ndof], not aliased. */
 dfm_status dfm_apply(dfm_op op, const double *x, double *y, int nrhs, int transpose, void *stream);
 
-/* y = B32 x for nrhs right-hand sides on the FP32 matrix cores, with B32 the FP32
- * copy of B (made on first use, kept with the operator).  x and y device f32
- * [nrhs][ndof], not aliased.  Each block row (12 per tet: 3 blocks of K x K) is
- * read once per 128 right-hand sides; products accumulate in FP32.
+/* y = B32 x for nrhs right-hand sides, with B32 the FP32 copy of B (made on first
+ * use, kept with the operator; the stored B itself when dtype = 1).  x and y device
+ * f32 [nrhs][ndof], not aliased.  From 16 right-hand sides on, the product runs on
+ * the FP32 matrix cores, reading each block row (3 blocks of K x K) once per 128
+ * right-hand sides and accumulating in FP32; below 16 it streams B32 once per 4
+ * right-hand sides with FP64 accumulation.  These are the kernels of the batched
+ * Neumann solver (precision 1).
  * Errors: DFM_E_INVALID, DFM_E_NOMEM (the FP32 copy). */
 dfm_status dfm_apply_f32(dfm_op op, const float *x, float *y, int nrhs, void *stream);
 

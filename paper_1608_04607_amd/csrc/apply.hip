@@ -400,6 +400,12 @@ hipError_t spmm32(dfm_op op, const float *x, float *y, float *e, int R, hipStrea
   return hipGetLastError();
 }
 
+// y = B32 x (and e += y) with the kernel suited to R: the streaming product below
+// 16 right-hand sides, the matrix-core product from 16 on
+hipError_t product32(dfm_op op, const float *x, float *y, float *e, int R, hipStream_t st) {
+  return R >= 16 ? spmm32(op, x, y, e, R, st) : spmv32_rhs(op, x, y, e, R, st);
+}
+
 // FP32 copy of B for the mixed-precision solver (made once, kept with the operator)
 hipError_t ensure_fp32(dfm_op op, hipStream_t st) {
   if (op->B32) return hipSuccess;
@@ -451,7 +457,7 @@ extern "C" dfm_status dfm_apply_f32(dfm_op op, const float *x, float *y, int nrh
     return DFM_E_NOMEM;
   }
   DFM_HIP(e);
-  DFM_HIP(spmm32(op, x, y, nullptr, nrhs, st));
+  DFM_HIP(product32(op, x, y, nullptr, nrhs, st));
   return DFM_OK;
 }
 

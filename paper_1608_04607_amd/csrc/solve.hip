@@ -26,8 +26,7 @@ hipError_t spmv(dfm_op op, const double *x, const double *v, double *y, double a
 hipError_t spmv32(dfm_op op, const float *x, const float *v, float *y, float alpha, float beta, hipStream_t st);
 hipError_t spmv_t(dfm_op op, const double *x, const double *v, double *y, double alpha, double beta, hipStream_t st);
 hipError_t ensure_fp32(dfm_op op, hipStream_t st);
-hipError_t spmm32(dfm_op op, const float *x, float *y, float *e, int R, hipStream_t st);
-hipError_t spmv32_rhs(dfm_op op, const float *x, float *y, float *e, int R, hipStream_t st);
+hipError_t product32(dfm_op op, const float *x, float *y, float *e, int R, hipStream_t st);
 
 namespace {
 
@@ -410,9 +409,6 @@ static dfm_status solve_neumann_batched(dfm_op op, const double *rho0, double *r
   };
   // t1 = B32 t0 and e += t1: on the matrix cores for many right-hand sides, by
   // streaming the operator once per four for a few (the matrix-core tile holds 128)
-  auto product32 = [&](const float *x, float *y) -> hipError_t {
-    return R >= 16 ? spmm32(op, x, y, e32, R, st) : spmv32_rhs(op, x, y, e32, R, st);
-  };
   std::vector<double> bn(R), rn(R), rel(R, 1.0), tprev(R);
   std::vector<char> done(R, 0);
   TRYB(norms2_f64(rho0));
@@ -457,7 +453,7 @@ static dfm_status solve_neumann_batched(dfm_op op, const double *rho0, double *r
     TRYB(hipGetLastError());
     std::fill(tprev.begin(), tprev.end(), 1.0);
     while (iters < opts->max_iter) {
-      TRYB(product32(t0, t1));
+      TRYB(product32(op, t0, t1, e32, R, st));
       std::swap(t0, t1);
       ++iters;
       if (iters % CHECK) continue;
