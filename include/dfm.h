@@ -91,8 +91,10 @@ typedef struct {
                                   accumulation, one right-hand side after the other;
                         Neumann -- FP32 Neumann partial sums for all nrhs right-hand
                                   sides together, one FP32 product per term (the
-                                  kernels of dfm_apply_f32), until the estimated
-                                  tail of every active series is below 1e-4.
+                                  kernels of dfm_apply_f32), until the next term of
+                                  every active series (the residual the partial sum
+                                  leaves) is below max(1e-4, rtol |rho0| / (2 |r|))
+                                  relative to the residual |r| it started from.
                         The stop test is the FP64 residual in every case.               */
   int warm_start; /* 0: start from rho = 0; 1 (method 0 with precision 1 only): rho holds
                      the starting iterate on entry, so a solve stopped at max_iter can

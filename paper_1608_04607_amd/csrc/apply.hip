@@ -93,9 +93,11 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv(const TB *__restrict__ B,
 }
 
 // A few right-hand sides at once from one stream of the FP32 operator: as k_spmv,
-// but each thread keeps NR accumulators, the x panels of all NR right-hand sides
-// are staged in LDS, and the running Neumann sum is updated in the same pass:
-// y[r] = B32 x[r], e[r] += y[r] (x, y, e f32 [NR][ndof] at stride ndof).
+// but each thread keeps NR accumulators and the running Neumann sum is updated in
+// the same pass: y[r] = B32 x[r], e[r] += y[r] (x, y, e f32 [NR][ndof] at stride
+// ndof).  The x panels of the workgroup's block rows are staged in LDS one inbound
+// face s at a time (NR x rows x K floats), which keeps the LDS per workgroup small
+// enough for several workgroups per CU to have their loads of B in flight.
 template <int NR>
 __global__ __launch_bounds__(SPMV_THREADS) void k_spmv_rhs(const float *__restrict__ B, const int32_t *__restrict__ dest,
                                                           int64_t nthreads, int K, int Kp, int64_t ndof,
@@ -109,21 +111,12 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv_rhs(const float *__restri
   int64_t glast = g0 + SPMV_THREADS - 1;
   if (glast >= nthreads) glast = nthreads - 1;
   const int nrows_b = (int)(glast / GPB - br0 + 1);
-  const int panel = 3 * K;
-  const int per_rhs = nrows_b * panel;
-  for (int i = threadIdx.x; i < NR * per_rhs; i += SPMV_THREADS) {
-    const int r = i / per_rhs, q = i - r * per_rhs;
-    const int b = q / panel, c = q - b * panel;
-    const int s = c / K, col = c - s * K;
-    const int64_t br = br0 + b;
-    xs_rhs[i] = x[r * ndof + (4 * (br >> 2) + in_face((int)(br & 3), s)) * (int64_t)K + col];
-  }
-  __syncthreads();
+  const int per_rhs = nrows_b * K;
   const int64_t g = g0 + threadIdx.x;
-  if (g >= nthreads) return;
-  const int64_t br = g / GPB;
+  const bool active = g < nthreads;
+  const int64_t br = active ? g / GPB : br0;
   const int row0 = (int)(g - br * GPB) * 4;
-  const float *xp = xs_rhs + (br - br0) * panel;
+  const float *xp = xs_rhs + (br - br0) * K;
   const f4 *Bv = reinterpret_cast<const f4 *>(B + br * 3 * (int64_t)K * Kp + row0);
   const int cstride = Kp / 4;
   double acc[NR][4];
@@ -131,16 +124,30 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv_rhs(const float *__restri
   for (int r = 0; r < NR; ++r)
 #pragma unroll
     for (int u = 0; u < 4; ++u) acc[r][u] = 0.0;
+  for (int s = 0; s < 3; ++s) {
+    if (s) __syncthreads();  // every thread is done with the previous face's panel
+    for (int i = threadIdx.x; i < NR * per_rhs; i += SPMV_THREADS) {
+      const int r = i / per_rhs, q = i - r * per_rhs;
+      const int b = q / K, col = q - b * K;
+      const int64_t bb = br0 + b;
+      xs_rhs[i] = x[r * ndof + (4 * (bb >> 2) + in_face((int)(bb & 3), s)) * (int64_t)K + col];
+    }
+    __syncthreads();
+    if (active) {
+      const f4 *Bs = Bv + (int64_t)s * K * cstride;
 #pragma unroll 4
-  for (int c = 0; c < panel; ++c) {
-    const f4 bv = __builtin_nontemporal_load(Bv + (int64_t)c * cstride);
+      for (int c = 0; c < K; ++c) {
+        const f4 bv = __builtin_nontemporal_load(Bs + (int64_t)c * cstride);
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      const double xc = xp[r * per_rhs + c];
+        for (int r = 0; r < NR; ++r) {
+          const double xc = xp[r * per_rhs + c];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) acc[r][u] = fma((double)bv[u], xc, acc[r][u]);
+          for (int u = 0; u < 4; ++u) acc[r][u] = fma((double)bv[u], xc, acc[r][u]);
+        }
+      }
     }
   }
+  if (!active) return;
   const int64_t ob = (int64_t)dest[br] * K;
 #pragma unroll
   for (int r = 0; r < NR; ++r)
@@ -365,7 +372,7 @@ hipError_t spmv32_rhs(dfm_op op, const float *x, float *y, float *e, int R, hipS
   const int64_t rows = (SPMV_THREADS + gpb - 1) / gpb + 1;
   for (int r0 = 0; r0 < R; r0 += 4) {
     const int nr = R - r0 < 4 ? R - r0 : 4;
-    const size_t lds = sizeof(float) * (size_t)(nr * rows * 3 * op->K);
+    const size_t lds = sizeof(float) * (size_t)(nr * rows * op->K);
     const float *xr = x + (int64_t)r0 * op->ndof;
     float *yr = y + (int64_t)r0 * op->ndof;
     float *er = e ? e + (int64_t)r0 * op->ndof : nullptr;

@@ -1332,12 +1332,16 @@ hipError_t launch_t(const AsmArgs &a, size_t lds, hipStream_t st) {
 }
 
 // Instantiated kernels: (rows, cols) rectangle per wave, position pairs PQ and
-// the momentum-degree bound of the node code -- the rectangles that the layout
-// search below picks for every degree D <= 16 of both position bases.
+// the momentum-degree bound of the node code.  The first three rows are the
+// rectangles that the layout search below picks for every degree D <= 16 of both
+// position bases with the bounds 8, 12 and 16; the last row repeats the rectangles
+// of degrees 4, 6 and 10 with the degree itself as the bound, so that their node
+// code has no runtime degree guards.
 #define DFM_SHAPES(X)                                                                                \
   X(1, 1, 1, 8) X(3, 1, 1, 8) X(1, 3, 9, 8) X(1, 5, 9, 8) X(3, 4, 9, 8)                                 \
   X(2, 1, 1, 12) X(3, 2, 1, 12) X(2, 5, 9, 12) X(5, 3, 9, 12) X(3, 5, 9, 12)                           \
-  X(4, 2, 1, 16) X(3, 5, 1, 16) X(5, 3, 1, 16) X(4, 4, 9, 16) X(5, 3, 9, 16)
+  X(4, 2, 1, 16) X(3, 5, 1, 16) X(5, 3, 1, 16) X(4, 4, 9, 16) X(5, 3, 9, 16)                           \
+  X(1, 1, 1, 4) X(1, 3, 9, 4) X(1, 1, 1, 6) X(1, 5, 9, 6) X(3, 2, 1, 10) X(5, 3, 9, 10)
 #define DFM_SHAPE_ROW(r, c, pq, d) {r, c, pq, d},
 constexpr int SHAPES[][4] = {DFM_SHAPES(DFM_SHAPE_ROW)};
 constexpr int NSHAPES = sizeof(SHAPES) / sizeof(SHAPES[0]);
@@ -1533,9 +1537,14 @@ extern "C" dfm_status dfm_assemble(dfm_mesh mesh, const dfm_basis *basis, const 
   const int Mp = (M + 15) / 16 * 16;
   const int PQ = P * P;
   const int R = Mp / 16;
-  // degree bound of the node code: 8, 12 or 16 (the degree itself when it is one of them)
-  const TileLayout lay = choose_layout(R, PQ * Mp / 16, PQ, D <= 8 ? 8 : (D <= 12 ? 12 : 16));
+  // degree bound of the node code: 8, 12 or 16, or the degree itself where its
+  // rectangle is instantiated with that bound (no runtime degree guards then)
+  TileLayout lay = choose_layout(R, PQ * Mp / 16, PQ, D <= 8 ? 8 : (D <= 12 ? 12 : 16));
   DFM_REQUIRE(lay.shape >= 0, DFM_E_UNSUPPORTED, "no contraction layout for this basis size");
+  for (int k = 0; k < NSHAPES; ++k)
+    if (SHAPES[k][0] == SHAPES[lay.shape][0] && SHAPES[k][1] == SHAPES[lay.shape][1] && SHAPES[k][2] == PQ &&
+        SHAPES[k][3] == D)
+      lay.shape = k;
   // nodes per chunk: two halves of 64 when the LDS allows
   int chunk;
   size_t lds;

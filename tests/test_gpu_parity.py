@@ -104,6 +104,11 @@ CASES = [
     ("box2-p0-zern5-n6-paper", (2, 0.2), 0.05, oa.Basis(0, 1, 5, 6, oq.PAPER_RULE)),
     ("box2-p1-zern3-n4-seam-bigmu", (2, 0.1), 9.0, oa.Basis(1, 1, 3, 4, oq.SEAM_RULE)),
     ("box1-p0-leg7-n3-paper-bigmu", (1, 0.1), 6.0, oa.Basis(0, 0, 7, 3, oq.PAPER_RULE)),
+    # degrees whose node code is compiled for the degree itself (4 above, 6, 8, 10)
+    ("box1-p1-leg6-n4-seam", (1, 0.1), 0.2, oa.Basis(1, 0, 6, 4, oq.SEAM_RULE)),
+    ("box1-p0-leg10-n6-seam", (1, 0.1), 0.1, oa.Basis(0, 0, 10, 6, oq.SEAM_RULE)),
+    ("box1-p1-leg10-n4-paper", (1, 0.1), 0.1, oa.Basis(1, 0, 10, 4, oq.PAPER_RULE)),
+    ("box1-p0-zern10-n5-seam", (1, 0.2), 0.4, oa.Basis(0, 1, 10, 5, oq.SEAM_RULE)),
 ]
 
 
@@ -275,7 +280,7 @@ def test_batched_mixed_neumann_warm_start(small):
         assert rel(rho[r].cpu().numpy(), osv.solve_direct(A, rhs[r])) < 1e-7
 
 
-@pytest.mark.parametrize("order,family,degree", [(1, 0, 8), (0, 1, 6)])
+@pytest.mark.parametrize("order,family,degree", [(1, 0, 8), (0, 1, 6), (0, 0, 10), (0, 0, 4)])
 def test_fp32_assembly_matches_oracle(order, family, degree):
     """dtype 1: contraction on the FP32 matrix cores, B stored in FP32 -- blocks within
     1e-5 of the oracle (relative to the largest entry), and the mixed solves refine
