@@ -101,16 +101,18 @@ def cpu_baseline(prob, rule, ntets, label="3072-tet box"):
 # --------------------------------------------------------------------------- HBM byte counters
 
 COUNTERS = os.path.join(ROOT, "profiles", "counters_box8x8x8_P1_D8_n12.txt")
+COUNTERS_UNEVEN = os.path.join(ROOT, "profiles", "counters_uneven16_D10group.txt")
 
 
-def measured_traffic(label):
+def measured_traffic(label, path=COUNTERS, field="bytes"):
     """HBM bytes per launch of a kernel from the committed rocprofv3 byte counters
-    (FETCH_SIZE / WRITE_SIZE scaled by a plain-copy calibration), or None when the
-    kernel's source file changed since the counters were taken."""
+    (FETCH_SIZE / WRITE_SIZE scaled by a plain-copy calibration), or their ratio to
+    the algorithmic bytes (field="ratio"), or None when the kernel's source file
+    changed since the counters were taken."""
     import hashlib
-    if not os.path.exists(COUNTERS):
+    if not os.path.exists(path):
         return None
-    for line in open(COUNTERS):
+    for line in open(path):
         if not line.startswith("kernel="):
             continue
         kv = dict(tok.split("=", 1) for tok in line.split())
@@ -119,7 +121,7 @@ def measured_traffic(label):
         src = os.path.join(ROOT, kv["source"])
         if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != kv["sha256"]:
             return None
-        return float(kv["bytes"])
+        return float(kv[field])
     return None
 
 
@@ -494,6 +496,20 @@ def main_uneven(args):
     def ev():
         return torch.cuda.Event(enable_timing=True)
 
+    if args.kernels_only:
+        # the largest group only: FP32 assembly and five 4-rhs streaming products
+        batch = UnevenBatch(probs, rule=rule, dtype=1)
+        g = max(batch.groups, key=lambda g: g.tet_offsets[-1] * (g.key[2] + 1) ** 4)
+        batch.assemble(g)
+        x32 = g.rho0.float()
+        for _ in range(5):
+            g.op.apply_f32(x32)
+        torch.cuda.synchronize()
+        print(json.dumps({"kernels_only": True, "workload": f"uneven-{len(probs)}", "degree": g.key[2],
+                          "boxes": len(g.members), "tets": g.mesh.nt, "K": g.op.K, "nrhs": g.nsrc,
+                          "B_bytes": g.op.nbytes, "product_bytes": g.op.nbytes + 16.0 * g.nsrc * g.op.ndof}))
+        return
+
     def run(batch, label):
         """Every group once; per group (mesh+assembly, sources, solve) ms and stats."""
         rows = []
@@ -582,9 +598,12 @@ def main_uneven(args):
     t_src = sum(r["ms_sources"] for r in rows)
     t_solve = sum(r["ms_solve"] for r in rows)
     nrhs = sum(r["boxes"] * r["nrhs"] for r in rows)
-    big = max(rows, key=lambda r: r["B_bytes"])
-    prod_bytes = big["B_bytes"] + 16.0 * big["nrhs"] * 4 * big["tets"] * big["K"]
-    prod_gbs = prod_bytes / (big["ms_product"] / 1e3) / 1e9
+    # the streaming product over all groups, weighted by the launches each solve made
+    pb = [r["B_bytes"] + 16.0 * r["nrhs"] * 4 * r["tets"] * r["K"] for r in rows]
+    n_l = sum(r["products"] for r in rows)
+    prod_bytes = sum(r["products"] * b for r, b in zip(rows, pb)) / n_l
+    prod_ms = sum(r["products"] * r["ms_product"] for r in rows) / n_l
+    prod_gbs = prod_bytes / (prod_ms / 1e3) / 1e9
     flops_asm = sum(2.0 * r["nodes"] * r["K"] ** 2 for r in rows)
     for r in rows:
         r.pop("rho", None)
@@ -619,9 +638,13 @@ def main_uneven(args):
         "rel_diff_vs_fp64_sampled": worst_diff,
         "roofline": {"kernel": "k_spmv_rhs<4>", "bound": "hbm", "achieved": prod_gbs, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": prod_gbs / HBM_PEAK_GBS, "traffic": None,
-                     "algorithmic": f"B32 bytes + 16*R*ndof (x, y, e read+write in fp32) per launch, degree "
-                                    f"{big['degree']} group: {prod_bytes:.3e} B",
-                     "ms_per_launch": big["ms_product"]},
+                     "algorithmic": "B32 bytes + 16*R*ndof (x, y, e read+write in fp32) per launch, R = 4; "
+                                    f"mean over the {n_l} launches of the solves: {prod_bytes:.3e} B",
+                     "ms_per_launch": prod_ms,
+                     "traffic_ratio_small_group": measured_traffic("k_spmv_rhs4", COUNTERS_UNEVEN, "ratio"),
+                     "traffic_note": "traffic is not measured at this size; traffic_ratio_small_group is HBM bytes / "
+                                     "algorithmic bytes of the same kernel on the degree-10 group of the first 16 boxes",
+                     "per_group_GBs": {f"D{r['degree']}": b / r["ms_product"] / 1e6 for r, b in zip(rows, pb)}},
         "cpu_baseline": base,
     }
     print(json.dumps(out))
