@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--instances", type=int, default=256, help="uneven: number of boxes")
     ap.add_argument("--fp64-sample", type=int, default=2,
                     help="uneven: boxes per degree solved one by one in plain FP64 for the comparison")
-    ap.add_argument("--restart", type=int, default=50)
+    ap.add_argument("--restart", type=int, default=100)
     ap.add_argument("--cpu-tets", type=int, default=24, help="tets in the oracle's timed sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calib", action="store_true", help="only run a plain device copy of known size")

@@ -9,8 +9,11 @@
 // corrections are FP32 Neumann partial sums e = sum_k B32^k (r/|r|), one batched
 // product for all right-hand sides per term on the FP32 matrix cores, refined
 // with FP64 residuals of the FP64 operator.
-// The host drives the iterations; every vector operation and every product with
-// B runs on the GPU.
+// GMRES builds its Arnoldi basis with B itself (same Krylov space as I - B, and
+// w = B v keeps most of its norm outside the basis, so the second Gram-Schmidt
+// pass is rarely needed); the Hessenberg update, the Givens rotations and the
+// residual estimate run on the device, and the host reads the estimate every few
+// steps.  Every vector operation and every product with B runs on the GPU.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -30,59 +33,112 @@ hipError_t product32(dfm_op op, const float *x, float *y, float *e, int R, hipSt
 
 namespace {
 
+#ifndef DFM_DOT_BLOCKS
+#define DFM_DOT_BLOCKS 1024
+#endif
+#ifndef DFM_DOT_VC
+#define DFM_DOT_VC 16
+#endif
 constexpr int RED_BLOCKS = 2048;
+constexpr int DOT_BLOCKS = DFM_DOT_BLOCKS;  // partial sums per vector of the Krylov dot products
 constexpr int RED_THREADS = 256;
 constexpr int NWAVE = RED_THREADS / 64;
 constexpr int MAXV = 201;
+constexpr int VC = DFM_DOT_VC;  // vectors per register sweep of k_multidot
+static_assert(DOT_BLOCKS <= RED_BLOCKS, "the partial-sum buffer holds RED_BLOCKS sums per vector");
 
-// partial[i][blk] = sum over this block's rows of V[i][row] * w[row], i < nvec.
-// Each thread keeps a slice of w in registers, so V is read exactly once.
-template <typename T>
+// VW consecutive elements of one vector: a 16-byte load when VW > 1 (the caller
+// checks alignment and n % VW == 0)
+template <typename T, int VW>
+__device__ inline void load_rows(const T *__restrict__ p, int64_t r, double (&o)[VW]) {
+  if constexpr (VW == 1) {
+    o[0] = (double)p[r];
+  } else {
+    typedef T vt __attribute__((ext_vector_type(VW)));
+    const vt v = *reinterpret_cast<const vt *>(p + r * VW);
+#pragma unroll
+    for (int u = 0; u < VW; ++u) o[u] = (double)v[u];
+  }
+}
+
+template <typename T, int VW>
+__device__ inline void store_rows(T *__restrict__ p, int64_t r, const double (&o)[VW]) {
+  if constexpr (VW == 1) {
+    p[r] = (T)o[0];
+  } else {
+    typedef T vt __attribute__((ext_vector_type(VW)));
+    vt v;
+#pragma unroll
+    for (int u = 0; u < VW; ++u) v[u] = (T)o[u];
+    *reinterpret_cast<vt *>(p + r * VW) = v;
+  }
+}
+
+// partial[i][blk] = sum over this block's rows of V[i][row] * w[row] for i < nvec,
+// and partial[nvec][blk] the same for `extra` when it is given.  Each thread keeps
+// VC accumulators in registers over all of its rows (VW rows per 16-byte load), and
+// the wave and block reductions run once per VC vectors.  Nothing is written when
+// `gate` is given and zero (a second Gram-Schmidt pass that is not needed).
+template <typename T, int VW>
 __global__ __launch_bounds__(RED_THREADS) void k_multidot(const T *__restrict__ V, int64_t ldv, int nvec,
                                                         const T *__restrict__ extra, const T *__restrict__ w,
-                                                        int64_t n, double *__restrict__ partial) {
-  // vectors 0..nvec-1 are V[i], vector nvec (when extra != null) is `extra`
-  if (extra) ++nvec;
-  constexpr int RPT = 8;  // rows per thread kept in registers per sweep
-  __shared__ double red[NWAVE][64];
+                                                        int64_t n, double *__restrict__ partial,
+                                                        const int *__restrict__ gate) {
+  if (gate && !*gate) return;
+  __shared__ double red[NWAVE][VC + 1];
+  const int64_t nr = n / VW;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t r0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int i0 = 0; i0 < nvec; i0 += 64) {
-    const int ni = min(64, nvec - i0);
-    double accs = 0.0;  // lane l keeps the wave's sum for vector i0 + l
-    for (int64_t base = r0; base < n; base += stride * RPT) {
-      double wr[RPT];
+  const int nchunks = nvec > 0 ? (nvec + VC - 1) / VC : 1;
+  for (int c = 0; c < nchunks; ++c) {
+    const int i0 = c * VC;
+    const int ni = min(VC, nvec - i0);
+    const bool ex = extra != nullptr && c == 0;
+    double acc[VC + 1];
 #pragma unroll
-      for (int u = 0; u < RPT; ++u) {
-        int64_t r = base + u * stride;
-        wr[u] = r < n ? (double)w[r] : 0.0;
-      }
-      for (int i = 0; i < ni; ++i) {
-        const T *vi = (extra && i0 + i == nvec - 1) ? extra : V + (int64_t)(i0 + i) * ldv;
-        double a = 0.0;
+    for (int i = 0; i <= VC; ++i) acc[i] = 0.0;
+    for (int64_t r = r0; r < nr; r += stride) {
+      double wr[VW], vr[VW];
+      load_rows<T, VW>(w, r, wr);
 #pragma unroll
-        for (int u = 0; u < RPT; ++u) {
-          int64_t r = base + u * stride;
-          if (r < n) a = fma((double)vi[r], wr[u], a);
+      for (int i = 0; i < VC; ++i)
+        if (i < ni) {
+          load_rows<T, VW>(V + (int64_t)(i0 + i) * ldv, r, vr);
+#pragma unroll
+          for (int u = 0; u < VW; ++u) acc[i] = fma(vr[u], wr[u], acc[i]);
         }
-        for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
-        if (lane == i) accs += a;
+      if (ex) {
+        load_rows<T, VW>(extra, r, vr);
+#pragma unroll
+        for (int u = 0; u < VW; ++u) acc[VC] = fma(vr[u], wr[u], acc[VC]);
       }
     }
-    red[wv][lane] = accs;
+#pragma unroll
+    for (int i = 0; i <= VC; ++i) {
+      if (i < ni || (i == VC && ex)) {
+        double a = acc[i];
+        for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+        if (lane == 0) red[wv][i] = a;
+      }
+    }
     __syncthreads();
-    if (threadIdx.x < ni) {
-      double s = 0.0;
-      for (int k = 0; k < NWAVE; ++k) s += red[k][threadIdx.x];
-      partial[(int64_t)(i0 + threadIdx.x) * gridDim.x + blockIdx.x] = s;
+    if (threadIdx.x <= VC) {
+      const int i = threadIdx.x;
+      if (i < ni || (i == VC && ex)) {
+        double s = 0.0;
+        for (int k = 0; k < NWAVE; ++k) s += red[k][i];
+        partial[(int64_t)(i < VC ? i0 + i : nvec) * gridDim.x + blockIdx.x] = s;
+      }
     }
     __syncthreads();
   }
 }
 
-// out[i] = sum_b partial[i][b]
-__global__ void k_reduce_partials(const double *__restrict__ partial, int nb, double *__restrict__ out) {
+// out[i] = sum_b partial[i][b] (nothing when `gate` is given and zero)
+__global__ void k_reduce_partials(const double *__restrict__ partial, int nb, double *__restrict__ out,
+                                  const int *__restrict__ gate) {
+  if (gate && !*gate) return;
   __shared__ double red[NWAVE];
   int i = blockIdx.x;
   double acc = 0.0;
@@ -98,22 +154,36 @@ __global__ void k_reduce_partials(const double *__restrict__ partial, int nb, do
 }
 
 // w[row] += sign * sum_i V[i][row] * h[i]; when partial != null also the block
-// partial sums of ||w_new||^2 (grid-stride, RED_BLOCKS blocks)
-template <typename T>
+// partial sums of ||w_new||^2 (grid-stride, RED_BLOCKS blocks).  Nothing is done
+// when `gate` is given and zero.
+template <typename T, int VW>
 __global__ __launch_bounds__(RED_THREADS) void k_combine(const T *__restrict__ V, int64_t ldv, int nvec,
                                                        const double *__restrict__ h, double sign, T *__restrict__ w,
-                                                       int64_t n, double *__restrict__ partial) {
+                                                       int64_t n, double *__restrict__ partial,
+                                                       const int *__restrict__ gate) {
+  if (gate && !*gate) return;
   __shared__ double hs[MAXV];
   __shared__ double red[NWAVE];
   for (int i = threadIdx.x; i < nvec; i += blockDim.x) hs[i] = h[i];
   __syncthreads();
   double nrm = 0.0;
-  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
-    double acc = 0.0;
-    for (int i = 0; i < nvec; ++i) acc = fma((double)V[(int64_t)i * ldv + r], hs[i], acc);
-    T nw = (T)fma(sign, acc, (double)w[r]);
-    w[r] = nw;
-    nrm = fma((double)nw, (double)nw, nrm);
+  const int64_t nr = n / VW;
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < nr; r += (int64_t)gridDim.x * blockDim.x) {
+    double acc[VW], vr[VW], wr[VW];
+#pragma unroll
+    for (int u = 0; u < VW; ++u) acc[u] = 0.0;
+    for (int i = 0; i < nvec; ++i) {
+      load_rows<T, VW>(V + (int64_t)i * ldv, r, vr);
+#pragma unroll
+      for (int u = 0; u < VW; ++u) acc[u] = fma(vr[u], hs[i], acc[u]);
+    }
+    load_rows<T, VW>(w, r, wr);
+#pragma unroll
+    for (int u = 0; u < VW; ++u) {
+      wr[u] = (double)(T)fma(sign, acc[u], wr[u]);
+      nrm = fma(wr[u], wr[u], nrm);
+    }
+    store_rows<T, VW>(w, r, wr);
   }
   if (!partial) return;
   for (int off = 32; off > 0; off >>= 1) nrm += __shfl_down(nrm, off, 64);
@@ -126,17 +196,82 @@ __global__ __launch_bounds__(RED_THREADS) void k_combine(const T *__restrict__ V
   }
 }
 
+// Device scalars of the GMRES cycle (Ctx::dsc): [0] norm scratch, [1] ||w||^2
+// after orthogonalisation, [2] ||w|| that scales the next basis vector, [3] the
+// Arnoldi estimate |g_{k+1}| / ||b|| of the relative residual, [4] valid basis
+// columns of the cycle, [5] breakdown (||w|| = 0) seen in this cycle.
+constexpr int DS_NRM = 1, DS_HN = 2, DS_REL = 3, DS_NCOL = 4, DS_BRK = 5, DS_H1 = 8;
+
+// second Gram-Schmidt pass needed: the first lost more than 30 % of ||w||
+__global__ void k_reorth_gate(const double *__restrict__ before2, const double *__restrict__ dsc,
+                              int *__restrict__ gate) {
+  *gate = sqrt(dsc[DS_NRM]) < 0.7 * sqrt(*before2) ? 1 : 0;
+}
+
+// start of a cycle: g = (beta, 0, ...), no breakdown, no columns
+__global__ void k_cycle_init(double *__restrict__ g, int m, double beta, double *__restrict__ dsc) {
+  for (int i = threadIdx.x; i <= m; i += blockDim.x) g[i] = i == 0 ? beta : 0.0;
+  if (threadIdx.x == 0) {
+    dsc[DS_BRK] = 0.0;
+    dsc[DS_NCOL] = 0.0;
+  }
+}
+
+// Arnoldi step k on the device.  The basis is built with B (the Krylov spaces of
+// B and I - B coincide): B v_k = V h + ||w|| v_{k+1} with h = h1 (+ h2 after a
+// second pass), so column k of the Hessenberg matrix of I - B is e_k - h with
+// entry -||w|| below the diagonal.  The rotations of the earlier columns are
+// applied, a new Givens rotation zeroes the subdiagonal entry, and the rotated
+// right-hand side g and the residual estimate are updated.  After a breakdown
+// the cycle's later steps change nothing.
+__global__ void k_arnoldi(int k, int m, double bnorm, const double *__restrict__ h1, const double *__restrict__ h2,
+                          const int *__restrict__ gate, double *__restrict__ dsc, double *__restrict__ H,
+                          double *__restrict__ cs, double *__restrict__ sn, double *__restrict__ g) {
+  if (dsc[DS_BRK] != 0.0) return;
+  double *col = H + (int64_t)k * (m + 1);
+  const bool two = *gate != 0;
+  for (int i = 0; i <= k; ++i) col[i] = (i == k ? 1.0 : 0.0) - (h1[i] + (two ? h2[i] : 0.0));
+  const double hn = sqrt(dsc[DS_NRM]);
+  col[k + 1] = -hn;
+  for (int i = 0; i < k; ++i) {
+    const double a = col[i], b = col[i + 1];
+    col[i] = cs[i] * a + sn[i] * b;
+    col[i + 1] = -sn[i] * a + cs[i] * b;
+  }
+  const double a = col[k], b = col[k + 1];
+  const double rr = hypot(a, b);
+  cs[k] = rr > 0.0 ? a / rr : 1.0;
+  sn[k] = rr > 0.0 ? b / rr : 0.0;
+  col[k] = rr;
+  col[k + 1] = 0.0;
+  g[k + 1] = -sn[k] * g[k];
+  g[k] = cs[k] * g[k];
+  dsc[DS_HN] = hn;
+  dsc[DS_REL] = fabs(g[k + 1]) / bnorm;
+  dsc[DS_NCOL] = (double)(k + 1);
+  if (!(hn > 0.0)) dsc[DS_BRK] = 1.0;
+}
+
+// y = x / s with s on the device (zero when s is not positive)
+template <typename T>
+__global__ void k_scale_dev(const T *__restrict__ x, const double *__restrict__ s, T *__restrict__ y, int64_t n) {
+  const double d = *s;
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
+    y[r] = d > 0.0 ? (T)((double)x[r] / d) : (T)0;
+}
+
 template <typename T>
 __global__ void k_scale_by(const T *__restrict__ x, double s, T *__restrict__ y, int64_t n) {
   for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
     y[r] = (T)((double)x[r] / s);
 }
 
-// y = a * x + b * y
+// y = a * x + b * y (y is not read when b == 0: it may be uninitialised memory,
+// and 0 * NaN would not vanish)
 template <typename TX, typename TY>
 __global__ void k_axpby(double a, const TX *__restrict__ x, double b, TY *__restrict__ y, int64_t n) {
   for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
-    y[r] = (TY)fma(a, (double)x[r], b * (double)y[r]);
+    y[r] = (TY)(b == 0.0 ? a * (double)x[r] : fma(a, (double)x[r], b * (double)y[r]));
 }
 
 template <typename TX, typename TY>
@@ -151,33 +286,52 @@ __global__ void k_zero(T *__restrict__ y, int64_t n) {
     y[r] = (T)0;
 }
 
+inline bool al16(const void *p) { return ((uintptr_t)p & 15) == 0; }
+
 struct Ctx {
   dfm_op op;
   hipStream_t st;
   bool transpose = false;  // solve (I - B)^T x = b (FP64 only)
   int64_t n;
   double *partial = nullptr;  // [MAXV][RED_BLOCKS]
-  double *dsc = nullptr;      // device scalars
+  double *dsc = nullptr;      // device scalars (DS_*), then the GMRES cycle arrays
+  int *gate = nullptr;        // device flag of the second Gram-Schmidt pass
   unsigned grid() const { return ew_grid(n); }
+  // 16-byte loads when every vector and the leading dimension allow them
+  template <typename T>
+  bool wide(const T *V, int64_t ldv, const T *w, const T *extra) const {
+    constexpr int VW = 16 / sizeof(T);
+    return n % VW == 0 && (ldv * (int64_t)sizeof(T)) % 16 == 0 && al16(V) && al16(w) && (!extra || al16(extra));
+  }
   // out[0..nvec) = V^T w, and out[nvec] = extra . w when extra != null (device)
   template <typename T>
-  hipError_t dots(const T *V, int64_t ldv, int nvec, const T *w, double *out, const T *extra = nullptr) {
+  hipError_t dots(const T *V, int64_t ldv, int nvec, const T *w, double *out, const T *extra = nullptr,
+                  const int *g = nullptr) {
     int nout = nvec + (extra ? 1 : 0);
-    hipLaunchKernelGGL(k_multidot<T>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, st, V, ldv, nvec, extra, w, n, partial);
-    hipLaunchKernelGGL(k_reduce_partials, dim3(nout), dim3(RED_THREADS), 0, st, partial, RED_BLOCKS, out);
+    constexpr int VW = 16 / sizeof(T);
+    if (wide<T>(V, ldv, w, extra))
+      hipLaunchKernelGGL((k_multidot<T, VW>), dim3(DOT_BLOCKS), dim3(RED_THREADS), 0, st, V, ldv, nvec, extra, w, n,
+                         partial, g);
+    else
+      hipLaunchKernelGGL((k_multidot<T, 1>), dim3(DOT_BLOCKS), dim3(RED_THREADS), 0, st, V, ldv, nvec, extra, w, n,
+                         partial, g);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(nout), dim3(RED_THREADS), 0, st, partial, DOT_BLOCKS, out, g);
     return hipGetLastError();
   }
   // w += sign V h; *nrm2_out = ||w||^2 (device) when nrm2_out != null
   template <typename T>
-  hipError_t combine(const T *V, int64_t ldv, int nvec, const double *h, double sign, T *w, double *nrm2_out) {
-    if (nrm2_out) {
-      hipLaunchKernelGGL(k_combine<T>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, st, V, ldv, nvec, h, sign, w, n,
-                         partial);
-      hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(RED_THREADS), 0, st, partial, RED_BLOCKS, nrm2_out);
-    } else {
-      hipLaunchKernelGGL(k_combine<T>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, st, V, ldv, nvec, h, sign, w, n,
-                         (double *)nullptr);
-    }
+  hipError_t combine(const T *V, int64_t ldv, int nvec, const double *h, double sign, T *w, double *nrm2_out,
+                     const int *g = nullptr) {
+    constexpr int VW = 16 / sizeof(T);
+    double *part = nrm2_out ? partial : nullptr;
+    if (wide<T>(V, ldv, w, nullptr))
+      hipLaunchKernelGGL((k_combine<T, VW>), dim3(RED_BLOCKS), dim3(RED_THREADS), 0, st, V, ldv, nvec, h, sign, w, n,
+                         part, g);
+    else
+      hipLaunchKernelGGL((k_combine<T, 1>), dim3(RED_BLOCKS), dim3(RED_THREADS), 0, st, V, ldv, nvec, h, sign, w, n,
+                         part, g);
+    if (nrm2_out)
+      hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(RED_THREADS), 0, st, partial, RED_BLOCKS, nrm2_out, g);
     return hipGetLastError();
   }
   template <typename T>
@@ -198,7 +352,12 @@ struct Ctx {
     return transpose ? spmv_t(op, x, nullptr, y, 0.0, 1.0, st) : spmv(op, x, nullptr, y, 0.0, 1.0, st);
   }
   hipError_t apply_ImB(const float *x, float *y) { return spmv32(op, x, x, y, 1.0f, -1.0f, st); }
+  hipError_t apply_B(const float *x, float *y) { return spmv32(op, x, nullptr, y, 0.0f, 1.0f, st); }
 };
+
+// doubles of Ctx::dsc: scalars, h1 and h2 (MAXV + 1 each), H ((MAXV + 1) x MAXV),
+// cs, sn (MAXV each), g (MAXV + 1)
+constexpr size_t DSC_DOUBLES = DS_H1 + 2 * (MAXV + 1) + (size_t)(MAXV + 1) * MAXV + 2 * MAXV + (MAXV + 1);
 
 // GMRES(m) on (I - B) x = b with x0 = 0, vectors of type T.  Stops when the
 // relative residual is <= rtol: the true residual when check_true (FP64 solves),
@@ -251,17 +410,23 @@ __global__ void k_zero_f64(double *__restrict__ y, int n) {
 template <typename T>
 hipError_t gmres(Ctx &c, const T *b, T *x, T *V, T *w, T *t, int m, double rtol, int max_iter, bool check_true,
                  int &its, int &restarts, double &rel, bool &done) {
+  // the residual estimate is read back every CHK steps; the steps in between are
+  // queued without a host round trip (extra steps only enlarge the Krylov space)
+  constexpr int CHK = 8;
   const unsigned G = c.grid();
   const int64_t n = c.n;
-  const int nvmax = m + 1;
-  double *h1 = c.dsc + 8, *h2 = c.dsc + 8 + nvmax;
-  std::vector<double> hh(2 * nvmax + 8);
+  double *h1 = c.dsc + DS_H1, *h2 = h1 + (MAXV + 1);
+  double *Hd = h2 + (MAXV + 1), *csd = Hd + (size_t)(MAXV + 1) * MAXV, *snd = csd + MAXV, *gd = snd + MAXV;
   double bnorm;
   hipError_t e = c.norm2<T>(b, bnorm);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_zero<T>, dim3(G), dim3(256), 0, c.st, x, n);
   done = false;
   rel = 1.0;
+  if (!std::isfinite(bnorm)) {
+    rel = bnorm;  // reported as a non-finite residual
+    return hipGetLastError();
+  }
   if (!(bnorm > 0.0)) {
     done = true;
     rel = 0.0;
@@ -269,64 +434,51 @@ hipError_t gmres(Ctx &c, const T *b, T *x, T *V, T *w, T *t, int m, double rtol,
   }
   hipLaunchKernelGGL((k_copy<T, T>), dim3(G), dim3(256), 0, c.st, b, w, n);
   double beta = bnorm;
-  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  std::vector<double> H((size_t)(m + 1) * m), g(m + 1), y(m), hs(8);
   while (!done && its < max_iter) {
     hipLaunchKernelGGL(k_scale_by<T>, dim3(G), dim3(256), 0, c.st, w, beta, V, n);
-    std::fill(g.begin(), g.end(), 0.0);
-    g[0] = beta;
-    int k = 0;
-    for (; k < m && its < max_iter; ++k) {
+    hipLaunchKernelGGL(k_cycle_init, dim3(1), dim3(256), 0, c.st, gd, m, beta, c.dsc);
+    for (int k = 0; k < m && its < max_iter; ++k) {
       T *vk = V + (int64_t)k * n;
-      if ((e = c.apply_ImB(vk, w)) != hipSuccess) return e;
+      if ((e = c.apply_B(vk, w)) != hipSuccess) return e;
       its++;
       // classical Gram-Schmidt: one pass for V^T w and ||w||^2, one for w -= V h
-      // and ||w||^2; a second pass when the first lost > 30 % of ||w||
+      // and ||w||^2; a second pass, decided on the device, when the first lost
+      // more than 30 % of ||w||
       if ((e = c.dots<T>(V, n, k + 1, w, h1, w)) != hipSuccess) return e;  // h1[k+1] = ||w||^2
-      if ((e = c.combine<T>(V, n, k + 1, h1, -1.0, w, c.dsc + 1)) != hipSuccess) return e;
-      if ((e = hipMemcpyAsync(hh.data(), c.dsc, sizeof(double) * (8 + nvmax), hipMemcpyDeviceToHost, c.st)))
-        return e;
-      if ((e = hipStreamSynchronize(c.st)) != hipSuccess) return e;
-      double before = std::sqrt(hh[8 + k + 1]), hn = std::sqrt(hh[1]);
-      for (int i = 0; i <= k; ++i) H[(size_t)i * m + k] = hh[8 + i];
-      if (hn < 0.7 * before) {
-        if ((e = c.dots<T>(V, n, k + 1, w, h2)) != hipSuccess) return e;
-        if ((e = c.combine<T>(V, n, k + 1, h2, -1.0, w, c.dsc + 1)) != hipSuccess) return e;
-        if ((e = hipMemcpyAsync(hh.data() + 1, c.dsc + 1, sizeof(double), hipMemcpyDeviceToHost, c.st))) return e;
-        if ((e = hipMemcpyAsync(hh.data() + 8 + nvmax, h2, sizeof(double) * (k + 1), hipMemcpyDeviceToHost, c.st)))
-          return e;
+      if ((e = c.combine<T>(V, n, k + 1, h1, -1.0, w, c.dsc + DS_NRM)) != hipSuccess) return e;
+      hipLaunchKernelGGL(k_reorth_gate, dim3(1), dim3(1), 0, c.st, h1 + k + 1, c.dsc, c.gate);
+      if ((e = c.dots<T>(V, n, k + 1, w, h2, nullptr, c.gate)) != hipSuccess) return e;
+      if ((e = c.combine<T>(V, n, k + 1, h2, -1.0, w, c.dsc + DS_NRM, c.gate)) != hipSuccess) return e;
+      hipLaunchKernelGGL(k_arnoldi, dim3(1), dim3(1), 0, c.st, k, m, bnorm, h1, h2, c.gate, c.dsc, Hd, csd, snd, gd);
+      hipLaunchKernelGGL(k_scale_dev<T>, dim3(G), dim3(256), 0, c.st, w, c.dsc + DS_HN, V + (int64_t)(k + 1) * n, n);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      if ((k + 1) % CHK == 0 || k + 1 == m || its >= max_iter) {
+        if ((e = hipMemcpyAsync(hs.data(), c.dsc, sizeof(double) * 8, hipMemcpyDeviceToHost, c.st))) return e;
         if ((e = hipStreamSynchronize(c.st)) != hipSuccess) return e;
-        hn = std::sqrt(hh[1]);
-        for (int i = 0; i <= k; ++i) H[(size_t)i * m + k] += hh[8 + nvmax + i];
-      }
-      H[(size_t)(k + 1) * m + k] = hn;
-      if (hn > 0.0) hipLaunchKernelGGL(k_scale_by<T>, dim3(G), dim3(256), 0, c.st, w, hn, V + (int64_t)(k + 1) * n, n);
-      for (int i = 0; i < k; ++i) {
-        double a = H[(size_t)i * m + k], cc = H[(size_t)(i + 1) * m + k];
-        H[(size_t)i * m + k] = cs[i] * a + sn[i] * cc;
-        H[(size_t)(i + 1) * m + k] = -sn[i] * a + cs[i] * cc;
-      }
-      double a = H[(size_t)k * m + k], cc = H[(size_t)(k + 1) * m + k];
-      double rr = std::hypot(a, cc);
-      cs[k] = rr > 0.0 ? a / rr : 1.0;
-      sn[k] = rr > 0.0 ? cc / rr : 0.0;
-      H[(size_t)k * m + k] = rr;
-      H[(size_t)(k + 1) * m + k] = 0.0;
-      g[k + 1] = -sn[k] * g[k];
-      g[k] = cs[k] * g[k];
-      rel = std::fabs(g[k + 1]) / bnorm;
-      if (!std::isfinite(rel)) return hipSuccess;
-      if (rel <= (check_true ? 0.5 : 1.0) * rtol || hn == 0.0) {
-        ++k;
-        break;
+        rel = hs[DS_REL];
+        if (!std::isfinite(rel)) return hipSuccess;
+        if (rel <= (check_true ? 0.5 : 1.0) * rtol || hs[DS_BRK] != 0.0) break;
       }
     }
+    // the columns of this cycle: R (rotated H) and g from the device
+    if ((e = hipMemcpyAsync(hs.data(), c.dsc, sizeof(double) * 8, hipMemcpyDeviceToHost, c.st))) return e;
+    if ((e = hipMemcpyAsync(H.data(), Hd, sizeof(double) * (m + 1) * m, hipMemcpyDeviceToHost, c.st))) return e;
+    if ((e = hipMemcpyAsync(g.data(), gd, sizeof(double) * (m + 1), hipMemcpyDeviceToHost, c.st))) return e;
+    if ((e = hipStreamSynchronize(c.st)) != hipSuccess) return e;
+    const int k = (int)hs[DS_NCOL];
+    rel = hs[DS_REL];
+    if (!std::isfinite(rel)) return hipSuccess;
+    // back substitution R y = g (column j of R at H[j (m + 1) ...])
     for (int i = k - 1; i >= 0; --i) {
       double s = g[i];
-      for (int l = i + 1; l < k; ++l) s -= H[(size_t)i * m + l] * y[l];
-      y[i] = s / H[(size_t)i * m + i];
+      for (int l = i + 1; l < k; ++l) s -= H[(size_t)l * (m + 1) + i] * y[l];
+      y[i] = s / H[(size_t)i * (m + 1) + i];
     }
-    if ((e = hipMemcpyAsync(h1, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, c.st))) return e;
-    if ((e = c.combine<T>(V, n, k, h1, 1.0, x, nullptr)) != hipSuccess) return e;
+    if (k > 0) {
+      if ((e = hipMemcpyAsync(h1, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, c.st))) return e;
+      if ((e = c.combine<T>(V, n, k, h1, 1.0, x, nullptr)) != hipSuccess) return e;
+    }
     if (!check_true && rel <= rtol) {
       if ((e = hipStreamSynchronize(c.st)) != hipSuccess) return e;
       done = true;
@@ -549,6 +701,7 @@ dfm_status solve_impl(dfm_op op, const double *rho0, double *rho, int nrhs, cons
     (void)hipFree(b32);
     (void)hipFree(e32);
     (void)hipFree(c.dsc);
+    (void)hipFree(c.gate);
     (void)hipFree(c.partial);
   };
 #define TRY(expr)                                                                            \
@@ -562,8 +715,9 @@ dfm_status solve_impl(dfm_op op, const double *rho0, double *rho, int nrhs, cons
   } while (0)
   const int nvmax = m + 1;
   const bool mixed = opts->precision == 1;
-  TRY(hipMalloc(&c.dsc, sizeof(double) * (8 + 2 * MAXV)));
-  TRY(hipMalloc(&c.partial, sizeof(double) * (size_t)RED_BLOCKS * MAXV));
+  TRY(hipMalloc(&c.dsc, sizeof(double) * DSC_DOUBLES));
+  TRY(hipMalloc(&c.gate, sizeof(int) * 16));
+  TRY(hipMalloc(&c.partial, sizeof(double) * (size_t)RED_BLOCKS * (MAXV + 1)));
   if (opts->method == 0 || !mixed) TRY(hipMalloc(&V, sizeof(double) * (size_t)n * (opts->method == 1 ? nvmax : 2)));
   TRY(hipMalloc(&w, sizeof(double) * (size_t)n));
   TRY(hipMalloc(&t, sizeof(double) * (size_t)n));
@@ -631,6 +785,10 @@ dfm_status solve_impl(dfm_op op, const double *rho0, double *rho, int nrhs, cons
                          idone));
         inf.iters += its;
         inf.restarts += rs;
+        if (!std::isfinite(irel)) {
+          rel = irel;
+          break;
+        }
         // x += ||r|| e ; r = b - (I - B) x in FP64
         hipLaunchKernelGGL((k_axpby<float, double>), dim3(G), dim3(256), 0, st, rn, e32, 1.0, x, n);
         TRY(spmv(op, x, x, t, 1.0, -1.0, st));
