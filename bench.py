@@ -238,9 +238,20 @@ def main():
     torch.cuda.synchronize()
     t_spmv = e0.elapsed_time(e1) / nrep
     op.close()
+    # FP32 assembly (dtype 1) of the same operator, for the precision comparison
+    t32 = []
+    for i in range(args.steps + 1):
+        e0, e1 = ev(), ev()
+        e0.record(stream)
+        op32 = dfm.Operator(op_mesh, mu, prob.pos_order, dfm.LEGENDRE, prob.mom_degree, prob.quad_n, rule=rule,
+                            dtype=1)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if i:
+            t32.append(e0.elapsed_time(e1))
+        op32.close()
     op_mesh.close()
-    # FP32 products (the mixed solver's inner operator) are only reachable through
-    # dfm_solve; their share is read from the solve time per iteration
+    t_asm32 = sum(t32) / len(t32)
 
     flops_asm = 2.0 * nodes * K * K
     asm_tflops = flops_asm / (t_asm / 1e3) / 1e12
@@ -283,6 +294,9 @@ def main():
         "solve_speedup_vs_fp64": t_solve / t_mixed,
         "solve_rel_diff_vs_fp64": diff,
         "spmv_ms": t_spmv,
+        "assemble_fp32_ms": t_asm32,
+        "assemble_fp32_blocks_per_s": nblocks / (t_asm32 / 1e3),
+        "assemble_fp32_tflops": flops_asm / (t_asm32 / 1e3) / 1e12,
         "roofline": dominant,
         "roofline_other": other,
         "cpu_baseline": base,

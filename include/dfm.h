@@ -162,6 +162,15 @@ dfm_status dfm_op_info(dfm_op op, int64_t *ndof, int64_t *K, int64_t *nblocks, i
  * device i32 [nt][4], the slot that receives what leaves tet j through face l_out. */
 dfm_status dfm_op_export(dfm_op op, double *blocks, int32_t *dest, void *stream);
 
+/* The blocks of selected tets only (for checking large operators): tets device
+ * i64 [ntets] (ids in [0, nt), validated by the caller; an id outside gives NaN
+ * blocks and dest -1), blocks device f64 [ntets][4][3][K][K] and dest device i32
+ * [ntets][4] in the layout of dfm_op_export; either output may be NULL, and
+ * ntets = 0 does nothing (tets may then be NULL).
+ * Errors: DFM_E_INVALID. */
+dfm_status dfm_op_export_tets(dfm_op op, const int64_t *tets, int64_t ntets, double *blocks, int32_t *dest,
+                              void *stream);
+
 /* y = B x (transpose = 0) or y = B^T x (transpose = 1) for nrhs right-hand sides,
  * x and y device f64 [nrhs][ndof], not aliased. */
 dfm_status dfm_apply(dfm_op op, const double *x, double *y, int nrhs, int transpose, void *stream);

@@ -45,6 +45,7 @@ _PROTOS = [
     ("dfm_op_info", C.c_int, [_P, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64),
                               C.POINTER(_I64)]),
     ("dfm_op_export", C.c_int, [_P, _P, _P, _P]),
+    ("dfm_op_export_tets", C.c_int, [_P, _P, _I64, _P, _P, _P]),
     ("dfm_apply", C.c_int, [_P, _P, _P, C.c_int, C.c_int, _P]),
     ("dfm_apply_f32", C.c_int, [_P, _P, _P, C.c_int, _P]),
     ("dfm_solve", C.c_int, [_P, _P, _P, C.c_int, C.POINTER(SolveOpts), C.POINTER(SolveInfo), _P]),

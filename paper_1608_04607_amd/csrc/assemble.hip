@@ -1766,3 +1766,41 @@ extern "C" dfm_status dfm_op_export(dfm_op op, double *blocks, int32_t *dest, vo
   if (dest) DFM_HIP(hipMemcpyAsync(dest, op->dest, sizeof(int32_t) * 4 * op->nt, hipMemcpyDeviceToDevice, st));
   return DFM_OK;
 }
+
+namespace {
+// blocks of the listed tets: out [ns][4][3][K][K] row-major, dest [ns][4];
+// tet ids outside [0, nt) leave NaN blocks and dest -1 (the host checks the
+// list first, this is only the kernel's own guard)
+template <typename TB>
+__global__ void k_export_tets(const TB *B, const int32_t *dsl, const int64_t *tets, int64_t ns, int64_t nt, int K,
+                              int Kp, double *out, int32_t *dest) {
+  const int64_t kk = (int64_t)K * K, per = 12 * kk;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ns * per; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t s = i / per, e = i - s * per;
+    const int64_t j = tets[s];
+    const int64_t b = e / kk, f = e - b * kk;
+    const int row = (int)(f / K), col = (int)(f - (int64_t)row * K);
+    const bool ok = j >= 0 && j < nt;
+    if (out) out[i] = ok ? (double)B[(12 * j + b) * (int64_t)K * Kp + (int64_t)col * Kp + row] : __builtin_nan("");
+    if (dest && f == 0 && b < 4) dest[4 * s + b] = ok ? dsl[4 * j + b] : -1;
+  }
+}
+}  // namespace
+
+extern "C" dfm_status dfm_op_export_tets(dfm_op op, const int64_t *tets, int64_t ntets, double *blocks,
+                                         int32_t *dest, void *stream_) {
+  DFM_REQUIRE(op != nullptr, DFM_E_INVALID, "null operator");
+  DFM_REQUIRE(ntets >= 0, DFM_E_INVALID, "ntets must be >= 0");
+  if (ntets == 0 || (!blocks && !dest)) return DFM_OK;
+  DFM_REQUIRE(tets != nullptr, DFM_E_INVALID, "null tet list");
+  hipStream_t st = (hipStream_t)stream_;
+  const int64_t tot = ntets * 12 * op->K * op->K;
+  if (op->B)
+    hipLaunchKernelGGL(k_export_tets<double>, dim3(ew_grid(tot)), dim3(256), 0, st, op->B, op->dest, tets, ntets,
+                       op->nt, op->K, op->Kp, blocks, dest);
+  else
+    hipLaunchKernelGGL(k_export_tets<float>, dim3(ew_grid(tot)), dim3(256), 0, st, op->B32, op->dest, tets, ntets,
+                       op->nt, op->K, op->Kp, blocks, dest);
+  DFM_HIP(hipGetLastError());
+  return DFM_OK;
+}

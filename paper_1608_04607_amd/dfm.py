@@ -105,6 +105,17 @@ class Operator:
         check(_lib.load().dfm_op_export(self.handle, _ptr(blocks), _ptr(dest), _stream(stream)))
         return blocks, dest
 
+    def export_tets(self, tets, stream=None):
+        """Blocks [ns][4][3][K][K] (f64) and dest [ns][4] of the listed tets."""
+        tets = _dev(tets, torch.int64)
+        if tets.numel() and (int(tets.min()) < 0 or int(tets.max()) >= self.mesh.nt):
+            raise ValueError("tet ids must lie in [0, nt)")
+        ns = tets.shape[0]
+        blocks = torch.empty((ns, 4, 3, self.K, self.K), dtype=torch.float64, device=self.device)
+        dest = torch.empty((ns, 4), dtype=torch.int32, device=self.device)
+        check(_lib.load().dfm_op_export_tets(self.handle, _ptr(tets), ns, _ptr(blocks), _ptr(dest), _stream(stream)))
+        return blocks, dest
+
     def apply(self, x, transpose=False, stream=None):
         x = _dev(x, torch.float64)
         nrhs = 1 if x.dim() == 1 else x.shape[0]

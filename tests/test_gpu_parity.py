@@ -94,6 +94,59 @@ def test_mesh_errors():
              rho_f=torch.tensor([1.5, 1.5], dtype=torch.float64, device=DEV))
 
 
+def test_argument_errors():
+    """Empty and out-of-range arguments are rejected before any work is queued."""
+    import ctypes as C
+
+    from paper_1608_04607_amd import _lib, dfm
+    from paper_1608_04607_amd._lib import DFMError
+    say("[argument errors]")
+    lib = _lib.load()
+    v, t, refl = box(1, 0.1, seed=2)
+    # a mesh needs tets
+    with pytest.raises(DFMError, match="INVALID"):
+        gpu_mesh(v, np.zeros((0, 4), dtype=np.int64))
+    g = gpu_mesh(v, t, refl)
+    mu = torch.full((t.shape[0],), 0.1, dtype=torch.float64, device=DEV)
+    for kw in (dict(mom_degree=17), dict(quad_n=0), dict(quad_n=33), dict(pos_order=2), dict(mom_family=2),
+               dict(rule=2), dict(dtype=2)):
+        args = dict(pos_order=0, mom_family=0, mom_degree=4, quad_n=4, rule=oq.SEAM_RULE, dtype=0)
+        args.update(kw)
+        with pytest.raises(DFMError, match="INVALID"):
+            dfm.Operator(g, mu, args["pos_order"], args["mom_family"], args["mom_degree"], args["quad_n"],
+                         rule=args["rule"], dtype=args["dtype"])
+    op = dfm.Operator(g, mu, 0, dfm.LEGENDRE, 4, 4, rule=oq.SEAM_RULE)
+    rho0 = torch.ones((2, op.ndof), dtype=torch.float64, device=DEV)
+    rho = torch.empty_like(rho0)
+    st = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    info = (_lib.SolveInfo * 2)()
+    # no right-hand sides
+    opts = _lib.SolveOpts(1, 30, 100, 1e-8, 0, 0)
+    assert lib.dfm_solve(op.handle, C.c_void_p(rho0.data_ptr()), C.c_void_p(rho.data_ptr()), 0, C.byref(opts), info,
+                         st) == -1
+    # restart outside 1..200, unknown precision, zero tolerance; warm start outside
+    # the batched Neumann solver is not implemented
+    for o, code in ((_lib.SolveOpts(1, 0, 100, 1e-8, 0, 0), -1), (_lib.SolveOpts(1, 201, 100, 1e-8, 0, 0), -1),
+                    (_lib.SolveOpts(1, 30, 100, 1e-8, 2, 0), -1), (_lib.SolveOpts(1, 30, 100, 0.0, 0, 0), -1),
+                    (_lib.SolveOpts(1, 30, 100, 1e-8, 0, 1), -6)):
+        assert lib.dfm_solve(op.handle, C.c_void_p(rho0.data_ptr()), C.c_void_p(rho.data_ptr()), 2, C.byref(o),
+                             info, st) == code
+    # no products in place, no empty source lists
+    x = torch.ones(op.ndof, dtype=torch.float64, device=DEV)
+    assert lib.dfm_apply(op.handle, C.c_void_p(x.data_ptr()), C.c_void_p(x.data_ptr()), 1, 0, st) == -1
+    with pytest.raises(DFMError, match="INVALID"):
+        op.source_points(torch.zeros((0, 3), dtype=torch.float64, device=DEV))
+    # a point off the boundary
+    with pytest.raises(DFMError, match="INVALID"):
+        op.source_points(torch.tensor([[0.5, 0.5, 0.5]], dtype=torch.float64, device=DEV))
+    # sampled export: empty list is fine, ids outside the mesh are refused on the host
+    b, d = op.export_tets(torch.zeros(0, dtype=torch.int64, device=DEV))
+    assert b.shape[0] == 0 and d.shape[0] == 0
+    with pytest.raises(ValueError):
+        op.export_tets(torch.tensor([t.shape[0]], dtype=torch.int64, device=DEV))
+    op.close()
+
+
 # ---------------------------------------------------------------------------- assembly
 
 CASES = [
@@ -166,6 +219,54 @@ def test_full_size_box8_sampled():
     say(f"    rel err {err:.3e}")
     assert err < TOL
     assert torch.isfinite(blocks).all()
+
+
+def test_full_size_box32_sampled():
+    """The 49152-tet box (P0, Legendre D = 12, n = 16, lognormal mu, seam rule)
+    assembled whole on the GPU in FP64 and in FP32 -- the launches the batched
+    bench times -- and sampled tets checked against the oracle."""
+    from paper_1608_04607_amd import dfm
+    say("[assemble] box32 P0 D12 n16 full size, FP64 and FP32, sampled")
+    p = synth.problem_c3(nsrc=1)
+    bs = oa.Basis(p.pos_order, 0, p.mom_degree, p.quad_n, oq.SEAM_RULE)
+    sample = np.random.default_rng(12).choice(p.nt, 4, replace=False)
+    Bo, desto = oa.assemble(om.build_mesh(p.verts, p.tets, p.refl), bs, p.mu, tets=sample)
+    g = gpu_mesh(p.verts, p.tets, p.refl)
+    mu = torch.tensor(p.mu, device=DEV)
+    for dtype, tol in ((0, TOL), (1, 1e-5)):
+        op = dfm.Operator(g, mu, p.pos_order, dfm.LEGENDRE, p.mom_degree, p.quad_n, rule=oq.SEAM_RULE, dtype=dtype)
+        blocks, dest = op.export_tets(torch.tensor(sample, device=DEV))
+        err = rel(blocks.cpu().numpy(), Bo)
+        say(f"    dtype {dtype}: rel err {err:.3e}")
+        assert np.array_equal(dest.cpu().numpy(), desto)
+        assert err < tol
+        op.close()
+
+
+def test_full_size_uneven_degree10_group_sampled():
+    """The degree-10 group of the 256-box uneven batch (64 boxes, 362508 tets,
+    P0 x Legendre D = 10, n = 14) assembled in FP32 as one launch, as the bench
+    does; a tet of its first and of its last box checked against the oracle on
+    that box's own mesh."""
+    from paper_1608_04607_amd.batch import UnevenBatch
+    say("[assemble] uneven batch, degree-10 group full size (FP32), sampled")
+    probs = synth.problem_c5()
+    ub = UnevenBatch(probs, rule=oq.SEAM_RULE, dtype=1)
+    grp = next(g for g in ub.groups if g.key[2] == 10)
+    ub.assemble(grp)
+    say(f"    {len(grp.members)} boxes, {grp.mesh.nt} tets")
+    for m in (0, len(grp.members) - 1):
+        p = probs[grp.members[m]]
+        j = int(np.random.default_rng(13 + m).integers(p.nt))
+        bs = oa.Basis(p.pos_order, 0, p.mom_degree, p.quad_n, oq.SEAM_RULE)
+        Bo, desto = oa.assemble(om.build_mesh(p.verts, p.tets, p.refl), bs, p.mu, tets=[j])
+        off = grp.tet_offsets[m]
+        blocks, dest = grp.op.export_tets(torch.tensor([off + j], device=DEV))
+        err = rel(blocks.cpu().numpy(), Bo)
+        say(f"    box {grp.members[m]} tet {j}: rel err {err:.3e}")
+        assert np.array_equal(dest.cpu().numpy(), np.asarray(desto) + 4 * off)
+        assert err < 1e-5
+    ub.release(grp)
 
 
 # ---------------------------------------------------------------------------- apply / solve
