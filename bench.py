@@ -37,8 +37,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--rule", choices=["seam", "paper"], default="seam")
-    ap.add_argument("--workload", choices=["box8", "box32-batched", "uneven"], default="box8",
+    ap.add_argument("--workload", choices=["box8", "box32-batched", "box32-adjoint", "uneven"], default="box8",
                     help="box8: the 3072-tet single-rhs case (default); box32-batched: 49152 tets, 128 sources; "
+                         "box32-adjoint: receiver-energy gradients on the same box (64 sources); "
                          "uneven: 256 independent boxes of 500-20000 tets, degrees 4-10, 4 sources each")
     ap.add_argument("--instances", type=int, default=256, help="uneven: number of boxes")
     ap.add_argument("--fp64-sample", type=int, default=2,
@@ -139,6 +140,8 @@ def main():
         return main_box32(args)
     if args.workload == "uneven":
         return main_uneven(args)
+    if args.workload == "box32-adjoint":
+        return main_box32_adjoint(args)
 
     import numpy as np
 
@@ -543,7 +546,7 @@ def main_uneven(args):
 
             def progress(g, worst):
                 print(f"bench: {label} D={g.key[2]} ({len(g.members)} boxes, {g.mesh.nt} tets): "
-                      f"{g.products} batched products, global relres {worst:.2e}", file=sys.stderr, flush=True)
+                      f"{g.products} batched products, worst box relres {worst:.2e}", file=sys.stderr, flush=True)
 
             batch.solve(g, rtol=1e-8, progress=progress)
             torch.cuda.synchronize()
@@ -552,6 +555,8 @@ def main_uneven(args):
                          "blocks": g.op.nblocks, "nodes": g.op.nodes, "B_bytes": g.op.nbytes, "nrhs": g.nsrc,
                          "ms_assemble": e[0].elapsed_time(e[1]), "ms_sources": e[1].elapsed_time(e[2]),
                          "ms_solve": t_solve, "products": g.products,
+                         "work_fraction": sum(mp * (g.tet_offsets[m + 1] - g.tet_offsets[m])
+                                              for m, mp in enumerate(g.member_products)) / (g.products * g.mesh.nt),
                          "worst_member_relres": max(max(r) for r in g.relres)})
             if label == "step":
                 # the streaming FP32 product alone, 4 right-hand sides (HIP events on this stream)
@@ -612,11 +617,11 @@ def main_uneven(args):
     t_src = sum(r["ms_sources"] for r in rows)
     t_solve = sum(r["ms_solve"] for r in rows)
     nrhs = sum(r["boxes"] * r["nrhs"] for r in rows)
-    # the streaming product over all groups, weighted by the launches each solve made
+    # the streaming product with every box multiplied, on the largest group
     pb = [r["B_bytes"] + 16.0 * r["nrhs"] * 4 * r["tets"] * r["K"] for r in rows]
-    n_l = sum(r["products"] for r in rows)
-    prod_bytes = sum(r["products"] * b for r, b in zip(rows, pb)) / n_l
-    prod_ms = sum(r["products"] * r["ms_product"] for r in rows) / n_l
+    ib = max(range(len(rows)), key=lambda i: rows[i]["B_bytes"])
+    big = rows[ib]
+    prod_bytes, prod_ms = pb[ib], big["ms_product"]
     prod_gbs = prod_bytes / (prod_ms / 1e3) / 1e9
     flops_asm = sum(2.0 * r["nodes"] * r["K"] ** 2 for r in rows)
     for r in rows:
@@ -642,7 +647,10 @@ def main_uneven(args):
         "phase_ms": {"mesh_and_assemble": t_asm, "sources": t_src, "solve_batched": t_solve},
         "assemble_tflops_fp32": flops_asm / (t_asm / 1e3) / 1e12,
         "solve_ms_per_rhs": t_solve / nrhs,
-        "solve_precision": "fp32 Neumann products on fp32-stored B, fp64 residuals; every box's own relres <= 1e-8",
+        "solve_precision": "fp32 Neumann products on fp32-stored B, fp64 residuals; every box's own relres <= 1e-8; "
+                           "converged boxes leave the products",
+        "solve_work_fraction": sum(r["work_fraction"] * r["products"] * r["tets"] for r in rows)
+                               / sum(r["products"] * r["tets"] for r in rows),
         "solve_worst_member_relres": max(r["worst_member_relres"] for r in rows),
         "solve_fp64_ms_per_rhs_est": t64_est / nrhs,
         "solve_fp64_method": f"plain fp64, box by box: fp64 assembly + fp64 Neumann per source, {args.fp64_sample} "
@@ -652,8 +660,8 @@ def main_uneven(args):
         "rel_diff_vs_fp64_sampled": worst_diff,
         "roofline": {"kernel": "k_spmv_rhs<4>", "bound": "hbm", "achieved": prod_gbs, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": prod_gbs / HBM_PEAK_GBS, "traffic": None,
-                     "algorithmic": "B32 bytes + 16*R*ndof (x, y, e read+write in fp32) per launch, R = 4; "
-                                    f"mean over the {n_l} launches of the solves: {prod_bytes:.3e} B",
+                     "algorithmic": "B32 bytes + 16*R*ndof (x, y, e read+write in fp32) per launch, R = 4, "
+                                    f"degree-{big['degree']} group, every box multiplied: {prod_bytes:.3e} B",
                      "ms_per_launch": prod_ms,
                      "traffic_ratio_small_group": measured_traffic("k_spmv_rhs4", COUNTERS_UNEVEN, "ratio"),
                      "traffic_note": "traffic is not measured at this size; traffic_ratio_small_group is HBM bytes / "
@@ -661,6 +669,124 @@ def main_uneven(args):
                      "per_group_GBs": {f"D{r['degree']}": b / r["ms_product"] / 1e6 for r, b in zip(rows, pb)}},
         "cpu_baseline": base,
     }
+    print(json.dumps(out))
+
+
+def main_box32_adjoint(args):
+    """Receiver-energy gradients on the 49152-tet box: J = energy in [1.6,1.9] x
+    [0.4,0.6]^2 of the stationary density for rho0 = sum_s w_s src_s over the first
+    64 of the 128 point sources (w_s = 1).  One step = FP64 assembly -> 64 sources
+    -> forward FP64 GMRES(100) to 1e-10 -> receiver functional -> adjoint
+    (transposed FP64 GMRES(100) to 1e-10, dB/dmu contraction, dJ/dw = lambda .
+    src_s).  Checks, after the timed steps: duality g.rho = lambda.rho0, and a
+    central finite difference (step 1e-6, FP64 solves to 1e-12) of J in the mu of
+    the element with the largest gradient.  `value` is assembly blocks/s."""
+    import numpy as np
+
+    import synth
+    prob = synth.problem_c3(nsrc=128)
+    import torch
+
+    from paper_1608_04607_amd import dfm
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    T = lambda a: torch.tensor(a, device=dev)  # noqa: E731
+    verts, tets, refl, mu = T(prob.verts), T(prob.tets), T(prob.refl), T(prob.mu)
+    xyz = T(prob.source["xyz"][:64])
+    box = (1.6, 1.9, 0.4, 0.6, 0.4, 0.6)
+    rule = 1 if args.rule == "seam" else 0
+    mesh = dfm.Mesh(verts, tets, refl=refl)
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    def forward(mu_, rtol):
+        op = dfm.Operator(mesh, mu_, prob.pos_order, dfm.LEGENDRE, prob.mom_degree, prob.quad_n, rule=rule)
+        src = op.source_points(xyz)
+        rho0 = src.sum(0)
+        rho, info = op.solve(rho0, method="gmres", rtol=rtol, restart=100, max_iter=40000)
+        g = op.receiver_functional(box)
+        return op, src, rho0, rho, g, info
+
+    recs = []
+    t0 = time.perf_counter()
+    for i in range(args.warmup + args.steps):
+        e = [ev() for _ in range(5)]
+        e[0].record(stream)
+        op = dfm.Operator(mesh, mu, prob.pos_order, dfm.LEGENDRE, prob.mom_degree, prob.quad_n, rule=rule)
+        e[1].record(stream)
+        src = op.source_points(xyz)
+        rho0 = src.sum(0)
+        rho, info = op.solve(rho0, method="gmres", rtol=1e-10, restart=100, max_iter=40000)
+        e[2].record(stream)
+        g = op.receiver_functional(box)
+        J = float((g * rho).sum())
+        e[3].record(stream)
+        lam, dmu, dw, ainfo = op.adjoint(rho, box, src=src, rtol=1e-10, restart=100, max_iter=40000)
+        e[4].record(stream)
+        torch.cuda.synchronize()
+        print(f"bench: step {i}: forward {info[0][0]} iterations, adjoint {ainfo[0]} iterations", file=sys.stderr,
+              flush=True)
+        if i == args.warmup:
+            t0 = time.perf_counter()
+        if i >= args.warmup:
+            recs.append([e[k].elapsed_time(e[k + 1]) for k in range(4)])
+        if i < args.warmup + args.steps - 1:
+            op.close()
+    wall = time.perf_counter() - t0
+    t_asm, t_fwd, t_g, t_adj = np.array(recs).mean(axis=0)
+    duality = abs(J - float((lam * rho0).sum())) / abs(J)
+    dmu_h = dmu.cpu().numpy()
+    e_max = int(np.abs(dmu_h).argmax())
+    op.close()
+    del src, rho0, rho, lam
+    torch.cuda.empty_cache()
+    print(f"bench: central difference in mu[{e_max}]", file=sys.stderr, flush=True)
+    h = 1e-6
+    Js = []
+    for sgn in (1.0, -1.0):
+        mu_p = mu.clone()
+        mu_p[e_max] += sgn * h
+        op_p, src_p, rho0_p, rho_p, g_p, _ = forward(mu_p, 1e-12)
+        Js.append(float((g_p * rho_p).sum()))
+        op_p.close()
+        del src_p, rho0_p, rho_p, g_p
+        torch.cuda.empty_cache()
+        print(f"bench: J(mu{'+' if sgn > 0 else '-'}h) = {Js[-1]:.15e}", file=sys.stderr, flush=True)
+    fd = (Js[0] - Js[1]) / (2 * h)
+    nblocks = 12 * prob.nt
+    out = {
+        "metric": METRIC,
+        "value": nblocks / (t_asm / 1e3),
+        "unit": "blocks/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"box32x16x16-kuhn-49152tets-jitter0.1_P0xLegendreD12_n16_{args.rule}-rule"
+                               "_mu-lognormal(ln0.02,0.5)_R0.9_64-point-sources_receiver[1.6,1.9]x[0.4,0.6]^2"
+                               "_adjoint-gradients",
+                   "tets": int(prob.nt), "blocks": int(nblocks), "sources": 64,
+                   "gradient_sizes": {"d_mu": int(prob.nt), "d_w": 64}},
+        "phase_ms": {"assemble": t_asm, "sources_and_forward_solve": t_fwd, "receiver_functional": t_g,
+                     "adjoint": t_adj},
+        "forward_iters": info[0][0],
+        "adjoint_iters": ainfo[0],
+        "adjoint_relres": ainfo[2],
+        "J": J,
+        "duality_rel_diff": duality,
+        "fd_check": {"element": e_max, "adjoint": float(dmu_h[e_max]), "central_difference": fd,
+                     "rel_diff": abs(fd - dmu_h[e_max]) / abs(dmu_h[e_max]), "step": h},
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    mesh.close()
     print(json.dumps(out))
 
 

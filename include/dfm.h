@@ -194,6 +194,19 @@ dfm_status dfm_apply_f32(dfm_op op, const float *x, float *y, int nrhs, void *st
 dfm_status dfm_solve(dfm_op op, const double *rho0, double *rho, int nrhs, const dfm_solve_opts *opts,
                      dfm_solve_info *info, void *stream);
 
+/* Independent instances packed into one operator (Sec. 2, Eq. GovIE for each):
+ * instance g owns tets [tet_offsets[g], tet_offsets[g+1]) (host i64 [ngroups+1],
+ * strictly increasing from 0 to nt) and no face of its tets leads into another
+ * instance (checked: DFM_E_INVALID otherwise).  Solves all nrhs right-hand sides
+ * with the batched FP32-Neumann-in-FP64-refinement method (opts: method 0,
+ * precision 1; warm_start as for dfm_solve).  Every pair (instance, rhs) stops on
+ * its own relative residual over the instance's unknowns, and an instance all of
+ * whose pairs have converged is no longer multiplied.  info: host [ngroups][nrhs]
+ * (iters = batched products that included the instance).  Errors as dfm_solve;
+ * DFM_E_UNSUPPORTED for other methods. */
+dfm_status dfm_solve_groups(dfm_op op, const double *rho0, double *rho, int nrhs, const dfm_solve_opts *opts,
+                            const int64_t *tet_offsets, int ngroups, dfm_solve_info *info, void *stream);
+
 /* Project sources onto the basis (Galerkin in ds cos(theta)dOmega, as the initial
  * densities of Sec. 4 are projected onto Eq. FBApprox).
  *

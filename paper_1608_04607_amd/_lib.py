@@ -49,6 +49,8 @@ _PROTOS = [
     ("dfm_apply", C.c_int, [_P, _P, _P, C.c_int, C.c_int, _P]),
     ("dfm_apply_f32", C.c_int, [_P, _P, _P, C.c_int, _P]),
     ("dfm_solve", C.c_int, [_P, _P, _P, C.c_int, C.POINTER(SolveOpts), C.POINTER(SolveInfo), _P]),
+    ("dfm_solve_groups", C.c_int, [_P, _P, _P, C.c_int, C.POINTER(SolveOpts), C.POINTER(_I64), C.c_int,
+                                   C.POINTER(SolveInfo), _P]),
     ("dfm_source_points", C.c_int, [_P, _P, _I64, C.c_double, _P, _P]),
     ("dfm_source_points_sum", C.c_int, [_P, _P, _I64, _P, C.c_int, C.c_double, _P, _P]),
     ("dfm_source_plane", C.c_int, [_P, C.c_int, C.c_double, C.c_int, C.POINTER(C.c_double), C.c_double, _P, _P]),

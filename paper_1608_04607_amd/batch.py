@@ -5,9 +5,10 @@ Instances that share a discretisation (position order, momentum family and degre
 Gauss points) are concatenated into one mesh.  Its components are disjoint, so B is
 block diagonal and one dfm_assemble launch assembles every instance of the group;
 right-hand side s of the group carries the s-th source of every instance
-(dfm_source_points_sum), and one batched solve (dfm_solve, Neumann with FP32
-corrections and FP64 refinement) solves all of them.  The global stopping test is
-tightened until every instance meets the tolerance on its own part of the residual.
+(dfm_source_points_sum), and one batched solve (dfm_solve_groups: Neumann with
+FP32 corrections and FP64 refinement) solves all of them, each instance and
+source stopping on its own residual and each instance leaving the products once
+all its sources have converged.
 This module only arranges arrays and calls the library; every step of the method
 runs in its kernels.
 """
@@ -31,7 +32,8 @@ class Group:
     op: dfm.Operator = None
     rho0: torch.Tensor = None
     rho: torch.Tensor = None
-    products: int = 0
+    products: int = 0                # batched product launches
+    member_products: list = field(default_factory=list)   # products that included each member
     relres: list = field(default_factory=list)   # [member][rhs] on the member's own residual
 
 
@@ -100,22 +102,22 @@ class UnevenBatch:
         return out
 
     def solve(self, g, rtol=1e-8, segment=2500, max_products=100000, progress=None, stream=None):
-        tol = rtol
+        """Solve the group to relative residual rtol on every instance and source
+        (dfm_solve_groups), in warm-started segments of at most `segment` batched
+        products; instances stop being multiplied once all their sources converged."""
         while True:
-            g.rho, info = g.op.solve(g.rho0, method="neumann", rtol=tol, precision=1, max_iter=segment,
-                                     rho=g.rho, raise_nonconv=False, stream=stream)
-            g.products += info[0][0]
-            worst_global = max(i[2] for i in info)
+            g.rho, info = g.op.solve_groups(g.rho0, g.tet_offsets, rtol=rtol, max_iter=segment, rho=g.rho,
+                                            raise_nonconv=False, stream=stream)
+            g.products += max(x[0] for row in info for x in row)
+            if not g.member_products:
+                g.member_products = [0] * len(g.members)
+            for m, row in enumerate(info):
+                g.member_products[m] += row[0][0]
+            g.relres = [[x[2] for x in row] for row in info]
+            worst = max(max(r) for r in g.relres)
             if progress:
-                progress(g, worst_global)
-            if worst_global <= tol:
-                g.relres = self.member_relres(g, stream=stream)
-                worst = max(max(x) for x in g.relres)
-                if worst <= rtol:
-                    return
-                tol = max(tol * rtol / worst / 2.0, 1e-15)    # tighten the union's test and continue
-            if g.products >= max_products:
-                g.relres = self.member_relres(g, stream=stream)
+                progress(g, worst)
+            if worst <= rtol or g.products >= max_products:
                 return
 
     def solution(self, i):

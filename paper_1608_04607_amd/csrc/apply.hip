@@ -102,7 +102,8 @@ template <int NR>
 __global__ __launch_bounds__(SPMV_THREADS) void k_spmv_rhs(const float *__restrict__ B, const int32_t *__restrict__ dest,
                                                           int64_t nthreads, int K, int Kp, int64_t ndof,
                                                           const float *__restrict__ x, float *__restrict__ y,
-                                                          float *__restrict__ e) {
+                                                          float *__restrict__ e, const int32_t *__restrict__ gid,
+                                                          const uint8_t *__restrict__ gact) {
   typedef float f4 __attribute__((ext_vector_type(4)));
   extern __shared__ float xs_rhs[];
   const int GPB = Kp / 4;
@@ -113,8 +114,10 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv_rhs(const float *__restri
   const int nrows_b = (int)(glast / GPB - br0 + 1);
   const int per_rhs = nrows_b * K;
   const int64_t g = g0 + threadIdx.x;
-  const bool active = g < nthreads;
-  const int64_t br = active ? g / GPB : br0;
+  const bool inrange = g < nthreads;
+  const int64_t br = inrange ? g / GPB : br0;
+  // rows of an instance that is not being multiplied (gact[gid[tet]] == 0) get y = 0
+  const bool active = inrange && (gact == nullptr || gact[gid[br >> 2]] != 0);
   const int row0 = (int)(g - br * GPB) * 4;
   const float *xp = xs_rhs + (br - br0) * K;
   const f4 *Bv = reinterpret_cast<const f4 *>(B + br * 3 * (int64_t)K * Kp + row0);
@@ -147,7 +150,7 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv_rhs(const float *__restri
       }
     }
   }
-  if (!active) return;
+  if (!inrange) return;
   const int64_t ob = (int64_t)dest[br] * K;
 #pragma unroll
   for (int r = 0; r < NR; ++r)
@@ -157,7 +160,7 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv_rhs(const float *__restri
       if (row < K) {
         const float v = (float)acc[r][u];
         y[r * ndof + ob + row] = v;
-        if (e) e[r * ndof + ob + row] += v;
+        if (e && active) e[r * ndof + ob + row] += v;
       }
     }
 }
@@ -174,29 +177,52 @@ __global__ void k_to_fp32(const double *__restrict__ a, float *__restrict__ b, i
     b[i] = (float)a[i];
 }
 
-// y[4j + l_in][col] = alpha v[...] + beta sum_{l_out != l_in} sum_row B[j,l_out,s(l_in)][col][row] x[dest(j,l_out)][row]
-__global__ void k_spmv_t(const double *__restrict__ B, const int32_t *__restrict__ dest, int64_t nrows, int K, int Kp,
-                         const double *__restrict__ x, const double *__restrict__ v, double *__restrict__ y,
-                         double alpha, double beta) {
-  int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (g >= nrows) return;
-  int64_t slot = g / K;
-  int col = (int)(g - slot * K);
-  int64_t j = slot >> 2;
-  int l_in = (int)(slot & 3);
-  const int64_t KKp = (int64_t)K * Kp;
-  double acc = 0.0;
-  for (int l_out = 0; l_out < 4; ++l_out) {
-    if (l_out == l_in) continue;
-    int s = l_in < l_out ? l_in : l_in - 1;
-    int64_t br = 4 * j + l_out;
-    const double *Bb = B + (br * 3 + s) * KKp + (int64_t)col * Kp;
-    const double *xs = x + (int64_t)dest[br] * K;
-    for (int row = 0; row < K; ++row) acc = fma(Bb[row], xs[row], acc);
+// Transposed product (adjoint solve):
+//   y[4j + l_in][col] = alpha v + beta sum_{l_out != l_in} sum_row
+//                       B[4j + l_out, s(l_in)][col][row] x[dest(4j + l_out)][row].
+// One workgroup per tet: the four destination panels x[dest(4j + l_out)] are
+// staged in LDS; every output (l_in, col) belongs to one wave, which reads the
+// three contributing block columns (K contiguous doubles each, 16-byte aligned
+// since Kp is a multiple of 4) with coalesced 16-byte loads and reduces across
+// the wave, so B is read once, in order.
+constexpr int SPMVT_THREADS = 256;
+__global__ __launch_bounds__(SPMVT_THREADS) void k_spmv_t(const double *__restrict__ B,
+                                                         const int32_t *__restrict__ dest, int K, int Kp,
+                                                         const double *__restrict__ x, const double *__restrict__ v,
+                                                         double *__restrict__ y, double alpha, double beta) {
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  extern __shared__ double xd[];  // [4][K]
+  const int64_t j = blockIdx.x;
+  for (int i = threadIdx.x; i < 4 * K; i += SPMVT_THREADS) {
+    const int l = i / K, row = i - l * K;
+    xd[i] = x[(int64_t)dest[4 * j + l] * K + row];
   }
-  double r = beta * acc;
-  if (v) r = fma(alpha, v[g], r);
-  y[g] = r;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t KKp = (int64_t)K * Kp;
+  for (int o = wave; o < 4 * K; o += SPMVT_THREADS / 64) {
+    const int l_in = o / K, col = o - l_in * K;
+    double acc = 0.0;
+#pragma unroll
+    for (int l_out = 0; l_out < 4; ++l_out) {
+      if (l_out == l_in) continue;
+      const int s = l_in < l_out ? l_in : l_in - 1;
+      const d2 *Bc = reinterpret_cast<const d2 *>(B + ((4 * j + l_out) * 3 + s) * KKp + (int64_t)col * Kp);
+      const double *xs = xd + l_out * K;
+      for (int r2 = lane; 2 * r2 < K; r2 += 64) {
+        const d2 b = __builtin_nontemporal_load(Bc + r2);   // rows 2 r2, 2 r2 + 1 (< Kp)
+        acc = fma(b[0], xs[2 * r2], acc);
+        if (2 * r2 + 1 < K) acc = fma(b[1], xs[2 * r2 + 1], acc);
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) {
+      const int64_t g = (4 * j + l_in) * (int64_t)K + col;
+      double r = beta * acc;
+      if (v) r = fma(alpha, v[g], r);
+      y[g] = r;
+    }
+  }
 }
 
 // Batched product for R right-hand sides on the FP32 matrix cores
@@ -228,7 +254,9 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(SPMM_THREADS, 4) void k_spmm32(const float *__restrict__ B,
                                                            const int32_t *__restrict__ dest, int64_t nt, int K, int Kp,
                                                            int64_t ndof, int R, const float *__restrict__ x,
-                                                           float *__restrict__ y, float *__restrict__ e) {
+                                                           float *__restrict__ y, float *__restrict__ e,
+                                                           const int32_t *__restrict__ gid,
+                                                           const uint8_t *__restrict__ gact) {
   extern __shared__ float lds[];
   float *bs = lds;                              // [SPMM_KC][SPMM_BLD]
   float *xs = lds + SPMM_KC * SPMM_BLD;         // [SPMM_KC][SPMM_XLD]
@@ -250,6 +278,17 @@ __global__ __launch_bounds__(SPMM_THREADS, 4) void k_spmm32(const float *__restr
   const int ncol = 3 * K;                       // contraction length of the block row
   const int nchunk = (ncol + SPMM_KC - 1) / SPMM_KC;
   const float *Bbr = B + br * 3 * (int64_t)K * Kp;   // 3K columns of length Kp
+  if (gact != nullptr && gact[gid[j]] == 0) {
+    // an instance that is not being multiplied: y = 0 on its rows (the whole
+    // workgroup takes this branch, before any barrier)
+    const int nrows = min(SPMM_ROWS, K - m0);
+    const int64_t ob = (int64_t)dest[br] * K + m0;
+    for (int i = tid; i < SPMM_RT * nrows; i += SPMM_THREADS) {
+      const int r = i / nrows, m = i - r * nrows;
+      if (r0 + r < R) y[(int64_t)(r0 + r) * ndof + ob + m] = 0.0f;
+    }
+    return;
+  }
 
   // coalesced chunk loads.  B chunk value i = tid + u * SPMM_THREADS -> (column
   // i / SPMM_ROWS, row i % SPMM_ROWS), offsets fixed per thread; x chunk value i ->
@@ -365,7 +404,8 @@ hipError_t spmv32(dfm_op op, const float *x, const float *v, float *y, float alp
 
 // y = B32 x (and e += y when e != null) for R right-hand sides, up to four per
 // stream of the operator
-hipError_t spmv32_rhs(dfm_op op, const float *x, float *y, float *e, int R, hipStream_t st) {
+hipError_t spmv32_rhs(dfm_op op, const float *x, float *y, float *e, int R, const int32_t *gid, const uint8_t *gact,
+                      hipStream_t st) {
   const int64_t nthreads = 4 * op->nt * (int64_t)(op->Kp / 4);
   const unsigned grid = (unsigned)((nthreads + SPMV_THREADS - 1) / SPMV_THREADS);
   const int gpb = op->Kp / 4;
@@ -379,7 +419,7 @@ hipError_t spmv32_rhs(dfm_op op, const float *x, float *y, float *e, int R, hipS
 #define DFM_RHS_CASE(NRV)                                                                                  \
   case NRV:                                                                                                \
     hipLaunchKernelGGL(k_spmv_rhs<NRV>, dim3(grid), dim3(SPMV_THREADS), lds, st, op->B32, op->dest, nthreads, \
-                       op->K, op->Kp, op->ndof, xr, yr, er);                                               \
+                       op->K, op->Kp, op->ndof, xr, yr, er, gid, gact);                                    \
     break;
     switch (nr) {
       DFM_RHS_CASE(1)
@@ -396,21 +436,25 @@ hipError_t spmv32_rhs(dfm_op op, const float *x, float *y, float *e, int R, hipS
 }
 
 // y = B32 x for R right-hand sides on the matrix cores (and e += y when e != null)
-hipError_t spmm32(dfm_op op, const float *x, float *y, float *e, int R, hipStream_t st) {
+hipError_t spmm32(dfm_op op, const float *x, float *y, float *e, int R, const int32_t *gid, const uint8_t *gact,
+                  hipStream_t st) {
   dim3 grid((unsigned)(4 * op->nt), (unsigned)((R + SPMM_RT - 1) / SPMM_RT),
             (unsigned)((op->K + SPMM_ROWS - 1) / SPMM_ROWS));
   hipError_t err = hipFuncSetAttribute((const void *)k_spmm32, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)SPMM_LDS);
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL(k_spmm32, grid, dim3(SPMM_THREADS), SPMM_LDS, st, op->B32, op->dest, op->nt, op->K, op->Kp,
-                     op->ndof, R, x, y, e);
+                     op->ndof, R, x, y, e, gid, gact);
   return hipGetLastError();
 }
 
 // y = B32 x (and e += y) with the kernel suited to R: the streaming product below
-// 16 right-hand sides, the matrix-core product from 16 on
-hipError_t product32(dfm_op op, const float *x, float *y, float *e, int R, hipStream_t st) {
-  return R >= 16 ? spmm32(op, x, y, e, R, st) : spmv32_rhs(op, x, y, e, R, st);
+// 16 right-hand sides, the matrix-core product from 16 on.  With gid/gact (tet ->
+// instance, instance -> multiplied?) the rows of instances with gact = 0 get y = 0
+// and leave e unchanged, without reading their blocks.
+hipError_t product32(dfm_op op, const float *x, float *y, float *e, int R, const int32_t *gid, const uint8_t *gact,
+                     hipStream_t st) {
+  return R >= 16 ? spmm32(op, x, y, e, R, gid, gact, st) : spmv32_rhs(op, x, y, e, R, gid, gact, st);
 }
 
 // FP32 copy of B for the mixed-precision solver (made once, kept with the operator)
@@ -428,10 +472,8 @@ hipError_t ensure_fp32(dfm_op op, hipStream_t st) {
 
 hipError_t spmv_t(dfm_op op, const double *x, const double *v, double *y, double alpha, double beta, hipStream_t st) {
   if (!op->B) return hipErrorNotSupported;   // transposed products need the FP64 operator
-  int64_t nrows = op->ndof;
-  unsigned grid = (unsigned)((nrows + 255) / 256);
-  hipLaunchKernelGGL(k_spmv_t, dim3(grid), dim3(256), 0, st, op->B, op->dest, nrows, op->K, op->Kp, x, v, y, alpha,
-                     beta);
+  hipLaunchKernelGGL(k_spmv_t, dim3((unsigned)op->nt), dim3(SPMVT_THREADS), sizeof(double) * 4 * op->K, st, op->B,
+                     op->dest, op->K, op->Kp, x, v, y, alpha, beta);
   return hipGetLastError();
 }
 
@@ -464,7 +506,7 @@ extern "C" dfm_status dfm_apply_f32(dfm_op op, const float *x, float *y, int nrh
     return DFM_E_NOMEM;
   }
   DFM_HIP(e);
-  DFM_HIP(product32(op, x, y, nullptr, nrhs, st));
+  DFM_HIP(product32(op, x, y, nullptr, nrhs, nullptr, nullptr, st));
   return DFM_OK;
 }
 

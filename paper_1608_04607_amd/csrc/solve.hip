@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <cmath>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "dfm_internal.h"
@@ -29,7 +30,8 @@ hipError_t spmv(dfm_op op, const double *x, const double *v, double *y, double a
 hipError_t spmv32(dfm_op op, const float *x, const float *v, float *y, float alpha, float beta, hipStream_t st);
 hipError_t spmv_t(dfm_op op, const double *x, const double *v, double *y, double alpha, double beta, hipStream_t st);
 hipError_t ensure_fp32(dfm_op op, hipStream_t st);
-hipError_t product32(dfm_op op, const float *x, float *y, float *e, int R, hipStream_t st);
+hipError_t product32(dfm_op op, const float *x, float *y, float *e, int R, const int32_t *gid, const uint8_t *gact,
+                     hipStream_t st);
 
 namespace {
 
@@ -407,6 +409,65 @@ __global__ void k_zero_f64(double *__restrict__ y, int n) {
   if (i < n) y[i] = 0.0;
 }
 
+// Segmented rows: instance g owns elements [off[g], off[g+1]) of every rhs row
+// (grid: x = blocks per segment, y = rhs, z = instance).
+// out[r * G + g] += squared norm of instance g's part of v[r]
+template <typename T>
+__global__ __launch_bounds__(RED_THREADS) void k_seg_norms2(const T *__restrict__ v, int64_t n,
+                                                          const int64_t *__restrict__ off, int G,
+                                                          double *__restrict__ out) {
+  __shared__ double red[NWAVE];
+  const int r = blockIdx.y, g = blockIdx.z;
+  const T *row = v + (int64_t)r * n;
+  const int64_t b = off[g + 1];
+  double acc = 0.0;
+  for (int64_t i = off[g] + blockIdx.x * (int64_t)RED_THREADS + threadIdx.x; i < b;
+       i += (int64_t)gridDim.x * RED_THREADS) {
+    const double a = (double)row[i];
+    acc = fma(a, a, acc);
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < NWAVE; ++w) t += red[w];
+    atomicAdd(out + (int64_t)r * G + g, t);
+  }
+}
+
+// t = e = (float)(s[r * G + g] * v) on instance g's part of row r
+__global__ void k_seg_to_f32(const double *__restrict__ v, int64_t n, const int64_t *__restrict__ off, int G,
+                             const double *__restrict__ s, float *__restrict__ t, float *__restrict__ e) {
+  const int r = blockIdx.y, g = blockIdx.z;
+  const double sc = s[(int64_t)r * G + g];
+  const int64_t b = off[g + 1];
+  for (int64_t i = off[g] + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < b;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t o = (int64_t)r * n + i;
+    const float a = (float)(sc * v[o]);
+    t[o] = a;
+    e[o] = a;
+  }
+}
+
+// gid[j] = g for the tets j of instance g (tet offsets toff; grid z = instance)
+__global__ void k_fill_gid(const int64_t *__restrict__ toff, int32_t *__restrict__ gid) {
+  const int g = blockIdx.z;
+  for (int64_t j = toff[g] + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < toff[g + 1];
+       j += (int64_t)gridDim.x * blockDim.x)
+    gid[j] = g;
+}
+
+__global__ void k_fill_u32(unsigned *__restrict__ p, unsigned v) { *p = v; }
+
+// *bad = 1 when some exit slot of a tet leads into another instance
+__global__ void k_check_groups(const int32_t *__restrict__ dest, const int32_t *__restrict__ gid, int64_t nt,
+                               unsigned *__restrict__ bad) {
+  for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < 4 * nt; s += (int64_t)gridDim.x * blockDim.x)
+    if (gid[dest[s] >> 2] != gid[s >> 2]) atomicOr(bad, 1u);
+}
+
 template <typename T>
 hipError_t gmres(Ctx &c, const T *b, T *x, T *V, T *w, T *t, int m, double rtol, int max_iter, bool check_true,
                  int &its, int &restarts, double &rel, bool &done) {
@@ -505,22 +566,32 @@ hipError_t gmres(Ctx &c, const T *b, T *x, T *V, T *w, T *t, int m, double rtol,
 using namespace dfm;
 
 namespace dfm {
-// Batched mixed-precision Neumann refinement (method 0, precision 1), all R
-// right-hand sides at once:
-//   r = rho0 - (I - B) rho in FP64;  e = sum_{k <= m} t_k, t_k = B32^k (r / |r|),
-//   in FP32 until |t_m| is below max(INNER_TOL, rtol |rho0| / (2 |r|)) for every
-//   active right-hand side: the partial sum leaves the residual (I - B) e - r/|r|
-//   = -t_{m+1}, no larger than t_m for a contraction, so this is no more accuracy
-//   than the outer test needs and no less than the FP32 sums deliver;
-//   rho += |r| e.
-// Iterations count the batched products with B32 (the same for every rhs).
-static dfm_status solve_neumann_batched(dfm_op op, const double *rho0, double *rho, int R, const dfm_solve_opts *opts,
-                                        dfm_solve_info *info, hipStream_t st) {
-  const int64_t n = op->ndof;
+// Batched mixed-precision Neumann refinement (method 0, precision 1) of R
+// right-hand sides on G independent instances packed into one operator
+// (instance g owns tets [toff[g], toff[g+1]); B does not couple instances).  For
+// every pair (instance g, rhs r) with residual r_gr = (rho0 - (I - B) rho)_{g,r}
+// (FP64):  e = sum_{k <= m} t_k, t_k = B32^k (r / |r|) in FP32 (|r| the norm of
+// the whole rhs row), until |t_m|_g |r| <= max(INNER_TOL |r_gr|, rtol |rho0_gr| / 2)
+// for the pair -- the partial sum leaves the residual -t_{m+1}, no larger than
+// t_m for a contraction, so this is no more accuracy than the outer test needs
+// and no less than the FP32 sums deliver; then rho += |r| e.  A pair stops when
+// its own relative residual |r_gr| / |rho0_gr| <= rtol, and an instance all of
+// whose pairs are done (or, inside the series, below their inner target) is no
+// longer multiplied: its rows of t get y = 0 without reading its blocks.  G = 1
+// is the plain batched solve.  info: [G][R]; iters = batched products that
+// included the instance.
+static dfm_status solve_groups_impl(dfm_op op, const double *rho0, double *rho, int R, const dfm_solve_opts *opts,
+                                    const std::vector<int64_t> &toff, dfm_solve_info *info, hipStream_t st) {
+  const int64_t n = op->ndof, K = op->K;
+  const int G = (int)toff.size() - 1;
   constexpr double INNER_TOL = 1e-4;
-  constexpr int CHECK = 8;            // norms of the series term every CHECK products
+  constexpr int CHECK = 8;  // norms of the series term every CHECK products
   float *t0 = nullptr, *t1 = nullptr, *e32 = nullptr;
   double *res = nullptr, *tmp = nullptr, *sc = nullptr;
+  int64_t *off_d = nullptr, *toff_d = nullptr;
+  int32_t *gid = nullptr;
+  uint8_t *gact_d = nullptr;
+  unsigned *bad_d = nullptr;
   auto cleanup = [&]() {
     (void)hipFree(t0);
     (void)hipFree(t1);
@@ -528,6 +599,11 @@ static dfm_status solve_neumann_batched(dfm_op op, const double *rho0, double *r
     (void)hipFree(res);
     (void)hipFree(tmp);
     (void)hipFree(sc);
+    (void)hipFree(off_d);
+    (void)hipFree(toff_d);
+    (void)hipFree(gid);
+    (void)hipFree(gact_d);
+    (void)hipFree(bad_d);
   };
 #define TRYB(expr)                                                                           \
   do {                                                                                       \
@@ -538,39 +614,77 @@ static dfm_status solve_neumann_batched(dfm_op op, const double *rho0, double *r
       return e_ == hipErrorOutOfMemory ? DFM_E_NOMEM : DFM_E_HIP;                            \
     }                                                                                        \
   } while (0)
+  const size_t RG = (size_t)R * G;
   TRYB(ensure_fp32(op, st));
   TRYB(hipMalloc(&t0, sizeof(float) * (size_t)R * n));
   TRYB(hipMalloc(&t1, sizeof(float) * (size_t)R * n));
   TRYB(hipMalloc(&e32, sizeof(float) * (size_t)R * n));
   TRYB(hipMalloc(&res, sizeof(double) * (size_t)R * n));
   TRYB(hipMalloc(&tmp, sizeof(double) * n));
-  TRYB(hipMalloc(&sc, sizeof(double) * 2 * (size_t)R));
-  const dim3 eg((unsigned)((n + 255) / 256), (unsigned)R);
-  const dim3 rg((unsigned)std::min<int64_t>(256, (n + RED_THREADS - 1) / RED_THREADS), (unsigned)R);
-  std::vector<double> h(2 * (size_t)R);
-  // per-rhs squared norms of a [R][n] block into sc[0..R) (host copy in h)
-  auto norms2_f64 = [&](const double *v) -> hipError_t {
-    hipLaunchKernelGGL(k_zero_f64, dim3((R + 255) / 256), dim3(256), 0, st, sc, R);
-    hipLaunchKernelGGL(k_row_norms2<double>, rg, dim3(RED_THREADS), 0, st, v, n, sc);
-    hipError_t e = hipMemcpyAsync(h.data(), sc, sizeof(double) * R, hipMemcpyDeviceToHost, st);
+  TRYB(hipMalloc(&sc, sizeof(double) * 2 * RG));
+  TRYB(hipMalloc(&off_d, sizeof(int64_t) * (G + 1)));
+  TRYB(hipMalloc(&toff_d, sizeof(int64_t) * (G + 1)));
+  const bool grouped = G > 1;
+  std::vector<int64_t> off(G + 1);
+  for (int g = 0; g <= G; ++g) off[g] = 4 * K * toff[g];
+  TRYB(hipMemcpyAsync(off_d, off.data(), sizeof(int64_t) * (G + 1), hipMemcpyHostToDevice, st));
+  TRYB(hipMemcpyAsync(toff_d, toff.data(), sizeof(int64_t) * (G + 1), hipMemcpyHostToDevice, st));
+  int64_t maxseg = 0;
+  for (int g = 0; g < G; ++g) maxseg = std::max(maxseg, off[g + 1] - off[g]);
+  if (grouped) {
+    // instance of every tet, and the check that B does not couple instances
+    int64_t maxt = 0;
+    for (int g = 0; g < G; ++g) maxt = std::max(maxt, toff[g + 1] - toff[g]);
+    TRYB(hipMalloc(&gid, sizeof(int32_t) * op->nt));
+    TRYB(hipMalloc(&gact_d, sizeof(uint8_t) * G));
+    TRYB(hipMalloc(&bad_d, sizeof(unsigned)));
+    hipLaunchKernelGGL(k_fill_gid, dim3((unsigned)std::min<int64_t>((maxt + 255) / 256, 4096), 1, G), dim3(256), 0, st,
+                       toff_d, gid);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, st, bad_d, 0u);
+    hipLaunchKernelGGL(k_check_groups, dim3(ew_grid(4 * op->nt)), dim3(256), 0, st, op->dest, gid, op->nt, bad_d);
+    unsigned bad = 0;
+    TRYB(hipMemcpyAsync(&bad, bad_d, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+    TRYB(hipStreamSynchronize(st));
+    if (bad) {
+      cleanup();
+      set_error("the operator couples tets of different instances");
+      return DFM_E_INVALID;
+    }
+  }
+  const dim3 sg((unsigned)std::min<int64_t>((maxseg + 255) / 256, 1024), (unsigned)R, (unsigned)G);
+  const dim3 rg((unsigned)std::min<int64_t>((maxseg + RED_THREADS - 1) / RED_THREADS, grouped ? 64 : 256),
+                (unsigned)R, (unsigned)G);
+  std::vector<double> h(2 * RG);
+  // squared norms per (rhs, instance) of a [R][n] block into sc[0..RG) (host copy in h)
+  auto seg_norms2 = [&](auto *v) -> hipError_t {
+    using T = std::remove_const_t<std::remove_pointer_t<decltype(v)>>;
+    hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)((RG + 255) / 256)), dim3(256), 0, st, sc, (int)RG);
+    hipLaunchKernelGGL(k_seg_norms2<T>, rg, dim3(RED_THREADS), 0, st, v, n, off_d, G, sc);
+    hipError_t e = hipMemcpyAsync(h.data(), sc, sizeof(double) * RG, hipMemcpyDeviceToHost, st);
     return e != hipSuccess ? e : hipStreamSynchronize(st);
   };
-  auto norms2_f32 = [&](const float *v) -> hipError_t {
-    hipLaunchKernelGGL(k_zero_f64, dim3((R + 255) / 256), dim3(256), 0, st, sc, R);
-    hipLaunchKernelGGL(k_row_norms2<float>, rg, dim3(RED_THREADS), 0, st, v, n, sc);
-    hipError_t e = hipMemcpyAsync(h.data(), sc, sizeof(double) * R, hipMemcpyDeviceToHost, st);
-    return e != hipSuccess ? e : hipStreamSynchronize(st);
+  // r = rho0 - (I - B) rho for every rhs (FP64, one product per rhs)
+  auto residual = [&]() -> hipError_t {
+    for (int r = 0; r < R; ++r) {
+      double *x = rho + (int64_t)r * n, *rr = res + (int64_t)r * n;
+      hipError_t e = spmv(op, x, x, tmp, -1.0, 1.0, st);   // tmp = B x - x
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((k_copy<double, double>), dim3(ew_grid(n)), dim3(256), 0, st, rho0 + (int64_t)r * n, rr, n);
+      hipLaunchKernelGGL((k_axpby<double, double>), dim3(ew_grid(n)), dim3(256), 0, st, 1.0, tmp, 1.0, rr, n);
+    }
+    return hipGetLastError();
   };
-  // t1 = B32 t0 and e += t1: on the matrix cores for many right-hand sides, by
-  // streaming the operator once per four for a few (the matrix-core tile holds 128)
-  std::vector<double> bn(R), rn(R), rel(R, 1.0), target(R);
-  std::vector<char> done(R, 0);
-  TRYB(norms2_f64(rho0));
-  for (int r = 0; r < R; ++r) {
-    bn[r] = std::sqrt(h[r]);
-    if (!(bn[r] > 0.0)) {
-      done[r] = 1;
-      rel[r] = 0.0;
+  // pair (r, g) at index r * G + g
+  std::vector<double> bn(RG), rn(RG), rel(RG, 1.0), target(RG), rrow(R), scale(RG);
+  std::vector<char> done(RG, 0), inner(RG, 0);
+  std::vector<uint8_t> gact(G, 0);   // host copy of gact_d; the first update_active uploads it
+  std::vector<int> gprod(G, 0);
+  TRYB(seg_norms2(rho0));
+  for (size_t i = 0; i < RG; ++i) {
+    bn[i] = std::sqrt(h[i]);
+    if (!(bn[i] > 0.0)) {
+      done[i] = 1;
+      rel[i] = 0.0;
     }
   }
   if (!opts->warm_start) {
@@ -581,81 +695,100 @@ static dfm_status solve_neumann_batched(dfm_op op, const double *rho0, double *r
     TRYB(hipGetLastError());
     rn = bn;
   } else {
-    // r = rho0 - (I - B) rho for the given iterate
-    for (int r = 0; r < R; ++r) {
-      double *x = rho + (int64_t)r * n, *rr = res + (int64_t)r * n;
-      TRYB(spmv(op, x, x, tmp, -1.0, 1.0, st));
-      hipLaunchKernelGGL((k_copy<double, double>), dim3(ew_grid(n)), dim3(256), 0, st, rho0 + (int64_t)r * n, rr, n);
-      hipLaunchKernelGGL((k_axpby<double, double>), dim3(ew_grid(n)), dim3(256), 0, st, 1.0, tmp, 1.0, rr, n);
-      TRYB(hipGetLastError());
-    }
-    TRYB(norms2_f64(res));
-    for (int r = 0; r < R; ++r) {
-      rn[r] = std::sqrt(h[r]);
-      if (done[r]) continue;
-      rel[r] = rn[r] / bn[r];
-      if (rel[r] <= opts->rtol) done[r] = 1;
+    TRYB(residual());
+    TRYB(seg_norms2(res));
+    for (size_t i = 0; i < RG; ++i) {
+      rn[i] = std::sqrt(h[i]);
+      if (done[i]) continue;
+      rel[i] = rn[i] / bn[i];
+      if (rel[i] <= opts->rtol) done[i] = 1;
     }
   }
+  auto all_done = [&]() {
+    for (size_t i = 0; i < RG; ++i)
+      if (!done[i]) return false;
+    return true;
+  };
+  // instances still multiplied: some pair neither done nor below its inner target
+  auto update_active = [&]() -> hipError_t {
+    bool changed = false;
+    for (int g = 0; g < G; ++g) {
+      uint8_t a = 0;
+      for (int r = 0; r < R; ++r) a |= (!done[(size_t)r * G + g] && !inner[(size_t)r * G + g]) ? 1 : 0;
+      changed |= a != gact[g];
+      gact[g] = a;
+    }
+    if (!grouped || !changed) return hipSuccess;
+    hipError_t e = hipMemcpyAsync(gact_d, gact.data(), sizeof(uint8_t) * G, hipMemcpyHostToDevice, st);
+    return e != hipSuccess ? e : hipStreamSynchronize(st);
+  };
   int iters = 0;
   bool finite = true;
-  for (int outer = 0; outer < 40 && iters < opts->max_iter; ++outer) {
-    // t = e = r / |r| for the active right-hand sides (zero for the others)
-    for (int r = 0; r < R; ++r) h[r] = (!done[r] && rn[r] > 0.0) ? 1.0 / rn[r] : 0.0;
-    TRYB(hipMemcpyAsync(sc + R, h.data(), sizeof(double) * R, hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_rows_to_f32, eg, dim3(256), 0, st, res, sc + R, t0, e32, n);
+  for (int outer = 0; outer < 40 && iters < opts->max_iter && !all_done(); ++outer) {
+    // t = e = r / |r| on the pairs not done (zero on the others)
+    for (int r = 0; r < R; ++r) {
+      double s2 = 0.0;
+      for (int g = 0; g < G; ++g)
+        if (!done[(size_t)r * G + g]) s2 += rn[(size_t)r * G + g] * rn[(size_t)r * G + g];
+      rrow[r] = std::sqrt(s2);
+      for (int g = 0; g < G; ++g) {
+        const size_t i = (size_t)r * G + g;
+        scale[i] = (!done[i] && rrow[r] > 0.0) ? 1.0 / rrow[r] : 0.0;
+        inner[i] = 0;
+        target[i] = std::max(INNER_TOL * rn[i], 0.5 * opts->rtol * bn[i]) / (rrow[r] > 0.0 ? rrow[r] : 1.0);
+      }
+    }
+    std::copy(scale.begin(), scale.end(), h.begin());
+    TRYB(hipMemcpyAsync(sc + RG, h.data(), sizeof(double) * RG, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_seg_to_f32, sg, dim3(256), 0, st, res, n, off_d, G, sc + RG, t0, e32);
     TRYB(hipGetLastError());
-    for (int r = 0; r < R; ++r)
-      target[r] = done[r] ? 1.0 : std::min(0.5, std::max(INNER_TOL, 0.5 * opts->rtol * bn[r] / rn[r]));
+    TRYB(update_active());
     while (iters < opts->max_iter) {
-      TRYB(product32(op, t0, t1, e32, R, st));
+      TRYB(product32(op, t0, t1, e32, R, grouped ? gid : nullptr, grouped ? gact_d : nullptr, st));
       std::swap(t0, t1);
       ++iters;
+      for (int g = 0; g < G; ++g) gprod[g] += gact[g];
       if (iters % CHECK) continue;
-      TRYB(norms2_f32(t0));
+      TRYB(seg_norms2(t0));
       bool inner_done = true;
-      for (int r = 0; r < R; ++r) {
-        if (done[r]) continue;
-        const double tn = std::sqrt(h[r]);
+      for (size_t i = 0; i < RG; ++i) {
+        if (done[i] || inner[i]) continue;
+        const double tn = std::sqrt(h[i]);
         if (!std::isfinite(tn)) finite = false;
-        if (!(tn <= target[r])) inner_done = false;
+        if (tn <= target[i]) inner[i] = 1;
+        else inner_done = false;
       }
       if (inner_done || !finite) break;
+      TRYB(update_active());
     }
     if (!finite) break;
     // rho += |r| e;  r = rho0 - (I - B) rho  (FP64, one product per rhs)
-    for (int r = 0; r < R; ++r) h[r] = done[r] ? 0.0 : rn[r];
-    TRYB(hipMemcpyAsync(sc + R, h.data(), sizeof(double) * R, hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_rows_axpy, eg, dim3(256), 0, st, sc + R, e32, rho, n);
+    for (int r = 0; r < R; ++r) h[r] = rrow[r];
+    TRYB(hipMemcpyAsync(sc + RG, h.data(), sizeof(double) * R, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_rows_axpy, dim3((unsigned)((n + 255) / 256), (unsigned)R), dim3(256), 0, st, sc + RG, e32,
+                       rho, n);
     TRYB(hipGetLastError());
-    for (int r = 0; r < R; ++r) {
-      if (done[r]) continue;
-      double *x = rho + (int64_t)r * n, *rr = res + (int64_t)r * n;
-      TRYB(spmv(op, x, x, tmp, -1.0, 1.0, st));   // tmp = B x - x
-      hipLaunchKernelGGL((k_copy<double, double>), dim3(ew_grid(n)), dim3(256), 0, st, rho0 + (int64_t)r * n, rr, n);
-      hipLaunchKernelGGL((k_axpby<double, double>), dim3(ew_grid(n)), dim3(256), 0, st, 1.0, tmp, 1.0, rr, n);
-      TRYB(hipGetLastError());
+    TRYB(residual());
+    TRYB(seg_norms2(res));
+    for (size_t i = 0; i < RG; ++i) {
+      if (done[i]) continue;
+      rn[i] = std::sqrt(h[i]);
+      rel[i] = rn[i] / bn[i];
+      if (!std::isfinite(rel[i])) finite = false;
+      if (rel[i] <= opts->rtol) done[i] = 1;
     }
-    TRYB(norms2_f64(res));
-    bool all = true;
-    for (int r = 0; r < R; ++r) {
-      if (done[r]) continue;
-      rn[r] = std::sqrt(h[r]);
-      rel[r] = rn[r] / bn[r];
-      if (!std::isfinite(rel[r])) finite = false;
-      if (rel[r] <= opts->rtol) done[r] = 1;
-      else all = false;
-    }
-    if (all || !finite) break;
+    if (!finite) break;
   }
 #undef TRYB
   cleanup();
   dfm_status status = DFM_OK;
-  for (int r = 0; r < R; ++r) {
-    if (info) info[r] = dfm_solve_info{iters, 0, rel[r]};
-    if (!std::isfinite(rel[r])) status = DFM_E_NUMERIC;
-    else if (!done[r] && status == DFM_OK) status = DFM_E_NOCONV;
-  }
+  for (int g = 0; g < G; ++g)
+    for (int r = 0; r < R; ++r) {
+      const size_t i = (size_t)r * G + g;
+      if (info) info[(size_t)g * R + r] = dfm_solve_info{grouped ? gprod[g] : iters, 0, rel[i]};
+      if (!std::isfinite(rel[i])) status = DFM_E_NUMERIC;
+      else if (!done[i] && status == DFM_OK) status = DFM_E_NOCONV;
+    }
   if (!finite) status = DFM_E_NUMERIC;
   if (status == DFM_E_NOCONV) set_error("solver stopped at max_iter above the tolerance");
   if (status == DFM_E_NUMERIC) set_error("non-finite residual in the solver");
@@ -680,7 +813,7 @@ dfm_status solve_impl(dfm_op op, const double *rho0, double *rho, int nrhs, cons
   DFM_REQUIRE(!(opts->warm_start && !(opts->method == 0 && opts->precision == 1)), DFM_E_UNSUPPORTED,
               "warm_start is implemented for method 0 with precision 1 only");
   if (opts->method == 0 && opts->precision == 1)
-    return solve_neumann_batched(op, rho0, rho, nrhs, opts, info, (hipStream_t)stream_);
+    return solve_groups_impl(op, rho0, rho, nrhs, opts, std::vector<int64_t>{0, op->nt}, info, (hipStream_t)stream_);
   hipStream_t st = (hipStream_t)stream_;
   const int64_t n = op->ndof;
   Ctx c;
@@ -820,4 +953,22 @@ dfm_status solve_impl(dfm_op op, const double *rho0, double *rho, int nrhs, cons
 extern "C" dfm_status dfm_solve(dfm_op op, const double *rho0, double *rho, int nrhs, const dfm_solve_opts *opts,
                                 dfm_solve_info *info, void *stream_) {
   return solve_impl(op, rho0, rho, nrhs, opts, info, false, stream_);
+}
+
+extern "C" dfm_status dfm_solve_groups(dfm_op op, const double *rho0, double *rho, int nrhs,
+                                       const dfm_solve_opts *opts, const int64_t *tet_offsets, int ngroups,
+                                       dfm_solve_info *info, void *stream_) {
+  DFM_REQUIRE(op && rho0 && rho && opts && tet_offsets, DFM_E_INVALID, "null argument");
+  DFM_REQUIRE(nrhs >= 1 && nrhs <= 65535, DFM_E_INVALID, "nrhs must be in 1..65535");
+  DFM_REQUIRE(ngroups >= 1 && ngroups <= 65535, DFM_E_INVALID, "ngroups must be in 1..65535");
+  DFM_REQUIRE(opts->method == 0 && opts->precision == 1, DFM_E_UNSUPPORTED,
+              "instance groups are solved with method 0 and precision 1");
+  DFM_REQUIRE(opts->max_iter >= 1 && opts->rtol > 0.0, DFM_E_INVALID, "need max_iter >= 1 and rtol > 0");
+  DFM_REQUIRE(opts->warm_start == 0 || opts->warm_start == 1, DFM_E_INVALID, "warm_start must be 0 or 1");
+  DFM_REQUIRE(tet_offsets[0] == 0 && tet_offsets[ngroups] == op->nt, DFM_E_INVALID,
+              "tet_offsets must start at 0 and end at nt");
+  std::vector<int64_t> toff(tet_offsets, tet_offsets + ngroups + 1);
+  for (int g = 0; g < ngroups; ++g)
+    DFM_REQUIRE(toff[g + 1] > toff[g], DFM_E_INVALID, "tet_offsets must increase strictly");
+  return solve_groups_impl(op, rho0, rho, nrhs, opts, toff, info, (hipStream_t)stream_);
 }

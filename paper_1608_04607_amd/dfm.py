@@ -150,6 +150,30 @@ class Operator:
             check(code)
         return rho, [(i.iters, i.restarts, i.relres) for i in info]
 
+    def solve_groups(self, rho0, tet_offsets, rtol=1e-8, max_iter=20000, stream=None, raise_nonconv=True, rho=None):
+        """Batched solve of independent instances packed into this operator
+        (dfm_solve_groups): instance g owns tets [tet_offsets[g], tet_offsets[g+1]).
+        Returns rho and info [ngroups][nrhs] of (iters, restarts, relres)."""
+        rho0 = _dev(rho0, torch.float64)
+        nrhs = 1 if rho0.dim() == 1 else rho0.shape[0]
+        warm = rho is not None
+        if warm:
+            if rho.shape != rho0.shape or rho.dtype != torch.float64 or not rho.is_cuda or not rho.is_contiguous():
+                raise TypeError("rho must be a contiguous CUDA float64 tensor shaped like rho0")
+        else:
+            rho = torch.empty_like(rho0)
+        G = len(tet_offsets) - 1
+        offs = (C.c_int64 * (G + 1))(*[int(v) for v in tet_offsets])
+        opts = SolveOpts(0, 1, max_iter, rtol, 1, int(warm))
+        info = (SolveInfo * (G * nrhs))()
+        code = _lib.load().dfm_solve_groups(self.handle, _ptr(rho0), _ptr(rho), nrhs, C.byref(opts), offs, G, info,
+                                            _stream(stream))
+        if code != 0 and (raise_nonconv or code != -5):
+            check(code)
+        out = [[(info[g * nrhs + r].iters, info[g * nrhs + r].restarts, info[g * nrhs + r].relres)
+                for r in range(nrhs)] for g in range(G)]
+        return rho, out
+
     def source_points(self, xyz, flux=1.0, stream=None):
         xyz = _dev(xyz, torch.float64)
         ns = xyz.shape[0]

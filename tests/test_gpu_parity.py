@@ -381,6 +381,55 @@ def test_batched_mixed_neumann_warm_start(small):
         assert rel(rho[r].cpu().numpy(), osv.solve_direct(A, rhs[r])) < 1e-7
 
 
+def test_solve_groups_matches_oracle():
+    """dfm_solve_groups on two instances packed into one operator: a box with strong
+    damping (fast) and one with weak damping (slow).  Every (instance, rhs) pair
+    meets the tolerance against the oracle's direct solve of that instance alone,
+    the fast instance leaves the products early, and offsets that cut a connected
+    mesh are refused."""
+    from paper_1608_04607_amd import dfm
+    from paper_1608_04607_amd._lib import DFMError
+    say("[solve] instance groups, batched FP32 Neumann + FP64 refinement")
+    bs = oa.Basis(0, 0, 4, 6, oq.SEAM_RULE)
+    va, ta, ra = box(1, 0.1, seed=21)
+    vb, tb, rb = box(2, 0.1, seed=22)
+    mua, mub = np.full(ta.shape[0], 3.0), np.full(tb.shape[0], 0.02)
+    v = np.concatenate([va, vb + np.array([3.0, 0.0, 0.0])])
+    t = np.concatenate([ta, tb + va.shape[0]])
+    refl = np.concatenate([ra, rb])
+    mu = np.concatenate([mua, mub])
+    g = gpu_mesh(v, t, refl)
+    op = gpu_op(g, mu, bs)
+    offs = [0, ta.shape[0], t.shape[0]]
+    rhs = np.random.default_rng(23).standard_normal((3, op.ndof))
+    rho, info = op.solve_groups(torch.tensor(rhs, device=DEV), offs, rtol=1e-10)
+    _, info1 = op.solve_groups(torch.tensor(rhs, device=DEV), [0, t.shape[0]], rtol=1e-10)
+    say(f"    products per instance {[row[0][0] for row in info]} (one group: {info1[0][0][0]}), "
+        f"relres {[max(x[2] for x in row) for row in info]}")
+    # the fast instance leaves early; the slow one needs about what the whole operator needs
+    assert info[0][0][0] < info[1][0][0] // 4
+    assert info[1][0][0] <= 1.25 * info1[0][0][0] + 16
+    rho = rho.cpu().numpy()
+    K = op.K
+    for gi, (vv, tt, rr, mm) in enumerate(((va, ta, ra, mua), (vb, tb, rb, mub))):
+        Bo, desto = oa.assemble(om.build_mesh(vv, tt, rr), bs, mm)
+        A = osv.to_sparse(Bo, desto)
+        a, b = 4 * K * offs[gi], 4 * K * offs[gi + 1]
+        for r in range(3):
+            assert info[gi][r][2] <= 1e-10
+            assert osv.relres(A, rhs[r, a:b], rho[r, a:b]) <= 2e-10
+            ref = osv.solve_direct(A, rhs[r, a:b])
+            assert rel(rho[r, a:b], ref) < 1e-8
+    # a connected mesh cut in two
+    v2, t2, r2 = box(2, 0.1, seed=24)
+    g2 = gpu_mesh(v2, t2, r2)
+    op2 = gpu_op(g2, np.full(t2.shape[0], 0.1), bs)
+    with pytest.raises(DFMError, match="INVALID"):
+        op2.solve_groups(torch.ones((1, op2.ndof), dtype=torch.float64, device=DEV), [0, 10, t2.shape[0]])
+    op2.close()
+    op.close()
+
+
 @pytest.mark.parametrize("order,family,degree", [(1, 0, 8), (0, 1, 6), (0, 0, 10), (0, 0, 4)])
 def test_fp32_assembly_matches_oracle(order, family, degree):
     """dtype 1: contraction on the FP32 matrix cores, B stored in FP32 -- blocks within
