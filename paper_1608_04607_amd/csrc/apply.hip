@@ -240,13 +240,29 @@ constexpr int SPMM_THREADS = 512;
 constexpr int SPMM_RT = 128;                  // right-hand sides per workgroup
 constexpr int SPMM_ROWS = 96;                 // output rows per workgroup
 constexpr int SPMM_KC = 32;                   // contraction chunk (columns)
-constexpr int SPMM_BLD = SPMM_ROWS + 4;       // LDS row stride of the B chunk [col][row]
-constexpr int SPMM_XLD = SPMM_RT + 4;         // LDS row stride of the x chunk [col][rhs]
+#ifndef DFM_SPMM_BPAD
+#define DFM_SPMM_BPAD 16
+#endif
+#ifndef DFM_SPMM_XPAD
+#define DFM_SPMM_XPAD 4
+#endif
+#ifndef DFM_SPMM_XT
+#define DFM_SPMM_XT 1
+#endif
+constexpr int SPMM_BLD = SPMM_ROWS + DFM_SPMM_BPAD;   // LDS row stride of the B chunk [col][row]
+constexpr int SPMM_XLD = SPMM_RT + DFM_SPMM_XPAD;     // LDS row stride of the x chunk [col][rhs]
+// x chunk stored [rhs][col] with row stride SPMM_XLDT instead: the coalesced loads
+// (lanes along columns) store to consecutive banks, and the MFMA fragment reads
+// (lanes along rhs, 2 columns per half-wave) hit 2 rhs + column, all distinct
+constexpr bool SPMM_XT = DFM_SPMM_XT != 0;
+constexpr int SPMM_XLDT = 34;
 constexpr int SPMM_YLD = SPMM_ROWS + 1;       // LDS row stride of the result [rhs][row]
 constexpr int SPMM_NB = SPMM_KC * SPMM_ROWS / SPMM_THREADS;   // B chunk values per thread
 constexpr int SPMM_NX = SPMM_KC * SPMM_RT / SPMM_THREADS;     // x chunk values per thread
-constexpr int SPMM_LDS_CHUNK = SPMM_KC * (SPMM_BLD + SPMM_XLD), SPMM_LDS_OUT = SPMM_RT * SPMM_YLD;
+constexpr int SPMM_LDS_CHUNK = SPMM_KC * SPMM_BLD + (SPMM_XT ? SPMM_RT * SPMM_XLDT : SPMM_KC * SPMM_XLD),
+              SPMM_LDS_OUT = SPMM_RT * SPMM_YLD;
 constexpr size_t SPMM_LDS = sizeof(float) * (size_t)(SPMM_LDS_CHUNK > SPMM_LDS_OUT ? SPMM_LDS_CHUNK : SPMM_LDS_OUT);
+constexpr int SPMM_EPT = (SPMM_RT * SPMM_ROWS + SPMM_THREADS - 1) / SPMM_THREADS;  // output values per thread
 static_assert(SPMM_NB * SPMM_THREADS == SPMM_KC * SPMM_ROWS && SPMM_NX * SPMM_THREADS == SPMM_KC * SPMM_RT, "");
 
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -259,7 +275,7 @@ __global__ __launch_bounds__(SPMM_THREADS, 4) void k_spmm32(const float *__restr
                                                            const uint8_t *__restrict__ gact) {
   extern __shared__ float lds[];
   float *bs = lds;                              // [SPMM_KC][SPMM_BLD]
-  float *xs = lds + SPMM_KC * SPMM_BLD;         // [SPMM_KC][SPMM_XLD]
+  float *xs = lds + SPMM_KC * SPMM_BLD;         // [SPMM_RT][SPMM_XLDT] (or [SPMM_KC][SPMM_XLD])
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   // workgroups are dealt to the 8 XCDs in turn (blockIdx.x % 8): the four block
@@ -321,7 +337,10 @@ __global__ __launch_bounds__(SPMM_THREADS, 4) void k_spmm32(const float *__restr
 #pragma unroll
     for (int u = 0; u < SPMM_NB; ++u) bs[bcol[u] * SPMM_BLD + brow[u] - m0] = pb[u];
 #pragma unroll
-    for (int u = 0; u < SPMM_NX; ++u) xs[xc * SPMM_XLD + (xr - r0) + u * XRS] = px[u];
+    for (int u = 0; u < SPMM_NX; ++u) {
+      if (SPMM_XT) xs[(xr - r0 + u * XRS) * SPMM_XLDT + xc] = px[u];
+      else xs[xc * SPMM_XLD + (xr - r0) + u * XRS] = px[u];
+    }
   };
 
   const int wr = wave >> 2, wc = wave & 3;      // row half, rhs quarter
@@ -332,11 +351,7 @@ __global__ __launch_bounds__(SPMM_THREADS, 4) void k_spmm32(const float *__restr
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
 
-  load_chunk(0);
-  for (int ch = 0; ch < nchunk; ++ch) {
-    store_chunk();
-    __syncthreads();
-    if (ch + 1 < nchunk) load_chunk(ch + 1);   // in flight while this chunk is contracted
+  auto contract = [&]() {
 #pragma unroll
     for (int ks = 0; ks < SPMM_KC / 4; ++ks) {
       const int c = ks * 4 + kq;
@@ -344,14 +359,41 @@ __global__ __launch_bounds__(SPMM_THREADS, 4) void k_spmm32(const float *__restr
 #pragma unroll
       for (int a = 0; a < 3; ++a) av[a] = bs[c * SPMM_BLD + (wr * 3 + a) * 16 + col];
 #pragma unroll
-      for (int b = 0; b < 2; ++b) bv[b] = xs[c * SPMM_XLD + (wc * 2 + b) * 16 + col];
+      for (int b = 0; b < 2; ++b)
+        bv[b] = SPMM_XT ? xs[((wc * 2 + b) * 16 + col) * SPMM_XLDT + c] : xs[c * SPMM_XLD + (wc * 2 + b) * 16 + col];
 #pragma unroll
       for (int a = 0; a < 3; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
     }
+  };
+  // output element k of this thread: i = tid + k * SPMM_THREADS -> (rhs i / nrows, row i % nrows)
+  const int nrows = min(SPMM_ROWS, K - m0);
+  const int64_t ob = (int64_t)dest[br] * K + m0;
+  float epre[SPMM_EPT];
+
+  load_chunk(0);
+  for (int ch = 0; ch + 1 < nchunk; ++ch) {
+    store_chunk();
+    __syncthreads();
+    load_chunk(ch + 1);   // in flight while this chunk is contracted
+    contract();
     __syncthreads();
   }
+  store_chunk();
+  __syncthreads();
+  if (e) {
+    // last chunk: the running-sum values of the output tile load while it is
+    // contracted (the chunk prefetch registers are free by now)
+#pragma unroll
+    for (int k = 0; k < SPMM_EPT; ++k) {
+      const int i = tid + k * SPMM_THREADS;
+      const int r = i / nrows, m = i - r * nrows;
+      epre[k] = (i < SPMM_RT * nrows && r0 + r < R) ? e[(int64_t)(r0 + r) * ndof + ob + m] : 0.0f;
+    }
+  }
+  contract();
+  __syncthreads();
   // result tile: lane holds rows 4 (lane / 16) + q of each 16-row tile, rhs lane % 16
   float *ys = lds;                              // [SPMM_RT][SPMM_YLD]
 #pragma unroll
@@ -362,15 +404,15 @@ __global__ __launch_bounds__(SPMM_THREADS, 4) void k_spmm32(const float *__restr
       for (int q = 0; q < 4; ++q)
         ys[((wc * 2 + b) * 16 + col) * SPMM_YLD + (wr * 3 + a) * 16 + 4 * kq + q] = acc[a][b][q];
   __syncthreads();
-  const int nrows = min(SPMM_ROWS, K - m0);
-  const int64_t ob = (int64_t)dest[br] * K + m0;
-  for (int i = tid; i < SPMM_RT * nrows; i += SPMM_THREADS) {
+#pragma unroll
+  for (int k = 0; k < SPMM_EPT; ++k) {
+    const int i = tid + k * SPMM_THREADS;
     const int r = i / nrows, m = i - r * nrows;
-    if (r0 + r < R) {
+    if (i < SPMM_RT * nrows && r0 + r < R) {
       const float v = ys[r * SPMM_YLD + m];
       const int64_t o = (int64_t)(r0 + r) * ndof + ob + m;
       y[o] = v;
-      if (e) e[o] += v;
+      if (e) e[o] = epre[k] + v;
     }
   }
 }
