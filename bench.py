@@ -676,11 +676,13 @@ def main_box32_adjoint(args):
     """Receiver-energy gradients on the 49152-tet box: J = energy in [1.6,1.9] x
     [0.4,0.6]^2 of the stationary density for rho0 = sum_s w_s src_s over the first
     64 of the 128 point sources (w_s = 1).  One step = FP64 assembly -> 64 sources
-    -> forward FP64 GMRES(100) to 1e-10 -> receiver functional -> adjoint
-    (transposed FP64 GMRES(100) to 1e-10, dB/dmu contraction, dJ/dw = lambda .
-    src_s).  Checks, after the timed steps: duality g.rho = lambda.rho0, and a
-    central finite difference (step 1e-6, FP64 solves to 1e-12) of J in the mu of
-    the element with the largest gradient.  `value` is assembly blocks/s."""
+    -> forward GMRES(100) to 1e-10 -> receiver functional -> adjoint (transposed
+    GMRES(100) to 1e-10, dB/dmu contraction, dJ/dw = lambda . src_s), both solves
+    with FP32 corrections inside FP64 refinement.  After the timed steps: the same
+    two solves in plain FP64 (time and gradient difference), duality g.rho =
+    lambda.rho0, and a central finite difference (step 1e-6, FP64 solves to 1e-12)
+    of J in the mu of the element with the largest gradient.  `value` is assembly
+    blocks/s."""
     import numpy as np
 
     import synth
@@ -721,12 +723,12 @@ def main_box32_adjoint(args):
         e[1].record(stream)
         src = op.source_points(xyz)
         rho0 = src.sum(0)
-        rho, info = op.solve(rho0, method="gmres", rtol=1e-10, restart=100, max_iter=40000)
+        rho, info = op.solve(rho0, method="gmres", rtol=1e-10, restart=100, max_iter=40000, precision=1)
         e[2].record(stream)
         g = op.receiver_functional(box)
         J = float((g * rho).sum())
         e[3].record(stream)
-        lam, dmu, dw, ainfo = op.adjoint(rho, box, src=src, rtol=1e-10, restart=100, max_iter=40000)
+        lam, dmu, dw, ainfo = op.adjoint(rho, box, src=src, rtol=1e-10, restart=100, max_iter=40000, precision=1)
         e[4].record(stream)
         torch.cuda.synchronize()
         print(f"bench: step {i}: forward {info[0][0]} iterations, adjoint {ainfo[0]} iterations", file=sys.stderr,
@@ -740,6 +742,19 @@ def main_box32_adjoint(args):
     t_asm, t_fwd, t_g, t_adj = np.array(recs).mean(axis=0)
     duality = abs(J - float((lam * rho0).sum())) / abs(J)
     dmu_h = dmu.cpu().numpy()
+    # plain FP64 forward and adjoint solves of the same step, for comparison
+    print("bench: plain FP64 forward and adjoint solves", file=sys.stderr, flush=True)
+    e = [ev() for _ in range(3)]
+    e[0].record(stream)
+    rho64, info64 = op.solve(rho0, method="gmres", rtol=1e-10, restart=100, max_iter=40000)
+    e[1].record(stream)
+    _, dmu64, dw64, ainfo64 = op.adjoint(rho64, box, src=src, rtol=1e-10, restart=100, max_iter=40000)
+    e[2].record(stream)
+    torch.cuda.synchronize()
+    t_fwd64, t_adj64 = e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2])
+    grad_diff = max(float((dmu - dmu64).abs().max() / dmu64.abs().max()),
+                    float((dw - dw64).abs().max() / dw64.abs().max()))
+    del rho64, dmu64, dw64
     e_max = int(np.abs(dmu_h).argmax())
     op.close()
     del src, rho0, rho, lam
@@ -778,9 +793,16 @@ def main_box32_adjoint(args):
                    "gradient_sizes": {"d_mu": int(prob.nt), "d_w": 64}},
         "phase_ms": {"assemble": t_asm, "sources_and_forward_solve": t_fwd, "receiver_functional": t_g,
                      "adjoint": t_adj},
+        "solve_precision": "fp32 GMRES(100) corrections inside fp64 refinement, forward and transposed, to 1e-10",
         "forward_iters": info[0][0],
         "adjoint_iters": ainfo[0],
         "adjoint_relres": ainfo[2],
+        "fp64_forward_ms": t_fwd64,
+        "fp64_adjoint_ms": t_adj64,
+        "fp64_forward_iters": info64[0][0],
+        "fp64_adjoint_iters": ainfo64[0],
+        "speedup_vs_fp64": (t_fwd64 + t_adj64) / (t_fwd + t_adj),
+        "gradient_rel_diff_vs_fp64": grad_diff,
         "J": J,
         "duality_rel_diff": duality,
         "fd_check": {"element": e_max, "adjoint": float(dmu_h[e_max]), "central_difference": fd,

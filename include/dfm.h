@@ -88,7 +88,8 @@ typedef struct {
                         FP32 corrections on an FP32 copy of B (made on first use, kept
                         with the operator):
                         GMRES  -- FP32 GMRES with FP32 Krylov vectors and FP64
-                                  accumulation, one right-hand side after the other;
+                                  accumulation, one right-hand side after the other
+                                  (also for the transposed solve of dfm_adjoint);
                         Neumann -- FP32 Neumann partial sums for all nrhs right-hand
                                   sides together, one FP32 product per term (the
                                   kernels of dfm_apply_f32), until the next term of
@@ -249,7 +250,8 @@ dfm_status dfm_source_plane(dfm_op op, int axis, double value, int profile, cons
 dfm_status dfm_receiver_functional(dfm_op op, const double *mu, const double *box, double *g, void *stream);
 
 /* Gradients of J = g . rho by the adjoint of (I - B) rho = rho0 (Sec. 2, Eq. GovIE):
- * solves (I - B)^T lambda = g (FP64 GMRES or Neumann per opts, precision 0 only),
+ * solves (I - B)^T lambda = g (GMRES with precision 0 or 1, or FP64 Neumann, per
+ * opts; precision 1 needs the FP64 operator, dtype 0, and its FP32 copy),
  * then dJ/dmu_j = lambda^T dB/dmu_j rho + rho . dg/dmu_j for every tet and, for the
  * source weights w of rho0 = sum_s w_s rho0_s, dJ/dw_s = lambda . rho0_s.
  *   mu, box as for dfm_receiver_functional; rho device f64 [ndof] the forward

@@ -79,7 +79,8 @@ extern "C" dfm_status dfm_adjoint(dfm_op op, const double *mu, const double *box
                                   double *d_mu, double *d_w, dfm_solve_info *info, void *stream_) {
   DFM_REQUIRE(op && mu && box && rho && opts && lambda && d_mu, DFM_E_INVALID, "null argument");
   DFM_REQUIRE(nsrc >= 0 && (nsrc == 0 || (src && d_w)), DFM_E_INVALID, "src and d_w are needed when nsrc > 0");
-  DFM_REQUIRE(opts->precision == 0, DFM_E_UNSUPPORTED, "the adjoint solve is implemented in FP64 only");
+  DFM_REQUIRE(opts->precision == 0 || (opts->precision == 1 && opts->method == 1), DFM_E_UNSUPPORTED,
+              "the adjoint solve is FP64, or mixed precision with GMRES");
   hipStream_t st = (hipStream_t)stream_;
   const int64_t nblk = 12 * op->nt;
   double *blk_vec = nullptr, *blk_e = nullptr, *blk_b = nullptr, *g = nullptr;

@@ -186,41 +186,54 @@ __global__ void k_to_fp32(const double *__restrict__ a, float *__restrict__ b, i
 // since Kp is a multiple of 4) with coalesced 16-byte loads and reduces across
 // the wave, so B is read once, in order.
 constexpr int SPMVT_THREADS = 256;
-__global__ __launch_bounds__(SPMVT_THREADS) void k_spmv_t(const double *__restrict__ B,
-                                                         const int32_t *__restrict__ dest, int K, int Kp,
-                                                         const double *__restrict__ x, const double *__restrict__ v,
-                                                         double *__restrict__ y, double alpha, double beta) {
-  typedef double d2 __attribute__((ext_vector_type(2)));
+template <typename TB, typename TX>
+__global__ __launch_bounds__(SPMVT_THREADS) void k_spmv_t(const TB *__restrict__ B, const int32_t *__restrict__ dest,
+                                                         int K, int Kp, const TX *__restrict__ x,
+                                                         const TX *__restrict__ v, TX *__restrict__ y, double alpha,
+                                                         double beta) {
+  constexpr int VW = Vec<TB>::W;   // rows per 16-byte load
+  typedef typename Vec<TB>::T VT;
   extern __shared__ double xd[];  // [4][K]
   const int64_t j = blockIdx.x;
   for (int i = threadIdx.x; i < 4 * K; i += SPMVT_THREADS) {
     const int l = i / K, row = i - l * K;
-    xd[i] = x[(int64_t)dest[4 * j + l] * K + row];
+    xd[i] = (double)x[(int64_t)dest[4 * j + l] * K + row];
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t KKp = (int64_t)K * Kp;
-  for (int o = wave; o < 4 * K; o += SPMVT_THREADS / 64) {
-    const int l_in = o / K, col = o - l_in * K;
+  // lanes per output: the power of two that covers a column in 16-byte loads, so
+  // a wave reduces 64 / lpo outputs at once (one for long FP64 columns)
+  int lpo = 1;
+  while (lpo < 64 && lpo * VW < K) lpo <<= 1;
+  const int opw = 64 / lpo, sub = lane / lpo, li = lane - sub * lpo;
+  const int nout = 4 * K;
+  for (int o0 = wave * opw; o0 < nout; o0 += (SPMVT_THREADS / 64) * opw) {
+    const int o = o0 + sub;
+    const bool live = o < nout;
+    const int l_in = live ? o / K : 0, col = live ? o - l_in * K : 0;
     double acc = 0.0;
+    if (live) {
 #pragma unroll
-    for (int l_out = 0; l_out < 4; ++l_out) {
-      if (l_out == l_in) continue;
-      const int s = l_in < l_out ? l_in : l_in - 1;
-      const d2 *Bc = reinterpret_cast<const d2 *>(B + ((4 * j + l_out) * 3 + s) * KKp + (int64_t)col * Kp);
-      const double *xs = xd + l_out * K;
-      for (int r2 = lane; 2 * r2 < K; r2 += 64) {
-        const d2 b = __builtin_nontemporal_load(Bc + r2);   // rows 2 r2, 2 r2 + 1 (< Kp)
-        acc = fma(b[0], xs[2 * r2], acc);
-        if (2 * r2 + 1 < K) acc = fma(b[1], xs[2 * r2 + 1], acc);
+      for (int l_out = 0; l_out < 4; ++l_out) {
+        if (l_out == l_in) continue;
+        const int s = l_in < l_out ? l_in : l_in - 1;
+        const VT *Bc = reinterpret_cast<const VT *>(B + ((4 * j + l_out) * 3 + s) * KKp + (int64_t)col * Kp);
+        const double *xs = xd + l_out * K;
+        for (int rv = li; VW * rv < K; rv += lpo) {
+          const VT b = __builtin_nontemporal_load(Bc + rv);   // rows VW rv .. VW rv + VW - 1 (< Kp)
+#pragma unroll
+          for (int u = 0; u < VW; ++u)
+            if (VW * rv + u < K) acc = fma((double)b[u], xs[VW * rv + u], acc);
+        }
       }
     }
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-    if (lane == 0) {
+    for (int off = lpo >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (live && li == 0) {
       const int64_t g = (4 * j + l_in) * (int64_t)K + col;
       double r = beta * acc;
-      if (v) r = fma(alpha, v[g], r);
-      y[g] = r;
+      if (v) r = fma(alpha, (double)v[g], r);
+      y[g] = (TX)r;
     }
   }
 }
@@ -514,8 +527,18 @@ hipError_t ensure_fp32(dfm_op op, hipStream_t st) {
 
 hipError_t spmv_t(dfm_op op, const double *x, const double *v, double *y, double alpha, double beta, hipStream_t st) {
   if (!op->B) return hipErrorNotSupported;   // transposed products need the FP64 operator
-  hipLaunchKernelGGL(k_spmv_t, dim3((unsigned)op->nt), dim3(SPMVT_THREADS), sizeof(double) * 4 * op->K, st, op->B,
-                     op->dest, op->K, op->Kp, x, v, y, alpha, beta);
+  hipLaunchKernelGGL((k_spmv_t<double, double>), dim3((unsigned)op->nt), dim3(SPMVT_THREADS),
+                     sizeof(double) * 4 * op->K, st, op->B, op->dest, op->K, op->Kp, x, v, y, alpha, beta);
+  return hipGetLastError();
+}
+
+// y = alpha v + beta B32^T x for FP32 vectors (the inner solves of transposed
+// mixed-precision GMRES), FP64 accumulation
+hipError_t spmv32_t(dfm_op op, const float *x, const float *v, float *y, float alpha, float beta, hipStream_t st) {
+  if (!op->B32) return hipErrorNotSupported;
+  hipLaunchKernelGGL((k_spmv_t<float, float>), dim3((unsigned)op->nt), dim3(SPMVT_THREADS),
+                     sizeof(double) * 4 * op->K, st, op->B32, op->dest, op->K, op->Kp, x, v, y, (double)alpha,
+                     (double)beta);
   return hipGetLastError();
 }
 

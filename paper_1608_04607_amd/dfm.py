@@ -203,8 +203,10 @@ class Operator:
         check(_lib.load().dfm_receiver_functional(self.handle, _ptr(self.mu), bx, _ptr(g), _stream(stream)))
         return g
 
-    def adjoint(self, rho, box, src=None, method="gmres", rtol=1e-10, restart=50, max_iter=20000, stream=None):
-        """(lambda, dJ/dmu, dJ/dw, info) for J = receiver energy in `box`."""
+    def adjoint(self, rho, box, src=None, method="gmres", rtol=1e-10, restart=50, max_iter=20000, precision=0,
+                stream=None):
+        """(lambda, dJ/dmu, dJ/dw, info) for J = receiver energy in `box`; precision 1:
+        FP32 GMRES corrections inside FP64 refinement for the transposed solve."""
         rho = _dev(rho, torch.float64)
         nsrc = 0 if src is None else src.shape[0]
         src = _dev(src, torch.float64) if src is not None else None
@@ -212,7 +214,7 @@ class Operator:
         dmu = torch.empty((self.mesh.nt,), dtype=torch.float64, device=self.device)
         dw = torch.empty((max(nsrc, 1),), dtype=torch.float64, device=self.device)
         bx = (C.c_double * 6)(*box)
-        opts = SolveOpts(1 if method == "gmres" else 0, restart, max_iter, rtol, 0, 0)
+        opts = SolveOpts(1 if method == "gmres" else 0, restart, max_iter, rtol, int(precision), 0)
         info = SolveInfo()
         check(_lib.load().dfm_adjoint(self.handle, _ptr(self.mu), bx, _ptr(rho), _ptr(src), nsrc, C.byref(opts),
                                       _ptr(lam), _ptr(dmu), _ptr(dw), C.byref(info), _stream(stream)))

@@ -556,6 +556,33 @@ def test_adjoint_gradients_match_oracle(adj, order):
     assert rel(dw.cpu().numpy(), rho0s @ lam_o) < 1e-9
 
 
+def test_adjoint_mixed_precision_matches_oracle(adj):
+    """The transposed solve with FP32 GMRES corrections inside FP64 refinement
+    (precision 1) gives the oracle's adjoint and gradients."""
+    say("[adjoint] mixed precision")
+    v, t, refl, mu, box, pts = adj
+    bs = oa.Basis(1, 0, 2, 4, oq.SEAM_RULE)
+    m = om.build_mesh(v, t, refl)
+    op = gpu_op(gpu_mesh(v, t, refl), mu, bs)
+    src = op.source_points(torch.tensor(pts, device=DEV))
+    rho0 = src.sum(0)
+    rho, _ = op.solve(rho0, rtol=1e-13, restart=40, precision=1)
+    lam, dmu, dw, info = op.adjoint(rho, box, src=src, rtol=1e-12, restart=40, precision=1)
+    say(f"    adjoint info {info}")
+    assert info[2] <= 1e-12
+    B, dest = oa.assemble(m, bs, mu)
+    A = osv.to_sparse(B, dest)
+    g = oj.receiver_functional(m, bs, mu, box)
+    lam_o = osv.solve_direct(A.T.tocsr(), g)
+    rho_o = osv.solve_direct(A, osrc.project(m, bs, {"kind": "points", "xyz": pts}).sum(0))
+    assert rel(lam.cpu().numpy(), lam_o) < 1e-9
+    assert rel(dmu.cpu().numpy(), oj.gradient_mu(m, bs, mu, lam_o, rho_o, box)) < 1e-9
+    # and the FP64 transposed product of the same operator
+    x = torch.tensor(np.random.default_rng(31).standard_normal(op.ndof), device=DEV)
+    yt = op.apply(x, transpose=True).cpu().numpy()
+    assert rel(yt, A.T @ x.cpu().numpy()) < TOL
+
+
 def test_adjoint_gradient_vs_central_differences(adj):
     """GPU gradient against central differences of GPU forward solves (step 1e-6)."""
     say("[adjoint] central differences")
