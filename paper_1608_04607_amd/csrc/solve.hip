@@ -366,40 +366,6 @@ struct Ctx {
 // cs, sn (MAXV each), g (MAXV + 1)
 constexpr size_t DSC_DOUBLES = DS_H1 + 2 * (MAXV + 1) + (size_t)(MAXV + 1) * MAXV + 2 * MAXV + (MAXV + 1);
 
-// GMRES(m) on (I - B) x = b with x0 = 0, vectors of type T.  Stops when the
-// relative residual is <= rtol: the true residual when check_true (FP64 solves),
-// the Arnoldi estimate otherwise (inner solves of the refinement).
-// out[r] += sum_i v[r][i]^2 for the rows r of a [R][n] block (grid.y = R)
-template <typename T>
-__global__ __launch_bounds__(RED_THREADS) void k_row_norms2(const T *__restrict__ v, int64_t n, double *__restrict__ out) {
-  __shared__ double red[NWAVE];
-  const T *row = v + blockIdx.y * n;
-  double acc = 0.0;
-  for (int64_t i = blockIdx.x * (int64_t)RED_THREADS + threadIdx.x; i < n; i += (int64_t)gridDim.x * RED_THREADS) {
-    const double a = (double)row[i];
-    acc = fma(a, a, acc);
-  }
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = 0.0;
-    for (int w = 0; w < NWAVE; ++w) t += red[w];
-    atomicAdd(out + blockIdx.y, t);
-  }
-}
-
-// t[r][i] = e[r][i] = (float)(s[r] * v[r][i])
-__global__ void k_rows_to_f32(const double *__restrict__ v, const double *__restrict__ s, float *__restrict__ t,
-                              float *__restrict__ e, int64_t n) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int64_t o = blockIdx.y * n + i;
-  const float a = (float)(s[blockIdx.y] * v[o]);
-  t[o] = a;
-  e[o] = a;
-}
-
 // x[r][i] += a[r] * e[r][i]
 __global__ void k_rows_axpy(const double *__restrict__ a, const float *__restrict__ e, double *__restrict__ x,
                             int64_t n) {
@@ -473,6 +439,9 @@ __global__ void k_check_groups(const int32_t *__restrict__ dest, const int32_t *
     if (gid[dest[s] >> 2] != gid[s >> 2]) atomicOr(bad, 1u);
 }
 
+// GMRES(m) on (I - B) x = b with x0 = 0, vectors of type T.  Stops when the
+// relative residual is <= rtol: the true residual when check_true (FP64 solves),
+// the Arnoldi estimate otherwise (inner solves of the refinement).
 template <typename T>
 hipError_t gmres(Ctx &c, const T *b, T *x, T *V, T *w, T *t, int m, double rtol, int max_iter, bool check_true,
                  int &its, int &restarts, double &rel, bool &done) {
