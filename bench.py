@@ -261,9 +261,12 @@ def main():
     spmv_bytes = 8.0 * (12 * (ndof // (4 * K)) * K * K + 2 * ndof)
     spmv_gbs = spmv_bytes / (t_spmv / 1e3) / 1e9
     t_spmv_step = t_spmv * info[0]  # FP64 solve's operator applications
+    asm_traffic = measured_traffic("k_assemble")
     roof_asm = {"kernel": "k_assemble", "bound": "mfma", "achieved": asm_tflops, "peak": FP64_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": asm_tflops / FP64_PEAK_TFLOPS, "traffic": measured_traffic("k_assemble"),
-                "algorithmic": f"2*Q*K^2 flop per block, Q summed over blocks = {nodes}, K = {K}"}
+                "unit": "TFLOP/s", "frac": asm_tflops / FP64_PEAK_TFLOPS, "traffic": asm_traffic,
+                "algorithmic": f"2*Q*K^2 flop per block, Q summed over blocks = {nodes}, K = {K}",
+                "hbm_GBs": None if asm_traffic is None else asm_traffic / (t_asm / 1e3) / 1e9,
+                "hbm_frac": None if asm_traffic is None else asm_traffic / (t_asm / 1e3) / 1e9 / HBM_PEAK_GBS}
     roof_spmv = {"kernel": "k_spmv", "bound": "hbm", "achieved": spmv_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                  "frac": spmv_gbs / HBM_PEAK_GBS, "traffic": measured_traffic("k_spmv_f64"),
                  "algorithmic": "8*(12*N*K^2 + 2*ndof) bytes per launch (B once, x and y once)"}
