@@ -28,7 +28,12 @@
 // vertices Y, Z, D.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1371,10 +1376,17 @@ struct TileLayout {
   int nsplit, wr_waves, shape;
 };
 
-TileLayout choose_layout(int R, int C, int pq, int dm) {
-  TileLayout best{0, 0, -1};
-  int best_mm = 0, best_ml = 0;
-  for (int nsplit = 1; nsplit <= C && best.shape < 0; ++nsplit) {
+// Every layout whose rectangles are instantiated, cheapest first: fewest column
+// splits, then MFMA work on the busiest SIMD, then fragment loads.  Splits beyond
+// the fewest that works plus two are not considered.
+std::vector<TileLayout> layout_candidates(int R, int C, int pq, int dm) {
+  struct Cand {
+    TileLayout lay;
+    int mm, ml;
+  };
+  std::vector<Cand> all;
+  int first = 0;
+  for (int nsplit = 1; nsplit <= C && (first == 0 || nsplit <= first + 2); ++nsplit) {
     for (int WR : {1, 2, 4, 8}) {
       const int WC = 8 / WR;
       int rbmax = 0, cbmax = 0, rbmin = 1 << 30, cbmin = 1 << 30;
@@ -1409,14 +1421,104 @@ TileLayout choose_layout(int R, int C, int pq, int dm) {
         mm = simd_mfma[s] > mm ? simd_mfma[s] : mm;
         ml = simd_load[s] > ml ? simd_load[s] : ml;
       }
-      if (best.shape < 0 || mm < best_mm || (mm == best_mm && ml < best_ml)) {
-        best = TileLayout{nsplit, WR, shape};
-        best_mm = mm;
-        best_ml = ml;
-      }
+      if (first == 0) first = nsplit;
+      all.push_back(Cand{TileLayout{nsplit, WR, shape}, mm, ml});
     }
   }
-  return best;
+  std::stable_sort(all.begin(), all.end(), [](const Cand &x, const Cand &y) {
+    if (x.lay.nsplit != y.lay.nsplit) return x.lay.nsplit < y.lay.nsplit;
+    if (x.mm != y.mm) return x.mm < y.mm;
+    return x.ml < y.ml;
+  });
+  std::vector<TileLayout> out;
+  for (const Cand &c : all) out.push_back(c.lay);
+  return out;
+}
+
+TileLayout choose_layout(int R, int C, int pq, int dm) {
+  std::vector<TileLayout> c = layout_candidates(R, C, pq, dm);
+  return c.empty() ? TileLayout{0, 0, -1} : c[0];
+}
+
+// the same rectangle compiled for the degree itself, when there is one
+int exact_shape(int shape, int pq, int D) {
+  for (int k = 0; k < NSHAPES; ++k)
+    if (SHAPES[k][0] == SHAPES[shape][0] && SHAPES[k][1] == SHAPES[shape][1] && SHAPES[k][2] == pq && SHAPES[k][3] == D)
+      return k;
+  return shape;
+}
+
+// Layout autotuning: on the first operator of a basis (per process), the three
+// cheapest candidate layouts are timed on the operator's first blocks and the
+// fastest is kept.  Every layout sums each entry over the same directions in the
+// same order, so the choice changes speed only, never B.  DFM_TUNE=0 turns it off;
+// DFM_TUNE_LOG=1 reports the timings on stderr.
+struct TuneKey {
+  int R, C, PQ, D, dtype, n, family, rule;
+  bool operator<(const TuneKey &o) const {
+    const int a[8] = {R, C, PQ, D, dtype, n, family, rule}, b[8] = {o.R, o.C, o.PQ, o.D, o.dtype, o.n, o.family, o.rule};
+    for (int i = 0; i < 8; ++i)
+      if (a[i] != b[i]) return a[i] < b[i];
+    return false;
+  }
+};
+std::map<TuneKey, TileLayout> g_tuned;
+std::mutex g_tune_mu;
+constexpr int TUNE_CANDIDATES = 3;
+constexpr int64_t TUNE_BLOCKS = 1024;
+
+hipError_t tune_layout(const TuneKey &key, const std::vector<TileLayout> &cand, AsmArgs a, size_t lds, bool fp32,
+                       hipStream_t st, TileLayout &chosen) {
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tuned.find(key);
+    if (it != g_tuned.end()) {
+      chosen = it->second;
+      return hipSuccess;
+    }
+  }
+  const int nc = (int)std::min<size_t>(cand.size(), TUNE_CANDIDATES);
+  a.nblocks = std::min<int64_t>(a.nblocks, TUNE_BLOCKS);
+  hipEvent_t e0, e1;
+  hipError_t e = hipEventCreate(&e0);
+  if (e != hipSuccess) return e;
+  e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return e;
+  }
+  float best_ms = 0.0f;
+  std::vector<float> ms(nc, 0.0f);
+  chosen = cand[0];
+  for (int i = 0; i < nc && e == hipSuccess; ++i) {
+    a.nsplit = cand[i].nsplit;
+    a.wr_waves = cand[i].wr_waves;
+    e = launch_shape(cand[i].shape, fp32, a, lds, st);   // first launch of the shape: not timed
+    if (e == hipSuccess) e = hipEventRecord(e0, st);
+    if (e == hipSuccess) e = launch_shape(cand[i].shape, fp32, a, lds, st);
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms[i], e0, e1);
+    if (e == hipSuccess && (i == 0 || ms[i] < best_ms)) {
+      best_ms = ms[i];
+      chosen = cand[i];
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return e;
+  const char *log = getenv("DFM_TUNE_LOG");
+  if (log && log[0] == '1') {
+    fprintf(stderr, "dfm: layout for R=%d C=%d PQ=%d D=%d dtype=%d n=%d:", key.R, key.C, key.PQ, key.D, key.dtype,
+            key.n);
+    for (int i = 0; i < nc; ++i)
+      fprintf(stderr, " [%dx%d rect, %d split, %d wave rows] %.3f ms%s", SHAPES[cand[i].shape][0],
+              SHAPES[cand[i].shape][1], cand[i].nsplit, cand[i].wr_waves, ms[i], i == 0 ? " (search)" : "");
+    fprintf(stderr, " -> %dx%d, %d split\n", SHAPES[chosen.shape][0], SHAPES[chosen.shape][1], chosen.nsplit);
+  }
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  g_tuned[key] = chosen;
+  return hipSuccess;
 }
 
 // node-chunk length and dynamic LDS bytes of the block kernels for an operator
@@ -1546,12 +1648,10 @@ extern "C" dfm_status dfm_assemble(dfm_mesh mesh, const dfm_basis *basis, const 
   const int R = Mp / 16;
   // degree bound of the node code: 8, 12 or 16, or the degree itself where its
   // rectangle is instantiated with that bound (no runtime degree guards then)
-  TileLayout lay = choose_layout(R, PQ * Mp / 16, PQ, D <= 8 ? 8 : (D <= 12 ? 12 : 16));
-  DFM_REQUIRE(lay.shape >= 0, DFM_E_UNSUPPORTED, "no contraction layout for this basis size");
-  for (int k = 0; k < NSHAPES; ++k)
-    if (SHAPES[k][0] == SHAPES[lay.shape][0] && SHAPES[k][1] == SHAPES[lay.shape][1] && SHAPES[k][2] == PQ &&
-        SHAPES[k][3] == D)
-      lay.shape = k;
+  std::vector<TileLayout> cands = layout_candidates(R, PQ * Mp / 16, PQ, D <= 8 ? 8 : (D <= 12 ? 12 : 16));
+  DFM_REQUIRE(!cands.empty(), DFM_E_UNSUPPORTED, "no contraction layout for this basis size");
+  for (TileLayout &c : cands) c.shape = exact_shape(c.shape, PQ, D);
+  TileLayout lay = cands[0];
   // nodes per chunk: two halves of 64 when the LDS allows
   int chunk;
   size_t lds;
@@ -1696,6 +1796,18 @@ extern "C" dfm_status dfm_assemble(dfm_mesh mesh, const dfm_basis *basis, const 
   hipLaunchKernelGGL(k_cells, dim3((unsigned)((nblocks + CELL_THREADS - 1) / CELL_THREADS)), dim3(CELL_THREADS), 0,
                      st, a);
   TRY(hipGetLastError());
+  {
+    const char *tune = getenv("DFM_TUNE");
+    if (cands.size() > 1 && nblocks >= 4 * TUNE_BLOCKS && !(tune && tune[0] == '0')) {
+      const TuneKey key{R, PQ * Mp / 16, PQ, D, bs.dtype, bs.quad_n, bs.mom_family, bs.rule};
+      TRY(tune_layout(key, cands, a, lds, bs.dtype == 1, st, lay));
+      a.nsplit = lay.nsplit;
+      a.wr_waves = lay.wr_waves;
+      // the trial launches counted nodes and may have raised flags: start again
+      hipLaunchKernelGGL(k_fill_zero_words, dim3(1), dim3(64), 0, st, flags, nodes);
+      TRY(hipGetLastError());
+    }
+  }
   hipError_t le = launch_shape(lay.shape, bs.dtype == 1, a, lds, st);
   TRY(le);
   unsigned hflags = 0;
