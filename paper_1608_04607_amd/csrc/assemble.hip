@@ -1452,7 +1452,7 @@ int exact_shape(int shape, int pq, int D) {
 // cheapest candidate layouts are timed on the operator's first blocks and the
 // fastest is kept.  Every layout sums each entry over the same directions in the
 // same order, so the choice changes speed only, never B.  DFM_TUNE=0 turns it off;
-// DFM_TUNE_LOG=1 reports the timings on stderr.
+// DFM_TUNE_LOG=1 reports the timings on stderr; DFM_LAYOUT=i forces candidate i.
 struct TuneKey {
   int R, C, PQ, D, dtype, n, family, rule;
   bool operator<(const TuneKey &o) const {
@@ -1797,8 +1797,15 @@ extern "C" dfm_status dfm_assemble(dfm_mesh mesh, const dfm_basis *basis, const 
                      st, a);
   TRY(hipGetLastError());
   {
+    // DFM_LAYOUT=i forces candidate i (experiments and the layout-independence
+    // test); otherwise the autotuner picks for large operators
+    const char *force = getenv("DFM_LAYOUT");
     const char *tune = getenv("DFM_TUNE");
-    if (cands.size() > 1 && nblocks >= 4 * TUNE_BLOCKS && !(tune && tune[0] == '0')) {
+    if (force && force[0] >= '0' && force[0] <= '9' && atoi(force) < (int)cands.size()) {
+      lay = cands[atoi(force)];
+      a.nsplit = lay.nsplit;
+      a.wr_waves = lay.wr_waves;
+    } else if (cands.size() > 1 && nblocks >= 4 * TUNE_BLOCKS && !(tune && tune[0] == '0')) {
       const TuneKey key{R, PQ * Mp / 16, PQ, D, bs.dtype, bs.quad_n, bs.mom_family, bs.rule};
       TRY(tune_layout(key, cands, a, lds, bs.dtype == 1, st, lay));
       a.nsplit = lay.nsplit;

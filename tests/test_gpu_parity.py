@@ -186,6 +186,25 @@ def test_assembly_matches_oracle(name, meshspec, mu, bs):
     assert err < TOL
 
 
+@pytest.mark.parametrize("order,dtype", [(1, 0), (0, 1)])
+def test_assembly_independent_of_layout(order, dtype, monkeypatch):
+    """Every contraction layout sums each entry over the same directions in the
+    same order: B is bit-identical whichever candidate layout runs (the autotuner
+    only changes speed)."""
+    from paper_1608_04607_amd import dfm
+    say(f"[assemble] layout independence P{order} dtype {dtype}")
+    v, t, refl = box(2, 0.15, seed=6)
+    mu = torch.full((t.shape[0],), 0.3, dtype=torch.float64, device=DEV)
+    mesh = gpu_mesh(v, t, refl)
+    out = []
+    for k in ("0", "1"):
+        monkeypatch.setenv("DFM_LAYOUT", k)
+        op = dfm.Operator(mesh, mu, order, dfm.LEGENDRE, 8, 4, rule=oq.SEAM_RULE, dtype=dtype)
+        out.append(op.export()[0].cpu().numpy())
+        op.close()
+    assert np.array_equal(out[0], out[1])
+
+
 def test_assembly_max_degree_p1_split():
     """D = 16 with the linear position basis (K = 459): the largest supported
     block, whose output tiles are spread over several workgroups."""
