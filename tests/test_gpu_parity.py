@@ -439,6 +439,20 @@ def test_solve_groups_matches_oracle():
             assert osv.relres(A, rhs[r, a:b], rho[r, a:b]) <= 2e-10
             ref = osv.solve_direct(A, rhs[r, a:b])
             assert rel(rho[r, a:b], ref) < 1e-8
+    # 20 right-hand sides: the matrix-core product, with the converged instance
+    # skipped by whole workgroups
+    rhs20 = np.random.default_rng(25).standard_normal((20, op.ndof))
+    rho20, info20 = op.solve_groups(torch.tensor(rhs20, device=DEV), offs, rtol=1e-9)
+    say(f"    20 rhs: products per instance {[row[0][0] for row in info20]}")
+    assert info20[0][0][0] < info20[1][0][0]
+    rho20 = rho20.cpu().numpy()
+    for gi, (vv, tt, rr, mm) in enumerate(((va, ta, ra, mua), (vb, tb, rb, mub))):
+        Bo, desto = oa.assemble(om.build_mesh(vv, tt, rr), bs, mm)
+        A = osv.to_sparse(Bo, desto)
+        a, b = 4 * K * offs[gi], 4 * K * offs[gi + 1]
+        for r in (0, 7, 19):
+            assert info20[gi][r][2] <= 1e-9
+            assert osv.relres(A, rhs20[r, a:b], rho20[r, a:b]) <= 2e-9
     # a connected mesh cut in two
     v2, t2, r2 = box(2, 0.1, seed=24)
     g2 = gpu_mesh(v2, t2, r2)
