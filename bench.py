@@ -42,6 +42,9 @@ def parse():
                          "box32-adjoint: receiver-energy gradients on the same box (64 sources); "
                          "uneven: 256 independent boxes of 500-20000 tets, degrees 4-10, 4 sources each")
     ap.add_argument("--instances", type=int, default=256, help="uneven: number of boxes")
+    ap.add_argument("--overlap", action="store_true",
+                    help="uneven: assemble the next group on a second stream beside the current solve "
+                         "(per-group assembly times then include the contention)")
     ap.add_argument("--fp64-sample", type=int, default=2,
                     help="uneven: boxes per degree solved one by one in plain FP64 for the comparison")
     ap.add_argument("--restart", type=int, default=100)
@@ -513,7 +516,7 @@ def main_uneven(args):
 
     stream = torch.cuda.current_stream()
 
-    def ev():
+    def ev_new():
         return torch.cuda.Event(enable_timing=True)
 
     if args.kernels_only:
@@ -531,41 +534,29 @@ def main_uneven(args):
         return
 
     def run(batch, label):
-        """Every group once; per group (mesh+assembly, sources, solve) ms and stats."""
+        """Every group once (with --overlap the next group is assembled beside the solve of
+        this one); per group (mesh+assembly, sources, solve) ms and stats."""
         rows = []
-        for g in batch.groups:
-            e = [ev() for _ in range(3)]
-            verts, tets, mu, refl, xyz, which = batch._concat(g)
-            torch.cuda.synchronize()
-            e[0].record(stream)
-            pos_order, family, degree, quad_n = g.key
-            g.mesh = dfm.Mesh(verts, tets, refl=refl)
-            g.op = dfm.Operator(g.mesh, mu, pos_order, family, degree, quad_n, rule=rule, dtype=1)
-            e[1].record(stream)
-            g.rho0 = g.op.source_points_sum(xyz, which, g.nsrc)
-            g.rho = None
-            e[2].record(stream)
-            t0 = time.perf_counter()
 
-            def progress(g, worst):
-                print(f"bench: {label} D={g.key[2]} ({len(g.members)} boxes, {g.mesh.nt} tets): "
-                      f"{g.products} batched products, worst box relres {worst:.2e}", file=sys.stderr, flush=True)
+        def progress(g, worst):
+            print(f"bench: {label} D={g.key[2]} ({len(g.members)} boxes, {g.mesh.nt} tets): "
+                  f"{g.products} batched products, worst box relres {worst:.2e}", file=sys.stderr, flush=True)
 
-            batch.solve(g, rtol=1e-8, progress=progress)
-            torch.cuda.synchronize()
-            t_solve = (time.perf_counter() - t0) * 1e3
-            rows.append({"degree": degree, "boxes": len(g.members), "tets": g.mesh.nt, "K": g.op.K,
+        def on_group(g, t_solve):
+            ev = g.events
+            rows.append({"degree": g.key[2], "boxes": len(g.members), "tets": g.mesh.nt, "K": g.op.K,
                          "blocks": g.op.nblocks, "nodes": g.op.nodes, "B_bytes": g.op.nbytes, "nrhs": g.nsrc,
-                         "ms_assemble": e[0].elapsed_time(e[1]), "ms_sources": e[1].elapsed_time(e[2]),
+                         "ms_assemble": ev[0].elapsed_time(ev[1]), "ms_sources": ev[1].elapsed_time(ev[2]),
                          "ms_solve": t_solve, "products": g.products,
                          "work_fraction": sum(mp * (g.tet_offsets[m + 1] - g.tet_offsets[m])
                                               for m, mp in enumerate(g.member_products)) / (g.products * g.mesh.nt),
                          "worst_member_relres": max(max(r) for r in g.relres)})
             if label == "step":
-                # the streaming FP32 product alone, 4 right-hand sides (HIP events on this stream)
+                # the streaming FP32 product alone, 4 right-hand sides (HIP events on this
+                # stream); the next group's assembly has finished by now
                 x32 = g.rho.float()
                 g.op.apply_f32(x32)
-                e0, e1 = ev(), ev()
+                e0, e1 = ev_new(), ev_new()
                 e0.record(stream)
                 for _ in range(5):
                     g.op.apply_f32(x32)
@@ -574,9 +565,8 @@ def main_uneven(args):
                 rows[-1]["ms_product"] = e0.elapsed_time(e1) / 5
                 del x32
                 rows[-1]["rho"] = [batch.solution(i).clone() for i in g.members[:args.fp64_sample]]
-            batch.release(g)
-            g.rho0 = g.rho = None
-            torch.cuda.empty_cache()
+
+        batch.solve_all(rtol=1e-8, overlap=args.overlap, progress=progress, on_group=on_group)
         return rows
 
     for _ in range(args.warmup):
@@ -648,6 +638,7 @@ def main_uneven(args):
                    "boxes": len(probs), "tets": int(sum(r["tets"] for r in rows)), "blocks": int(nblocks),
                    "rhs": int(nrhs), "groups": [{k: v for k, v in r.items()} for r in rows]},
         "phase_ms": {"mesh_and_assemble": t_asm, "sources": t_src, "solve_batched": t_solve},
+        "overlap": args.overlap,
         "assemble_tflops_fp32": flops_asm / (t_asm / 1e3) / 1e12,
         "solve_ms_per_rhs": t_solve / nrhs,
         "solve_precision": "fp32 Neumann products on fp32-stored B, fp64 residuals; every box's own relres <= 1e-8; "

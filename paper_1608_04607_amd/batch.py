@@ -35,6 +35,8 @@ class Group:
     products: int = 0                # batched product launches
     member_products: list = field(default_factory=list)   # products that included each member
     relres: list = field(default_factory=list)   # [member][rhs] on the member's own residual
+    t_assembled: float = 0.0         # host time when the group's operator was ready
+    events: list = field(default_factory=list)   # timing events of assemble()
 
 
 class UnevenBatch:
@@ -82,12 +84,19 @@ class UnevenBatch:
         return cat(verts), cat(tets), cat(mu), cat(refl), cat(xyz), cat(which)
 
     def assemble(self, g, stream=None):
+        """Mesh, operator and right-hand sides of group g; g.events brackets the mesh
+        build + assembly and the source projection on `stream` (for timing)."""
         verts, tets, mu, refl, xyz, which = self._concat(g)
         pos_order, family, degree, quad_n = g.key
+        st = stream if stream is not None else torch.cuda.current_stream(self.device)
+        g.events = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        g.events[0].record(st)
         g.mesh = dfm.Mesh(verts, tets, refl=refl, stream=stream)
         g.op = dfm.Operator(g.mesh, mu, pos_order, family, degree, quad_n, rule=self.rule, stream=stream,
                             dtype=self.dtype)
+        g.events[1].record(st)
         g.rho0 = g.op.source_points_sum(xyz, which, g.nsrc, stream=stream)
+        g.events[2].record(st)
 
     def member_relres(self, g, stream=None):
         """[member][rhs] relative residual of every instance on its own unknowns."""
@@ -119,6 +128,60 @@ class UnevenBatch:
                 progress(g, worst)
             if worst <= rtol or g.products >= max_products:
                 return
+
+    def solve_all(self, rtol=1e-8, segment=2500, max_products=100000, overlap=False, progress=None, on_group=None):
+        """Assemble and solve every group, releasing each group's operator after its
+        solve.  With overlap, group g + 1 is assembled on a second stream (from a second
+        host thread, since dfm_assemble waits for its kernels) while group g is solved.
+        Both phases fill every compute unit, so on the 256-box batch this saves only
+        about 1 % of the wall time (the solve slows by what the assembly takes).  on_group(g, t) is called
+        after each group's solve (and after the next group's assembly has finished)
+        with the solve's host time in ms, before the group is released."""
+        import threading
+        import time
+
+        main = torch.cuda.current_stream(self.device)
+        side = torch.cuda.Stream(self.device) if overlap else main
+        err = []
+
+        def build(g):
+            try:
+                with torch.cuda.stream(side):
+                    self.assemble(g, stream=side)
+                side.synchronize()
+                g.t_assembled = time.perf_counter()
+            except Exception as e:  # reported on the main thread
+                err.append(e)
+
+        groups = list(self.groups)
+        if not groups:
+            return
+        build(groups[0])
+        for k, g in enumerate(groups):
+            if err:
+                raise err[0]
+            worker = None
+            if k + 1 < len(groups):
+                if overlap:
+                    worker = threading.Thread(target=build, args=(groups[k + 1],))
+                    worker.start()
+            # group g's assembly finished before build() returned (side.synchronize()),
+            # so the solve on the main stream needs no event wait on the side stream
+            t0 = time.perf_counter()
+            self.solve(g, rtol=rtol, segment=segment, max_products=max_products, progress=progress, stream=main)
+            main.synchronize()
+            t_solve = (time.perf_counter() - t0) * 1e3
+            if worker is not None:
+                worker.join()  # on_group then runs with the GPU to itself
+            if on_group:
+                on_group(g, t_solve)
+            self.release(g)
+            g.rho0 = None
+            torch.cuda.empty_cache()
+            if worker is None and k + 1 < len(groups):
+                build(groups[k + 1])
+        if err:
+            raise err[0]
 
     def solution(self, i):
         """rho of instance i: [nsrc][4 nt K] (the group's rhs s is the instance's source s)."""

@@ -724,7 +724,8 @@ def test_uneven_batch_matches_separate_solves():
     """Instances of different sizes, damping and degree, grouped by degree into one
     mesh each, assembled in FP32 in one launch per group and solved together: every
     instance meets the tolerance on its own residual and matches a separate solve of
-    that instance alone."""
+    that instance alone, also when the next group is assembled beside the current
+    group's solve."""
     from paper_1608_04607_amd import batch, dfm
     say("[batch] uneven instances")
     probs = [p for p in synth.problem_c5(n_instances=64, seed=5, tets_range=(200, 1500)) if p.nt <= 900]
@@ -739,7 +740,22 @@ def test_uneven_batch_matches_separate_solves():
         say(f"    group D={g.key[2]}: {len(g.members)} instances, {g.products} batched products, "
             f"worst member relres {max(max(r) for r in g.relres):.2e}")
         assert max(max(r) for r in g.relres) <= 1e-9
+    # the same batch through the pipeline that assembles the next group on a second
+    # stream while the current one is solved
+    say("    pipelined: assembly of the next group beside the current solve")
+    piped, order = {}, []
+    ub2 = batch.UnevenBatch(probs, dtype=1)
+
+    def keep(g, t_solve):
+        order.append(g.key[2])
+        assert max(max(r) for r in g.relres) <= 1e-9
+        for i in g.members:
+            piped[i] = ub2.solution(i).clone()
+
+    ub2.solve_all(rtol=1e-9, overlap=True, on_group=keep)
+    assert order == [g.key[2] for g in ub.groups] and sorted(piped) == list(range(len(probs)))
     for i, p in enumerate(probs):
+        assert rel(piped[i].cpu().numpy(), ub.solution(i).cpu().numpy()) < 1e-8
         mesh = gpu_mesh(p.verts, p.tets, p.refl)
         op = dfm.Operator(mesh, torch.tensor(p.mu, device=DEV), p.pos_order, dfm.LEGENDRE, p.mom_degree, p.quad_n,
                           rule=oq.SEAM_RULE, dtype=1)
