@@ -135,8 +135,8 @@ def measured_traffic(label, path=COUNTERS, field="bytes"):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (--gpus {args.gpus} requested); "
-              "the multi-GPU sharding of the path is described in DESIGN.md, not implemented.", file=sys.stderr)
+        print(f"bench.py: runs on one GPU only (--gpus {args.gpus} requested); sharding the assembly "
+              "and solve over several GPUs is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "box32-batched":
