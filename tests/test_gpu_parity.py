@@ -240,6 +240,60 @@ def test_full_size_box8_sampled():
     assert torch.isfinite(blocks).all()
 
 
+def test_full_size_box8_product_and_solve_sampled():
+    """The 3072-tet box in the launch configuration the bench times: the FP64
+    product of a seeded vector, and the FP64 and the mixed-precision GMRES(100)
+    solutions to 1e-8 of the Gaussian-patch source, checked on the block rows of
+    sampled tets.  A block row of B needs only its own tet's blocks, so the oracle
+    assembles just those tets: product rows must agree to 1e-10, and the residual
+    rho0 - rho + B rho on those rows must stay within the solver's tolerance of
+    |rho0| (a solution of another equation leaves residual rows of the size of
+    rho itself)."""
+    say("[solve] box8 P1 D8 n12 full size: product and GMRES solutions on sampled block rows")
+    p = synth.problem_c2()
+    bs = oa.Basis(p.pos_order, 0, p.mom_degree, p.quad_n, oq.SEAM_RULE)
+    g = gpu_mesh(p.verts, p.tets, p.refl)
+    op = gpu_op(g, p.mu, bs)
+    K = op.K
+    m = om.build_mesh(p.verts, p.tets, p.refl)
+    sample = np.random.default_rng(14).choice(p.nt, 3, replace=False)
+    Bo, desto = oa.assemble(m, bs, p.mu, tets=sample)
+
+    def block_rows(v):
+        """{destination slot: its K rows of B v} for the block rows of the sampled tets"""
+        vs = v.reshape(p.nt, 4, K)
+        out = {}
+        for a, j in enumerate(sample):
+            for lo in range(4):
+                ins = [l for l in range(4) if l != lo]
+                out[int(desto[a, lo])] = sum(Bo[a, lo, s] @ vs[j, li] for s, li in enumerate(ins))
+        return out
+
+    x = np.random.default_rng(15).standard_normal(op.ndof)
+    y = op.apply(torch.tensor(x, device=DEV)).cpu().numpy().reshape(-1, K)
+    want = block_rows(x)
+    slots = sorted(want)
+    err = rel(np.stack([y[q] for q in slots]), np.stack([want[q] for q in slots]))
+    say(f"    product: {len(slots)} block rows, rel err {err:.3e}")
+    assert err < TOL
+
+    rho0_t = op.source_plane(0, 0.0, profile=1, params=(0.0, 0.5, 0.5, 0.1))
+    rho0 = rho0_t.cpu().numpy()
+    assert rel(rho0, osrc.project(m, bs, p.source)[0]) < TOL
+    n0 = np.linalg.norm(rho0)
+    for prec in (0, 1):
+        rho_t, info = op.solve(rho0_t, method="gmres", rtol=1e-8, restart=100, max_iter=20000, precision=prec)
+        rho = rho_t.cpu().numpy()
+        brho = block_rows(rho)
+        r = np.concatenate([rho0.reshape(-1, K)[q] - rho.reshape(-1, K)[q] + brho[q] for q in slots])
+        rs = np.concatenate([rho.reshape(-1, K)[q] for q in slots])
+        say(f"    precision {prec}: {info[0][0]} iterations, relres {info[0][2]:.2e}; sampled residual rows "
+            f"{np.linalg.norm(r) / n0:.2e} of |rho0| (the rows of rho: {np.linalg.norm(rs) / n0:.2e})")
+        assert info[0][2] <= 1e-8
+        assert np.linalg.norm(rs) > 1e-3 * n0
+        assert np.linalg.norm(r) <= 1.5e-8 * n0
+
+
 def test_full_size_box32_sampled():
     """The 49152-tet box (P0, Legendre D = 12, n = 16, lognormal mu, seam rule)
     assembled whole on the GPU in FP64 and in FP32 -- the launches the batched
