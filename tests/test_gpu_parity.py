@@ -340,7 +340,8 @@ def test_full_size_uneven_degree10_group_sampled():
     """The degree-10 group of the 256-box uneven batch (64 boxes, 362508 tets,
     P0 x Legendre D = 10, n = 14) assembled in FP32 as one launch, as the bench
     does; a tet of its first and of its last box checked against the oracle on
-    that box's own mesh."""
+    that box's own mesh, and the streaming product of 4 right-hand sides on the
+    block rows of those tets."""
     from paper_1608_04607_amd.batch import UnevenBatch
     say("[assemble] uneven batch, degree-10 group full size (FP32), sampled")
     probs = synth.problem_c5()
@@ -348,6 +349,11 @@ def test_full_size_uneven_degree10_group_sampled():
     grp = next(g for g in ub.groups if g.key[2] == 10)
     ub.assemble(grp)
     say(f"    {len(grp.members)} boxes, {grp.mesh.nt} tets")
+    # the streaming product of the batched solve (4 right-hand sides) on the whole group
+    K = grp.op.K
+    gen = torch.Generator(device=DEV).manual_seed(17)
+    x = torch.rand(4, grp.op.ndof, generator=gen, device=DEV, dtype=torch.float32) - 0.5
+    y = grp.op.apply_f32(x)
     for m in (0, len(grp.members) - 1):
         p = probs[grp.members[m]]
         j = int(np.random.default_rng(13 + m).integers(p.nt))
@@ -359,6 +365,17 @@ def test_full_size_uneven_degree10_group_sampled():
         say(f"    box {grp.members[m]} tet {j}: rel err {err:.3e}")
         assert np.array_equal(dest.cpu().numpy(), np.asarray(desto) + 4 * off)
         assert err < 1e-5
+        got, want = [], []
+        for lo in range(4):
+            q = int(desto[0, lo]) + 4 * off
+            got.append(y[:, q * K:(q + 1) * K].double().cpu().numpy())
+            ins = [l for l in range(4) if l != lo]
+            want.append(sum(x[:, (4 * (off + j) + li) * K:(4 * (off + j) + li + 1) * K].double().cpu().numpy()
+                            @ Bo[0, lo, s].T for s, li in enumerate(ins)))
+        err = rel(np.stack(got), np.stack(want))
+        say(f"    streaming product, 4 rhs, block rows of that tet: rel err {err:.3e}")
+        assert err < 1e-5
+    del x, y
     ub.release(grp)
 
 
