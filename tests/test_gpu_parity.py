@@ -242,7 +242,8 @@ def test_full_size_box8_sampled():
 
 def test_full_size_box8_product_and_solve_sampled():
     """The 3072-tet box in the launch configuration the bench times: the FP64
-    product of a seeded vector, and the FP64 and the mixed-precision GMRES(100)
+    product and transposed product of a seeded vector, and the FP64 and the
+    mixed-precision GMRES(100)
     solutions to 1e-8 of the Gaussian-patch source, checked on the block rows of
     sampled tets.  A block row of B needs only its own tet's blocks, so the oracle
     assembles just those tets: product rows must agree to 1e-10, and the residual
@@ -275,6 +276,18 @@ def test_full_size_box8_product_and_solve_sampled():
     slots = sorted(want)
     err = rel(np.stack([y[q] for q in slots]), np.stack([want[q] for q in slots]))
     say(f"    product: {len(slots)} block rows, rel err {err:.3e}")
+    assert err < TOL
+    # the transposed product (the adjoint's): the slots of a tet's own faces only
+    # receive from that tet's blocks, (B^T x)[4j + l_in] = sum_{l_out != l_in} B^T x[dest]
+    yt = op.apply(torch.tensor(x, device=DEV), transpose=True).cpu().numpy().reshape(-1, K)
+    xs = x.reshape(-1, K)
+    got, want = [], []
+    for a, j in enumerate(sample):
+        for li in range(4):
+            got.append(yt[4 * j + li])
+            want.append(sum(Bo[a, lo, li if li < lo else li - 1].T @ xs[desto[a, lo]] for lo in range(4) if lo != li))
+    err = rel(np.stack(got), np.stack(want))
+    say(f"    transposed product: {len(got)} slots, rel err {err:.3e}")
     assert err < TOL
 
     rho0_t = op.source_plane(0, 0.0, profile=1, params=(0.0, 0.5, 0.5, 0.1))
