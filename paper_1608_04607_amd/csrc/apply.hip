@@ -281,13 +281,12 @@ constexpr int SPMM_XLD = SPMM_RT + DFM_SPMM_XPAD;     // LDS row stride of the x
 constexpr bool SPMM_XT = DFM_SPMM_XT != 0;
 constexpr int SPMM_XLDT = 34;
 constexpr int SPMM_YLD = SPMM_ROWS + 1;       // LDS row stride of the result [rhs][row]
-constexpr int SPMM_NB = SPMM_KC * SPMM_ROWS / SPMM_THREADS;   // B chunk values per thread
 constexpr int SPMM_NX = SPMM_KC * SPMM_RT / SPMM_THREADS;     // x chunk values per thread
 constexpr int SPMM_LDS_CHUNK = SPMM_KC * SPMM_BLD + (SPMM_XT ? SPMM_RT * SPMM_XLDT : SPMM_KC * SPMM_XLD),
               SPMM_LDS_OUT = SPMM_RT * SPMM_YLD;
 constexpr size_t SPMM_LDS = sizeof(float) * (size_t)(SPMM_LDS_CHUNK > SPMM_LDS_OUT ? SPMM_LDS_CHUNK : SPMM_LDS_OUT);
 constexpr int SPMM_EPT = (SPMM_RT * SPMM_ROWS + SPMM_THREADS - 1) / SPMM_THREADS;  // output values per thread
-static_assert(SPMM_NB * SPMM_THREADS == SPMM_KC * SPMM_ROWS && SPMM_NX * SPMM_THREADS == SPMM_KC * SPMM_RT, "");
+static_assert(SPMM_ROWS % 4 == 0 && SPMM_BLD % 4 == 0 && SPMM_NX * SPMM_THREADS == SPMM_KC * SPMM_RT, "");
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 
@@ -330,25 +329,33 @@ __global__ __launch_bounds__(SPMM_THREADS, 4) void k_spmm32(const float *__restr
     return;
   }
 
-  // coalesced chunk loads.  B chunk value i = tid + u * SPMM_THREADS -> (column
-  // i / SPMM_ROWS, row i % SPMM_ROWS), offsets fixed per thread; x chunk value i ->
-  // (rhs i / SPMM_KC, column i % SPMM_KC), the column the same for every u.
-  int bcol[SPMM_NB], brow[SPMM_NB];
+  // coalesced chunk loads, offsets fixed per thread.  The B chunk moves in 16-byte
+  // pieces: piece i = tid + u * SPMM_THREADS -> (column i / (SPMM_ROWS / 4), rows
+  // m0 + 4 (i % (SPMM_ROWS / 4)) .. +3).  Kp, the block row's offset 3 K Kp and m0
+  // are multiples of 4, so every piece is 16-byte aligned and lies wholly inside or
+  // wholly outside the column's Kp rows.  x chunk value i -> (rhs i / SPMM_KC,
+  // column i % SPMM_KC), the column the same for every u.
+  constexpr int SPMM_B4 = SPMM_KC * SPMM_ROWS / 4;                       // pieces per chunk
+  constexpr int SPMM_NB4 = (SPMM_B4 + SPMM_THREADS - 1) / SPMM_THREADS;  // pieces per thread
+  int bcol[SPMM_NB4], brow[SPMM_NB4];
 #pragma unroll
-  for (int u = 0; u < SPMM_NB; ++u) {
+  for (int u = 0; u < SPMM_NB4; ++u) {
     const int i = tid + u * SPMM_THREADS;
-    bcol[u] = i / SPMM_ROWS;
-    brow[u] = m0 + i % SPMM_ROWS;
+    bcol[u] = i < SPMM_B4 ? i / (SPMM_ROWS / 4) : SPMM_KC;   // SPMM_KC: no piece
+    brow[u] = m0 + 4 * (i % (SPMM_ROWS / 4));
   }
   const int xc = tid % SPMM_KC, xr = r0 + tid / SPMM_KC;   // rhs xr + u * (SPMM_THREADS / SPMM_KC)
   constexpr int XRS = SPMM_THREADS / SPMM_KC;
-  float pb[SPMM_NB], px[SPMM_NX];
+  v4f pb[SPMM_NB4];
+  float px[SPMM_NX];
   auto load_chunk = [&](int ch) {
     const int c0 = ch * SPMM_KC;
 #pragma unroll
-    for (int u = 0; u < SPMM_NB; ++u) {
+    for (int u = 0; u < SPMM_NB4; ++u) {
       const int c = c0 + bcol[u];
-      pb[u] = (c < ncol && brow[u] < Kp) ? __builtin_nontemporal_load(Bbr + (int64_t)c * Kp + brow[u]) : 0.0f;
+      pb[u] = (bcol[u] < SPMM_KC && c < ncol && brow[u] < Kp)
+                  ? __builtin_nontemporal_load(reinterpret_cast<const v4f *>(Bbr + (int64_t)c * Kp + brow[u]))
+                  : v4f{0.0f, 0.0f, 0.0f, 0.0f};
     }
     const int c = c0 + xc;
     const int s = c / K;
@@ -359,7 +366,8 @@ __global__ __launch_bounds__(SPMM_THREADS, 4) void k_spmm32(const float *__restr
   };
   auto store_chunk = [&]() {
 #pragma unroll
-    for (int u = 0; u < SPMM_NB; ++u) bs[bcol[u] * SPMM_BLD + brow[u] - m0] = pb[u];
+    for (int u = 0; u < SPMM_NB4; ++u)
+      if (bcol[u] < SPMM_KC) *reinterpret_cast<v4f *>(bs + bcol[u] * SPMM_BLD + brow[u] - m0) = pb[u];
 #pragma unroll
     for (int u = 0; u < SPMM_NX; ++u) {
       if (SPMM_XT) xs[(xr - r0 + u * XRS) * SPMM_XLDT + xc] = px[u];
