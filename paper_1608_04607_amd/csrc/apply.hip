@@ -17,16 +17,11 @@ namespace {
 
 __device__ inline int in_face(int l_out, int s) { return s < l_out ? s : s + 1; }
 
-// Workgroups are dealt to the 8 XCDs in turn (workgroup w runs on XCD w % 8).  The
-// streaming products give each XCD one contiguous range of tiles instead: tile t
-// and t + 1 usually share a block row (its columns are split between them) and the
-// x panels of that row, so both halves then come through one L2.  XCD x takes
-// q + (x < r) tiles starting at x q + min(x, r), with G = 8 q + r; the map is a
-// bijection of [0, G).
-__device__ inline int64_t xcd_tile(int64_t w, int64_t G) {
-  const int64_t q = G >> 3, r = G & 7, x = w & 7, i = w >> 3;
-  return x * q + (x < r ? x : r) + i;
-}
+// The streaming products keep the plain workgroup order (workgroup w runs on XCD
+// w % 8).  Giving each XCD a contiguous range of tiles lets the two halves of a
+// split block row share one L2 (1 % fewer bytes fetched), but an instance whose
+// rows are masked off then exits on one XCD while the others keep working: the
+// batched solve of uneven instances became up to 21 % slower per group.
 
 // y[dest(br)][row] = alpha * v[dest(br)][row] + beta * sum_{s,col} B[br,s][col][row] x[4j+l_in(s)][col]
 // (v may be null when alpha == 0).  Columns have the padded length Kp (multiple
@@ -58,7 +53,7 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv(const TB *__restrict__ B,
   typedef typename Vec<TB>::T VT;
   extern __shared__ double xs_all[];
   const int GPB = Kp / VW;  // row groups per block row
-  const int64_t g0 = xcd_tile(blockIdx.x, gridDim.x) * SPMV_THREADS;
+  const int64_t g0 = blockIdx.x * (int64_t)SPMV_THREADS;
   const int64_t br0 = g0 / GPB;
   int64_t glast = g0 + SPMV_THREADS - 1;
   if (glast >= nthreads) glast = nthreads - 1;
@@ -118,7 +113,7 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv_rhs(const float *__restri
   typedef float f4 __attribute__((ext_vector_type(4)));
   extern __shared__ float xs_rhs[];
   const int GPB = Kp / 4;
-  const int64_t g0 = xcd_tile(blockIdx.x, gridDim.x) * SPMV_THREADS;
+  const int64_t g0 = blockIdx.x * (int64_t)SPMV_THREADS;
   const int64_t br0 = g0 / GPB;
   int64_t glast = g0 + SPMV_THREADS - 1;
   if (glast >= nthreads) glast = nthreads - 1;
