@@ -161,18 +161,20 @@ class UnevenBatch:
             if err:
                 raise err[0]
             worker = None
-            if k + 1 < len(groups):
-                if overlap:
-                    worker = threading.Thread(target=build, args=(groups[k + 1],))
-                    worker.start()
-            # group g's assembly finished before build() returned (side.synchronize()),
-            # so the solve on the main stream needs no event wait on the side stream
-            t0 = time.perf_counter()
-            self.solve(g, rtol=rtol, segment=segment, max_products=max_products, progress=progress, stream=main)
-            main.synchronize()
-            t_solve = (time.perf_counter() - t0) * 1e3
-            if worker is not None:
-                worker.join()  # on_group then runs with the GPU to itself
+            if overlap and k + 1 < len(groups):
+                worker = threading.Thread(target=build, args=(groups[k + 1],))
+                worker.start()
+            try:
+                # group g's assembly finished before build() returned (side.synchronize()),
+                # so the solve on the main stream needs no event wait on the side stream
+                t0 = time.perf_counter()
+                self.solve(g, rtol=rtol, segment=segment, max_products=max_products, progress=progress,
+                           stream=main)
+                main.synchronize()
+                t_solve = (time.perf_counter() - t0) * 1e3
+            finally:
+                if worker is not None:
+                    worker.join()  # also when the solve raised; on_group then has the GPU to itself
             if on_group:
                 on_group(g, t_solve)
             self.release(g)
