@@ -13,6 +13,8 @@
  * Conventions shared by every entry point
  *   - Every call returns a dfm_status; DFM_OK (0) on success, a negative code on
  *     failure, with a message available from dfm_last_error() (per thread).
+ *     A null handle or a null required pointer is rejected with DFM_E_INVALID
+ *     before any device work; dfm_mesh_destroy and dfm_op_destroy accept NULL.
  *   - Array arguments marked "device" are caller-owned device pointers to
  *     contiguous row-major memory; the library never frees or retains them
  *     beyond the call.  Arguments marked "host" are host pointers.
