@@ -12,7 +12,10 @@ margin:
   every wall but the absorbing one, all injected density leaves through that
   face) against the wall coefficient applied on interior faces and a dropped
   Gram solve (Eq. Bapprox);
-* flux conservation of a lossless tet (Sec. 2) against the dropped Gram solve.
+* flux conservation of a lossless tet (Sec. 2) against the dropped Gram solve;
+* central differences of the receiver energy against the adjoint gradient with
+  the sign of dB/dmu flipped, the wall coefficient left out of dB/dmu, or the
+  receiver functional's own dependence on mu dropped.
 """
 import math
 
@@ -21,6 +24,7 @@ import pytest
 
 import synth
 import oracle.assemble as oas
+from oracle import adjoint as oj
 from oracle import assemble as oa
 from oracle import basis as ob
 from oracle import geometry as og
@@ -33,6 +37,7 @@ from tests import refgeom as rg
 MC_Z = 5.5            # the Monte Carlo pin's bound (standard errors)
 BALANCE_REL = 1e-4    # the energy-balance pin's bound
 CONSERVATION = 1e-9   # the conservation pin's bound (Zernike, paper rule)
+FD_REL = 1e-6         # the central-difference pin's bound on dJ/dmu
 
 
 @pytest.fixture(scope="module")
@@ -100,7 +105,39 @@ def conservation_error(jm):
     return err
 
 
+def fd_error():
+    """Largest relative gap between the adjoint dJ/dmu_e and central differences
+    of J = g . rho on a 12-tet box with walls R = 0.8 (three elements e)."""
+    v, t = synth.kuhn_box((2, 1, 1), (1.0, 1.0, 1.0), 0.15, 3)
+    refl = np.full((t.shape[0], 4), 0.8)
+    mu = np.random.default_rng(1).uniform(0.1, 0.6, t.shape[0])
+    bs = oa.Basis(1, 0, 2, 4, oq.SEAM_RULE)
+    box = (0.5, 1.0, 0.0, 1.0, 0.0, 0.7)
+    src = {"kind": "points", "xyz": synth.uniform_points_on_box_surface((1, 1, 1), 3, np.random.default_rng(2))}
+    m = om.build_mesh(v, t, refl)
+    rho0 = osrc.project(m, bs, src).sum(0)
+
+    def J(mu_):
+        B, dest = oa.assemble(m, bs, mu_)
+        return oj.receiver_functional(m, bs, mu_, box) @ osv.solve_direct(osv.to_sparse(B, dest), rho0)
+
+    B, dest = oa.assemble(m, bs, mu)
+    A = osv.to_sparse(B, dest)
+    rho = osv.solve_direct(A, rho0)
+    lam = osv.solve_direct(A.T.tocsr(), oj.receiver_functional(m, bs, mu, box))
+    dmu = oj.gradient_mu(m, bs, mu, lam, rho, box)
+    h, err = 1e-6, 0.0
+    for e in (0, 7, 10):
+        mp, mm = mu.copy(), mu.copy()
+        mp[e] += h
+        mm[e] -= h
+        fd = (J(mp) - J(mm)) / (2 * h)
+        err = max(err, abs(dmu[e] - fd) / max(abs(fd), 1e-9 * np.abs(dmu).max()))
+    return err
+
+
 _g, _m, _dest, _gram, _ang = og.g_exp, og.moment_I, oas.destination, ob.gram, ob.direction_angles
+_dB, _jdest, _recv = oj.dB_dmu_block, oj.destination, oj.receiver_functional
 
 
 def _plant(monkeypatch, name):
@@ -120,6 +157,14 @@ def _plant(monkeypatch, name):
     elif name == "azimuth_from_y_axis":
         monkeypatch.setattr(ob, "direction_angles",
                             lambda d, fr: (lambda ct, ph: (ct, (ph - 0.5 * np.pi) % (2 * np.pi)))(*_ang(d, fr)))
+    elif name == "dB_dmu_sign":
+        monkeypatch.setattr(oj, "dB_dmu_block", lambda *a: (lambda r: (-r[0], r[1]))(_dB(*a)))
+    elif name == "wall_weight_missing_in_dB_dmu":
+        monkeypatch.setattr(oj, "destination", lambda mesh, j, lo: (lambda r: (r[0], r[1], 1.0, r[3]))(_jdest(mesh, j, lo)))
+    elif name == "receiver_mu_dependence_dropped":
+        monkeypatch.setattr(oj, "receiver_functional",
+                            lambda mesh, bs, mu, box, derivative=False:
+                            0.0 * _recv(mesh, bs, mu, box, True) if derivative else _recv(mesh, bs, mu, box))
     else:
         assert name == "none"
 
@@ -129,6 +174,7 @@ def test_unmodified_oracle_passes_the_detectors(jmesh):
     assert mc_z(jmesh, 1, 0.8, wall_case(jmesh)) < MC_Z
     assert balance_error() < BALANCE_REL
     assert conservation_error(jmesh) < CONSERVATION
+    assert fd_error() < FD_REL
 
 
 @pytest.mark.parametrize("name,detector", [
@@ -139,6 +185,9 @@ def test_unmodified_oracle_passes_the_detectors(jmesh):
     ("wall_weight_on_interior", "balance"),
     ("no_gram_solve", "balance"),
     ("no_gram_solve", "conservation"),
+    ("dB_dmu_sign", "fd"),
+    ("wall_weight_missing_in_dB_dmu", "fd"),
+    ("receiver_mu_dependence_dropped", "fd"),
 ])
 def test_planted_mistake_is_caught(jmesh, monkeypatch, name, detector):
     _plant(monkeypatch, name)
@@ -148,5 +197,7 @@ def test_planted_mistake_is_caught(jmesh, monkeypatch, name, detector):
         assert mc_z(jmesh, 1, 0.8, wall_case(jmesh)) > 4 * MC_Z
     elif detector == "balance":
         assert balance_error() > 10 * BALANCE_REL
+    elif detector == "fd":
+        assert fd_error() > 1e3 * FD_REL
     else:
         assert conservation_error(jmesh) > 1e6 * CONSERVATION
