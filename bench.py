@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--workload", choices=["box8", "box32-batched", "box32-adjoint", "uneven"], default="box8",
                     help="box8: the 3072-tet single-rhs case (default); box32-batched: 49152 tets, 128 sources; "
                          "box32-adjoint: receiver-energy gradients on the same box (64 sources); "
-                         "uneven: 256 independent boxes of 500-20000 tets, degrees 4-10, 4 sources each")
+                         "uneven: 256 independent boxes of 384-20412 tets, degrees 4-10, 4 sources each")
     ap.add_argument("--instances", type=int, default=256, help="uneven: number of boxes")
     ap.add_argument("--overlap", action="store_true",
                     help="uneven: assemble the next group on a second stream beside the current solve "
@@ -474,8 +474,8 @@ def main_box32(args):
 
 
 def main_uneven(args):
-    """Uneven batch of independent instances: 256 boxes (1, U[1,4], U[1,4]) of
-    log-uniform 500-20000 tets, jitter 0.2h, mu ~ U[0, 0.1] per box, R = 0.9, P0 x
+    """Uneven batch of independent instances: 256 boxes (1, U[1,4], U[1,4]) with a
+    log-uniform target of 500-20000 tets (384-20412 once the cells are rounded), jitter 0.2h, mu ~ U[0, 0.1] per box, R = 0.9, P0 x
     Legendre of degree uniform in {4,6,8,10} with n = D + 4, 4 isotropic point
     sources per box.  Instances of one degree form one mesh (block-diagonal B,
     assembled in FP32 by one launch); one step = for every group: mesh build ->
