@@ -7,12 +7,14 @@ margin:
 * Monte Carlo ray tracing of whole blocks (independent tracer, tests/refgeom.py)
   against a dropped or sign-flipped attenuation exp(-mu L) (Sec. 3.3, the
   chord integral), a forgotten wall reflection (Sec. 2, the specular map), and
-  an azimuth measured from the wrong frame axis (Sec. 3.3, the local face frame);
+  an azimuth measured from the wrong frame axis (Sec. 3.3, the local face frame),
+  and direction weights of the solid angle instead of the flux measure (Sec. 3.4);
 * the stationary energy balance of the cube (Sec. 2: with mu = 0 and R = 1 on
   every wall but the absorbing one, all injected density leaves through that
   face) against the wall coefficient applied on interior faces and a dropped
   Gram solve (Eq. Bapprox);
-* flux conservation of a lossless tet (Sec. 2) against the dropped Gram solve;
+* flux conservation of a lossless tet (Sec. 2) against the dropped Gram solve
+  and the solid-angle weights;
 * central differences of the receiver energy against the adjoint gradient with
   the sign of dB/dmu flipped, the wall coefficient left out of dB/dmu, or the
   receiver functional's own dependence on mu dropped.
@@ -137,6 +139,7 @@ def fd_error():
 
 
 _g, _m, _dest, _gram, _ang = og.g_exp, og.moment_I, oas.destination, ob.gram, ob.direction_angles
+_nodes = oq.block_nodes
 _dB, _jdest, _recv = oj.dB_dmu_block, oj.destination, oj.receiver_functional
 
 
@@ -157,6 +160,10 @@ def _plant(monkeypatch, name):
     elif name == "azimuth_from_y_axis":
         monkeypatch.setattr(ob, "direction_angles",
                             lambda d, fr: (lambda ct, ph: (ct, (ph - 0.5 * np.pi) % (2 * np.pi)))(*_ang(d, fr)))
+    elif name == "solid_angle_weights":
+        # d Omega instead of the flux measure cos(theta) d Omega (Sec. 3.4)
+        monkeypatch.setattr(oq, "block_nodes", lambda mesh, j, li, lo, n, rule=oq.PAPER_RULE: (
+            lambda d, w: (d, w / np.abs(d @ mesh.frame[j, li, 2])))(*_nodes(mesh, j, li, lo, n, rule)))
     elif name == "dB_dmu_sign":
         monkeypatch.setattr(oj, "dB_dmu_block", lambda *a: (lambda r: (-r[0], r[1]))(_dB(*a)))
     elif name == "wall_weight_missing_in_dB_dmu":
@@ -185,6 +192,8 @@ def test_unmodified_oracle_passes_the_detectors(jmesh):
     ("wall_weight_on_interior", "balance"),
     ("no_gram_solve", "balance"),
     ("no_gram_solve", "conservation"),
+    ("solid_angle_weights", "conservation"),
+    ("solid_angle_weights", "mc_interior"),
     ("dB_dmu_sign", "fd"),
     ("wall_weight_missing_in_dB_dmu", "fd"),
     ("receiver_mu_dependence_dropped", "fd"),
