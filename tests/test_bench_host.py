@@ -20,3 +20,40 @@ def test_bench_help_lists_the_workloads():
     assert r.returncode == 0
     for w in ("box8", "box32-batched", "box32-adjoint", "uneven"):
         assert w in r.stdout
+
+
+def _bench():
+    sys.path.insert(0, ROOT)
+    import bench
+    return bench
+
+
+def test_cpu_baseline_leg_times_the_oracle():
+    """The bench's CPU leg runs the unmodified oracle in a worker pool and reports
+    blocks/s, the cores used and what was sampled."""
+    import numpy as np
+
+    import synth
+    bench = _bench()
+    v, t = synth.kuhn_box((1, 1, 1), (1.0, 1.0, 1.0), jitter=0.1, seed=1)
+    p = synth.Problem(name="tiny", verts=v, tets=t, mu=np.full(t.shape[0], 0.05), refl=np.full((t.shape[0], 4), 0.9),
+                      pos_order=0, mom_degree=2, quad_n=4)
+    out = bench.cpu_baseline(p, 1, 3, "one-cell test box")
+    assert out["kind"] == "oracle" and out["unit"] == "blocks/s"
+    assert out["value"] > 0 and 1 <= out["cores"] <= 16
+    assert "3 tets (36 blocks)" in out["sample"]
+
+
+def test_measured_traffic_needs_the_counted_source(tmp_path):
+    """Byte counters are reported only while the kernel's source is the one counted."""
+    import hashlib
+    bench = _bench()
+    src = "paper_1608_04607_amd/csrc/apply.hip"
+    h = hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()[:16]
+    f = tmp_path / "counters.txt"
+    f.write_text(f"# test\nkernel=k source={src} sha256={h} bytes=123.0 ratio=1.5\n"
+                 f"kernel=old source={src} sha256=0000000000000000 bytes=9.0 ratio=2.0\n")
+    assert bench.measured_traffic("k", str(f)) == 123.0
+    assert bench.measured_traffic("k", str(f), "ratio") == 1.5
+    assert bench.measured_traffic("old", str(f)) is None
+    assert bench.measured_traffic("missing", str(f)) is None
