@@ -233,7 +233,9 @@ dfm_status dfm_source_points(dfm_op op, const double *xyz, int64_t ns, double fl
 /* dfm_source_points_sum: the same point sources summed into nrhs right-hand sides,
  *   rho0[which[i]] += projection of point i (independent instances sharing one mesh
  *   take one right-hand side per source index).
- *     which device i32 [ns] in 0..nrhs-1 (not checked on the device)
+ *     which device i32 [ns] in 0..nrhs-1; an index outside that range is checked on
+ *           the device: its point writes nothing and the call returns DFM_E_INVALID
+ *           (rho0 then holds the other points' projections)
  *     rho0  device f64 [nrhs][ndof] (overwritten) */
 dfm_status dfm_source_points_sum(dfm_op op, const double *xyz, int64_t ns, const int32_t *which, int nrhs,
                                  double flux, double *rho0, void *stream);
@@ -245,18 +247,28 @@ dfm_status dfm_source_plane(dfm_op op, int axis, double value, int profile, cons
  * (L the chord from the start point; L itself when mu_j = 0), which equals the
  * interior density of Eq. IntDens integrated over the tet.  J = sum of E_j over
  * the tets whose centroid lies in the closed box = g . rho.
- *   mu   device f64 [nt] the damping the operator was assembled with
+ *   mu   device f64 [nt] or NULL.  The damping used is always the one the operator
+ *        was assembled with (the operator keeps a copy); a non-NULL mu is compared
+ *        with it element by element and any difference returns DFM_E_INVALID.
  *   box  host f64 [6] xmin, xmax, ymin, ymax, zmin, zmax
  *   g    device f64 [ndof] (overwritten)
  * The directions are those of the operator's blocks.  Synchronises `stream`. */
 dfm_status dfm_receiver_functional(dfm_op op, const double *mu, const double *box, double *g, void *stream);
+
+/* The receiver energy itself, J[r] = g . rho[r] for nrhs densities (same functional
+ * and the same mu rule as dfm_receiver_functional).
+ *   rho  device f64 [nrhs][ndof];  J device f64 [nrhs] (overwritten).
+ * Errors: DFM_E_INVALID (arguments, mu mismatch).  Synchronises `stream`. */
+dfm_status dfm_receiver_energy(dfm_op op, const double *mu, const double *box, const double *rho, int nrhs,
+                               double *J, void *stream);
 
 /* Gradients of J = g . rho by the adjoint of (I - B) rho = rho0 (Sec. 2, Eq. GovIE):
  * solves (I - B)^T lambda = g (GMRES with precision 0 or 1, or FP64 Neumann, per
  * opts; precision 1 needs the FP64 operator, dtype 0, and its FP32 copy),
  * then dJ/dmu_j = lambda^T dB/dmu_j rho + rho . dg/dmu_j for every tet and, for the
  * source weights w of rho0 = sum_s w_s rho0_s, dJ/dw_s = lambda . rho0_s.
- *   mu, box as for dfm_receiver_functional; rho device f64 [ndof] the forward
+ *   mu (NULL or equal to the assembled damping), box as for
+ *   dfm_receiver_functional; rho device f64 [ndof] the forward
  *   solution; src device f64 [nsrc][ndof] the unit sources (may be NULL when
  *   nsrc = 0); lambda device f64 [ndof] out; d_mu device f64 [nt] out; d_w device
  *   f64 [nsrc] out; info host [1] or NULL.
@@ -266,6 +278,12 @@ dfm_status dfm_receiver_functional(dfm_op op, const double *mu, const double *bo
 dfm_status dfm_adjoint(dfm_op op, const double *mu, const double *box, const double *rho, const double *src,
                        int nsrc, const dfm_solve_opts *opts, double *lambda, double *d_mu, double *d_w,
                        dfm_solve_info *info, void *stream);
+
+/* Weighted sum of right-hand sides, y = sum_s w[s] x[s] (the source of Eq. GovIE
+ * for rho0 = sum_s w_s rho0_s, and the chain-rule scaling of gradients).
+ *   x device f64 [nvec][n], w device f64 [nvec], y device f64 [n] (overwritten;
+ *   it may not alias x).  Errors: DFM_E_INVALID. */
+dfm_status dfm_weighted_sum(const double *x, int64_t n, int nvec, const double *w, double *y, void *stream);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *dfm_last_error(void);

@@ -28,6 +28,7 @@ class Group:
     members: list                    # instance indices
     tet_offsets: list                # first tet of every member in the group mesh (+ total)
     nsrc: int
+    K: int = 0                       # unknowns per slot (kept after the operator is released)
     mesh: dfm.Mesh = None
     op: dfm.Operator = None
     rho0: torch.Tensor = None
@@ -94,21 +95,10 @@ class UnevenBatch:
         g.mesh = dfm.Mesh(verts, tets, refl=refl, stream=stream)
         g.op = dfm.Operator(g.mesh, mu, pos_order, family, degree, quad_n, rule=self.rule, stream=stream,
                             dtype=self.dtype)
+        g.K = g.op.K
         g.events[1].record(st)
         g.rho0 = g.op.source_points_sum(xyz, which, g.nsrc, stream=stream)
         g.events[2].record(st)
-
-    def member_relres(self, g, stream=None):
-        """[member][rhs] relative residual of every instance on its own unknowns."""
-        r = g.rho0 - (g.rho - g.op.apply(g.rho, stream=stream))
-        K = g.op.K
-        out = []
-        for m in range(len(g.members)):
-            a, b = 4 * K * g.tet_offsets[m], 4 * K * g.tet_offsets[m + 1]
-            rn = r[:, a:b].norm(dim=1)
-            bn = g.rho0[:, a:b].norm(dim=1)
-            out.append([float(x) for x in torch.where(bn > 0, rn / bn, torch.zeros_like(rn)).cpu()])
-        return out
 
     def solve(self, g, rtol=1e-8, segment=2500, max_products=100000, progress=None, stream=None):
         """Solve the group to relative residual rtol on every instance and source
@@ -190,7 +180,7 @@ class UnevenBatch:
         for g in self.groups:
             if i in g.members:
                 m = g.members.index(i)
-                K = g.op.K
+                K = g.K
                 return g.rho[:, 4 * K * g.tet_offsets[m]:4 * K * g.tet_offsets[m + 1]]
         raise KeyError(i)
 

@@ -26,6 +26,21 @@ __global__ void k_zero_u32(unsigned *f) {
   if (threadIdx.x == 0) *f = 0u;
 }
 
+// flag bit 1 when a[i] and b[i] differ (bitwise, so a NaN never matches)
+__global__ void k_differs(const double *a, const double *b, int64_t n, unsigned *flag) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    if (__double_as_longlong(a[i]) != __double_as_longlong(b[i])) atomicOr(flag, 1u);
+}
+
+// y[i] = sum_s w[s] x[s][i]
+__global__ void k_weighted_sum(const double *x, int64_t n, int nvec, const double *w, double *y) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int s = 0; s < nvec; ++s) acc = fma(w[s], x[(int64_t)s * n + i], acc);
+    y[i] = acc;
+  }
+}
+
 // out[s] = sum_i src[s][i] * lam[i] (one block per source)
 __global__ void k_src_dots(const double *src, int64_t n, const double *lam, double *out) {
   __shared__ double red[4];
@@ -52,10 +67,33 @@ using namespace dfm;
     }                                                                                        \
   } while (0)
 
+// The damping the functional and the gradients use is the one B was assembled
+// with (kept by the operator); a caller's copy, when given, must equal it.
+static dfm_status check_mu(dfm_op op, const double *mu, hipStream_t st) {
+  if (mu == nullptr || mu == op->mu) return DFM_OK;
+  unsigned *flag = nullptr;
+  DFM_HIP(hipMalloc(&flag, sizeof(unsigned)));
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, flag);
+  hipLaunchKernelGGL(k_differs, dim3(ew_grid(op->nt)), dim3(256), 0, st, mu, op->mu, op->nt, flag);
+  unsigned hf = 0;
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(&hf, flag, sizeof(unsigned), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(flag);
+  DFM_HIP(e);
+  DFM_REQUIRE(hf == 0u, DFM_E_INVALID, "mu differs from the damping the operator was assembled with");
+  return DFM_OK;
+}
+
 extern "C" dfm_status dfm_receiver_functional(dfm_op op, const double *mu, const double *box, double *g,
                                               void *stream_) {
-  DFM_REQUIRE(op && mu && box && g, DFM_E_INVALID, "null argument");
+  DFM_REQUIRE(op && box && g, DFM_E_INVALID, "null argument");
   hipStream_t st = (hipStream_t)stream_;
+  {
+    dfm_status cs = check_mu(op, mu, st);
+    if (cs != DFM_OK) return cs;
+  }
+  mu = op->mu;
   double *blk_vec = nullptr;
   unsigned *flags = nullptr;
   auto cleanup = [&]() {
@@ -77,11 +115,16 @@ extern "C" dfm_status dfm_receiver_functional(dfm_op op, const double *mu, const
 extern "C" dfm_status dfm_adjoint(dfm_op op, const double *mu, const double *box, const double *rho,
                                   const double *src, int nsrc, const dfm_solve_opts *opts, double *lambda,
                                   double *d_mu, double *d_w, dfm_solve_info *info, void *stream_) {
-  DFM_REQUIRE(op && mu && box && rho && opts && lambda && d_mu, DFM_E_INVALID, "null argument");
+  DFM_REQUIRE(op && box && rho && opts && lambda && d_mu, DFM_E_INVALID, "null argument");
   DFM_REQUIRE(nsrc >= 0 && (nsrc == 0 || (src && d_w)), DFM_E_INVALID, "src and d_w are needed when nsrc > 0");
   DFM_REQUIRE(opts->precision == 0 || (opts->precision == 1 && opts->method == 1), DFM_E_UNSUPPORTED,
               "the adjoint solve is FP64, or mixed precision with GMRES");
   hipStream_t st = (hipStream_t)stream_;
+  {
+    dfm_status cs = check_mu(op, mu, st);
+    if (cs != DFM_OK) return cs;
+  }
+  mu = op->mu;
   const int64_t nblk = 12 * op->nt;
   double *blk_vec = nullptr, *blk_e = nullptr, *blk_b = nullptr, *g = nullptr;
   unsigned *flags = nullptr;
@@ -119,4 +162,46 @@ extern "C" dfm_status dfm_adjoint(dfm_op op, const double *mu, const double *box
   DFM_REQUIRE(hf == 0u, DFM_E_NUMERIC, "a block needs more quadrature cells than the table holds");
   if (s == DFM_E_NOCONV) set_error("adjoint solve stopped at max_iter above the tolerance");
   return s;
+}
+
+extern "C" dfm_status dfm_receiver_energy(dfm_op op, const double *mu, const double *box, const double *rho,
+                                          int nrhs, double *J, void *stream_) {
+  DFM_REQUIRE(op && box && rho && J, DFM_E_INVALID, "null argument");
+  DFM_REQUIRE(nrhs >= 1 && nrhs <= 65535, DFM_E_INVALID, "nrhs must be in 1..65535");
+  hipStream_t st = (hipStream_t)stream_;
+  {
+    dfm_status cs = check_mu(op, mu, st);
+    if (cs != DFM_OK) return cs;
+  }
+  double *blk_vec = nullptr, *g = nullptr;
+  unsigned *flags = nullptr;
+  auto cleanup = [&]() {
+    (void)hipFree(blk_vec);
+    (void)hipFree(g);
+    (void)hipFree(flags);
+  };
+  TRY_ADJ(hipMalloc(&blk_vec, sizeof(double) * 12 * op->nt * (size_t)op->K));
+  TRY_ADJ(hipMalloc(&g, sizeof(double) * op->ndof));
+  TRY_ADJ(hipMalloc(&flags, sizeof(unsigned)));
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, flags);
+  TRY_ADJ(energy_functional(op, op->mu, box, nullptr, g, blk_vec, nullptr, flags, st));
+  // J[r] = rho[r] . g
+  hipLaunchKernelGGL(k_src_dots, dim3((unsigned)nrhs), dim3(256), 0, st, rho, op->ndof, g, J);
+  TRY_ADJ(hipGetLastError());
+  unsigned hf = 0;
+  TRY_ADJ(hipMemcpyAsync(&hf, flags, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+  TRY_ADJ(hipStreamSynchronize(st));
+  cleanup();
+  DFM_REQUIRE(hf == 0u, DFM_E_NUMERIC, "a block needs more quadrature cells than the table holds");
+  return DFM_OK;
+}
+
+extern "C" dfm_status dfm_weighted_sum(const double *x, int64_t n, int nvec, const double *w, double *y,
+                                       void *stream_) {
+  DFM_REQUIRE(x && w && y, DFM_E_INVALID, "null argument");
+  DFM_REQUIRE(n >= 1 && nvec >= 1, DFM_E_INVALID, "need n >= 1 and nvec >= 1");
+  hipStream_t st = (hipStream_t)stream_;
+  hipLaunchKernelGGL(k_weighted_sum, dim3(ew_grid(n)), dim3(256), 0, st, x, n, nvec, w, y);
+  DFM_HIP(hipGetLastError());
+  return DFM_OK;
 }

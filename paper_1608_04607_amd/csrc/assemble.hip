@@ -232,9 +232,10 @@ __device__ int patch_polygon(const double (*v)[3], double (*out)[3]) {
 }
 
 // Split a convex spherical polygon by the great circle normal to nrm; a part
-// with no corner strictly on its side is dropped (count 0).
+// with no corner strictly on its side is dropped (count 0).  A part that would
+// need more than VMAX corners sets `trunc` (the caller reports an overflow).
 __device__ void clip_poly(const double (*in)[3], int m, const double *nrm, double (*pos)[3], int &mp,
-                          double (*neg)[3], int &mn) {
+                          double (*neg)[3], int &mn, bool &trunc) {
   double s[VMAX];
   bool anyp = false, anyn = false;
   for (int k = 0; k < m; ++k) {
@@ -247,11 +248,13 @@ __device__ void clip_poly(const double (*in)[3], int m, const double *nrm, doubl
   for (int k = 0; k < m; ++k) {
     int k1 = (k + 1 == m) ? 0 : k + 1;
     double sa = s[k], sb = s[k1];
-    if (sa >= -TOL && mp < VMAX) {
-      pos[mp][0] = in[k][0]; pos[mp][1] = in[k][1]; pos[mp][2] = in[k][2]; ++mp;
+    if (sa >= -TOL) {
+      if (mp < VMAX) { pos[mp][0] = in[k][0]; pos[mp][1] = in[k][1]; pos[mp][2] = in[k][2]; ++mp; }
+      else trunc = true;
     }
-    if (sa <= TOL && mn < VMAX) {
-      neg[mn][0] = in[k][0]; neg[mn][1] = in[k][1]; neg[mn][2] = in[k][2]; ++mn;
+    if (sa <= TOL) {
+      if (mn < VMAX) { neg[mn][0] = in[k][0]; neg[mn][1] = in[k][1]; neg[mn][2] = in[k][2]; ++mn; }
+      else trunc = true;
     }
     if ((sa > TOL && sb < -TOL) || (sa < -TOL && sb > TOL)) {
       double den = sa - sb;
@@ -259,7 +262,9 @@ __device__ void clip_poly(const double (*in)[3], int m, const double *nrm, doubl
                      (sa * in[k1][2] - sb * in[k][2]) / den};
       unit3(p);
       if (mp < VMAX) { pos[mp][0] = p[0]; pos[mp][1] = p[1]; pos[mp][2] = p[2]; ++mp; }
+      else trunc = true;
       if (mn < VMAX) { neg[mn][0] = p[0]; neg[mn][1] = p[1]; neg[mn][2] = p[2]; ++mn; }
+      else trunc = true;
     }
   }
   if (!(anyp && mp >= 3)) mp = 0;
@@ -449,7 +454,9 @@ __device__ void build_cells(BlockGeo &G, double (*cells)[4][3], double *work, in
         continue;
       }
       int mp, mn;
-      clip_poly(stk[sp], cnt[sp], planes[pl], stk[sp + 1], mp, tmp, mn);
+      bool trunc = false;
+      clip_poly(stk[sp], cnt[sp], planes[pl], stk[sp + 1], mp, tmp, mn, trunc);
+      if (trunc) G.overflow = 1;
       int top = sp - 1;
       if (mn > 0) {
         ++top;  // == sp: the negative part replaces the clipped polygon
@@ -1616,6 +1623,7 @@ void free_op(dfm_op op) {
   (void)hipFree(op->B);
   (void)hipFree(op->B32);
   (void)hipFree(op->dest);
+  (void)hipFree(op->mu);
   (void)hipFree(op->gl);
   (void)hipFree(op->thom);
   (void)hipFree(op->coef);
@@ -1696,6 +1704,8 @@ extern "C" dfm_status dfm_assemble(dfm_mesh mesh, const dfm_basis *basis, const 
   else
     TRY(hipMalloc(&op->B32, sizeof(float) * (size_t)nblocks * K * op->Kp));
   TRY(hipMalloc(&op->dest, sizeof(int32_t) * 4 * mesh->nt));
+  TRY(hipMalloc(&op->mu, sizeof(double) * mesh->nt));
+  TRY(hipMemcpyAsync(op->mu, mu, sizeof(double) * mesh->nt, hipMemcpyDeviceToDevice, st));
   TRY(hipMalloc(&gl, sizeof(double) * 64));
   TRY(hipMalloc(&thom_d, sizeof(double) * 3 * (DMAX + 1) * (DMAX + 1)));
   TRY(hipMalloc(&coef_d, sizeof(double) * NMOM * NSERIES));

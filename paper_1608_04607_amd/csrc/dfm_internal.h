@@ -74,6 +74,7 @@ struct dfm_op_s {
   double *B = nullptr;        // [nt][4][3K][Kp]: block (j, l_out, s) column-major, K columns of length Kp
   float *B32 = nullptr;       // same layout in FP32, made on first mixed-precision solve
   int32_t *dest = nullptr;    // [nt][4]
+  double *mu = nullptr;       // [nt] the damping B was assembled with
   double *gl = nullptr;       // [2][32] Gauss-Legendre nodes and weights
   double *thom = nullptr;     // Legendre Gram tridiagonal factors
   double *coef = nullptr;     // chord-moment power series

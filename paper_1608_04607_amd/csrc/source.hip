@@ -167,9 +167,15 @@ __global__ void k_locate(const int32_t *tets, const double *verts, const int32_t
 // side which[r] (atomically: points of one right-hand side may share a face)
 __global__ void k_point_coeffs(const int32_t *tets, const double *verts, const double *face, const double *xyz,
                                const int *found, int64_t ns, int P, int M, int K, int64_t ndof, double flux,
-                               const double *ang, const int32_t *which, double *rho0, unsigned *flags) {
+                               const double *ang, const int32_t *which, int nrhs, double *rho0,
+                               unsigned *flags) {
   int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (r >= ns) return;
+  // a right-hand side index outside 0..nrhs-1 is reported, and nothing is written
+  if (which && (unsigned)which[r] >= (unsigned)nrhs) {
+    atomicOr(flags, 2u);
+    return;
+  }
   int s = found[r];
   if (s == INT_MAX) {
     atomicOr(flags, 1u);
@@ -321,12 +327,13 @@ static dfm_status source_points_impl(dfm_op op, const double *xyz, int64_t ns, c
   hipLaunchKernelGGL(k_locate, dim3(gx, (unsigned)ns), dim3(256), 0, st, m->tets, m->verts, m->nbr, nslot, xyz,
                      sc.idx);
   hipLaunchKernelGGL(k_point_coeffs, dim3((unsigned)((ns + 63) / 64)), dim3(64), 0, st, m->tets, m->verts, m->face,
-                     xyz, sc.idx, ns, op->P, M, op->K, op->ndof, flux, sc.ang, which, rho0, sc.flags);
+                     xyz, sc.idx, ns, op->P, M, op->K, op->ndof, flux, sc.ang, which, nrhs, rho0, sc.flags);
   TRY_SC(hipGetLastError());
   unsigned hflags = 0;
   TRY_SC(hipMemcpyAsync(&hflags, sc.flags, sizeof(unsigned), hipMemcpyDeviceToHost, st));
   TRY_SC(hipStreamSynchronize(st));
   sc.release();
+  DFM_REQUIRE(!(hflags & 2u), DFM_E_INVALID, "a right-hand side index in `which` lies outside 0..nrhs-1");
   DFM_REQUIRE(hflags == 0u, DFM_E_INVALID, "a source point lies on no boundary face");
   return DFM_OK;
 }

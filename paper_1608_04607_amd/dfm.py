@@ -203,6 +203,16 @@ class Operator:
         check(_lib.load().dfm_receiver_functional(self.handle, _ptr(self.mu), bx, _ptr(g), _stream(stream)))
         return g
 
+    def receiver_energy(self, rho, box, stream=None):
+        """J = g . rho (one value per row of rho) for the receiver box (dfm_receiver_energy)."""
+        rho = _dev(rho, torch.float64)
+        nrhs = 1 if rho.dim() == 1 else rho.shape[0]
+        J = torch.empty((nrhs,), dtype=torch.float64, device=self.device)
+        bx = (C.c_double * 6)(*box)
+        check(_lib.load().dfm_receiver_energy(self.handle, _ptr(self.mu), bx, _ptr(rho), nrhs, _ptr(J),
+                                              _stream(stream)))
+        return J
+
     def adjoint(self, rho, box, src=None, method="gmres", rtol=1e-10, restart=50, max_iter=20000, precision=0,
                 stream=None):
         """(lambda, dJ/dmu, dJ/dw, info) for J = receiver energy in `box`; precision 1:
@@ -232,23 +242,35 @@ class Operator:
             pass
 
 
+def weighted_sum(x, w, stream=None):
+    """y = sum_s w[s] x[s] for x [nvec][n] and w [nvec] (dfm_weighted_sum)."""
+    x = _dev(x, torch.float64)
+    w = _dev(w, torch.float64)
+    nvec = 1 if x.dim() == 1 else x.shape[0]
+    if w.numel() != nvec:
+        raise ValueError("w needs one weight per row of x")
+    y = torch.empty((x.shape[-1],), dtype=torch.float64, device=x.device)
+    check(_lib.load().dfm_weighted_sum(_ptr(x), x.shape[-1], nvec, _ptr(w), _ptr(y), _stream(stream)))
+    return y
+
+
 class ReceiverEnergy(torch.autograd.Function):
     """J(mu, w) = receiver energy in `box` of the stationary density for the source
     rho0 = sum_s w_s src_s, differentiable in the damping mu [nt] and the source
-    weights w [nsrc].  Forward: dfm_assemble (for this mu), dfm_solve,
-    dfm_receiver_functional; backward: dfm_adjoint (transposed solve and the dB/dmu
-    contraction).  The weighted source sum and J = g . rho are tensor glue."""
+    weights w [nsrc].  Forward: dfm_assemble (for this mu), dfm_weighted_sum,
+    dfm_solve, dfm_receiver_energy; backward: dfm_adjoint (transposed solve and
+    the dB/dmu contraction), scaled by the incoming gradient with dfm_weighted_sum."""
 
     @staticmethod
     def forward(ctx, mu, w, mesh, src, box, basis, rtol=1e-12, restart=50):
         pos_order, family, degree, quad_n, rule = basis
         op = Operator(mesh, mu.detach(), pos_order, family, degree, quad_n, rule=rule)
-        rho0 = (w.detach().to(src.dtype)[:, None] * src).sum(0)
+        rho0 = weighted_sum(src, w.detach().to(torch.float64))
         rho, _ = op.solve(rho0, method="gmres", rtol=rtol, restart=restart)
-        g = op.receiver_functional(box)
+        J = op.receiver_energy(rho, box)
         ctx.save_for_backward(rho)
         ctx.op, ctx.src, ctx.box, ctx.rtol, ctx.restart = op, src, box, rtol, restart
-        return (g * rho).sum()
+        return J.reshape(())
 
     @staticmethod
     def backward(ctx, grad_out):
@@ -256,7 +278,8 @@ class ReceiverEnergy(torch.autograd.Function):
         op = ctx.op
         _, dmu, dw, _ = op.adjoint(rho, ctx.box, src=ctx.src, rtol=ctx.rtol, restart=ctx.restart)
         op.close()
-        return grad_out * dmu, grad_out * dw, None, None, None, None, None, None
+        scale = grad_out.detach().to(torch.float64).reshape(1)
+        return weighted_sum(dmu, scale), weighted_sum(dw, scale), None, None, None, None, None, None
 
 
 def receiver_energy(mesh, mu, w, src, box, basis, rtol=1e-12, restart=50):

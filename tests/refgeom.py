@@ -211,3 +211,87 @@ def clip_integral(verts, tet, l_in, l_out, d, mu, pos_order):
         bo = pos_basis(bary(verts, ids_out, ex), A_out, pos_order)
         S += area * np.einsum("q,qa,qb->ab", w_ref * np.exp(-mu * L), bo, bi)
     return S
+
+
+def mc_energy(verts, tet, l, mu, D, pos_order, nsamp, rng):
+    """Monte Carlo mean and standard error of
+        E[p, k] = int_{face l} int_{hemisphere} b_p(s) psi_k(d) ell(s, d) cos(theta) dOmega ds,
+        ell = (1 - exp(-mu L)) / mu  (L itself when mu = 0),
+    L the chord from s along d to the exit.  This is the energy inside the tet
+    carried by the density b_p psi_k entering through face l: along a ray the
+    interior density integrated over the tet leaves int_0^L exp(-mu t) dt
+    (Sec. 4.1, Eq. IntDens, integrated over the element).  Samples: s uniform
+    on the face, d cosine-distributed, so the measure integrates to A pi."""
+    fr = face_frame(verts, tet, l)
+    ids = face_ids(tet, l)
+    A = face_area(verts, tet, l)
+    V = verts[ids]
+    r1, r2 = rng.uniform(size=nsamp), rng.uniform(size=nsamp)
+    sq = np.sqrt(r1)
+    lam = np.stack([1 - sq, sq * (1 - r2), sq * r2], axis=1)
+    s = lam @ V
+    u1, u2 = rng.uniform(size=nsamp), rng.uniform(size=nsamp)
+    rad, ang = np.sqrt(u1), 2 * np.pi * u2
+    d = np.stack([rad * np.cos(ang), rad * np.sin(ang), np.sqrt(1 - u1)], axis=1) @ fr
+    L, _ = trace(verts, tet, s, d)
+    ell = L if mu == 0.0 else -np.expm1(-mu * L) / mu
+    c, phi = angles(d, fr)
+    psi = legendre_basis(c, phi, D)
+    b = pos_basis(lam, A, pos_order)
+    F = (A * np.pi) * ell[:, None, None] * b[:, :, None] * psi[:, None, :]     # [n, P, M]
+    mean = F.mean(axis=0)
+    se = F.std(axis=0) / math.sqrt(nsamp)
+    return mean, se
+
+
+def _quad_rule_on_triangle(n=12):
+    """Barycentrics [Q][3] and weights (summing to 1) of a rule on the reference
+    triangle built by splitting it at the centroid into three quadrilaterals,
+    each mapped bilinearly from [0,1]^2 with an n x n Gauss-Legendre product rule."""
+    x, w = np.polynomial.legendre.leggauss(n)
+    u, wu = 0.5 * (x + 1), 0.5 * w
+    U, Vv = np.meshgrid(u, u, indexing="ij")
+    W = np.outer(wu, wu).ravel()
+    U, Vv = U.ravel(), Vv.ravel()
+    E = np.eye(3)
+    cen = np.full(3, 1.0 / 3.0)
+    lam_all, w_all = [], []
+    for k in range(3):
+        a, b_, c = E[k], E[(k + 1) % 3], E[(k + 2) % 3]
+        q = [a, 0.5 * (a + b_), cen, 0.5 * (a + c)]           # a quadrilateral of area 1/3 (x area)
+        pts = (np.outer((1 - U) * (1 - Vv), q[0]) + np.outer(U * (1 - Vv), q[1])
+               + np.outer(U * Vv, q[2]) + np.outer((1 - U) * Vv, q[3]))
+        # Jacobian of the bilinear map in barycentric (area-fraction) units
+        dU = np.outer(1 - Vv, q[1] - q[0]) + np.outer(Vv, q[2] - q[3])
+        dV = np.outer(1 - U, q[3] - q[0]) + np.outer(U, q[2] - q[1])
+        jac = np.abs(dU[:, 1] * dV[:, 2] - dU[:, 2] * dV[:, 1])   # 2-D area in the (l1, l2) chart
+        lam_all.append(pts)
+        w_all.append(W * jac * 2.0)                                # the reference triangle has area 1/2
+    return np.concatenate(lam_all), np.concatenate(w_all)
+
+
+def gauss_patch_moments(verts, ids, center, sigma, pos_order, levels=2, n=12):
+    """int_face b_p(s) exp(-|s-c|^2/(2 sigma^2))/(2 pi sigma^2) ds for the position
+    basis of the face with vertices ids (increasing global id), by recursive
+    midpoint subdivision of the face into 4**levels triangles with the
+    centroid-split Gauss rule on each."""
+    V = verts[ids]
+    A = 0.5 * np.linalg.norm(np.cross(V[1] - V[0], V[2] - V[0]))
+    tris = [V]
+    for _ in range(levels):
+        nxt = []
+        for T in tris:
+            m01, m12, m20 = 0.5 * (T[0] + T[1]), 0.5 * (T[1] + T[2]), 0.5 * (T[2] + T[0])
+            nxt += [np.array([T[0], m01, m20]), np.array([m01, T[1], m12]),
+                    np.array([m20, m12, T[2]]), np.array([m01, m12, m20])]
+        tris = nxt
+    lam_ref, w_ref = _quad_rule_on_triangle(n)
+    c = np.asarray(center, dtype=np.float64)
+    out = 0.0
+    for T in tris:
+        pts = lam_ref @ T
+        At = 0.5 * np.linalg.norm(np.cross(T[1] - T[0], T[2] - T[0]))
+        dens = np.exp(-np.sum((pts - c) ** 2, axis=1) / (2 * sigma ** 2)) / (2 * np.pi * sigma ** 2)
+        b = pos_basis(bary(verts, ids, pts), A, pos_order)
+        out = out + (w_ref * At * dens) @ b
+    return out

@@ -35,6 +35,23 @@ def rel(a, b):
     return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
 
 
+BLOCK_TOL = 1e-9      # each block against its own norm (Frobenius)
+BLOCK_FLOOR = 1e-6    # blocks below this fraction of the largest block norm are not judged alone
+
+
+def rel_blocks(a, b, floor=BLOCK_FLOOR):
+    """Largest ||a_blk - b_blk||_F / ||b_blk||_F over the K x K blocks (last two
+    axes) whose norm is at least `floor` times the largest block norm; a global
+    max-entry error can hide a large relative error in a small block."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    K2 = a.shape[-1] * a.shape[-2]
+    da = np.sqrt(((a - b) ** 2).reshape(-1, K2).sum(axis=1))
+    nb = np.sqrt((b ** 2).reshape(-1, K2).sum(axis=1))
+    keep = nb >= floor * nb.max()
+    return float((da[keep] / nb[keep]).max())
+
+
 def gpu_mesh(verts, tets, refl=None, **kw):
     from paper_1608_04607_amd import dfm
     t = lambda x: None if x is None else torch.tensor(x, device=DEV)  # noqa: E731
@@ -182,8 +199,10 @@ def test_assembly_matches_oracle(name, meshspec, mu, bs):
     Bo, desto = oa.assemble(m, bs, mu_arr)
     assert np.array_equal(dest, desto)
     err = rel(blocks, Bo)
-    say(f"    rel err {err:.3e}  nodes {op.nodes}")
+    berr = rel_blocks(blocks, Bo)
+    say(f"    rel err {err:.3e}  blockwise {berr:.3e}  nodes {op.nodes}")
     assert err < TOL
+    assert berr < BLOCK_TOL
 
 
 @pytest.mark.parametrize("order,dtype", [(1, 0), (0, 1)])
@@ -218,6 +237,7 @@ def test_assembly_max_degree_p1_split():
     blocks, _ = (x.cpu().numpy() for x in op.export())
     Bo, _ = oa.assemble(om.build_mesh(v, t, refl), bs, [0.2])
     assert rel(blocks, Bo) < TOL
+    assert rel_blocks(blocks, Bo) < BLOCK_TOL
 
 
 def test_full_size_box8_sampled():
@@ -235,8 +255,10 @@ def test_full_size_box8_sampled():
     got = blocks[torch.tensor(sample, device=DEV)].cpu().numpy()
     assert np.array_equal(dest.cpu().numpy()[sample], desto)
     err = rel(got, Bo)
-    say(f"    rel err {err:.3e}")
+    berr = rel_blocks(got, Bo)
+    say(f"    rel err {err:.3e}  blockwise {berr:.3e}")
     assert err < TOL
+    assert berr < BLOCK_TOL
     assert torch.isfinite(blocks).all()
 
 
@@ -668,6 +690,63 @@ def test_receiver_functional_matches_oracle(adj, order, family):
     assert rel(g_gpu, g_or) < TOL
 
 
+def test_receiver_energy_and_weighted_sum_match_oracle(adj):
+    """J = g . rho computed in the library (dfm_receiver_energy) for several
+    densities, and the weighted source sum (dfm_weighted_sum), against the oracle."""
+    from paper_1608_04607_amd import dfm
+    say("[adjoint] receiver energy, weighted sum")
+    v, t, refl, mu, box, pts = adj
+    bs = oa.Basis(1, 0, 3, 4, oq.SEAM_RULE)
+    m = om.build_mesh(v, t, refl)
+    op = gpu_op(gpu_mesh(v, t, refl), mu, bs)
+    src = op.source_points(torch.tensor(pts, device=DEV))
+    w = np.array([0.7, -1.3, 0.4])
+    rho0 = dfm.weighted_sum(src, torch.tensor(w, device=DEV)).cpu().numpy()
+    rho0s = osrc.project(m, bs, {"kind": "points", "xyz": pts})
+    assert rel(rho0, w @ rho0s) < TOL
+    rho = torch.tensor(np.random.default_rng(5).standard_normal((4, op.ndof)), device=DEV)
+    J = op.receiver_energy(rho, box).cpu().numpy()
+    g = oj.receiver_functional(m, bs, mu, box)
+    assert rel(J, rho.cpu().numpy() @ g) < TOL
+
+
+def test_device_checks_reject_bad_indices_and_damping(adj):
+    """dfm_source_points_sum range-checks `which` on the device, and the receiver
+    functional and the adjoint refuse a damping other than the assembled one."""
+    import ctypes as C
+
+    from paper_1608_04607_amd import _lib
+    from paper_1608_04607_amd._lib import DFMError
+    say("[checks] which out of range, mu mismatch")
+    v, t, refl, mu, box, pts = adj
+    op = gpu_op(gpu_mesh(v, t, refl), mu, oa.Basis(0, 0, 2, 4, oq.SEAM_RULE))
+    xyz = torch.tensor(pts, device=DEV)
+    ok = op.source_points_sum(xyz, torch.tensor([0, 1, 1], dtype=torch.int32, device=DEV), 2).cpu().numpy()
+    assert np.isfinite(ok).all()
+    for bad in ([0, 2, 1], [0, -1, 1]):
+        with pytest.raises(DFMError, match="INVALID"):
+            op.source_points_sum(xyz, torch.tensor(bad, dtype=torch.int32, device=DEV), 2)
+    lib = _lib.load()
+    st = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    g = torch.empty(op.ndof, dtype=torch.float64, device=DEV)
+    bx = (C.c_double * 6)(*box)
+    other = torch.tensor(mu, device=DEV)
+    other[3] += 1e-9
+    assert lib.dfm_receiver_functional(op.handle, C.c_void_p(other.data_ptr()), bx, C.c_void_p(g.data_ptr()),
+                                       st) == -1
+    same = torch.tensor(mu, device=DEV)
+    assert lib.dfm_receiver_functional(op.handle, C.c_void_p(same.data_ptr()), bx, C.c_void_p(g.data_ptr()), st) == 0
+    assert lib.dfm_receiver_functional(op.handle, None, bx, C.c_void_p(g.data_ptr()), st) == 0
+    rho = torch.zeros(op.ndof, dtype=torch.float64, device=DEV)
+    lam, dmu = torch.empty_like(rho), torch.empty(t.shape[0], dtype=torch.float64, device=DEV)
+    opts = _lib.SolveOpts(1, 20, 100, 1e-8, 0, 0)
+    info = _lib.SolveInfo()
+    assert lib.dfm_adjoint(op.handle, C.c_void_p(other.data_ptr()), bx, C.c_void_p(rho.data_ptr()), None, 0,
+                           C.byref(opts), C.c_void_p(lam.data_ptr()), C.c_void_p(dmu.data_ptr()), None,
+                           C.byref(info), st) == -1
+    op.close()
+
+
 @pytest.mark.parametrize("order", [0, 1])
 def test_adjoint_gradients_match_oracle(adj, order):
     say(f"[adjoint] gradients P{order}")
@@ -722,6 +801,7 @@ def test_adjoint_mixed_precision_matches_oracle(adj):
 
 def test_adjoint_gradient_vs_central_differences(adj):
     """GPU gradient against central differences of GPU forward solves (step 1e-6)."""
+    from paper_1608_04607_amd import dfm
     say("[adjoint] central differences")
     v, t, refl, mu, box, pts = adj
     bs = oa.Basis(0, 0, 2, 4, oq.SEAM_RULE)
@@ -730,8 +810,10 @@ def test_adjoint_gradient_vs_central_differences(adj):
 
     def J(mu_arr):
         op = gpu_op(mesh, mu_arr, bs)
-        rho, _ = op.solve(op.source_points(xyz).sum(0), rtol=1e-14, restart=60)
-        return float(op.receiver_functional(box) @ rho)
+        src_ = op.source_points(xyz)
+        rho, _ = op.solve(dfm.weighted_sum(src_, torch.ones(src_.shape[0], dtype=torch.float64, device=DEV)),
+                          rtol=1e-14, restart=60)
+        return float(op.receiver_energy(rho, box)[0])
 
     op = gpu_op(mesh, mu, bs)
     src = op.source_points(xyz)
@@ -744,7 +826,8 @@ def test_adjoint_gradient_vs_central_differences(adj):
         mp[e] += h
         mm[e] -= h
         fd = (J(mp) - J(mm)) / (2 * h)
-        assert dmu[e] == pytest.approx(fd, rel=1e-5, abs=1e-8 * np.abs(dmu).max())
+        say(f"    mu[{e}]: adjoint {dmu[e]:.12e} fd {fd:.12e} rel {abs(dmu[e] - fd) / abs(fd):.2e}")
+        assert dmu[e] == pytest.approx(fd, rel=1e-6, abs=1e-9 * np.abs(dmu).max())
 
 
 def test_receiver_energy_autograd(adj):
@@ -824,19 +907,26 @@ def test_cuboid_matches_exact_ray_solution():
 # ---------------------------------------------------------------------------- uneven batches of instances
 
 
-def test_uneven_batch_matches_separate_solves():
+def test_uneven_batch_matches_oracle():
     """Instances of different sizes, damping and degree, grouped by degree into one
     mesh each, assembled in FP32 in one launch per group and solved together: every
-    instance meets the tolerance on its own residual and matches a separate solve of
-    that instance alone, also when the next group is assembled beside the current
-    group's solve."""
-    from paper_1608_04607_amd import batch, dfm
-    say("[batch] uneven instances")
-    probs = [p for p in synth.problem_c5(n_instances=64, seed=5, tets_range=(200, 1500)) if p.nt <= 900]
-    probs = sorted(probs, key=lambda p: (p.mom_degree, p.nt))[::3][:8]
-    say(f"    {len(probs)} instances, degrees {sorted(set(p.mom_degree for p in probs))}, "
-        f"tets {[p.nt for p in probs]}")
-    assert len(set(p.mom_degree for p in probs)) >= 2
+    instance meets the tolerance on its own residual; its blocks match the oracle's
+    blocks of that instance alone (FP32 bound 1e-5) and its solution the oracle's
+    direct solve of that instance (the FP32 rounding of B, amplified by (I - B)^-1,
+    bounds the gap: 2e-5).  The same batch through the pipeline that assembles the
+    next group beside the current group's solve gives the same solutions."""
+    from paper_1608_04607_amd import batch
+    from tests import oracle_pool
+    say("[batch] uneven instances vs the oracle")
+    cand = synth.problem_c5(n_instances=64, seed=5, tets_range=(40, 300))
+    probs = []
+    for D, sizes in ((4, (48, 96, 168)), (6, (36, 72, 120))):
+        for nt in sizes:
+            probs.append(next(p for p in cand if p.mom_degree == D and p.nt == nt and all(p is not q for q in probs)))
+    say(f"    {len(probs)} instances, degrees {[p.mom_degree for p in probs]}, tets {[p.nt for p in probs]}")
+    ref = oracle_pool.pool_map(oracle_pool.instance_solution,
+                               [(p.verts, p.tets, p.refl, p.mu, p.pos_order, 0, p.mom_degree, p.quad_n,
+                                 oq.SEAM_RULE, p.source["xyz"]) for p in probs])
     ub = batch.UnevenBatch(probs, dtype=1)
     for g in ub.groups:
         ub.assemble(g)
@@ -844,8 +934,19 @@ def test_uneven_batch_matches_separate_solves():
         say(f"    group D={g.key[2]}: {len(g.members)} instances, {g.products} batched products, "
             f"worst member relres {max(max(r) for r in g.relres):.2e}")
         assert max(max(r) for r in g.relres) <= 1e-9
-    # the same batch through the pipeline that assembles the next group on a second
-    # stream while the current one is solved
+        for m, i in enumerate(g.members):
+            Bo, desto, rho_o = ref[i]
+            a = g.tet_offsets[m]
+            ids = torch.arange(a, g.tet_offsets[m + 1], dtype=torch.int64, device=DEV)
+            blocks, dest = g.op.export_tets(ids)
+            blocks = blocks.cpu().numpy()
+            assert np.array_equal(dest.cpu().numpy() - 4 * a, desto)
+            eb, ebb = rel(blocks, Bo), rel_blocks(blocks, Bo)
+            es = rel(ub.solution(i).cpu().numpy(), rho_o)
+            say(f"    instance {i} (D={probs[i].mom_degree}, {probs[i].nt} tets): blocks {eb:.2e} "
+                f"(blockwise {ebb:.2e}), solution {es:.2e}")
+            assert eb < 1e-5 and ebb < 1e-5
+            assert es < 2e-5
     say("    pipelined: assembly of the next group beside the current solve")
     piped, order = {}, []
     ub2 = batch.UnevenBatch(probs, dtype=1)
@@ -858,20 +959,5 @@ def test_uneven_batch_matches_separate_solves():
 
     ub2.solve_all(rtol=1e-9, overlap=True, on_group=keep)
     assert order == [g.key[2] for g in ub.groups] and sorted(piped) == list(range(len(probs)))
-    for i, p in enumerate(probs):
-        assert rel(piped[i].cpu().numpy(), ub.solution(i).cpu().numpy()) < 1e-8
-        mesh = gpu_mesh(p.verts, p.tets, p.refl)
-        op = dfm.Operator(mesh, torch.tensor(p.mu, device=DEV), p.pos_order, dfm.LEGENDRE, p.mom_degree, p.quad_n,
-                          rule=oq.SEAM_RULE, dtype=1)
-        rho0 = op.source_points(torch.tensor(p.source["xyz"], device=DEV))
-        got = ub.solution(i)
-        ref, _ = op.solve(rho0, method="gmres", rtol=1e-11, precision=0)
-        assert rel(got.cpu().numpy(), ref.cpu().numpy()) < 1e-6
-        # the group's right-hand sides restricted to the instance are its own sources
-        g = next(g for g in ub.groups if i in g.members)
-        m = g.members.index(i)
-        a, b = 4 * op.K * g.tet_offsets[m], 4 * op.K * g.tet_offsets[m + 1]
-        assert rel(g.rho0[:, a:b].cpu().numpy(), rho0.cpu().numpy()) < 1e-14
-        op.close()
-        mesh.close()
-
+    for i in range(len(probs)):
+        assert rel(piped[i].cpu().numpy(), ref[i][2]) < 2e-5
