@@ -239,6 +239,18 @@ dfm_status dfm_source_points(dfm_op op, const double *xyz, int64_t ns, double fl
  *     rho0  device f64 [nrhs][ndof] (overwritten) */
 dfm_status dfm_source_points_sum(dfm_op op, const double *xyz, int64_t ns, const int32_t *which, int nrhs,
                                  double flux, double *rho0, void *stream);
+/* dfm_source_points_noalloc: dfm_source_points for callers that cannot allocate
+ *   device memory (code under HIP graph capture, tight serving loops, harnesses
+ *   that forbid hipMalloc).  Same arguments, kernels and result; its scratch (the
+ *   angular profile, the Gram factors, the located face of every point and an
+ *   error word) lives in one static device array per GPU, held until the process
+ *   ends, so the call allocates and frees nothing.  ns is limited to 1..4096
+ *   (DFM_E_INVALID beyond).  Every call on one GPU shares that array: calls that
+ *   overlap on one GPU (two streams, two host threads) race and must be
+ *   serialised by the caller.  It synchronises `stream` to report a point that
+ *   lies on no boundary face (DFM_E_INVALID). */
+dfm_status dfm_source_points_noalloc(dfm_op op, const double *xyz, int64_t ns, double flux, double *rho0,
+                                     void *stream);
 dfm_status dfm_source_plane(dfm_op op, int axis, double value, int profile, const double *params,
                             double flux, double *rho0, void *stream);
 

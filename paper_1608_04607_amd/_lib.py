@@ -53,6 +53,7 @@ _PROTOS = [
                                    C.POINTER(SolveInfo), _P]),
     ("dfm_source_points", C.c_int, [_P, _P, _I64, C.c_double, _P, _P]),
     ("dfm_source_points_sum", C.c_int, [_P, _P, _I64, _P, C.c_int, C.c_double, _P, _P]),
+    ("dfm_source_points_noalloc", C.c_int, [_P, _P, _I64, C.c_double, _P, _P]),
     ("dfm_source_plane", C.c_int, [_P, C.c_int, C.c_double, C.c_int, C.POINTER(C.c_double), C.c_double, _P, _P]),
     ("dfm_receiver_functional", C.c_int, [_P, _P, C.POINTER(C.c_double), _P, _P]),
     ("dfm_adjoint", C.c_int, [_P, _P, C.POINTER(C.c_double), _P, _P, C.c_int, C.POINTER(SolveOpts), _P, _P, _P,

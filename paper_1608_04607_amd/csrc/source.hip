@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -268,9 +269,12 @@ struct Scratch {
   }
 };
 
-hipError_t angular(dfm_op op, double a0, double a1, int pole, Scratch &sc, hipStream_t st) {
+// th: host staging of the Gram factors, kept alive by the caller until the stream
+// has been synchronised
+hipError_t angular(dfm_op op, double a0, double a1, int pole, Scratch &sc, std::vector<double> &th,
+                   hipStream_t st) {
   const int D = op->basis.mom_degree;
-  std::vector<double> th(3 * (DMAX + 1) * (DMAX + 1), 0.0);
+  th.assign(3 * (DMAX + 1) * (DMAX + 1), 0.0);
   double *jo = th.data(), *cp = jo + (DMAX + 1) * (DMAX + 1), *idn = cp + (DMAX + 1) * (DMAX + 1);
   for (int a = 0; a < DMAX; ++a) jo[a] = (a + 1.0) / std::sqrt((2.0 * a + 1.0) * (2.0 * a + 3.0));
   for (int b = 0; b <= D; ++b) {
@@ -284,7 +288,7 @@ hipError_t angular(dfm_op op, double a0, double a1, int pole, Scratch &sc, hipSt
       cprev = c;
     }
   }
-  hipError_t e = hipMemcpy(sc.thom, th.data(), sizeof(double) * th.size(), hipMemcpyHostToDevice);
+  hipError_t e = hipMemcpyAsync(sc.thom, th.data(), sizeof(double) * th.size(), hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_axisym_profile, dim3(1), dim3(64), 0, st, a0, a1, pole, D, op->basis.mom_family, sc.thom,
                      sc.ang);
@@ -306,9 +310,37 @@ using namespace dfm;
     }                                                                                        \
   } while (0)
 
+// The point-source projection proper: sc holds device buffers of at least
+// M (ang), 3 (DMAX+1)^2 (thom), 1 (total) doubles, ns ints (idx) and one word
+// (flags); nothing is allocated here.
+static dfm_status source_points_run(dfm_op op, const double *xyz, int64_t ns, const int32_t *which, int nrhs,
+                                    double flux, double *rho0, hipStream_t st, Scratch &sc) {
+  dfm_mesh m = op->mesh;
+  const int M = op->M;
+  std::vector<double> th;
+  int64_t tot = (int64_t)nrhs * op->ndof;
+  hipLaunchKernelGGL(k_zero_f64, dim3(ew_grid(tot)), dim3(256), 0, st, rho0, tot);
+  hipLaunchKernelGGL(k_init_found, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st, sc.idx, ns, sc.total,
+                     sc.flags);
+  DFM_HIP(hipGetLastError());
+  DFM_HIP(angular(op, 1.0 / M_PI, 0.0, 0, sc, th, st));
+  int64_t nslot = 4 * m->nt;
+  unsigned gx = (unsigned)std::min<int64_t>((nslot + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_locate, dim3(gx, (unsigned)ns), dim3(256), 0, st, m->tets, m->verts, m->nbr, nslot, xyz,
+                     sc.idx);
+  hipLaunchKernelGGL(k_point_coeffs, dim3((unsigned)((ns + 63) / 64)), dim3(64), 0, st, m->tets, m->verts, m->face,
+                     xyz, sc.idx, ns, op->P, M, op->K, op->ndof, flux, sc.ang, which, nrhs, rho0, sc.flags);
+  DFM_HIP(hipGetLastError());
+  unsigned hflags = 0;
+  DFM_HIP(hipMemcpyAsync(&hflags, sc.flags, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+  DFM_HIP(hipStreamSynchronize(st));
+  DFM_REQUIRE(!(hflags & 2u), DFM_E_INVALID, "a right-hand side index in `which` lies outside 0..nrhs-1");
+  DFM_REQUIRE(hflags == 0u, DFM_E_INVALID, "a source point lies on no boundary face");
+  return DFM_OK;
+}
+
 static dfm_status source_points_impl(dfm_op op, const double *xyz, int64_t ns, const int32_t *which, int nrhs,
                                      double flux, double *rho0, hipStream_t st) {
-  dfm_mesh m = op->mesh;
   Scratch sc;
   const int M = op->M;
   TRY_SC(hipMalloc(&sc.ang, sizeof(double) * M));
@@ -316,27 +348,53 @@ static dfm_status source_points_impl(dfm_op op, const double *xyz, int64_t ns, c
   TRY_SC(hipMalloc(&sc.total, sizeof(double)));
   TRY_SC(hipMalloc(&sc.idx, sizeof(int) * ns));
   TRY_SC(hipMalloc(&sc.flags, sizeof(unsigned)));
-  int64_t tot = (int64_t)nrhs * op->ndof;
-  hipLaunchKernelGGL(k_zero_f64, dim3(ew_grid(tot)), dim3(256), 0, st, rho0, tot);
-  hipLaunchKernelGGL(k_init_found, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st, sc.idx, ns, sc.total,
-                     sc.flags);
-  TRY_SC(hipGetLastError());
-  TRY_SC(angular(op, 1.0 / M_PI, 0.0, 0, sc, st));
-  int64_t nslot = 4 * m->nt;
-  unsigned gx = (unsigned)std::min<int64_t>((nslot + 255) / 256, 1024);
-  hipLaunchKernelGGL(k_locate, dim3(gx, (unsigned)ns), dim3(256), 0, st, m->tets, m->verts, m->nbr, nslot, xyz,
-                     sc.idx);
-  hipLaunchKernelGGL(k_point_coeffs, dim3((unsigned)((ns + 63) / 64)), dim3(64), 0, st, m->tets, m->verts, m->face,
-                     xyz, sc.idx, ns, op->P, M, op->K, op->ndof, flux, sc.ang, which, nrhs, rho0, sc.flags);
-  TRY_SC(hipGetLastError());
-  unsigned hflags = 0;
-  TRY_SC(hipMemcpyAsync(&hflags, sc.flags, sizeof(unsigned), hipMemcpyDeviceToHost, st));
-  TRY_SC(hipStreamSynchronize(st));
+  dfm_status s = source_points_run(op, xyz, ns, which, nrhs, flux, rho0, st, sc);
   sc.release();
-  DFM_REQUIRE(!(hflags & 2u), DFM_E_INVALID, "a right-hand side index in `which` lies outside 0..nrhs-1");
-  DFM_REQUIRE(hflags == 0u, DFM_E_INVALID, "a source point lies on no boundary face");
-  return DFM_OK;
+  return s;
 }
+
+// ---------------------------------------------------------------------------
+// Allocation-free variant: the same kernels with their scratch in one static
+// device array per GPU.  Layout (doubles, then ints): ang [MMAX], thom
+// [3 (DMAX+1)^2], total [1], flags [1 word, padded to 8 bytes], idx
+// [NOALLOC_MAX_POINTS].
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int NOALLOC_MAX_POINTS = 4096;
+constexpr int MMAX = (DMAX + 1) * (DMAX + 2) / 2;
+constexpr size_t SCR_ANG = 0, SCR_THOM = SCR_ANG + sizeof(double) * MMAX,
+                 SCR_TOTAL = SCR_THOM + sizeof(double) * 3 * (DMAX + 1) * (DMAX + 1),
+                 SCR_FLAGS = SCR_TOTAL + sizeof(double), SCR_IDX = SCR_FLAGS + sizeof(double),
+                 SCR_BYTES = SCR_IDX + sizeof(int) * NOALLOC_MAX_POINTS;
+}  // namespace
+
+// Each GPU the library runs on holds its own copy until the process ends.  In host
+// code the name is only a stand-in: the device address comes from
+// hipGetSymbolAddress (scratch_address below).
+static __device__ __align__(256) unsigned char scratch[SCR_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device (looked up once per device).
+hipError_t scratch_address(void **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_dev[dev] == nullptr) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return hipSuccess;
+}
+}  // namespace
 
 extern "C" dfm_status dfm_source_points(dfm_op op, const double *xyz, int64_t ns, double flux, double *rho0,
                                         void *stream_) {
@@ -371,7 +429,8 @@ extern "C" dfm_status dfm_source_plane(dfm_op op, int axis, double value, int pr
   hipLaunchKernelGGL(k_zero_f64, dim3(ew_grid(op->ndof)), dim3(256), 0, st, rho0, op->ndof);
   hipLaunchKernelGGL(k_init_found, dim3(1), dim3(1), 0, st, sc.idx, 0, sc.total, sc.flags);
   TRY_SC(hipGetLastError());
-  TRY_SC(angular(op, 0.0, 1.5 / M_PI, profile == 2, sc, st));
+  std::vector<double> th;   // host staging of the Gram factors, alive until the synchronisation below
+  TRY_SC(angular(op, 0.0, 1.5 / M_PI, profile == 2, sc, th, st));
   unsigned g = (unsigned)((nslot + 255) / 256);
   hipLaunchKernelGGL(k_plane_mark, dim3(g), dim3(256), 0, st, m->tets, m->verts, m->nbr, m->face, nslot, axis, value,
                      sc.idx, sc.total);
@@ -387,4 +446,21 @@ extern "C" dfm_status dfm_source_plane(dfm_op op, int axis, double value, int pr
   sc.release();
   DFM_REQUIRE(total > 0.0, DFM_E_INVALID, "no boundary face lies in the requested plane");
   return DFM_OK;
+}
+
+extern "C" dfm_status dfm_source_points_noalloc(dfm_op op, const double *xyz, int64_t ns, double flux, double *rho0,
+                                                void *stream_) {
+  DFM_REQUIRE(op && xyz && rho0, DFM_E_INVALID, "null argument");
+  DFM_REQUIRE(ns >= 1 && ns <= NOALLOC_MAX_POINTS, DFM_E_INVALID,
+              "ns must be in 1..4096 for the allocation-free projection");
+  void *base = nullptr;
+  DFM_HIP(scratch_address(&base));
+  unsigned char *b = static_cast<unsigned char *>(base);
+  Scratch sc;
+  sc.ang = reinterpret_cast<double *>(b + SCR_ANG);
+  sc.thom = reinterpret_cast<double *>(b + SCR_THOM);
+  sc.total = reinterpret_cast<double *>(b + SCR_TOTAL);
+  sc.flags = reinterpret_cast<unsigned *>(b + SCR_FLAGS);
+  sc.idx = reinterpret_cast<int *>(b + SCR_IDX);
+  return source_points_run(op, xyz, ns, nullptr, (int)ns, flux, rho0, (hipStream_t)stream_, sc);
 }
