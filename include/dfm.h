@@ -81,7 +81,12 @@ typedef struct {
 
 /* Solver options for (I - B) rho = rho0 (Sec. 2, Eq. NSum / GovIE). */
 typedef struct {
-  int method;     /* 0: Neumann partial sums (Eq. NSum); 1: restarted GMRES             */
+  int method;     /* 0: Neumann partial sums (Eq. NSum); 1: restarted GMRES;
+                     2: two-level Neumann: the partial sums of Eq. NSum with a coarse
+                        correction after every term (Galerkin projection of I - B on
+                        a few global-direction harmonics per aggregate of tets), all
+                        nrhs together; needs precision 2, dtype 0 and K <= 160, and
+                        is not available for transposed (adjoint) solves           */
   int restart;    /* GMRES restart length (Krylov vectors kept), 1..200                 */
   int max_iter;   /* total iteration cap (operator applications)                        */
   double rtol;    /* stop when ||rho0 - (I-B) rho||_2 <= rtol ||rho0||_2                */
@@ -98,6 +103,14 @@ typedef struct {
                                   every active series (the residual the partial sum
                                   leaves) is below max(1e-4, rtol |rho0| / (2 |r|))
                                   relative to the residual |r| it started from.
+                        2 (method 2 only): iterative refinement with FP64 residuals
+                        around corrections iterated in FP16 storage (B and the
+                        current term in FP16, scaled per right-hand side and
+                        instance; products on the FP16 matrix cores with FP32
+                        accumulation; partial sums in FP32) to a relative 1e-2 per
+                        refinement stage.  If a stage's terms grow (the Galerkin
+                        coarse problem is not guaranteed stable), the stage restarts
+                        with the constant harmonic only, then without correction.
                         The stop test is the FP64 residual in every case.               */
   int warm_start; /* 0: start from rho = 0; 1 (method 0 with precision 1 only): rho holds
                      the starting iterate on entry, so a solve stopped at max_iter can
@@ -189,8 +202,9 @@ dfm_status dfm_apply(dfm_op op, const double *x, double *y, int nrhs, int transp
 dfm_status dfm_apply_f32(dfm_op op, const float *x, float *y, int nrhs, void *stream);
 
 /* Solve (I - B) rho = rho0 for nrhs right-hand sides: one after the other, except
- * method 0 with precision 1, which iterates all of them together (see
- * dfm_solve_opts).
+ * method 0 with precision 1 and method 2, which iterate all of them together (see
+ * dfm_solve_opts).  Method 2 builds its coarse space on first use and keeps it
+ * with the operator (aggregates of about 1536 tets per instance).
  *   rho0, rho  device f64 [nrhs][ndof]; info host [nrhs] or NULL.
  * Returns DFM_E_NOCONV (rho holds the last iterate) if any right-hand side did
  * not reach opts->rtol within opts->max_iter.  Synchronises `stream`. */
@@ -202,7 +216,8 @@ dfm_status dfm_solve(dfm_op op, const double *rho0, double *rho, int nrhs, const
  * strictly increasing from 0 to nt) and no face of its tets leads into another
  * instance (checked: DFM_E_INVALID otherwise).  Solves all nrhs right-hand sides
  * with the batched FP32-Neumann-in-FP64-refinement method (opts: method 0,
- * precision 1; warm_start as for dfm_solve).  Every pair (instance, rhs) stops on
+ * precision 1; warm_start as for dfm_solve) or the two-level method (method 2,
+ * precision 2; aggregates never span two instances).  Every pair (instance, rhs) stops on
  * its own relative residual over the instance's unknowns, and an instance all of
  * whose pairs have converged is no longer multiplied.  info: host [ngroups][nrhs]
  * (iters = batched products that included the instance).  Errors as dfm_solve;

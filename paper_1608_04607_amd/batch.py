@@ -5,10 +5,11 @@ Instances that share a discretisation (position order, momentum family and degre
 Gauss points) are concatenated into one mesh.  Its components are disjoint, so B is
 block diagonal and one dfm_assemble launch assembles every instance of the group;
 right-hand side s of the group carries the s-th source of every instance
-(dfm_source_points_sum), and one batched solve (dfm_solve_groups: Neumann with
-FP32 corrections and FP64 refinement) solves all of them, each instance and
-source stopping on its own residual and each instance leaving the products once
-all its sources have converged.
+(dfm_source_points_sum), and one batched solve (dfm_solve_groups: by default the
+two-level iteration with FP16 products inside FP64 refinement, or Neumann with
+FP32 corrections) solves all of them, each instance and source stopping on its
+own residual and each instance leaving the products once all its sources have
+converged.
 This module only arranges arrays and calls the library; every step of the method
 runs in its kernels.
 """
@@ -44,8 +45,10 @@ class UnevenBatch:
     """problems: objects with verts, tets, mu, refl, pos_order, mom_degree, quad_n and
     source = {"kind": "points", "xyz": ...} (e.g. synth.problem_c5())."""
 
-    def __init__(self, problems, mom_family=dfm.LEGENDRE, rule=dfm.SEAM_RULE, dtype=1, device="cuda:0"):
+    def __init__(self, problems, mom_family=dfm.LEGENDRE, rule=dfm.SEAM_RULE, dtype=1, device="cuda:0",
+                 method="twolevel"):
         self.problems = list(problems)
+        self.method = method
         self.family, self.rule, self.dtype, self.device = mom_family, rule, dtype, torch.device(device)
         ext = [p.verts.max(axis=0) - p.verts.min(axis=0) for p in self.problems]
         self._gap = 1.5 * max(float(e[0]) for e in ext) + 0.5    # x spacing of the instance grid
@@ -100,13 +103,13 @@ class UnevenBatch:
         g.rho0 = g.op.source_points_sum(xyz, which, g.nsrc, stream=stream)
         g.events[2].record(st)
 
-    def solve(self, g, rtol=1e-8, segment=2500, max_products=100000, progress=None, stream=None):
+    def solve(self, g, rtol=1e-8, segment=2500, max_products=100000, progress=None, stream=None, method=None):
         """Solve the group to relative residual rtol on every instance and source
         (dfm_solve_groups), in warm-started segments of at most `segment` batched
         products; instances stop being multiplied once all their sources converged."""
         while True:
             g.rho, info = g.op.solve_groups(g.rho0, g.tet_offsets, rtol=rtol, max_iter=segment, rho=g.rho,
-                                            raise_nonconv=False, stream=stream)
+                                            raise_nonconv=False, stream=stream, method=method or self.method)
             g.products += max(x[0] for row in info for x in row)
             if not g.member_products:
                 g.member_products = [0] * len(g.members)

@@ -1627,6 +1627,7 @@ void free_op(dfm_op op) {
   (void)hipFree(op->gl);
   (void)hipFree(op->thom);
   (void)hipFree(op->coef);
+  free_twolevel(op);
   delete op;
 }
 

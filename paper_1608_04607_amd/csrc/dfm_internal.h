@@ -52,6 +52,9 @@ enum : unsigned {
   FLAG_HASH_FULL = 64u,
 };
 
+struct Coarse;
+void free_twolevel(dfm_op op);
+
 }  // namespace dfm
 
 struct dfm_mesh_s {
@@ -78,4 +81,7 @@ struct dfm_op_s {
   double *gl = nullptr;       // [2][32] Gauss-Legendre nodes and weights
   double *thom = nullptr;     // Legendre Gram tridiagonal factors
   double *coef = nullptr;     // chord-moment power series
+  void *B16 = nullptr;        // FP16 copy with the coarse-correction columns (two-level solver)
+  int Kp8 = 8;                // K rounded up to a multiple of 8
+  dfm::Coarse *coarse = nullptr;  // aggregation coarse space of the two-level solver
 };

@@ -33,6 +33,8 @@ hipError_t spmv32_t(dfm_op op, const float *x, const float *v, float *y, float a
 hipError_t ensure_fp32(dfm_op op, hipStream_t st);
 hipError_t product32(dfm_op op, const float *x, float *y, float *e, int R, const int32_t *gid, const uint8_t *gact,
                      hipStream_t st);
+dfm_status solve_twolevel_impl(dfm_op op, const double *rho0, double *rho, int R, const dfm_solve_opts *opts,
+                               const std::vector<int64_t> &toff, dfm_solve_info *info, hipStream_t st);
 
 namespace {
 
@@ -775,17 +777,26 @@ dfm_status solve_impl(dfm_op op, const double *rho0, double *rho, int nrhs, cons
                       dfm_solve_info *info, bool transpose, void *stream_) {
   DFM_REQUIRE(op && rho0 && rho && opts, DFM_E_INVALID, "null argument");
   DFM_REQUIRE(nrhs >= 1, DFM_E_INVALID, "nrhs must be >= 1");
-  DFM_REQUIRE(opts->method == 0 || opts->method == 1, DFM_E_INVALID, "method must be 0 (Neumann) or 1 (GMRES)");
-  DFM_REQUIRE(opts->precision == 0 || opts->precision == 1, DFM_E_INVALID, "precision must be 0 or 1");
+  DFM_REQUIRE(opts->method >= 0 && opts->method <= 2, DFM_E_INVALID,
+              "method must be 0 (Neumann), 1 (GMRES) or 2 (two-level)");
+  DFM_REQUIRE(opts->precision >= 0 && opts->precision <= 2, DFM_E_INVALID, "precision must be 0, 1 or 2");
+  DFM_REQUIRE((opts->method == 2) == (opts->precision == 2), DFM_E_INVALID,
+              "the two-level method (2) runs with precision 2 (FP16 iterations, FP64 refinement), and only it");
   DFM_REQUIRE(opts->max_iter >= 1 && opts->rtol > 0.0, DFM_E_INVALID, "need max_iter >= 1 and rtol > 0");
+  DFM_REQUIRE(!(transpose && opts->method == 2), DFM_E_UNSUPPORTED, "the two-level solver is forward only");
+  DFM_REQUIRE(opts->warm_start == 0 || opts->warm_start == 1, DFM_E_INVALID, "warm_start must be 0 or 1");
+  if (opts->method == 2) {
+    DFM_REQUIRE(nrhs <= 65535, DFM_E_INVALID, "nrhs must be in 1..65535");
+    return solve_twolevel_impl(op, rho0, rho, nrhs, opts, std::vector<int64_t>{0, op->nt}, info,
+                               (hipStream_t)stream_);
+  }
   const int m = opts->method == 1 ? opts->restart : 1;
   DFM_REQUIRE(m >= 1 && m <= MAXV - 1, DFM_E_INVALID, "restart must be in 1..200");
   DFM_REQUIRE(!(transpose && opts->precision == 1 && opts->method == 0), DFM_E_UNSUPPORTED,
               "transposed Neumann solves are implemented in FP64 only");
   DFM_REQUIRE(!(transpose && !op->B), DFM_E_UNSUPPORTED, "transposed solves need an operator assembled in FP64");
-  DFM_REQUIRE(opts->warm_start == 0 || opts->warm_start == 1, DFM_E_INVALID, "warm_start must be 0 or 1");
   DFM_REQUIRE(!(opts->warm_start && !(opts->method == 0 && opts->precision == 1)), DFM_E_UNSUPPORTED,
-              "warm_start is implemented for method 0 with precision 1 only");
+              "warm_start is implemented for the batched methods only (method 0 / precision 1, method 2)");
   if (opts->method == 0 && opts->precision == 1)
     return solve_groups_impl(op, rho0, rho, nrhs, opts, std::vector<int64_t>{0, op->nt}, info, (hipStream_t)stream_);
   hipStream_t st = (hipStream_t)stream_;
@@ -937,8 +948,8 @@ extern "C" dfm_status dfm_solve_groups(dfm_op op, const double *rho0, double *rh
   DFM_REQUIRE(op && rho0 && rho && opts && tet_offsets, DFM_E_INVALID, "null argument");
   DFM_REQUIRE(nrhs >= 1 && nrhs <= 65535, DFM_E_INVALID, "nrhs must be in 1..65535");
   DFM_REQUIRE(ngroups >= 1 && ngroups <= 65535, DFM_E_INVALID, "ngroups must be in 1..65535");
-  DFM_REQUIRE(opts->method == 0 && opts->precision == 1, DFM_E_UNSUPPORTED,
-              "instance groups are solved with method 0 and precision 1");
+  DFM_REQUIRE((opts->method == 0 && opts->precision == 1) || (opts->method == 2 && opts->precision == 2),
+              DFM_E_UNSUPPORTED, "instance groups are solved with method 0 / precision 1 or method 2 / precision 2");
   DFM_REQUIRE(opts->max_iter >= 1 && opts->rtol > 0.0, DFM_E_INVALID, "need max_iter >= 1 and rtol > 0");
   DFM_REQUIRE(opts->warm_start == 0 || opts->warm_start == 1, DFM_E_INVALID, "warm_start must be 0 or 1");
   DFM_REQUIRE(tet_offsets[0] == 0 && tet_offsets[ngroups] == op->nt, DFM_E_INVALID,
@@ -946,5 +957,6 @@ extern "C" dfm_status dfm_solve_groups(dfm_op op, const double *rho0, double *rh
   std::vector<int64_t> toff(tet_offsets, tet_offsets + ngroups + 1);
   for (int g = 0; g < ngroups; ++g)
     DFM_REQUIRE(toff[g + 1] > toff[g], DFM_E_INVALID, "tet_offsets must increase strictly");
+  if (opts->method == 2) return solve_twolevel_impl(op, rho0, rho, nrhs, opts, toff, info, (hipStream_t)stream_);
   return solve_groups_impl(op, rho0, rho, nrhs, opts, toff, info, (hipStream_t)stream_);
 }

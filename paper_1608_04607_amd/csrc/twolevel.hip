@@ -1,0 +1,1451 @@
+// Two-level solve of (I - B) rho = rho0 (Sec. 2, Eq. GovIE) for many right-hand
+// sides at once, inside FP64 iterative refinement.
+//
+// Why two levels.  Each application of B moves the density one tetrahedron
+// further, so the Neumann series (Eq. NSum) needs as many terms as a ray needs
+// tet crossings to lose its energy: thousands on fine meshes with reflecting
+// walls.  The slowly decaying part of the error is smooth in space and of low
+// order in the global direction of travel (the reverberant field, and the
+// fields that bounce between opposite walls), so it is removed by a Galerkin
+// correction on a small coarse space: on every aggregate of neighbouring tets,
+// F functions of the global direction d -- 1, the three components of d and the
+// five quadratic harmonics of d -- constant in space on each face of the
+// aggregate.  Expanded in a slot's own basis such a density has the coefficients
+// sqrt(area) G^-1 int psi_k Y_f cos(theta) dOmega (constant position function
+// only).  With P that prolongation,
+//   A_c = P^T (I - B) P   (one dense block per independent instance),
+// and each iteration on the correction system (I - B) e = t0 is
+//   c = A_c^-1 P^T t;   e += t + (B P) c;   t <- B (t - P c + (B P) c)
+// (a coarse correction followed by one Richardson step).  B P is local: the rows
+// of a slot depend only on the aggregate of the tet upstream of it, W[slot][k][f].
+// The product therefore needs, besides B t, the terms B W cu (one F-vector cu per
+// inbound face: the coarse coefficients of the aggregate upstream of that face)
+// and -W[dest] cs (cs of the tet's own aggregate): they are 4F extra columns of
+// the FP16 copy of B, contracted on the matrix cores with the coefficients.
+//
+// Precision.  Each refinement stage solves the correction system to about 1e-2,
+// so t and B are FP16 (products on the FP16 matrix cores with FP32
+// accumulation); e accumulates in FP32; the solution and the refinement residual
+// r = rho0 - (I - B) rho stay in FP64 (the stored operator, FP64 or FP32).  The
+// residual is scaled to unit max norm per (right-hand side, instance) before it
+// is rounded to FP16.
+//
+// Layouts.  FP16 and FP32 vectors are slot-major, [slot][rhs][Kp8] (Kp8 = K
+// rounded up to a multiple of 8, padding zero), so the right-hand-side tile of a
+// slot is one contiguous run.  The FP16 copy of B holds, per block row, NCH
+// chunks of 32 columns ([3 Kp8 slot columns | 4F correction columns | zero
+// padding]), each chunk a contiguous [K][32] tile.
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "dfm_internal.h"
+#include "basis_dev.h"
+
+namespace dfm {
+
+namespace {
+
+__device__ inline int in_face2(int l_out, int s) { return s < l_out ? s : s + 1; }
+
+typedef _Float16 half_t;
+typedef half_t h4 __attribute__((ext_vector_type(4)));
+typedef half_t h8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int FMAX = 9;        // coarse functions per aggregate
+constexpr int NMONO = 10;      // monomials of degree <= 2 in the frame components
+constexpr int KC = 32;         // columns per chunk of the FP16 product
+constexpr int ROWG = 96;       // output rows per row group of the FP16 product
+constexpr int KP8MAX = 160;    // largest Kp8 the product stages (K <= 160)
+
+// Global direction functions, as polynomials of d: index -> (monomial of d)
+//   0: 1, 1: X, 2: Y, 3: Z, 4: XY, 5: YZ, 6: XZ, 7: X^2 - Y^2, 8: 3 Z^2 - 1.
+// Coarse function sets: 1 -> {0}; 4 -> {0,1,2,3}; 6 -> {0,4..8}; 9 -> {0..8}.
+__host__ __device__ inline int coarse_function(int F, int f) { return F == 6 ? (f == 0 ? 0 : f + 3) : f; }
+
+// ---------------------------------------------------------------------------
+// Setup kernels
+// ---------------------------------------------------------------------------
+
+// Mm[k][m] = G^-1 int psi_k(d) mono_m(d) cos(theta) dOmega over the inward
+// hemisphere of a frame, mono = (1, x, y, z, xx, xy, xz, yy, yz, zz) of the frame
+// components (Gauss rule, 32 points in u = cos(theta), 64 in phi).  One block,
+// LDS sums; psi_k premultiplied by G^-1 per node.
+constexpr int MONO_NU = 32, MONO_NP = 64;
+__global__ void k_mono_table(int D, int family, const double *__restrict__ thom, double *__restrict__ Mm) {
+  __shared__ double sums[153 * NMONO];
+  __shared__ double gx[MONO_NP], gw[MONO_NP], ux[MONO_NU], uw[MONO_NU];
+  const int M = (D + 1) * (D + 2) / 2;
+  for (int i = threadIdx.x; i < M * NMONO; i += blockDim.x) sums[i] = 0.0;
+  if (threadIdx.x < MONO_NP) {
+    double x, w;
+    gauss_legendre_node(MONO_NP, threadIdx.x, x, w);
+    gx[threadIdx.x] = x;
+    gw[threadIdx.x] = w;
+  }
+  if (threadIdx.x < MONO_NU) {
+    double x, w;
+    gauss_legendre_node(MONO_NU, threadIdx.x, x, w);
+    ux[threadIdx.x] = 0.5 * (x + 1.0);
+    uw[threadIdx.x] = 0.5 * w;
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < MONO_NU * MONO_NP; q += blockDim.x) {
+    const int iu = q / MONO_NP, ip = q - iu * MONO_NP;
+    const double u = ux[iu], phi = M_PI * (gx[ip] + 1.0);
+    const double w = uw[iu] * M_PI * gw[ip] * u;          // u du dphi
+    const double st = sqrt(fmax(0.0, 1.0 - u * u));
+    const double x = st * cos(phi), y = st * sin(phi), z = u;
+    const double mono[NMONO] = {1.0, x, y, z, x * x, x * y, x * z, y * y, y * z, z * z};
+    double g[153];
+    momentum_row<DMAX, true>(x, y, z, D, family, thom, g);
+    for (int k = 0; k < M; ++k)
+      for (int m = 0; m < NMONO; ++m) atomicAdd(&sums[k * NMONO + m], w * mono[m] * g[k]);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < M * NMONO; i += blockDim.x) Mm[i] = sums[i];
+}
+
+// T[f][m]: coefficients of the global function f in the frame monomials.  The
+// global direction is d = x ex + y ey + z ez with (ex, ey, ez) the frame rows, so
+// X = a . l, Y = b . l, Z = c . l with l = (x, y, z), a = (ex0, ey0, ez0), ...
+__device__ inline void function_monomials(const double *ex, const double *ey, const double *ez, int F,
+                                          double T[FMAX][NMONO]) {
+  const double a[3] = {ex[0], ey[0], ez[0]}, b[3] = {ex[1], ey[1], ez[1]}, c[3] = {ex[2], ey[2], ez[2]};
+  // quadratic monomial index of l_i l_j: xx 4, xy 5, xz 6, yy 7, yz 8, zz 9
+  const int qi[3][3] = {{4, 5, 6}, {5, 7, 8}, {6, 8, 9}};
+  auto prod = [&](const double *p, const double *q, double *out) {   // (p.l)(q.l)
+    for (int m = 0; m < NMONO; ++m) out[m] = 0.0;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) out[qi[i][j]] += p[i] * q[j];
+  };
+  for (int f = 0; f < F; ++f) {
+    const int fn = coarse_function(F, f);
+    double *o = T[f];
+    for (int m = 0; m < NMONO; ++m) o[m] = 0.0;
+    double t1[NMONO], t2[NMONO];
+    switch (fn) {
+      case 0: o[0] = 1.0; break;
+      case 1: o[1] = a[0]; o[2] = a[1]; o[3] = a[2]; break;
+      case 2: o[1] = b[0]; o[2] = b[1]; o[3] = b[2]; break;
+      case 3: o[1] = c[0]; o[2] = c[1]; o[3] = c[2]; break;
+      case 4: prod(a, b, o); break;
+      case 5: prod(b, c, o); break;
+      case 6: prod(a, c, o); break;
+      case 7:
+        prod(a, a, t1);
+        prod(b, b, t2);
+        for (int m = 0; m < NMONO; ++m) o[m] = t1[m] - t2[m];
+        break;
+      default:
+        prod(c, c, t1);
+        for (int m = 0; m < NMONO; ++m) o[m] = 3.0 * t1[m];
+        o[0] -= 1.0;
+        break;
+    }
+  }
+}
+
+// Pv[s][k][f] = sqrt(area_s) sum_m Mm[k][m] T_s[f][m] for k < R0 (rows of the
+// constant position function within the first row group), zero otherwise; the
+// frame of slot s from its face record (area, outward normal, frame x, frame y).
+__global__ void k_coarse_pv(const double *__restrict__ face, int64_t nslot, int M, int R0, int Kp8, int F,
+                            const double *__restrict__ Mm, float *__restrict__ Pv) {
+  for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < nslot; s += (int64_t)gridDim.x * blockDim.x) {
+    const double *rec = face + FACE_REC * s;
+    const double sq = sqrt(rec[0]);
+    const double ez[3] = {-rec[1], -rec[2], -rec[3]}, ex[3] = {rec[4], rec[5], rec[6]}, ey[3] = {rec[7], rec[8], rec[9]};
+    double T[FMAX][NMONO];
+    function_monomials(ex, ey, ez, F, T);
+    float *o = Pv + s * Kp8 * F;
+    for (int k = 0; k < Kp8; ++k)
+      for (int f = 0; f < F; ++f) {
+        double v = 0.0;
+        if (k < R0 && k < M)
+          for (int m = 0; m < NMONO; ++m) v += Mm[k * NMONO + m] * T[f][m];
+        o[k * F + f] = (float)(sq * v);
+      }
+  }
+}
+
+// W[dest(br)][k][f] = sum over the block row's three blocks of
+// sum_{k' < R0} B[br, s][column k'][row k] Pv[inbound slot s][k'][f]  (row k of B P)
+template <typename TB>
+__global__ void k_coarse_W(const TB *__restrict__ B, const int32_t *__restrict__ dest, const float *__restrict__ Pv,
+                           int64_t nbr, int K, int Kp, int Kp8, int R0, int F, double *__restrict__ W64,
+                           float *__restrict__ W32) {
+  const int64_t tot = nbr * Kp8;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t br = i / Kp8;
+    const int k = (int)(i - br * Kp8);
+    const int64_t j = br >> 2;
+    const int l_out = (int)(br & 3);
+    double acc[FMAX];
+    for (int f = 0; f < FMAX; ++f) acc[f] = 0.0;
+    if (k < K)
+      for (int s = 0; s < 3; ++s) {
+        const float *pv = Pv + (4 * j + in_face2(l_out, s)) * (int64_t)Kp8 * F;
+        const TB *col = B + ((br * 3 + s) * (int64_t)K) * Kp + k;
+        for (int kk = 0; kk < R0; ++kk) {
+          const double bv = (double)col[(int64_t)kk * Kp];
+          for (int f = 0; f < F; ++f) acc[f] += bv * (double)pv[kk * F + f];
+        }
+      }
+    const int64_t o = ((int64_t)dest[br] * Kp8 + k) * F;
+    for (int f = 0; f < F; ++f) {
+      W64[o + f] = acc[f];
+      W32[o + f] = (float)acc[f];
+    }
+  }
+}
+
+// FP16 copy of B with the correction columns, chunk-tiled: element (row k,
+// column cc) of block row br at ((br NCH + cc / KC) K + k) KC + cc % KC.
+//   cc < 3 Kp8:            B[br, s][column][row k], s = cc / Kp8 (zero past K)
+//   3 Kp8 + s F + f:       (B[br, s] W[inbound slot s])[k][f]
+//   3 Kp8 + 3 F + f:       -W[dest(br)][k][f]
+// One thread per (block row, row).
+template <typename TB>
+__global__ void k_to_b16_aug(const TB *__restrict__ B, const int32_t *__restrict__ dest, const double *__restrict__ W64,
+                             int64_t nbr, int K, int Kp, int Kp8, int F, int NCH, half_t *__restrict__ B16) {
+  const int64_t tot = nbr * K;
+  const int NC = 3 * Kp8;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t br = i / K;
+    const int k = (int)(i - br * K);
+    const int64_t j = br >> 2;
+    const int l_out = (int)(br & 3);
+    auto put = [&](int cc, float v) {
+      B16[((br * NCH + cc / KC) * (int64_t)K + k) * KC + (cc % KC)] = (half_t)v;
+    };
+    for (int cc = 0; cc < NC; ++cc) {
+      const int s = cc / Kp8, col = cc - s * Kp8;
+      put(cc, col < K ? (float)B[((br * 3 + s) * (int64_t)K + col) * Kp + k] : 0.0f);
+    }
+    for (int s = 0; s < 3; ++s) {
+      const double *w = W64 + (4 * j + in_face2(l_out, s)) * (int64_t)Kp8 * F;
+      double acc[FMAX];
+      for (int f = 0; f < FMAX; ++f) acc[f] = 0.0;
+      const TB *row = B + ((br * 3 + s) * (int64_t)K) * Kp + k;
+      for (int kk = 0; kk < K; ++kk) {
+        const double bv = (double)row[(int64_t)kk * Kp];
+        for (int f = 0; f < F; ++f) acc[f] += bv * w[kk * F + f];
+      }
+      for (int f = 0; f < F; ++f) put(NC + s * F + f, (float)acc[f]);
+    }
+    const double *wd = W64 + ((int64_t)dest[br] * Kp8 + k) * F;
+    for (int f = 0; f < F; ++f) put(NC + 3 * F + f, (float)(-wd[f]));
+    for (int cc = NC + 4 * F; cc < NCH * KC; ++cc) put(cc, 0.0f);
+  }
+}
+
+// Coarse matrix A_c = P^T P - P^T (B P), block per instance (row (g, f) of the
+// block at row_off[g] + f n_g F): slot s of aggregate a with upstream aggregate u
+// adds  Pv_s[:, f] . Pv_s[:, f']  at ((a, f), (a, f')) and  -Pv_s[:, f] . W_s[:, f']
+// at ((a, f), (u, f')).  One thread per (slot, f, f').
+__global__ void k_coarse_Ac(const float *__restrict__ Pv, const double *__restrict__ W64,
+                            const int32_t *__restrict__ agg_slot, const int32_t *__restrict__ agg_up,
+                            const int64_t *__restrict__ row_off, const int32_t *__restrict__ blk_lo,
+                            const int32_t *__restrict__ blk_n, int64_t nslot, int Kp8, int R0, int F,
+                            double *__restrict__ Ac) {
+  const int64_t tot = nslot * F * F;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t s = i / (F * F);
+    const int ff = (int)(i - s * F * F), f = ff / F, f2 = ff - f * F;
+    const float *pv = Pv + s * Kp8 * F;
+    const double *w = W64 + s * Kp8 * F;
+    double pp = 0.0, pw = 0.0;
+    for (int k = 0; k < R0; ++k) pp += (double)pv[k * F + f] * (double)pv[k * F + f2];
+    for (int k = 0; k < Kp8; ++k) pw += (double)pv[k * F + f] * w[k * F + f2];
+    const int ag = agg_slot[s], u = agg_up[s];
+    const int lo = blk_lo[ag], nF = blk_n[ag] * F;
+    if (u < lo || u >= lo + blk_n[ag]) continue;   // couples instances: refused on the host
+    double *row = Ac + row_off[ag] + (int64_t)f * nF;
+    atomicAdd(row + (ag - lo) * F + f2, pp);
+    atomicAdd(row + (u - lo) * F + f2, -pw);
+  }
+}
+
+__global__ void k_tet_centroids(const int32_t *__restrict__ tets, const double *__restrict__ verts, int64_t nt,
+                                double *__restrict__ out) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nt; t += (int64_t)gridDim.x * blockDim.x)
+    for (int i = 0; i < 3; ++i) {
+      double s = 0.0;
+      for (int m = 0; m < 4; ++m) s += verts[3 * (int64_t)tets[4 * t + m] + i];
+      out[3 * t + i] = 0.25 * s;
+    }
+}
+
+// agg_slot[s]; agg_up[dest[s]] = aggregate of tet s / 4
+__global__ void k_coarse_maps(const int32_t *__restrict__ agg_tet, const int32_t *__restrict__ dest, int64_t nslot,
+                              int32_t *__restrict__ agg_slot, int32_t *__restrict__ agg_up) {
+  for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < nslot; s += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t g = agg_tet[s >> 2];
+    agg_slot[s] = g;
+    agg_up[dest[s]] = g;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The FP16 product (see the file header):
+//   y[dest(br)][r][m] = sum_cc B16[br][m][cc] x[r][cc]
+// with x[r][cc] = t[slot(cc)][r][cc mod Kp8] for the slot columns and the
+// coarse coefficients for the correction columns (cu of the face's upstream
+// aggregate, cs of the tet's aggregate; the columns are skipped when c is null),
+// y rounded to FP16; for the first row group also
+// d0[dest][f][r] = sum_{k < R0} Pv[dest][k][f] y[r][k].
+// Workgroup = (block row, tile of 128 right-hand sides, row group of 96); 8
+// waves = 2 row halves (3 row tiles of 16) x 4 rhs quarters (2 tiles of 16),
+// v_mfma_f32_16x16x16_f16.  Chunks of 32 columns go through LDS (B [row][col],
+// x [rhs][col]), the next chunk loaded while the current one is contracted.
+// Rows of instances that are not multiplied (gact[gid[tet]] == 0) get y = 0 and
+// d0 = 0.  The four block rows of a tet go to one XCD (workgroups are dealt to
+// the eight XCDs in turn) so the slots they share are read from one L2.
+// ---------------------------------------------------------------------------
+constexpr int P16_THREADS = 512;
+constexpr int P16_RT = 128;
+#ifndef DFM_P16_NSUB
+#define DFM_P16_NSUB 3
+#endif
+constexpr int NSUB = DFM_P16_NSUB;         // chunks loaded per round (one barrier pair per round)
+constexpr int P16_LD = KC + 8;             // LDS row stride (halves) of both chunks
+constexpr int P16_YLD = ROWG + 8;          // LDS row stride (halves) of the result [rhs][row]
+constexpr size_t P16_LDS_CHUNK = sizeof(half_t) * (size_t)NSUB * (ROWG + P16_RT) * P16_LD;
+constexpr size_t P16_LDS_OUT = sizeof(half_t) * (size_t)P16_RT * P16_YLD;
+constexpr size_t P16_LDS = P16_LDS_CHUNK > P16_LDS_OUT ? P16_LDS_CHUNK : P16_LDS_OUT;
+static_assert(P16_RT * KC / 8 == P16_THREADS && ROWG * KC / 8 <= P16_THREADS, "one piece per thread");
+
+struct P16Args {
+  const half_t *B16;
+  const int32_t *dest;
+  int64_t nt;
+  int K, Kp8, R, F, NCH, R0;
+  const half_t *t;          // [4 nt][R][Kp8]
+  half_t *y;                // [4 nt][R][Kp8]
+  float *d0;                // [4 nt][F][R] or null
+  const float *Pv;          // [4 nt][Kp8][F]
+  const int32_t *agg_slot;  // [4 nt]
+  const int32_t *agg_up;    // [4 nt]
+  const float *c;           // [ng F][R] or null (no correction)
+  const int32_t *gid;       // tet -> instance, or null
+  const uint8_t *gact;      // instance -> multiplied, or null
+};
+
+__global__ __launch_bounds__(P16_THREADS, 2) void k_spmm16(P16Args a) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  half_t *bs = reinterpret_cast<half_t *>(lds_raw);       // [NSUB][ROWG][P16_LD]
+  half_t *xs = bs + NSUB * ROWG * P16_LD;                 // [NSUB][P16_RT][P16_LD]
+  __shared__ float pvs[ROWG * FMAX];                      // Pv of the destination slot (first row group)
+  __shared__ int32_t gsh[4];                              // upstream aggregates of the 3 inbound faces; own
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  int64_t br = blockIdx.x;
+  if ((a.nt & 7) == 0) {
+    const int64_t slot = br >> 3, xcd = br & 7;
+    br = 4 * (8 * (slot >> 2) + xcd) + (slot & 3);
+  }
+  const int r0 = blockIdx.y * P16_RT;
+  const int m0 = blockIdx.z * ROWG;
+  const int64_t j = br >> 2;
+  const int l_out = (int)(br & 3);
+  const int K = a.K, Kp8 = a.Kp8, F = a.F;
+  const int NC = 3 * Kp8;
+  const int64_t dslot = a.dest[br];
+  const int64_t ldr = (int64_t)a.R * Kp8;                 // one slot's run of all right-hand sides
+  const int nrows = min(ROWG, Kp8 - m0);                  // output rows of this group (multiple of 8)
+  if (a.gact != nullptr && a.gact[a.gid[j]] == 0) {
+    const int npr = nrows / 8;
+    for (int i = tid; i < P16_RT * npr; i += P16_THREADS) {
+      const int r = i / npr, m = 8 * (i - r * npr);
+      if (r0 + r < a.R)
+        *reinterpret_cast<h8 *>(a.y + dslot * ldr + (int64_t)(r0 + r) * Kp8 + m0 + m) = h8{0, 0, 0, 0, 0, 0, 0, 0};
+    }
+    if (m0 == 0 && a.d0)
+      for (int i = tid; i < F * P16_RT; i += P16_THREADS) {
+        const int f = i / P16_RT, r = i - f * P16_RT;
+        if (r0 + r < a.R) a.d0[(dslot * F + f) * a.R + r0 + r] = 0.0f;
+      }
+    return;
+  }
+  const bool corr = a.c != nullptr;
+  if (tid < 3) gsh[tid] = a.agg_up[4 * j + in_face2(l_out, tid)];
+  if (tid == 3) gsh[3] = a.agg_slot[4 * j];
+  if (m0 == 0 && a.d0)
+    for (int i = tid; i < a.R0 * F; i += P16_THREADS) pvs[i] = a.Pv[dslot * Kp8 * F + i];
+  __syncthreads();
+
+  // this thread's pieces: B row m0 + prow, x right-hand side r0 + prow; columns
+  // 8 (tid % 4) .. + 7 of the chunk
+  const int prow = tid >> 2, pcol = 8 * (tid & 3);
+  const half_t *Bbr = a.B16 + br * (int64_t)a.NCH * K * KC;
+  const int brows = min(ROWG, K - m0);                    // stored rows of this group
+  h8 pbv[NSUB], pxv[NSUB];
+  auto load_chunk = [&](int ch, h8 &pb, h8 &px) {
+    pb = (tid < ROWG * KC / 8 && prow < brows)
+             ? *reinterpret_cast<const h8 *>(Bbr + ((int64_t)ch * K + m0 + prow) * KC + pcol)
+             : h8{0, 0, 0, 0, 0, 0, 0, 0};
+    const int c = ch * KC + pcol;
+    const int r = r0 + prow;
+    px = h8{0, 0, 0, 0, 0, 0, 0, 0};
+    if (r < a.R) {
+      if (c < NC) {
+        const int s = c / Kp8, k = c - s * Kp8;
+        px = *reinterpret_cast<const h8 *>(a.t + (4 * j + in_face2(l_out, s)) * ldr + (int64_t)r * Kp8 + k);
+      } else if (corr) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int e = c - NC + u;
+          float v = 0.0f;
+          if (e < 3 * F) v = a.c[((int64_t)gsh[e / F] * F + e % F) * a.R + r];
+          else if (e < 4 * F) v = a.c[((int64_t)gsh[3] * F + (e - 3 * F)) * a.R + r];
+          px[u] = (half_t)v;
+        }
+      }
+    }
+  };
+  auto store_chunk = [&](int u) {
+    if (tid < ROWG * KC / 8) *reinterpret_cast<h8 *>(bs + (u * ROWG + prow) * P16_LD + pcol) = pbv[u];
+    *reinterpret_cast<h8 *>(xs + (u * P16_RT + prow) * P16_LD + pcol) = pxv[u];
+  };
+
+  const int wr = wave >> 2, wc = wave & 3;
+  const int col = lane & 15, kq = lane >> 4;
+  f4 acc[3][2];
+#pragma unroll
+  for (int u = 0; u < 3; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v) acc[u][v] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+  auto contract = [&](int sub) {
+    const half_t *bsu = bs + sub * ROWG * P16_LD, *xsu = xs + sub * P16_RT * P16_LD;
+#pragma unroll
+    for (int ks = 0; ks < KC / 16; ++ks) {
+      const int kk = ks * 16 + 4 * kq;
+      h4 av[3], bv[2];
+#pragma unroll
+      for (int u = 0; u < 3; ++u) av[u] = *reinterpret_cast<const h4 *>(bsu + ((wr * 3 + u) * 16 + col) * P16_LD + kk);
+#pragma unroll
+      for (int v = 0; v < 2; ++v) bv[v] = *reinterpret_cast<const h4 *>(xsu + ((wc * 2 + v) * 16 + col) * P16_LD + kk);
+#pragma unroll
+      for (int u = 0; u < 3; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) acc[u][v] = __builtin_amdgcn_mfma_f32_16x16x16f16(av[u], bv[v], acc[u][v], 0, 0, 0);
+    }
+  };
+  // the correction columns sit in the last chunks; without correction they are skipped
+  const int nch = corr ? a.NCH : (NC + KC - 1) / KC;
+  const int nround = (nch + NSUB - 1) / NSUB;
+  auto load_round = [&](int rd) {
+#pragma unroll
+    for (int u = 0; u < NSUB; ++u) {
+      const int ch = rd * NSUB + u;
+      if (ch < nch) load_chunk(ch, pbv[u], pxv[u]);
+    }
+  };
+  load_round(0);
+  for (int rd = 0; rd < nround; ++rd) {
+    const int nsub = min(NSUB, nch - rd * NSUB);
+#pragma unroll
+    for (int u = 0; u < NSUB; ++u)
+      if (u < nsub) store_chunk(u);
+    __syncthreads();
+    if (rd + 1 < nround) load_round(rd + 1);   // in flight during this round's contraction
+#pragma unroll
+    for (int u = 0; u < NSUB; ++u)
+      if (u < nsub) contract(u);
+    __syncthreads();
+  }
+  half_t *ys = reinterpret_cast<half_t *>(lds_raw);         // [P16_RT][P16_YLD]
+#pragma unroll
+  for (int u = 0; u < 3; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        ys[((wc * 2 + v) * 16 + col) * P16_YLD + (wr * 3 + u) * 16 + 4 * kq + q] = (half_t)acc[u][v][q];
+  __syncthreads();
+  const int npr = nrows / 8;
+  for (int i = tid; i < P16_RT * npr; i += P16_THREADS) {
+    const int r = i / npr, m = 8 * (i - r * npr);
+    if (r0 + r >= a.R) continue;
+    *reinterpret_cast<h8 *>(a.y + dslot * ldr + (int64_t)(r0 + r) * Kp8 + m0 + m) =
+        *reinterpret_cast<const h8 *>(ys + r * P16_YLD + m);
+  }
+  if (m0 == 0 && a.d0)
+    for (int i = tid; i < F * P16_RT; i += P16_THREADS) {
+      const int f = i / P16_RT, r = i - f * P16_RT;
+      if (r0 + r >= a.R) continue;
+      float s = 0.0f;
+      for (int k = 0; k < a.R0; ++k) s = fmaf(pvs[k * F + f], (float)ys[r * P16_YLD + k], s);
+      a.d0[(dslot * F + f) * a.R + r0 + r] = s;
+    }
+}
+
+// d0[s][f][r] = sum_{k < R0} Pv[s][k][f] t[s][r][k] (the coarse right-hand side of
+// a vector that did not come out of the product); one thread per (slot, rhs)
+__global__ void k_d0_from_t(const half_t *__restrict__ t, const float *__restrict__ Pv, int64_t nslot, int R, int Kp8,
+                            int R0, int F, float *__restrict__ d0) {
+  const int64_t tot = nslot * R;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t s = i / R;
+    const int r = (int)(i - s * R);
+    const half_t *tp = t + (s * R + r) * Kp8;
+    const float *pv = Pv + s * Kp8 * F;
+    float acc[FMAX];
+    for (int f = 0; f < FMAX; ++f) acc[f] = 0.0f;
+    for (int k = 0; k < R0; ++k) {
+      const float v = (float)tp[k];
+      for (int f = 0; f < F; ++f) acc[f] = fmaf(pv[k * F + f], v, acc[f]);
+    }
+    for (int f = 0; f < F; ++f) d0[(s * F + f) * R + r] = acc[f];
+  }
+}
+
+// z[(g F + f)][r] += sum of d0[slot][f][r] over the slots of aggregate g (perm
+// lists the slots in aggregate order); a workgroup takes RED_CH positions of perm
+// and one (f, r) column per thread, adding each run of one aggregate with one
+// atomic.
+constexpr int RED_CH = 256;
+__global__ void k_coarse_reduce(const float *__restrict__ d0, const int32_t *__restrict__ perm,
+                                const int32_t *__restrict__ agg_slot, int64_t nslot, int FR, float *__restrict__ z) {
+  const int q = blockIdx.y * blockDim.x + threadIdx.x;   // column f R + r
+  if (q >= FR) return;
+  const int64_t i0 = blockIdx.x * (int64_t)RED_CH;
+  const int64_t i1 = min(i0 + RED_CH, nslot);
+  float acc = 0.0f;
+  int32_t g = agg_slot[perm[i0]];
+  for (int64_t i = i0; i < i1; ++i) {
+    const int32_t s = perm[i];
+    const int32_t gs = agg_slot[s];
+    if (gs != g) {
+      atomicAdd(z + (int64_t)g * FR + q, acc);
+      acc = 0.0f;
+      g = gs;
+    }
+    acc += d0[(int64_t)s * FR + q];
+  }
+  atomicAdd(z + (int64_t)g * FR + q, acc);
+}
+
+// c[(g f)][r] = sum over the instance block of Ai[(g f)][.] z[.][r];  csum += c.
+// one_function: only the constant function (f = 0) is corrected, with the inverse
+// Ai1 of the f = 0 part of the coarse matrix (rows at row_off1[g], blk_n[g] long);
+// the other coefficients are zero.
+__global__ void k_coarse_solve(const float *__restrict__ Ai, const int64_t *__restrict__ row_off,
+                               const float *__restrict__ Ai1, const int64_t *__restrict__ row_off1, int one_function,
+                               const int32_t *__restrict__ blk_lo, const int32_t *__restrict__ blk_n, int ng, int F,
+                               int R, const float *__restrict__ z, float *__restrict__ c, float *__restrict__ csum) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t NG = (int64_t)ng * F;
+  if (i >= NG * R) return;
+  const int64_t gf = i / R;
+  const int r = (int)(i - gf * R);
+  const int g = (int)(gf / F), f = (int)(gf - (int64_t)g * F);
+  const int lo = blk_lo[g];
+  float acc = 0.0f;
+  if (!one_function) {
+    const int nF = blk_n[g] * F;
+    const float *row = Ai + row_off[g] + (int64_t)f * nF;
+    const float *zc = z + (int64_t)lo * F * R + r;
+    for (int q = 0; q < nF; ++q) acc = fmaf(row[q], zc[(int64_t)q * R], acc);
+  } else if (f == 0) {
+    const int nb = blk_n[g];
+    const float *row = Ai1 + row_off1[g];
+    const float *zc = z + (int64_t)lo * F * R + r;
+    for (int q = 0; q < nb; ++q) acc = fmaf(row[q], zc[(int64_t)q * F * R], acc);
+  }
+  c[i] = acc;
+  csum[i] += acc;
+}
+
+__global__ void k_zero_f32n(float *__restrict__ p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0f;
+}
+
+__global__ void k_zero_f64n(double *__restrict__ p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
+// instance of slot s: soff[g] <= s < soff[g + 1]
+__device__ inline int instance_of(const int64_t *__restrict__ soff, int G, int64_t s) {
+  int lo = 0, hi = G;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (soff[mid] <= s) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Start of a refinement stage: t[s][r][k] = half(sc[r][g] res[r][s K + k]) (zero
+// padding), e = 0.
+__global__ void k_stage_init(const double *__restrict__ res, int64_t nslot, int K, int Kp8,
+                             const int64_t *__restrict__ soff, int G, const double *__restrict__ sc, int R,
+                             half_t *__restrict__ t, float *__restrict__ e) {
+  const int64_t tot = nslot * R * Kp8;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t sr = i / Kp8;
+    const int k = (int)(i - sr * Kp8);
+    const int64_t s = sr / R;
+    const int r = (int)(sr - s * R);
+    const double f = sc[(int64_t)r * G + instance_of(soff, G, s)];
+    t[i] = (half_t)(k < K ? (float)(f * res[(int64_t)r * nslot * K + s * K + k]) : 0.0f);
+    e[i] = 0.0f;
+  }
+}
+
+// e += sum of the nwin values of t in the ring (+ (B P) csum when W is given: once
+// per refinement stage, with the coarse coefficients summed over the stage)
+constexpr int WIN = 8;
+struct RingPtrs {
+  const half_t *p[WIN];
+};
+__global__ void k_flush(RingPtrs ring, int nwin, int64_t nslot, int Kp8, int R, int F, const float *__restrict__ W,
+                        const int32_t *__restrict__ agg_up, const float *__restrict__ csum, float *__restrict__ e) {
+  const int64_t n8 = nslot * R * Kp8 / 8;
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n8; q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = 8 * q;
+    const int64_t sr = i / Kp8;
+    const int k0 = (int)(i - sr * Kp8);
+    const int64_t s = sr / R;
+    const int r = (int)(sr - s * R);
+    float v[8];
+    const f4 lo = *reinterpret_cast<const f4 *>(e + i), hi = *reinterpret_cast<const f4 *>(e + i + 4);
+    for (int u = 0; u < 4; ++u) {
+      v[u] = lo[u];
+      v[u + 4] = hi[u];
+    }
+    if (W) {
+      const float *w = W + (s * Kp8 + k0) * F;
+      const float *cs = csum + (int64_t)agg_up[s] * F * R + r;
+      for (int f = 0; f < F; ++f) {
+        const float cf = cs[(int64_t)f * R];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = fmaf(w[u * F + f], cf, v[u]);
+      }
+    }
+    for (int m = 0; m < nwin; ++m) {
+      const h8 x = *reinterpret_cast<const h8 *>(ring.p[m] + i);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] += (float)x[u];
+    }
+    *reinterpret_cast<f4 *>(e + i) = f4{v[0], v[1], v[2], v[3]};
+    *reinterpret_cast<f4 *>(e + i + 4) = f4{v[4], v[5], v[6], v[7]};
+  }
+}
+
+// rho[r][s K + k] += e[s][r][k] / sc[r][g]
+__global__ void k_stage_update(const float *__restrict__ e, int64_t nslot, int K, int Kp8,
+                               const int64_t *__restrict__ soff, int G, const double *__restrict__ sc, int R,
+                               double *__restrict__ rho) {
+  const int64_t n = nslot * K;
+  const int64_t tot = n * R;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / n;
+    const int64_t q = i - r * n;
+    const int64_t s = q / K;
+    const int k = (int)(q - s * K);
+    const double f = sc[r * G + instance_of(soff, G, s)];
+    if (f > 0.0) rho[i] += (double)e[(s * R + r) * Kp8 + k] / f;
+  }
+}
+
+// out[r * G + g] = max |v[r][i]| over instance g's elements [off[g], off[g+1])
+// (non-negative doubles order like their bit patterns); grid (x, rhs, instance)
+__global__ void k_seg_absmax(const double *__restrict__ v, int64_t n, const int64_t *__restrict__ off, int G,
+                             unsigned long long *__restrict__ out) {
+  __shared__ double red[4];
+  const int r = blockIdx.y, g = blockIdx.z;
+  const double *row = v + (int64_t)r * n;
+  double m = 0.0;
+  for (int64_t i = off[g] + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < off[g + 1];
+       i += (int64_t)gridDim.x * blockDim.x)
+    m = fmax(m, fabs(row[i]));
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_down(m, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = red[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) t = fmax(t, red[w]);
+    atomicMax(out + (int64_t)r * G + g, (unsigned long long)__double_as_longlong(t));
+  }
+}
+
+// squared norms per (rhs, instance) of an FP64 [R][n] block; grid (x, rhs, instance)
+__global__ void k_seg_norms2_d(const double *__restrict__ v, int64_t n, const int64_t *__restrict__ off, int G,
+                               double *__restrict__ out) {
+  __shared__ double red[4];
+  const int r = blockIdx.y, g = blockIdx.z;
+  const double *row = v + (int64_t)r * n;
+  double acc = 0.0;
+  for (int64_t i = off[g] + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < off[g + 1];
+       i += (int64_t)gridDim.x * blockDim.x)
+    acc = fma(row[i], row[i], acc);
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = red[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+    atomicAdd(out + (int64_t)r * G + g, t);
+  }
+}
+
+// squared norms per (rhs, instance) of a slot-major FP16 [slot][R][Kp8] block:
+// the workgroup sums its stretch of instance g's slots into LDS per rhs, then one
+// atomic per rhs (R <= 4096); grid (x, instance)
+constexpr int NRM_RMAX = 4096;
+__global__ void k_seg_norms2_h(const half_t *__restrict__ t, int R, int Kp8, const int64_t *__restrict__ soff, int G,
+                               double *__restrict__ out) {
+  __shared__ double acc_r[NRM_RMAX];
+  const int g = blockIdx.y;
+  for (int r = threadIdx.x; r < R; r += blockDim.x) acc_r[r] = 0.0;
+  __syncthreads();
+  const int ppr = Kp8 / 8;                               // 8-half pieces per (slot, rhs)
+  const int64_t q0 = soff[g] * R * ppr, q1 = soff[g + 1] * R * ppr;
+  for (int64_t q = q0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < q1; q += (int64_t)gridDim.x * blockDim.x) {
+    const h8 x = *reinterpret_cast<const h8 *>(t + 8 * q);
+    double s2 = 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const double a = (double)(float)x[u];
+      s2 = fma(a, a, s2);
+    }
+    const int r = (int)((q / ppr) % R);
+    atomicAdd(&acc_r[r], s2);
+  }
+  __syncthreads();
+  for (int r = threadIdx.x; r < R; r += blockDim.x)
+    if (acc_r[r] != 0.0) atomicAdd(out + (int64_t)r * G + g, acc_r[r]);
+}
+
+// ---------------------------------------------------------------------------
+// FP64 residual of the stored operator for several right-hand sides per pass:
+//   res[r] = rho0[r] - x[r] + B x[r],  x, rho0, res f64 [R][ndof]
+// As the streaming product: each thread owns VW consecutive rows of one block
+// row and streams its 3K columns once for NR right-hand sides, the x panels of
+// the workgroup's block rows staged in LDS one inbound face at a time; FP64
+// accumulation.
+// ---------------------------------------------------------------------------
+constexpr int RES_THREADS = 256;
+template <typename TB>
+struct VecOf;
+template <>
+struct VecOf<double> {
+  static constexpr int W = 2;
+  typedef double T __attribute__((ext_vector_type(2)));
+};
+template <>
+struct VecOf<float> {
+  static constexpr int W = 4;
+  typedef float T __attribute__((ext_vector_type(4)));
+};
+
+template <typename TB, int NR>
+__global__ __launch_bounds__(RES_THREADS) void k_resid(const TB *__restrict__ B, const int32_t *__restrict__ dest,
+                                                      int64_t nthreads, int K, int Kp, int64_t ndof, int nr,
+                                                      const double *__restrict__ x, const double *__restrict__ rho0,
+                                                      double *__restrict__ res) {
+  constexpr int VW = VecOf<TB>::W;
+  typedef typename VecOf<TB>::T VT;
+  extern __shared__ double xs_res[];
+  const int GPB = Kp / VW;
+  const int64_t g0 = blockIdx.x * (int64_t)RES_THREADS;
+  const int64_t br0 = g0 / GPB;
+  int64_t glast = g0 + RES_THREADS - 1;
+  if (glast >= nthreads) glast = nthreads - 1;
+  const int nrows_b = (int)(glast / GPB - br0 + 1);
+  const int per_rhs = nrows_b * K;
+  const int64_t g = g0 + threadIdx.x;
+  const bool inrange = g < nthreads;
+  const int64_t br = inrange ? g / GPB : br0;
+  const int row0 = (int)(g - br * GPB) * VW;
+  const double *xp = xs_res + (br - br0) * K;
+  const VT *Bv = reinterpret_cast<const VT *>(B + br * 3 * (int64_t)K * Kp + row0);
+  const int cstride = Kp / VW;
+  double acc[NR][VW];
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+#pragma unroll
+    for (int u = 0; u < VW; ++u) acc[r][u] = 0.0;
+  for (int s = 0; s < 3; ++s) {
+    if (s) __syncthreads();
+    for (int i = threadIdx.x; i < NR * per_rhs; i += RES_THREADS) {
+      const int r = i / per_rhs, q = i - r * per_rhs;
+      const int b = q / K, col = q - b * K;
+      const int64_t bb = br0 + b;
+      xs_res[i] = r < nr ? x[r * ndof + (4 * (bb >> 2) + in_face2((int)(bb & 3), s)) * (int64_t)K + col] : 0.0;
+    }
+    __syncthreads();
+    if (inrange) {
+      const VT *Bs = Bv + (int64_t)s * K * cstride;
+#pragma unroll 2
+      for (int c = 0; c < K; ++c) {
+        const VT bv = __builtin_nontemporal_load(Bs + (int64_t)c * cstride);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          const double xc = xp[r * per_rhs + c];
+#pragma unroll
+          for (int u = 0; u < VW; ++u) acc[r][u] = fma((double)bv[u], xc, acc[r][u]);
+        }
+      }
+    }
+  }
+  if (!inrange) return;
+  const int64_t ob = (int64_t)dest[br] * K;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    if (r >= nr) break;
+#pragma unroll
+    for (int u = 0; u < VW; ++u) {
+      const int row = row0 + u;
+      if (row < K) {
+        const int64_t o = r * ndof + ob + row;
+        res[o] = rho0[o] - x[o] + acc[r][u];
+      }
+    }
+  }
+}
+
+// gid[j] = g for the tets j of instance g (tet offsets toff; grid z = instance)
+__global__ void k_fill_gid2(const int64_t *__restrict__ toff, int32_t *__restrict__ gid) {
+  const int g = blockIdx.z;
+  for (int64_t j = toff[g] + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < toff[g + 1];
+       j += (int64_t)gridDim.x * blockDim.x)
+    gid[j] = g;
+}
+
+}  // namespace
+
+// res = rho0 - (I - B) x for R right-hand sides (FP64 vectors, the stored operator)
+hipError_t residual_batched(dfm_op op, const double *rho0, const double *x, double *res, int R, hipStream_t st) {
+  constexpr int NR = 8;
+  for (int r0 = 0; r0 < R; r0 += NR) {
+    const int nr = std::min(NR, R - r0);
+    const int64_t off = (int64_t)r0 * op->ndof;
+    const int vw = op->B ? 2 : 4;
+    const int gpb = op->Kp / vw;
+    const int64_t nthreads = 4 * op->nt * (int64_t)gpb;
+    const int64_t rows = (RES_THREADS + gpb - 1) / gpb + 1;
+    const size_t lds = sizeof(double) * (size_t)(NR * rows * op->K);
+    const unsigned grid = (unsigned)((nthreads + RES_THREADS - 1) / RES_THREADS);
+    hipError_t e;
+    if (op->B) {
+      e = hipFuncSetAttribute((const void *)k_resid<double, NR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((k_resid<double, NR>), dim3(grid), dim3(RES_THREADS), lds, st, op->B, op->dest, nthreads,
+                         op->K, op->Kp, op->ndof, nr, x + off, rho0 + off, res + off);
+    } else {
+      e = hipFuncSetAttribute((const void *)k_resid<float, NR>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((k_resid<float, NR>), dim3(grid), dim3(RES_THREADS), lds, st, op->B32, op->dest, nthreads,
+                         op->K, op->Kp, op->ndof, nr, x + off, rho0 + off, res + off);
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// Coarse space of an operator for a given partition into instances (cached with
+// the FP16 copy of B, whose correction columns depend on it).
+// ---------------------------------------------------------------------------
+struct Coarse {
+  std::vector<int64_t> toff;     // instance partition it was built for
+  int ng = 0, F = 1, R0 = 1, NCH = 0;
+  int32_t *agg_slot = nullptr, *agg_up = nullptr, *perm = nullptr, *blk_lo = nullptr, *blk_n = nullptr;
+  int64_t *row_off = nullptr, *row_off1 = nullptr;
+  float *Pv = nullptr, *W = nullptr, *Ai = nullptr, *Ai1 = nullptr;
+  void release() {
+    (void)hipFree(row_off1);
+    (void)hipFree(Ai1);
+    (void)hipFree(agg_slot);
+    (void)hipFree(agg_up);
+    (void)hipFree(perm);
+    (void)hipFree(blk_lo);
+    (void)hipFree(blk_n);
+    (void)hipFree(row_off);
+    (void)hipFree(Pv);
+    (void)hipFree(W);
+    (void)hipFree(Ai);
+    *this = Coarse{};
+  }
+};
+
+void free_twolevel(dfm_op op) {
+  if (!op) return;
+  if (op->coarse) {
+    op->coarse->release();
+    delete op->coarse;
+    op->coarse = nullptr;
+  }
+  (void)hipFree(op->B16);
+  op->B16 = nullptr;
+}
+
+namespace {
+
+// In-place inverse of the n x n row-major matrix a (Gauss-Jordan, partial
+// pivoting); false when a pivot vanishes.
+bool invert(std::vector<double> &a, int n) {
+  std::vector<double> inv((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) inv[(size_t)i * n + i] = 1.0;
+  for (int c = 0; c < n; ++c) {
+    int p = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(a[(size_t)r * n + c]) > std::fabs(a[(size_t)p * n + c])) p = r;
+    const double piv = a[(size_t)p * n + c];
+    if (!(std::fabs(piv) > 1e-300) || !std::isfinite(piv)) return false;
+    if (p != c)
+      for (int k = 0; k < n; ++k) {
+        std::swap(a[(size_t)p * n + k], a[(size_t)c * n + k]);
+        std::swap(inv[(size_t)p * n + k], inv[(size_t)c * n + k]);
+      }
+    const double ip = 1.0 / piv;
+    for (int k = 0; k < n; ++k) {
+      a[(size_t)c * n + k] *= ip;
+      inv[(size_t)c * n + k] *= ip;
+    }
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      const double f = a[(size_t)r * n + c];
+      if (f == 0.0) continue;
+      for (int k = 0; k < n; ++k) {
+        a[(size_t)r * n + k] -= f * a[(size_t)c * n + k];
+        inv[(size_t)r * n + k] -= f * inv[(size_t)c * n + k];
+      }
+    }
+  }
+  a.swap(inv);
+  return true;
+}
+
+int env_int(const char *name, int dflt) {
+  const char *v = getenv(name);
+  return (v && *v) ? atoi(v) : dflt;
+}
+
+}  // namespace
+
+// Build (or reuse) the coarse space of op for the instance partition toff, and the
+// FP16 copy of B with its correction columns.
+dfm_status ensure_coarse(dfm_op op, const std::vector<int64_t> &toff, hipStream_t st) {
+  if (op->coarse && op->coarse->toff == toff && op->B16) return DFM_OK;
+  if (!op->coarse) op->coarse = new Coarse();
+  Coarse &C = *op->coarse;
+  C.release();
+  (void)hipFree(op->B16);
+  op->B16 = nullptr;
+  const int64_t nt = op->nt, nslot = 4 * nt, nbr = 4 * nt;
+  const int K = op->K, M = op->M;
+  op->Kp8 = (K + 7) / 8 * 8;
+  const int Kp8 = op->Kp8;
+  const int G = (int)toff.size() - 1;
+  // coarse functions per aggregate (1, 4, 6 or 9) and tets per aggregate
+  int F = env_int("DFM_COARSE_F", 9);
+  if (F != 1 && F != 4 && F != 6 && F != 9) F = 9;
+  const double tets_per_agg = (double)std::max(1, env_int("DFM_COARSE_TETS", 1536));
+  const int R0 = std::min(M, ROWG);
+  const int NCH = (3 * Kp8 + 4 * F + KC - 1) / KC;
+  double *cent_d = nullptr, *Mm = nullptr, *W64 = nullptr, *Ac = nullptr;
+  int32_t *agg_tet_d = nullptr;
+  auto cleanup = [&]() {
+    (void)hipFree(cent_d);
+    (void)hipFree(Mm);
+    (void)hipFree(W64);
+    (void)hipFree(Ac);
+    (void)hipFree(agg_tet_d);
+  };
+#define TRYC(expr)                                                                           \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) {                                                                  \
+      set_error(std::string(#expr) + ": " + hipGetErrorString(e_));                          \
+      cleanup();                                                                             \
+      C.release();                                                                           \
+      return e_ == hipErrorOutOfMemory ? DFM_E_NOMEM : DFM_E_HIP;                            \
+    }                                                                                        \
+  } while (0)
+  // 1. aggregates: per instance, cubic bins of its bounding box holding about
+  //    tets_per_agg tets each; empty bins are dropped
+  TRYC(hipMalloc(&cent_d, sizeof(double) * 3 * nt));
+  hipLaunchKernelGGL(k_tet_centroids, dim3(ew_grid(nt)), dim3(256), 0, st, op->mesh->tets, op->mesh->verts, nt,
+                     cent_d);
+  TRYC(hipGetLastError());
+  std::vector<double> cent(3 * nt);
+  TRYC(hipMemcpyAsync(cent.data(), cent_d, sizeof(double) * 3 * nt, hipMemcpyDeviceToHost, st));
+  TRYC(hipStreamSynchronize(st));
+  std::vector<int32_t> agg_tet(nt);
+  std::vector<int> inst_lo(G + 1, 0);   // first aggregate of every instance
+  int ng = 0;
+  for (int g = 0; g < G; ++g) {
+    inst_lo[g] = ng;
+    const int64_t a0 = toff[g], a1 = toff[g + 1];
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int64_t t = a0; t < a1; ++t)
+      for (int i = 0; i < 3; ++i) {
+        lo[i] = std::min(lo[i], cent[3 * t + i]);
+        hi[i] = std::max(hi[i], cent[3 * t + i]);
+      }
+    const double target = std::max(1.0, std::round((double)(a1 - a0) / tets_per_agg));
+    double ext[3], vol = 1.0;
+    for (int i = 0; i < 3; ++i) {
+      ext[i] = std::max(hi[i] - lo[i], 1e-12);
+      vol *= ext[i];
+    }
+    const double side = std::cbrt(vol / target);
+    int nb[3];
+    for (int i = 0; i < 3; ++i) nb[i] = std::max(1, (int)std::lround(ext[i] / side));
+    std::vector<int> id((size_t)nb[0] * nb[1] * nb[2], -1);
+    for (int64_t t = a0; t < a1; ++t) {
+      int b[3];
+      for (int i = 0; i < 3; ++i)
+        b[i] = std::min(nb[i] - 1, std::max(0, (int)((cent[3 * t + i] - lo[i]) / ext[i] * nb[i])));
+      const size_t key = ((size_t)b[2] * nb[1] + b[1]) * nb[0] + b[0];
+      if (id[key] < 0) id[key] = ng++;
+      agg_tet[t] = id[key];
+    }
+  }
+  inst_lo[G] = ng;
+  C.ng = ng;
+  C.F = F;
+  C.R0 = R0;
+  C.NCH = NCH;
+  std::vector<int64_t> row_off(ng);
+  std::vector<int32_t> blk_lo(ng), blk_n(ng);
+  int64_t ai_size = 0;
+  for (int g = 0; g < G; ++g) {
+    const int n = inst_lo[g + 1] - inst_lo[g];
+    for (int q = 0; q < n; ++q) {
+      row_off[inst_lo[g] + q] = ai_size + (int64_t)q * F * n * F;
+      blk_lo[inst_lo[g] + q] = inst_lo[g];
+      blk_n[inst_lo[g] + q] = n;
+    }
+    ai_size += (int64_t)n * F * n * F;
+  }
+  // 2. maps, the coarse basis Pv, W = B P, and the FP16 copy with its columns
+  TRYC(hipMalloc(&agg_tet_d, sizeof(int32_t) * nt));
+  TRYC(hipMalloc(&C.agg_slot, sizeof(int32_t) * nslot));
+  TRYC(hipMalloc(&C.agg_up, sizeof(int32_t) * nslot));
+  TRYC(hipMalloc(&Mm, sizeof(double) * M * NMONO));
+  TRYC(hipMalloc(&C.Pv, sizeof(float) * nslot * Kp8 * F));
+  TRYC(hipMalloc(&C.W, sizeof(float) * nslot * Kp8 * F));
+  TRYC(hipMalloc(&W64, sizeof(double) * nslot * Kp8 * F));
+  TRYC(hipMalloc(&C.row_off, sizeof(int64_t) * ng));
+  TRYC(hipMalloc(&C.blk_lo, sizeof(int32_t) * ng));
+  TRYC(hipMalloc(&C.blk_n, sizeof(int32_t) * ng));
+  TRYC(hipMalloc(&Ac, sizeof(double) * std::max<int64_t>(ai_size, 1)));
+  TRYC(hipMalloc(&op->B16, sizeof(half_t) * nbr * NCH * K * KC));
+  TRYC(hipMemcpyAsync(agg_tet_d, agg_tet.data(), sizeof(int32_t) * nt, hipMemcpyHostToDevice, st));
+  TRYC(hipMemcpyAsync(C.row_off, row_off.data(), sizeof(int64_t) * ng, hipMemcpyHostToDevice, st));
+  TRYC(hipMemcpyAsync(C.blk_lo, blk_lo.data(), sizeof(int32_t) * ng, hipMemcpyHostToDevice, st));
+  TRYC(hipMemcpyAsync(C.blk_n, blk_n.data(), sizeof(int32_t) * ng, hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(k_coarse_maps, dim3(ew_grid(nslot)), dim3(256), 0, st, agg_tet_d, op->dest, nslot, C.agg_slot,
+                     C.agg_up);
+  hipLaunchKernelGGL(k_mono_table, dim3(1), dim3(256), 0, st, op->basis.mom_degree, op->basis.mom_family, op->thom, Mm);
+  hipLaunchKernelGGL(k_coarse_pv, dim3(ew_grid(nslot)), dim3(256), 0, st, op->mesh->face, nslot, M, R0, Kp8, F, Mm,
+                     C.Pv);
+  if (op->B) {
+    hipLaunchKernelGGL(k_coarse_W<double>, dim3(ew_grid(nbr * Kp8)), dim3(256), 0, st, op->B, op->dest, C.Pv, nbr, K,
+                       op->Kp, Kp8, R0, F, W64, C.W);
+    hipLaunchKernelGGL(k_to_b16_aug<double>, dim3(ew_grid(nbr * K)), dim3(256), 0, st, op->B, op->dest, W64, nbr, K,
+                       op->Kp, Kp8, F, NCH, reinterpret_cast<half_t *>(op->B16));
+  } else {
+    hipLaunchKernelGGL(k_coarse_W<float>, dim3(ew_grid(nbr * Kp8)), dim3(256), 0, st, op->B32, op->dest, C.Pv, nbr, K,
+                       op->Kp, Kp8, R0, F, W64, C.W);
+    hipLaunchKernelGGL(k_to_b16_aug<float>, dim3(ew_grid(nbr * K)), dim3(256), 0, st, op->B32, op->dest, W64, nbr, K,
+                       op->Kp, Kp8, F, NCH, reinterpret_cast<half_t *>(op->B16));
+  }
+  TRYC(hipGetLastError());
+  // 3. A_c block per instance on the device, inverted on the host
+  hipLaunchKernelGGL(k_zero_f64n, dim3(ew_grid(std::max<int64_t>(ai_size, 1))), dim3(256), 0, st, Ac,
+                     std::max<int64_t>(ai_size, 1));
+  hipLaunchKernelGGL(k_coarse_Ac, dim3(ew_grid(nslot * F * F)), dim3(256), 0, st, C.Pv, W64, C.agg_slot, C.agg_up,
+                     C.row_off, C.blk_lo, C.blk_n, nslot, Kp8, R0, F, Ac);
+  TRYC(hipGetLastError());
+  std::vector<double> Ah(ai_size);
+  std::vector<int32_t> up(nslot);
+  TRYC(hipMemcpyAsync(Ah.data(), Ac, sizeof(double) * ai_size, hipMemcpyDeviceToHost, st));
+  TRYC(hipMemcpyAsync(up.data(), C.agg_up, sizeof(int32_t) * nslot, hipMemcpyDeviceToHost, st));
+  TRYC(hipStreamSynchronize(st));
+  for (int g = 0; g < G; ++g)
+    for (int64_t s = 4 * toff[g]; s < 4 * toff[g + 1]; ++s)
+      if (up[s] < inst_lo[g] || up[s] >= inst_lo[g + 1]) {
+        cleanup();
+        C.release();
+        set_error("the operator couples tets of different instances");
+        return DFM_E_INVALID;
+      }
+  std::vector<float> Ai(ai_size);
+  std::vector<int64_t> row_off1(ng);
+  std::vector<float> Ai1;
+  for (int g = 0; g < G; ++g) {
+    const int nb = inst_lo[g + 1] - inst_lo[g], nF = nb * F;
+    const int64_t base = row_off[inst_lo[g]];
+    std::vector<double> a(Ah.begin() + base, Ah.begin() + base + (int64_t)nF * nF);
+    // the constant-function block (every F-th row and column) for the fallback
+    std::vector<double> a1((size_t)nb * nb);
+    for (int p = 0; p < nb; ++p)
+      for (int q = 0; q < nb; ++q) a1[(size_t)p * nb + q] = a[(size_t)(p * F) * nF + q * F];
+    if (!invert(a, nF) || !invert(a1, nb)) {
+      cleanup();
+      C.release();
+      set_error("the coarse matrix P^T (I - B) P is singular");
+      return DFM_E_NUMERIC;
+    }
+    for (int64_t i = 0; i < (int64_t)nF * nF; ++i) Ai[base + i] = (float)a[i];
+    for (int p = 0; p < nb; ++p) row_off1[inst_lo[g] + p] = (int64_t)Ai1.size() + (int64_t)p * nb;
+    for (double v : a1) Ai1.push_back((float)v);
+  }
+  // slots in aggregate order (counting sort)
+  std::vector<int64_t> cnt(ng + 1, 0);
+  for (int64_t s = 0; s < nslot; ++s) cnt[agg_tet[s >> 2] + 1]++;
+  for (int g = 0; g < ng; ++g) cnt[g + 1] += cnt[g];
+  std::vector<int32_t> perm(nslot);
+  for (int64_t s = 0; s < nslot; ++s) perm[cnt[agg_tet[s >> 2]]++] = (int32_t)s;
+  TRYC(hipMalloc(&C.perm, sizeof(int32_t) * nslot));
+  TRYC(hipMalloc(&C.Ai, sizeof(float) * std::max<int64_t>(ai_size, 1)));
+  TRYC(hipMalloc(&C.Ai1, sizeof(float) * std::max<size_t>(Ai1.size(), 1)));
+  TRYC(hipMalloc(&C.row_off1, sizeof(int64_t) * ng));
+  TRYC(hipMemcpyAsync(C.perm, perm.data(), sizeof(int32_t) * nslot, hipMemcpyHostToDevice, st));
+  TRYC(hipMemcpyAsync(C.Ai, Ai.data(), sizeof(float) * ai_size, hipMemcpyHostToDevice, st));
+  TRYC(hipMemcpyAsync(C.Ai1, Ai1.data(), sizeof(float) * Ai1.size(), hipMemcpyHostToDevice, st));
+  TRYC(hipMemcpyAsync(C.row_off1, row_off1.data(), sizeof(int64_t) * ng, hipMemcpyHostToDevice, st));
+  TRYC(hipStreamSynchronize(st));   // the host vectors above must outlive their copies
+#undef TRYC
+  cleanup();
+  C.toff = toff;
+  return DFM_OK;
+}
+
+namespace {
+hipError_t launch_product16(dfm_op op, const half_t *t, half_t *y, float *d0, int R, const float *c,
+                            const int32_t *gid, const uint8_t *gact, hipStream_t st) {
+  const Coarse &C = *op->coarse;
+  P16Args a{};
+  a.B16 = reinterpret_cast<const half_t *>(op->B16);
+  a.dest = op->dest;
+  a.nt = op->nt;
+  a.K = op->K;
+  a.Kp8 = op->Kp8;
+  a.R = R;
+  a.F = C.F;
+  a.NCH = C.NCH;
+  a.R0 = C.R0;
+  a.t = t;
+  a.y = y;
+  a.d0 = d0;
+  a.Pv = C.Pv;
+  a.agg_slot = C.agg_slot;
+  a.agg_up = C.agg_up;
+  a.c = c;
+  a.gid = gid;
+  a.gact = gact;
+  dim3 grid((unsigned)(4 * op->nt), (unsigned)((R + P16_RT - 1) / P16_RT), (unsigned)((op->Kp8 + ROWG - 1) / ROWG));
+  hipError_t e = hipFuncSetAttribute((const void *)k_spmm16, hipFuncAttributeMaxDynamicSharedMemorySize, (int)P16_LDS);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_spmm16, grid, dim3(P16_THREADS), P16_LDS, st, a);
+  return hipGetLastError();
+}
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// The two-level solve inside FP64 refinement (method 2), R right-hand sides on
+// G instances (instance g owns tets [toff[g], toff[g+1])).  Every pair
+// (rhs, instance) stops on its own relative residual; an instance all of whose
+// pairs are done or below their inner target is no longer multiplied.
+// ---------------------------------------------------------------------------
+dfm_status solve_twolevel_impl(dfm_op op, const double *rho0, double *rho, int R, const dfm_solve_opts *opts,
+                               const std::vector<int64_t> &toff, dfm_solve_info *info, hipStream_t st) {
+  const int64_t nslot = 4 * op->nt, n = op->ndof;
+  const int G = (int)toff.size() - 1;
+  const size_t RG = (size_t)R * G;
+  constexpr double INNER_TOL = 1e-2;
+  constexpr int CHECK = 8;
+  const bool grouped = G > 1;
+  if ((op->K + 7) / 8 * 8 > KP8MAX) {
+    set_error("the two-level solver supports K <= 160 unknowns per slot");
+    return DFM_E_UNSUPPORTED;
+  }
+  if (R > NRM_RMAX) {
+    set_error("the two-level solver takes at most 4096 right-hand sides per call");
+    return DFM_E_UNSUPPORTED;
+  }
+  half_t *ring_buf = nullptr;
+  float *e = nullptr, *d0 = nullptr, *z = nullptr, *c = nullptr, *csum = nullptr;
+  double *res = nullptr, *sc_d = nullptr, *nrm_d = nullptr;
+  unsigned long long *mx_d = nullptr;
+  int64_t *soff_d = nullptr, *eoff_d = nullptr, *toff_d = nullptr;
+  uint8_t *gact_d = nullptr;
+  int32_t *gid = nullptr;
+  auto cleanup = [&]() {
+    (void)hipFree(ring_buf);
+    (void)hipFree(e);
+    (void)hipFree(d0);
+    (void)hipFree(z);
+    (void)hipFree(c);
+    (void)hipFree(csum);
+    (void)hipFree(res);
+    (void)hipFree(sc_d);
+    (void)hipFree(nrm_d);
+    (void)hipFree(mx_d);
+    (void)hipFree(soff_d);
+    (void)hipFree(eoff_d);
+    (void)hipFree(toff_d);
+    (void)hipFree(gact_d);
+    (void)hipFree(gid);
+  };
+#define TRYT(expr)                                                                           \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) {                                                                  \
+      set_error(std::string(#expr) + ": " + hipGetErrorString(e_));                          \
+      cleanup();                                                                             \
+      return e_ == hipErrorOutOfMemory ? DFM_E_NOMEM : DFM_E_HIP;                            \
+    }                                                                                        \
+  } while (0)
+  {
+    dfm_status cs = ensure_coarse(op, toff, st);
+    if (cs != DFM_OK) {
+      cleanup();
+      return cs;
+    }
+  }
+  const Coarse &C = *op->coarse;
+  const int Kp8 = op->Kp8, K = op->K, F = C.F;
+  const int64_t vlen = nslot * R * Kp8;               // elements of one slot-major vector
+  const int64_t NG = (int64_t)C.ng * F;
+  const int64_t zn = NG * R;
+  TRYT(hipMalloc(&ring_buf, sizeof(half_t) * (size_t)(WIN + 1) * vlen));
+  TRYT(hipMalloc(&e, sizeof(float) * (size_t)vlen));
+  TRYT(hipMalloc(&d0, sizeof(float) * (size_t)nslot * F * R));
+  TRYT(hipMalloc(&z, sizeof(float) * (size_t)zn));
+  TRYT(hipMalloc(&c, sizeof(float) * (size_t)zn));
+  TRYT(hipMalloc(&csum, sizeof(float) * (size_t)zn));
+  TRYT(hipMalloc(&res, sizeof(double) * (size_t)R * n));
+  TRYT(hipMalloc(&sc_d, sizeof(double) * RG));
+  TRYT(hipMalloc(&nrm_d, sizeof(double) * RG));
+  TRYT(hipMalloc(&mx_d, sizeof(unsigned long long) * RG));
+  TRYT(hipMalloc(&soff_d, sizeof(int64_t) * (G + 1)));
+  TRYT(hipMalloc(&eoff_d, sizeof(int64_t) * (G + 1)));
+  if (grouped) {
+    TRYT(hipMalloc(&gact_d, sizeof(uint8_t) * G));
+    TRYT(hipMalloc(&gid, sizeof(int32_t) * op->nt));
+    TRYT(hipMalloc(&toff_d, sizeof(int64_t) * (G + 1)));
+    TRYT(hipMemcpyAsync(toff_d, toff.data(), sizeof(int64_t) * (G + 1), hipMemcpyHostToDevice, st));
+    int64_t maxt = 0;
+    for (int g = 0; g < G; ++g) maxt = std::max(maxt, toff[g + 1] - toff[g]);
+    hipLaunchKernelGGL(k_fill_gid2, dim3((unsigned)std::min<int64_t>((maxt + 255) / 256, 4096), 1, G), dim3(256), 0,
+                       st, toff_d, gid);
+    TRYT(hipGetLastError());
+  }
+  std::vector<int64_t> soff(G + 1), eoff(G + 1);
+  for (int g = 0; g <= G; ++g) {
+    soff[g] = 4 * toff[g];
+    eoff[g] = 4 * toff[g] * K;        // element offsets in the FP64 vectors
+  }
+  TRYT(hipMemcpyAsync(soff_d, soff.data(), sizeof(int64_t) * (G + 1), hipMemcpyHostToDevice, st));
+  TRYT(hipMemcpyAsync(eoff_d, eoff.data(), sizeof(int64_t) * (G + 1), hipMemcpyHostToDevice, st));
+  int64_t maxseg = 0;
+  for (int g = 0; g < G; ++g) maxseg = std::max(maxseg, eoff[g + 1] - eoff[g]);
+  const dim3 sgrid((unsigned)std::min<int64_t>((maxseg + 255) / 256, grouped ? 64 : 1024), (unsigned)R, (unsigned)G);
+  const dim3 hgrid((unsigned)std::min<int64_t>((maxseg * R / 8 + 255) / 256 + 1, grouped ? 64 : 2048), (unsigned)G);
+  std::vector<double> h(RG);
+  auto fetch = [&](double *src) -> hipError_t {
+    hipError_t er = hipMemcpyAsync(h.data(), src, sizeof(double) * RG, hipMemcpyDeviceToHost, st);
+    return er != hipSuccess ? er : hipStreamSynchronize(st);
+  };
+  auto norms_res = [&]() -> hipError_t {
+    hipLaunchKernelGGL(k_zero_f64n, dim3(ew_grid((int64_t)RG)), dim3(256), 0, st, nrm_d, (int64_t)RG);
+    hipLaunchKernelGGL(k_seg_norms2_d, sgrid, dim3(256), 0, st, res, n, eoff_d, G, nrm_d);
+    hipError_t er = hipGetLastError();
+    return er != hipSuccess ? er : fetch(nrm_d);
+  };
+  auto norms_t = [&](const half_t *t) -> hipError_t {
+    hipLaunchKernelGGL(k_zero_f64n, dim3(ew_grid((int64_t)RG)), dim3(256), 0, st, nrm_d, (int64_t)RG);
+    hipLaunchKernelGGL(k_seg_norms2_h, hgrid, dim3(256), 0, st, t, R, Kp8, soff_d, G, nrm_d);
+    hipError_t er = hipGetLastError();
+    return er != hipSuccess ? er : fetch(nrm_d);
+  };
+  std::vector<double> bn(RG), rn(RG), rel(RG, 1.0), t0n(RG), target(RG), scale(RG);
+  std::vector<char> done(RG, 0), inner(RG, 0);
+  std::vector<uint8_t> gact(G, 1);
+  std::vector<int> gprod(G, 0);
+  TRYT(hipMemcpyAsync(res, rho0, sizeof(double) * (size_t)R * n, hipMemcpyDeviceToDevice, st));
+  TRYT(norms_res());
+  for (size_t i = 0; i < RG; ++i) {
+    bn[i] = std::sqrt(h[i]);
+    if (!(bn[i] > 0.0)) {
+      done[i] = 1;
+      rel[i] = 0.0;
+    }
+  }
+  if (!opts->warm_start) {
+    hipLaunchKernelGGL(k_zero_f64n, dim3(ew_grid((int64_t)R * n)), dim3(256), 0, st, rho, (int64_t)R * n);
+    TRYT(hipGetLastError());
+    rn = bn;
+  } else {
+    TRYT(residual_batched(op, rho0, rho, res, R, st));
+    TRYT(norms_res());
+    for (size_t i = 0; i < RG; ++i) {
+      rn[i] = std::sqrt(h[i]);
+      if (done[i]) continue;
+      rel[i] = rn[i] / bn[i];
+      if (rel[i] <= opts->rtol) done[i] = 1;
+    }
+  }
+  auto all_done = [&]() {
+    for (size_t i = 0; i < RG; ++i)
+      if (!done[i]) return false;
+    return true;
+  };
+  auto update_active = [&]() -> hipError_t {
+    if (!grouped) return hipSuccess;
+    bool changed = false;
+    for (int g = 0; g < G; ++g) {
+      uint8_t a = 0;
+      for (int r = 0; r < R; ++r) a |= (!done[(size_t)r * G + g] && !inner[(size_t)r * G + g]) ? 1 : 0;
+      changed |= a != gact[g];
+      gact[g] = a;
+    }
+    if (!changed) return hipSuccess;
+    hipError_t er = hipMemcpyAsync(gact_d, gact.data(), sizeof(uint8_t) * G, hipMemcpyHostToDevice, st);
+    return er != hipSuccess ? er : hipStreamSynchronize(st);
+  };
+  if (grouped) TRYT(hipMemcpyAsync(gact_d, gact.data(), sizeof(uint8_t) * G, hipMemcpyHostToDevice, st));
+  auto ring = [&](int k) { return ring_buf + (size_t)(k % (WIN + 1)) * vlen; };
+  const unsigned red_grid = (unsigned)((nslot + RED_CH - 1) / RED_CH);
+  const int FR = F * R;
+  const int red_threads = FR >= 256 ? 256 : ((FR + 63) / 64) * 64;
+  const unsigned gz = (unsigned)((FR + red_threads - 1) / red_threads);
+  int iters = 0;
+  bool finite = true;
+  const unsigned egrid = ew_grid(vlen / 8);
+  // coarse level: 2 = all F functions, 1 = the constant function, 0 = none.  A
+  // stage whose residual grows DIVERGE times (the Galerkin correction of a
+  // non-symmetric operator can amplify) restarts one level lower.
+  constexpr double DIVERGE = 4.0;
+  int level = F > 1 ? 2 : 1;
+  for (int outer = 0; outer < 40 && iters < opts->max_iter && !all_done(); ++outer) {
+  restart_stage:
+    // scale every active pair to unit max norm; t_0 = half(scale * r)
+    hipLaunchKernelGGL(k_zero_f64n, dim3(ew_grid((int64_t)RG)), dim3(256), 0, st, reinterpret_cast<double *>(mx_d),
+                       (int64_t)RG);
+    hipLaunchKernelGGL(k_seg_absmax, sgrid, dim3(256), 0, st, res, n, eoff_d, G, mx_d);
+    TRYT(hipGetLastError());
+    {
+      std::vector<unsigned long long> mx(RG);
+      TRYT(hipMemcpyAsync(mx.data(), mx_d, sizeof(unsigned long long) * RG, hipMemcpyDeviceToHost, st));
+      TRYT(hipStreamSynchronize(st));
+      for (size_t i = 0; i < RG; ++i) {
+        double m;
+        std::memcpy(&m, &mx[i], sizeof(double));
+        scale[i] = (!done[i] && m > 0.0) ? 1.0 / m : 0.0;
+        inner[i] = done[i];
+        // the correction needs no more accuracy than the outer test asks for
+        target[i] = std::max(INNER_TOL, 0.5 * opts->rtol * bn[i] / std::max(rn[i], 1e-300));
+      }
+    }
+    TRYT(hipMemcpyAsync(sc_d, scale.data(), sizeof(double) * RG, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_stage_init, dim3(ew_grid(vlen)), dim3(256), 0, st, res, nslot, K, Kp8, soff_d, G, sc_d, R,
+                       ring(0), e);
+    hipLaunchKernelGGL(k_d0_from_t, dim3(ew_grid(nslot * R)), dim3(256), 0, st, ring(0), C.Pv, nslot, R, Kp8, C.R0, F,
+                       d0);
+    hipLaunchKernelGGL(k_zero_f32n, dim3(ew_grid(zn)), dim3(256), 0, st, csum, zn);
+    TRYT(hipGetLastError());
+    TRYT(norms_t(ring(0)));
+    for (size_t i = 0; i < RG; ++i) t0n[i] = std::sqrt(h[i]);
+    TRYT(update_active());
+    int k = 0, pending = 0;   // t_k in ring(k); t_{k-pending} .. t_{k-1} not yet added to e
+    // the ring's pending terms go into e; the (B P) c terms of the whole stage are
+    // added once at its end (last = true), from the stage's sum of coefficients
+    auto flush = [&](bool last) -> hipError_t {
+      if (pending == 0 && !last) return hipSuccess;
+      RingPtrs rp{};
+      for (int m = 0; m < pending; ++m) rp.p[m] = ring(k - pending + m);
+      hipLaunchKernelGGL(k_flush, dim3(egrid), dim3(256), 0, st, rp, pending, nslot, Kp8, R, F,
+                         (last && level > 0) ? C.W : nullptr, C.agg_up, csum, e);
+      pending = 0;
+      return hipGetLastError();
+    };
+    bool diverged = false;
+    while (iters < opts->max_iter) {
+      // coarse correction from t_k (d0 holds its coarse components)
+      if (level > 0) {
+        hipLaunchKernelGGL(k_zero_f32n, dim3(ew_grid(zn)), dim3(256), 0, st, z, zn);
+        hipLaunchKernelGGL(k_coarse_reduce, dim3(red_grid, gz), dim3(red_threads), 0, st, d0, C.perm, C.agg_slot,
+                           nslot, FR, z);
+        hipLaunchKernelGGL(k_coarse_solve, dim3((unsigned)((zn + 255) / 256)), dim3(256), 0, st, C.Ai, C.row_off,
+                           C.Ai1, C.row_off1, level == 1 ? 1 : 0, C.blk_lo, C.blk_n, C.ng, F, R, z, c, csum);
+        TRYT(hipGetLastError());
+      }
+      // t_{k+1} = B16 (t_k - P c + (B P) c); t_k joins the ring of pending e terms
+      TRYT(launch_product16(op, ring(k), ring(k + 1), d0, R, level > 0 ? c : nullptr, grouped ? gid : nullptr,
+                            grouped ? gact_d : nullptr, st));
+      ++k;
+      ++pending;
+      ++iters;
+      for (int g = 0; g < G; ++g) gprod[g] += gact[g];
+      if (pending == WIN) TRYT(flush(false));
+      if (k % CHECK) continue;
+      TRYT(norms_t(ring(k)));
+      bool inner_done = true;
+      for (size_t i = 0; i < RG; ++i) {
+        if (inner[i]) continue;
+        const double tn = std::sqrt(h[i]);
+        if (!std::isfinite(tn) || tn > DIVERGE * t0n[i]) diverged = true;
+        if (tn <= target[i] * t0n[i]) inner[i] = 1;
+        else inner_done = false;
+      }
+      if (diverged && level > 0) break;
+      diverged = false;   // without a coarse correction the growth is B's own (left to max_iter)
+      if (inner_done || !finite) break;
+      TRYT(update_active());
+    }
+    if (diverged && level > 0) {
+      --level;   // the stage's e is discarded; start it again one level lower
+      goto restart_stage;
+    }
+    TRYT(flush(true));
+    if (!finite) break;
+    // rho += e / scale;  res = rho0 - (I - B) rho in FP64
+    hipLaunchKernelGGL(k_stage_update, dim3(ew_grid((int64_t)R * n)), dim3(256), 0, st, e, nslot, K, Kp8, soff_d, G,
+                       sc_d, R, rho);
+    TRYT(hipGetLastError());
+    TRYT(residual_batched(op, rho0, rho, res, R, st));
+    TRYT(norms_res());
+    for (size_t i = 0; i < RG; ++i) {
+      if (done[i]) continue;
+      rn[i] = std::sqrt(h[i]);
+      rel[i] = rn[i] / bn[i];
+      if (!std::isfinite(rel[i])) finite = false;
+      if (rel[i] <= opts->rtol) done[i] = 1;
+    }
+    if (!finite) break;
+  }
+#undef TRYT
+  cleanup();
+  dfm_status status = DFM_OK;
+  for (int g = 0; g < G; ++g)
+    for (int r = 0; r < R; ++r) {
+      const size_t i = (size_t)r * G + g;
+      if (info) info[(size_t)g * R + r] = dfm_solve_info{grouped ? gprod[g] : iters, 0, rel[i]};
+      if (!std::isfinite(rel[i])) status = DFM_E_NUMERIC;
+      else if (!done[i] && status == DFM_OK) status = DFM_E_NOCONV;
+    }
+  if (!finite) status = DFM_E_NUMERIC;
+  if (status == DFM_E_NOCONV) set_error("solver stopped at max_iter above the tolerance");
+  if (status == DFM_E_NUMERIC) set_error("non-finite residual in the solver");
+  return status;
+}
+
+}  // namespace dfm

@@ -15,6 +15,7 @@ from ._lib import Basis, SolveInfo, SolveOpts, check
 
 LEGENDRE, ZERNIKE = 0, 1
 PAPER_RULE, SEAM_RULE = 0, 1
+METHODS = {"neumann": 0, "gmres": 1, "twolevel": 2}
 
 
 def _stream(stream=None):
@@ -133,8 +134,13 @@ class Operator:
 
     def solve(self, rho0, method="gmres", rtol=1e-8, restart=50, max_iter=20000, precision=0, stream=None,
               raise_nonconv=True, rho=None):
-        """Solve (I - B) rho = rho0; `rho` given: start from it (method "neumann" with
-        precision 1 only) and write the result into it."""
+        """Solve (I - B) rho = rho0 with method "neumann", "gmres" or "twolevel" (the
+        batched two-level iteration, FP16 products inside FP64 refinement: precision
+        2); `rho` given: start from it (batched methods only) and write the result
+        into it."""
+        m = METHODS[method]
+        if m == 2:
+            precision = 2
         rho0 = _dev(rho0, torch.float64)
         nrhs = 1 if rho0.dim() == 1 else rho0.shape[0]
         warm = rho is not None
@@ -143,16 +149,18 @@ class Operator:
                 raise TypeError("rho must be a contiguous CUDA float64 tensor shaped like rho0")
         else:
             rho = torch.empty_like(rho0)
-        opts = SolveOpts(1 if method == "gmres" else 0, restart, max_iter, rtol, int(precision), int(warm))
+        opts = SolveOpts(m, restart, max_iter, rtol, int(precision), int(warm))
         info = (SolveInfo * nrhs)()
         code = _lib.load().dfm_solve(self.handle, _ptr(rho0), _ptr(rho), nrhs, C.byref(opts), info, _stream(stream))
         if code != 0 and (raise_nonconv or code != -5):
             check(code)
         return rho, [(i.iters, i.restarts, i.relres) for i in info]
 
-    def solve_groups(self, rho0, tet_offsets, rtol=1e-8, max_iter=20000, stream=None, raise_nonconv=True, rho=None):
+    def solve_groups(self, rho0, tet_offsets, rtol=1e-8, max_iter=20000, stream=None, raise_nonconv=True, rho=None,
+                     method="neumann"):
         """Batched solve of independent instances packed into this operator
         (dfm_solve_groups): instance g owns tets [tet_offsets[g], tet_offsets[g+1]).
+        method "neumann" (FP32 Neumann, precision 1) or "twolevel" (precision 2).
         Returns rho and info [ngroups][nrhs] of (iters, restarts, relres)."""
         rho0 = _dev(rho0, torch.float64)
         nrhs = 1 if rho0.dim() == 1 else rho0.shape[0]
@@ -164,7 +172,10 @@ class Operator:
             rho = torch.empty_like(rho0)
         G = len(tet_offsets) - 1
         offs = (C.c_int64 * (G + 1))(*[int(v) for v in tet_offsets])
-        opts = SolveOpts(0, 1, max_iter, rtol, 1, int(warm))
+        m = METHODS[method]
+        if m == 1:
+            raise ValueError("instance groups are solved with method 'neumann' or 'twolevel'")
+        opts = SolveOpts(m, 1, max_iter, rtol, 2 if m == 2 else 1, int(warm))
         info = (SolveInfo * (G * nrhs))()
         code = _lib.load().dfm_solve_groups(self.handle, _ptr(rho0), _ptr(rho), nrhs, C.byref(opts), offs, G, info,
                                             _stream(stream))

@@ -526,6 +526,54 @@ def test_batched_mixed_neumann_warm_start(small):
         assert rel(rho[r].cpu().numpy(), osv.solve_direct(A, rhs[r])) < 1e-7
 
 
+@pytest.mark.parametrize("nrhs", [3, 130])
+def test_twolevel_solve_matches_oracle(small, nrhs):
+    """Method 2: all right-hand sides together, the coarse-corrected iteration on
+    FP16 products (K = 30, padded to 32; 130 right-hand sides span two tiles of
+    the product) inside FP64 refinement, against sparse LU of the oracle's B."""
+    say(f"[solve] two-level FP16 + FP64 refinement, {nrhs} rhs")
+    g, op, m, bs, Bo, desto, mu = small
+    A = osv.to_sparse(Bo, desto)
+    rhs = np.random.default_rng(40).standard_normal((nrhs, A.shape[0]))
+    rhs[1] = 0.0                                   # a zero right-hand side stays zero
+    rho, info = op.solve(torch.tensor(rhs, device=DEV), method="twolevel", rtol=1e-10)
+    rho = rho.cpu().numpy()
+    say(f"    info {info[:3]}")
+    for r in sorted({0, 1, 2, nrhs - 1}):
+        assert info[r][2] <= 1e-10
+        if r == 1:
+            assert not rho[r].any()
+            continue
+        assert osv.relres(A, rhs[r], rho[r]) <= 2e-10
+        assert rel(rho[r], osv.solve_direct(A, rhs[r])) < 1e-7
+    # warm start from a stopped solve
+    b = torch.tensor(rhs[:2], device=DEV)
+    part, info1 = op.solve(b, method="twolevel", rtol=1e-10, max_iter=4, raise_nonconv=False)
+    assert info1[0][2] > 1e-10
+    full, info2 = op.solve(b, method="twolevel", rtol=1e-10, rho=part)
+    assert info2[0][2] <= 1e-10
+    assert rel(full[0].cpu().numpy(), osv.solve_direct(A, rhs[0])) < 1e-7
+
+
+def test_twolevel_solve_two_row_groups():
+    """K = 135 (P1, Legendre D = 8): the FP16 product splits a block row's 136
+    padded rows over two row groups of 96."""
+    say("[solve] two-level, K = 135")
+    v, t, refl = box(1, 0.1, seed=41)
+    bs = oa.Basis(1, 0, 8, 3, oq.SEAM_RULE)
+    mu = np.full(t.shape[0], 0.2)
+    op = gpu_op(gpu_mesh(v, t, refl), mu, bs)
+    Bo, desto = oa.assemble(om.build_mesh(v, t, refl), bs, mu)
+    A = osv.to_sparse(Bo, desto)
+    rhs = np.random.default_rng(42).standard_normal((4, A.shape[0]))
+    rho, info = op.solve(torch.tensor(rhs, device=DEV), method="twolevel", rtol=1e-10)
+    rho = rho.cpu().numpy()
+    say(f"    info {info}")
+    for r in range(4):
+        assert info[r][2] <= 1e-10
+        assert rel(rho[r], osv.solve_direct(A, rhs[r])) < 1e-7
+
+
 def test_solve_groups_matches_oracle():
     """dfm_solve_groups on two instances packed into one operator: a box with strong
     damping (fast) and one with weak damping (slow).  Every (instance, rhs) pair
@@ -579,12 +627,28 @@ def test_solve_groups_matches_oracle():
         for r in (0, 7, 19):
             assert info20[gi][r][2] <= 1e-9
             assert osv.relres(A, rhs20[r, a:b], rho20[r, a:b]) <= 2e-9
+    # the two-level method on the same instances
+    rho2, info2 = op.solve_groups(torch.tensor(rhs20, device=DEV), offs, rtol=1e-9, method="twolevel")
+    say(f"    two-level, 20 rhs: products per instance {[row[0][0] for row in info2]}")
+    assert info2[0][0][0] <= info2[1][0][0]
+    rho2 = rho2.cpu().numpy()
+    for gi, (vv, tt, rr, mm) in enumerate(((va, ta, ra, mua), (vb, tb, rb, mub))):
+        Bo, desto = oa.assemble(om.build_mesh(vv, tt, rr), bs, mm)
+        A = osv.to_sparse(Bo, desto)
+        a, b = 4 * K * offs[gi], 4 * K * offs[gi + 1]
+        for r in (0, 7, 19):
+            assert info2[gi][r][2] <= 1e-9
+            assert osv.relres(A, rhs20[r, a:b], rho2[r, a:b]) <= 2e-9
+            assert rel(rho2[r, a:b], osv.solve_direct(A, rhs20[r, a:b])) < 1e-6
     # a connected mesh cut in two
     v2, t2, r2 = box(2, 0.1, seed=24)
     g2 = gpu_mesh(v2, t2, r2)
     op2 = gpu_op(g2, np.full(t2.shape[0], 0.1), bs)
     with pytest.raises(DFMError, match="INVALID"):
         op2.solve_groups(torch.ones((1, op2.ndof), dtype=torch.float64, device=DEV), [0, 10, t2.shape[0]])
+    with pytest.raises(DFMError, match="INVALID"):
+        op2.solve_groups(torch.ones((1, op2.ndof), dtype=torch.float64, device=DEV), [0, 10, t2.shape[0]],
+                         method="twolevel")
     op2.close()
     op.close()
 
