@@ -82,11 +82,14 @@ typedef struct {
 /* Solver options for (I - B) rho = rho0 (Sec. 2, Eq. NSum / GovIE). */
 typedef struct {
   int method;     /* 0: Neumann partial sums (Eq. NSum); 1: restarted GMRES;
-                     2: two-level Neumann: the partial sums of Eq. NSum with a coarse
-                        correction after every term (Galerkin projection of I - B on
-                        a few global-direction harmonics per aggregate of tets), all
-                        nrhs together; needs precision 2, dtype 0 and K <= 160, and
-                        is not available for transposed (adjoint) solves           */
+                     2: two-level sweeps: Gauss-Seidel sweeps of B over a colouring
+                        of the tets (no two face neighbours alike; two colours on
+                        the Kuhn boxes, so a density crosses two tets per sweep),
+                        each preceded by a coarse correction (Galerkin projection of
+                        I - B on a few global-direction harmonics per aggregate of
+                        tets), all nrhs together; needs precision 2, dtype 0 and
+                        K <= 160, and is not available for transposed (adjoint)
+                        solves                                                      */
   int restart;    /* GMRES restart length (Krylov vectors kept), 1..200                 */
   int max_iter;   /* total iteration cap (operator applications)                        */
   double rtol;    /* stop when ||rho0 - (I-B) rho||_2 <= rtol ||rho0||_2                */

@@ -1,45 +1,54 @@
 // Two-level solve of (I - B) rho = rho0 (Sec. 2, Eq. GovIE) for many right-hand
 // sides at once, inside FP64 iterative refinement.
 //
-// Why two levels.  Each application of B moves the density one tetrahedron
-// further, so the Neumann series (Eq. NSum) needs as many terms as a ray needs
-// tet crossings to lose its energy: thousands on fine meshes with reflecting
-// walls.  The slowly decaying part of the error is smooth in space and of low
-// order in the global direction of travel (the reverberant field, and the
-// fields that bounce between opposite walls), so it is removed by a Galerkin
-// correction on a small coarse space: on every aggregate of neighbouring tets,
-// F functions of the global direction d -- 1, the three components of d and the
-// five quadratic harmonics of d -- constant in space on each face of the
-// aggregate.  Expanded in a slot's own basis such a density has the coefficients
-// sqrt(area) G^-1 int psi_k Y_f cos(theta) dOmega (constant position function
-// only).  With P that prolongation,
-//   A_c = P^T (I - B) P   (one dense block per independent instance),
-// and each iteration on the correction system (I - B) e = t0 is
-//   c = A_c^-1 P^T t;   e += t + (B P) c;   t <- B (t - P c + (B P) c)
-// (a coarse correction followed by one Richardson step).  B P is local: the rows
-// of a slot depend only on the aggregate of the tet upstream of it, W[slot][k][f].
-// The product therefore needs, besides B t, the terms B W cu (one F-vector cu per
-// inbound face: the coarse coefficients of the aggregate upstream of that face)
-// and -W[dest] cs (cs of the tet's own aggregate): they are 4F extra columns of
-// the FP16 copy of B, contracted on the matrix cores with the coefficients.
+// Why.  Each application of B moves the density one tetrahedron further, so the
+// Neumann series (Eq. NSum) needs as many terms as a ray needs tet crossings to
+// lose its energy: thousands on fine meshes with reflecting walls.  Two changes
+// cut that count.
+//
+// 1. Coloured sweeps (Gauss-Seidel order).  The tets are coloured so that no two
+//    that share a face are alike (two colours on the Kuhn boxes), and B is
+//    applied colour by colour.  A slot written by a tet of a lower colour than
+//    its own tet (type L) is read later in the same sweep, so its new value is
+//    used at once; all other slots (type U) carry over to the next sweep.  With
+//    the splitting B = L + U, one sweep maps the residual r to z = r + L z (the
+//    L-type slots updated in place) and the next residual U z, and the solution
+//    grows by z.  On two colours a density crosses two tets per sweep.
+// 2. A coarse correction.  The slowly decaying part of the error is smooth in
+//    space and of low order in the global direction of travel, so it is removed
+//    by a Galerkin correction on a small coarse space: on every aggregate of
+//    neighbouring tets, F functions of the global direction d (1, the components
+//    of d, the quadratic harmonics of d), constant in space on each face of the
+//    aggregate.  Expanded in a slot's own basis such a density has the
+//    coefficients sqrt(area) G^-1 int psi_k Y_f cos(theta) dOmega (constant
+//    position function only).  With P that prolongation,
+//      A_c = P^T (I - B) P   (one dense block per independent instance),
+//    and before each sweep c = A_c^-1 P^T r, the solution grows by P c and
+//    r' = r - P c + (B P) c is swept instead of r.  B P is local: the rows of a
+//    slot depend only on the aggregate of the tet upstream of it, W[slot][k][f].
+//    The sweep of r' therefore needs, besides B r, terms of the form
+//    (matrix) x (coarse coefficients of one aggregate); they are NAUG groups of
+//    extra columns of the FP16 copy of B (see k_to_b16_aug), contracted on the
+//    matrix cores with the coefficients.
 //
 // Precision.  Each refinement stage solves the correction system to about 1e-2,
-// so t and B are FP16 (products on the FP16 matrix cores with FP32
-// accumulation); e accumulates in FP32; the solution and the refinement residual
-// r = rho0 - (I - B) rho stay in FP64 (the stored operator, FP64 or FP32).  The
-// residual is scaled to unit max norm per (right-hand side, instance) before it
-// is rounded to FP16.
+// so r and B are FP16 (products on the FP16 matrix cores with FP32
+// accumulation); the solution of a stage accumulates in FP32; the solution and
+// the refinement residual rho0 - (I - B) rho stay in FP64 (the stored operator,
+// FP64 or FP32).  The residual is scaled to unit max norm per (right-hand side,
+// instance) before it is rounded to FP16.
 //
 // Layouts.  FP16 and FP32 vectors are slot-major, [slot][rhs][Kp8] (Kp8 = K
 // rounded up to a multiple of 8, padding zero), so the right-hand-side tile of a
 // slot is one contiguous run.  The FP16 copy of B holds, per block row, NCH
-// chunks of 32 columns ([3 Kp8 slot columns | 4F correction columns | zero
-// padding]), each chunk a contiguous [K][32] tile.
+// chunks of 32 columns (three slots of Kp32 columns, then the correction
+// groups and zero padding), each chunk a contiguous [K][32] tile.
 #include <hip/hip_runtime.h>
 #include <hip/hip_fp16.h>
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <string>
@@ -60,6 +69,9 @@ typedef half_t h8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int FMAX = 9;        // coarse functions per aggregate
+// correction columns of the FP16 copy come in 4 groups of FPAD(F) columns (F used,
+// the rest zero), so that 8 consecutive ones never straddle two groups
+__host__ __device__ constexpr int fpad(int F) { return F <= 8 ? 8 : 16; }
 constexpr int NMONO = 10;      // monomials of degree <= 2 in the frame components
 constexpr int KC = 32;         // columns per chunk of the FP16 product
 constexpr int ROWG = 96;       // output rows per row group of the FP16 product
@@ -208,41 +220,66 @@ __global__ void k_coarse_W(const TB *__restrict__ B, const int32_t *__restrict__
 
 // FP16 copy of B with the correction columns, chunk-tiled: element (row k,
 // column cc) of block row br at ((br NCH + cc / KC) K + k) KC + cc % KC.
-//   cc < 3 Kp8:            B[br, s][column][row k], s = cc / Kp8 (zero past K)
-//   3 Kp8 + s F + f:       (B[br, s] W[inbound slot s])[k][f]
-//   3 Kp8 + 3 F + f:       -W[dest(br)][k][f]
-// One thread per (block row, row).
+//   cc < 3 Kp32:           B[br, s][column][row k], s = cc / Kp32 (zero past K;
+//                          Kp32 = K rounded up to 32, so every slot starts a chunk)
+// then NAUG groups of FP = fpad(F) columns (f < F used, the rest zero):
+//   group s < 3:  (B[br, s] W[inbound slot s])[k][f]  when that slot is read
+//                 before it is written in a product (type U), else 0
+//   group 3:      U-type destination: -(sum over U-type inbound s of B[br, s] Pv_s)[k][f]
+//                 L-type destination: +(sum over L-type inbound s of B[br, s] Pv_s)[k][f]
+//   group 4:      L-type destination: -Pv[dest][k][f], else 0
+// (lmask[slot] = 1 marks the L-type slots, written in an earlier colour phase of
+// the same product than the one that reads them).  One thread per (block row, row).
+constexpr int NAUG = 5;
 template <typename TB>
 __global__ void k_to_b16_aug(const TB *__restrict__ B, const int32_t *__restrict__ dest, const double *__restrict__ W64,
-                             int64_t nbr, int K, int Kp, int Kp8, int F, int NCH, half_t *__restrict__ B16) {
+                             const float *__restrict__ Pv, const uint8_t *__restrict__ lmask, int64_t nbr, int K,
+                             int Kp, int Kp8, int R0, int F, int NCH, half_t *__restrict__ B16) {
   const int64_t tot = nbr * K;
-  const int NC = 3 * Kp8;
+  const int Kp32 = (K + KC - 1) / KC * KC;
+  const int NC = 3 * Kp32;
+  const int FP = fpad(F);
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t br = i / K;
     const int k = (int)(i - br * K);
     const int64_t j = br >> 2;
     const int l_out = (int)(br & 3);
+    const int64_t d = dest[br];
+    const bool dl = lmask[d] != 0;
     auto put = [&](int cc, float v) {
       B16[((br * NCH + cc / KC) * (int64_t)K + k) * KC + (cc % KC)] = (half_t)v;
     };
     for (int cc = 0; cc < NC; ++cc) {
-      const int s = cc / Kp8, col = cc - s * Kp8;
-      put(cc, col < K ? (float)B[((br * 3 + s) * (int64_t)K + col) * Kp + k] : 0.0f);
+      const int sl = cc / Kp32, col = cc - sl * Kp32;
+      put(cc, col < K ? (float)B[((br * 3 + sl) * (int64_t)K + col) * Kp + k] : 0.0f);
     }
-    for (int s = 0; s < 3; ++s) {
-      const double *w = W64 + (4 * j + in_face2(l_out, s)) * (int64_t)Kp8 * F;
-      double acc[FMAX];
-      for (int f = 0; f < FMAX; ++f) acc[f] = 0.0;
-      const TB *row = B + ((br * 3 + s) * (int64_t)K) * Kp + k;
+    double g3[FMAX];
+    for (int f = 0; f < FMAX; ++f) g3[f] = 0.0;
+    for (int sl = 0; sl < 3; ++sl) {
+      const int64_t slot = 4 * j + in_face2(l_out, sl);
+      const bool sL = lmask[slot] != 0;
+      const double *w = W64 + slot * (int64_t)Kp8 * F;
+      const float *pv = Pv + slot * (int64_t)Kp8 * F;
+      double bw[FMAX], bp[FMAX];
+      for (int f = 0; f < FMAX; ++f) bw[f] = bp[f] = 0.0;
+      const TB *row = B + ((br * 3 + sl) * (int64_t)K) * Kp + k;
       for (int kk = 0; kk < K; ++kk) {
         const double bv = (double)row[(int64_t)kk * Kp];
-        for (int f = 0; f < F; ++f) acc[f] += bv * w[kk * F + f];
+        for (int f = 0; f < F; ++f) {
+          bw[f] += bv * w[kk * F + f];
+          if (kk < R0) bp[f] += bv * (double)pv[kk * F + f];
+        }
       }
-      for (int f = 0; f < F; ++f) put(NC + s * F + f, (float)acc[f]);
+      for (int f = 0; f < FP; ++f) put(NC + sl * FP + f, (f < F && !sL) ? (float)bw[f] : 0.0f);
+      // group 3 sums the U-type inbound slots for a U-type destination and the
+      // L-type ones for an L-type destination
+      if (sL == dl)
+        for (int f = 0; f < F; ++f) g3[f] += dl ? bp[f] : -bp[f];
     }
-    const double *wd = W64 + ((int64_t)dest[br] * Kp8 + k) * F;
-    for (int f = 0; f < F; ++f) put(NC + 3 * F + f, (float)(-wd[f]));
-    for (int cc = NC + 4 * F; cc < NCH * KC; ++cc) put(cc, 0.0f);
+    for (int f = 0; f < FP; ++f) put(NC + 3 * FP + f, f < F ? (float)g3[f] : 0.0f);
+    const float *pvd = Pv + (d * Kp8 + k) * F;
+    for (int f = 0; f < FP; ++f) put(NC + 4 * FP + f, (dl && f < F && k < R0) ? -pvd[f] : 0.0f);
+    for (int cc = NC + NAUG * FP; cc < NCH * KC; ++cc) put(cc, 0.0f);
   }
 }
 
@@ -296,31 +333,36 @@ __global__ void k_coarse_maps(const int32_t *__restrict__ agg_tet, const int32_t
 // ---------------------------------------------------------------------------
 // The FP16 product (see the file header):
 //   y[dest(br)][r][m] = sum_cc B16[br][m][cc] x[r][cc]
-// with x[r][cc] = t[slot(cc)][r][cc mod Kp8] for the slot columns and the
-// coarse coefficients for the correction columns (cu of the face's upstream
-// aggregate, cs of the tet's aggregate; the columns are skipped when c is null),
-// y rounded to FP16; for the first row group also
-// d0[dest][f][r] = sum_{k < R0} Pv[dest][k][f] y[r][k].
-// Workgroup = (block row, tile of 128 right-hand sides, row group of 96); 8
-// waves = 2 row halves (3 row tiles of 16) x 4 rhs quarters (2 tiles of 16),
-// v_mfma_f32_16x16x16_f16.  Chunks of 32 columns go through LDS (B [row][col],
-// x [rhs][col]), the next chunk loaded while the current one is contracted.
+// with x[r][cc] = t[inbound slot s][r][cc - s Kp32] for the slot columns and the
+// coarse coefficients for the correction columns (of the upstream aggregates of
+// the three inbound faces, the tet's aggregate and the destination's aggregate;
+// skipped when c is null), y rounded to FP16.  The tets of one colour are
+// multiplied per launch (tlist); a destination slot of L type (read by a later
+// colour of the same product) is written in place into t, with its old value
+// added on the first product of a stage, one of U type into y.  For the first
+// row group of a U-type destination also
+// d0[dest][f][r] = sum_{k < R0} Pv[dest][k][f] y[r][k] (0 for L type).
+//
+// Workgroup = (tet, 128 right-hand sides, row group of 96), one wave per block
+// row (l_out = wave).  Each lane loads its MFMA fragments straight from memory,
+// 16 bytes at a time: B rows m0 + 16 rt + lane % 16, columns 8 (lane / 16) .. + 7
+// of a 32-column chunk, and the same 8 columns of right-hand side
+// r0 + 16 ct + lane % 16; v_mfma_f32_16x16x32_f16 takes them as they are (the
+// same column order on both sides).  No LDS and no barrier.
+//
+// Schedule: four phases, one per local face p of the tet.  In phase p the three
+// waves with l_out != p contract the chunks of inbound slot p, all at the same
+// step, so each slot run of x is fetched from memory once and the other two
+// waves find it in cache; wave l_out = p contracts its correction chunks
+// meanwhile.  Steps past a wave's chunks (and whole phases without correction)
+// read 16 zero bytes.  No load is conditional and every loop trip issues the
+// same loads: a load under a condition makes the compiler wait for it at once,
+// which leaves one load in flight.  DEPTH chunks are in flight per wave.
+//
 // Rows of instances that are not multiplied (gact[gid[tet]] == 0) get y = 0 and
-// d0 = 0.  The four block rows of a tet go to one XCD (workgroups are dealt to
-// the eight XCDs in turn) so the slots they share are read from one L2.
+// d0 = 0.
 // ---------------------------------------------------------------------------
-constexpr int P16_THREADS = 512;
 constexpr int P16_RT = 128;
-#ifndef DFM_P16_NSUB
-#define DFM_P16_NSUB 3
-#endif
-constexpr int NSUB = DFM_P16_NSUB;         // chunks loaded per round (one barrier pair per round)
-constexpr int P16_LD = KC + 8;             // LDS row stride (halves) of both chunks
-constexpr int P16_YLD = ROWG + 8;          // LDS row stride (halves) of the result [rhs][row]
-constexpr size_t P16_LDS_CHUNK = sizeof(half_t) * (size_t)NSUB * (ROWG + P16_RT) * P16_LD;
-constexpr size_t P16_LDS_OUT = sizeof(half_t) * (size_t)P16_RT * P16_YLD;
-constexpr size_t P16_LDS = P16_LDS_CHUNK > P16_LDS_OUT ? P16_LDS_CHUNK : P16_LDS_OUT;
-static_assert(P16_RT * KC / 8 == P16_THREADS && ROWG * KC / 8 <= P16_THREADS, "one piece per thread");
 
 struct P16Args {
   const half_t *B16;
@@ -334,157 +376,171 @@ struct P16Args {
   const int32_t *agg_slot;  // [4 nt]
   const int32_t *agg_up;    // [4 nt]
   const float *c;           // [ng F][R] or null (no correction)
+  const half_t *c16;        // [ng][R][fpad(F)] the same in FP16, zero past F
+  const half_t *zero16;     // 8 zero halves
   const int32_t *gid;       // tet -> instance, or null
   const uint8_t *gact;      // instance -> multiplied, or null
+  const int32_t *tlist;     // tets of this launch's colour
+  const uint8_t *lmask;     // [4 nt] slot written in place (L type)
+  int first;                // first product of a stage: L-type slots add their old value
 };
 
-__global__ __launch_bounds__(P16_THREADS, 2) void k_spmm16(P16Args a) {
-  extern __shared__ __align__(16) unsigned char lds_raw[];
-  half_t *bs = reinterpret_cast<half_t *>(lds_raw);       // [NSUB][ROWG][P16_LD]
-  half_t *xs = bs + NSUB * ROWG * P16_LD;                 // [NSUB][P16_RT][P16_LD]
-  __shared__ float pvs[ROWG * FMAX];                      // Pv of the destination slot (first row group)
-  __shared__ int32_t gsh[4];                              // upstream aggregates of the 3 inbound faces; own
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  int64_t br = blockIdx.x;
-  if ((a.nt & 7) == 0) {
-    const int64_t slot = br >> 3, xcd = br & 7;
-    br = 4 * (8 * (slot >> 2) + xcd) + (slot & 3);
-  }
-  const int r0 = blockIdx.y * P16_RT;
+template <int DEPTH, int CT>
+__global__ __launch_bounds__(64 * 4 * (P16_RT / 16 / CT), 1) void k_spmm16(P16Args a) {
+  constexpr int RT = ROWG / 16;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int l_out = wv & 3;
+  const int rw0 = blockIdx.y * P16_RT + (wv >> 2) * CT * 16;   // first right-hand side of this wave
+  const int64_t j = a.tlist[blockIdx.x];
+  const int64_t br = 4 * j + l_out;
   const int m0 = blockIdx.z * ROWG;
-  const int64_t j = br >> 2;
-  const int l_out = (int)(br & 3);
-  const int K = a.K, Kp8 = a.Kp8, F = a.F;
-  const int NC = 3 * Kp8;
+  const int K = a.K, Kp8 = a.Kp8, F = a.F, R = a.R;
   const int64_t dslot = a.dest[br];
-  const int64_t ldr = (int64_t)a.R * Kp8;                 // one slot's run of all right-hand sides
-  const int nrows = min(ROWG, Kp8 - m0);                  // output rows of this group (multiple of 8)
+  const bool dl = a.lmask[dslot] != 0;
+  const int64_t ldr = (int64_t)R * Kp8;
+  const int nrows = min(ROWG, Kp8 - m0);
+  const int col = lane & 15, kq = lane >> 4;
+  half_t *ybase = (dl ? const_cast<half_t *>(a.t) : a.y) + dslot * ldr + m0;
   if (a.gact != nullptr && a.gact[a.gid[j]] == 0) {
-    const int npr = nrows / 8;
-    for (int i = tid; i < P16_RT * npr; i += P16_THREADS) {
-      const int r = i / npr, m = 8 * (i - r * npr);
-      if (r0 + r < a.R)
-        *reinterpret_cast<h8 *>(a.y + dslot * ldr + (int64_t)(r0 + r) * Kp8 + m0 + m) = h8{0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      const int r = rw0 + ct * 16 + col;
+      if (r >= R) continue;
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+        if (rt * 16 + 4 * kq < nrows)
+          *reinterpret_cast<h4 *>(ybase + (int64_t)r * Kp8 + rt * 16 + 4 * kq) = h4{0, 0, 0, 0};
     }
     if (m0 == 0 && a.d0)
-      for (int i = tid; i < F * P16_RT; i += P16_THREADS) {
-        const int f = i / P16_RT, r = i - f * P16_RT;
-        if (r0 + r < a.R) a.d0[(dslot * F + f) * a.R + r0 + r] = 0.0f;
+      for (int i = lane; i < F * CT * 16; i += 64) {
+        const int f = i / (CT * 16), r = i - f * (CT * 16);
+        if (rw0 + r < R) a.d0[(dslot * F + f) * R + rw0 + r] = 0.0f;
       }
     return;
   }
   const bool corr = a.c != nullptr;
-  if (tid < 3) gsh[tid] = a.agg_up[4 * j + in_face2(l_out, tid)];
-  if (tid == 3) gsh[3] = a.agg_slot[4 * j];
-  if (m0 == 0 && a.d0)
-    for (int i = tid; i < a.R0 * F; i += P16_THREADS) pvs[i] = a.Pv[dslot * Kp8 * F + i];
-  __syncthreads();
-
-  // this thread's pieces: B row m0 + prow, x right-hand side r0 + prow; columns
-  // 8 (tid % 4) .. + 7 of the chunk
-  const int prow = tid >> 2, pcol = 8 * (tid & 3);
-  const half_t *Bbr = a.B16 + br * (int64_t)a.NCH * K * KC;
-  const int brows = min(ROWG, K - m0);                    // stored rows of this group
-  h8 pbv[NSUB], pxv[NSUB];
-  auto load_chunk = [&](int ch, h8 &pb, h8 &px) {
-    pb = (tid < ROWG * KC / 8 && prow < brows)
-             ? *reinterpret_cast<const h8 *>(Bbr + ((int64_t)ch * K + m0 + prow) * KC + pcol)
-             : h8{0, 0, 0, 0, 0, 0, 0, 0};
-    const int c = ch * KC + pcol;
-    const int r = r0 + prow;
-    px = h8{0, 0, 0, 0, 0, 0, 0, 0};
-    if (r < a.R) {
-      if (c < NC) {
-        const int s = c / Kp8, k = c - s * Kp8;
-        px = *reinterpret_cast<const h8 *>(a.t + (4 * j + in_face2(l_out, s)) * ldr + (int64_t)r * Kp8 + k);
-      } else if (corr) {
+  const int FP = fpad(F);
+  int gagg[NAUG];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int e = c - NC + u;
-          float v = 0.0f;
-          if (e < 3 * F) v = a.c[((int64_t)gsh[e / F] * F + e % F) * a.R + r];
-          else if (e < 4 * F) v = a.c[((int64_t)gsh[3] * F + (e - 3 * F)) * a.R + r];
-          px[u] = (half_t)v;
+  for (int s = 0; s < 3; ++s) gagg[s] = corr ? a.agg_up[4 * j + in_face2(l_out, s)] : 0;
+  gagg[3] = corr ? a.agg_slot[4 * j] : 0;
+  gagg[4] = corr ? a.agg_slot[dslot] : 0;
+  const int brows = min(ROWG, K - m0);
+  const int nsub = (K + KC - 1) / KC;                     // chunks per slot
+  const int naug = (NAUG * FP + KC - 1) / KC;             // correction chunks
+  const int L = max(nsub, naug);                          // steps per phase
+  const int nsteps = (4 * L + DEPTH - 1) / DEPTH * DEPTH;
+  const half_t *zero = a.zero16;
+  const half_t *Bbr = a.B16 + br * (int64_t)a.NCH * K * KC;
+  const half_t *abase = Bbr + (int64_t)(m0 + col) * KC + 8 * kq;
+  const half_t *tj = a.t + 4 * j * ldr;
+  int rofs[CT];
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct) rofs[ct] = min(rw0 + ct * 16 + col, R - 1);   // past R: never stored
+
+  h8 A[DEPTH][RT], X[DEPTH][CT];
+  auto load = [&](int it, h8 (&Ab)[RT], h8 (&Xb)[CT]) {
+    // wave-uniform: phase, step in it, chunk of B16 (-1: none)
+    const int p = it / L, c = it - p * L;
+    const bool aug = p == l_out;
+    int bch = -1;
+    if (it < 4 * L) {
+      if (!aug && c < nsub) bch = (p < l_out ? p : p - 1) * nsub + c;
+      if (aug && corr && c < naug) bch = 3 * nsub + c;
+    }
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      const bool ok = bch >= 0 && rt * 16 + col < brows;
+      Ab[rt] = *reinterpret_cast<const h8 *>(ok ? abase + (int64_t)bch * K * KC + rt * 16 * KC : zero);
+    }
+    // per lane: 8 columns starting at 32 c + 8 kq of slot p, or of the correction
+    const int e = c * KC + 8 * kq;
+    const int g = min(e / FP, NAUG - 1);
+    const int ga = g == 0 ? gagg[0] : (g == 1 ? gagg[1] : (g == 2 ? gagg[2] : (g == 3 ? gagg[3] : gagg[4])));
+    const bool xs = bch >= 0 && !aug && e < Kp8;
+    const bool xc = bch >= 0 && aug && e < NAUG * FP;
+    const half_t *xp = xs ? tj + p * ldr + e : (xc ? a.c16 + (int64_t)ga * R * FP + (e - g * FP) : zero);
+    const int xstride = xs ? Kp8 : (xc ? FP : 0);
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) Xb[ct] = *reinterpret_cast<const h8 *>(xp + (int64_t)rofs[ct] * xstride);
+  };
+  f4 acc[RT][CT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+  auto contract = [&](const h8 (&Ab)[RT], const h8 (&Xb)[CT]) {
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct)
+        acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_f16(Ab[rt], Xb[ct], acc[rt][ct], 0, 0, 0);
+  };
+#pragma unroll
+  for (int u = 0; u < DEPTH; ++u) load(u, A[u], X[u]);
+  for (int it0 = 0; it0 < nsteps; it0 += DEPTH) {
+#pragma unroll
+    for (int u = 0; u < DEPTH; ++u) {
+      contract(A[u], X[u]);
+      load(it0 + u + DEPTH, A[u], X[u]);
+    }
+  }
+  // store y (rows 16 rt + 4 kq + q, right-hand side rw0 + 16 ct + col), one rhs
+  // tile at a time; for the first row group also d0 = Pv^T y with the A operand
+  // Pv^T: row f = lane % 16 (< F), columns k = 16 rt + 4 (lane / 16) .. + 3 (< R0);
+  // the accumulator layout of y is the B-operand layout of v_mfma_f32_16x16x16_f16
+  const bool want_d0 = m0 == 0 && a.d0 != nullptr && !dl;
+  h4 pa[RT];
+  if (want_d0) {
+    const float *pv = a.Pv + dslot * Kp8 * F;
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = rt * 16 + 4 * kq + q;
+        pa[rt][q] = (col < F && k < a.R0) ? (half_t)pv[k * F + col] : (half_t)0.0f;
+      }
+  }
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct) {
+    const int r = rw0 + ct * 16 + col;
+    if (dl && a.first && r < R) {
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+        if (rt * 16 + 4 * kq < nrows) {
+          const h4 o = *reinterpret_cast<const h4 *>(ybase + (int64_t)r * Kp8 + rt * 16 + 4 * kq);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[rt][ct][q] += (float)o[q];
+        }
+    }
+    h4 yh[RT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+      yh[rt] = h4{(half_t)acc[rt][ct][0], (half_t)acc[rt][ct][1], (half_t)acc[rt][ct][2], (half_t)acc[rt][ct][3]};
+    if (r < R) {
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+        if (rt * 16 + 4 * kq < nrows) *reinterpret_cast<h4 *>(ybase + (int64_t)r * Kp8 + rt * 16 + 4 * kq) = yh[rt];
+    }
+    if (m0 == 0 && a.d0 != nullptr && dl && r < R) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (4 * kq + q < F) a.d0[(dslot * F + 4 * kq + q) * R + r] = 0.0f;
+    }
+    if (want_d0) {
+      f4 dacc = f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) dacc = __builtin_amdgcn_mfma_f32_16x16x16f16(pa[rt], yh[rt], dacc, 0, 0, 0);
+      if (r < R) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int f = 4 * kq + q;
+          if (f < F) a.d0[(dslot * F + f) * R + r] = dacc[q];
         }
       }
     }
-  };
-  auto store_chunk = [&](int u) {
-    if (tid < ROWG * KC / 8) *reinterpret_cast<h8 *>(bs + (u * ROWG + prow) * P16_LD + pcol) = pbv[u];
-    *reinterpret_cast<h8 *>(xs + (u * P16_RT + prow) * P16_LD + pcol) = pxv[u];
-  };
-
-  const int wr = wave >> 2, wc = wave & 3;
-  const int col = lane & 15, kq = lane >> 4;
-  f4 acc[3][2];
-#pragma unroll
-  for (int u = 0; u < 3; ++u)
-#pragma unroll
-    for (int v = 0; v < 2; ++v) acc[u][v] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-  auto contract = [&](int sub) {
-    const half_t *bsu = bs + sub * ROWG * P16_LD, *xsu = xs + sub * P16_RT * P16_LD;
-#pragma unroll
-    for (int ks = 0; ks < KC / 16; ++ks) {
-      const int kk = ks * 16 + 4 * kq;
-      h4 av[3], bv[2];
-#pragma unroll
-      for (int u = 0; u < 3; ++u) av[u] = *reinterpret_cast<const h4 *>(bsu + ((wr * 3 + u) * 16 + col) * P16_LD + kk);
-#pragma unroll
-      for (int v = 0; v < 2; ++v) bv[v] = *reinterpret_cast<const h4 *>(xsu + ((wc * 2 + v) * 16 + col) * P16_LD + kk);
-#pragma unroll
-      for (int u = 0; u < 3; ++u)
-#pragma unroll
-        for (int v = 0; v < 2; ++v) acc[u][v] = __builtin_amdgcn_mfma_f32_16x16x16f16(av[u], bv[v], acc[u][v], 0, 0, 0);
-    }
-  };
-  // the correction columns sit in the last chunks; without correction they are skipped
-  const int nch = corr ? a.NCH : (NC + KC - 1) / KC;
-  const int nround = (nch + NSUB - 1) / NSUB;
-  auto load_round = [&](int rd) {
-#pragma unroll
-    for (int u = 0; u < NSUB; ++u) {
-      const int ch = rd * NSUB + u;
-      if (ch < nch) load_chunk(ch, pbv[u], pxv[u]);
-    }
-  };
-  load_round(0);
-  for (int rd = 0; rd < nround; ++rd) {
-    const int nsub = min(NSUB, nch - rd * NSUB);
-#pragma unroll
-    for (int u = 0; u < NSUB; ++u)
-      if (u < nsub) store_chunk(u);
-    __syncthreads();
-    if (rd + 1 < nround) load_round(rd + 1);   // in flight during this round's contraction
-#pragma unroll
-    for (int u = 0; u < NSUB; ++u)
-      if (u < nsub) contract(u);
-    __syncthreads();
   }
-  half_t *ys = reinterpret_cast<half_t *>(lds_raw);         // [P16_RT][P16_YLD]
-#pragma unroll
-  for (int u = 0; u < 3; ++u)
-#pragma unroll
-    for (int v = 0; v < 2; ++v)
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        ys[((wc * 2 + v) * 16 + col) * P16_YLD + (wr * 3 + u) * 16 + 4 * kq + q] = (half_t)acc[u][v][q];
-  __syncthreads();
-  const int npr = nrows / 8;
-  for (int i = tid; i < P16_RT * npr; i += P16_THREADS) {
-    const int r = i / npr, m = 8 * (i - r * npr);
-    if (r0 + r >= a.R) continue;
-    *reinterpret_cast<h8 *>(a.y + dslot * ldr + (int64_t)(r0 + r) * Kp8 + m0 + m) =
-        *reinterpret_cast<const h8 *>(ys + r * P16_YLD + m);
-  }
-  if (m0 == 0 && a.d0)
-    for (int i = tid; i < F * P16_RT; i += P16_THREADS) {
-      const int f = i / P16_RT, r = i - f * P16_RT;
-      if (r0 + r >= a.R) continue;
-      float s = 0.0f;
-      for (int k = 0; k < a.R0; ++k) s = fmaf(pvs[k * F + f], (float)ys[r * P16_YLD + k], s);
-      a.d0[(dslot * F + f) * a.R + r0 + r] = s;
-    }
 }
 
 // d0[s][f][r] = sum_{k < R0} Pv[s][k][f] t[s][r][k] (the coarse right-hand side of
@@ -540,7 +596,8 @@ __global__ void k_coarse_reduce(const float *__restrict__ d0, const int32_t *__r
 __global__ void k_coarse_solve(const float *__restrict__ Ai, const int64_t *__restrict__ row_off,
                                const float *__restrict__ Ai1, const int64_t *__restrict__ row_off1, int one_function,
                                const int32_t *__restrict__ blk_lo, const int32_t *__restrict__ blk_n, int ng, int F,
-                               int R, const float *__restrict__ z, float *__restrict__ c, float *__restrict__ csum) {
+                               int R, const float *__restrict__ z, float *__restrict__ c, float *__restrict__ csum,
+                               half_t *__restrict__ c16) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t NG = (int64_t)ng * F;
   if (i >= NG * R) return;
@@ -562,6 +619,7 @@ __global__ void k_coarse_solve(const float *__restrict__ Ai, const int64_t *__re
   }
   c[i] = acc;
   csum[i] += acc;
+  c16[((int64_t)g * R + r) * fpad(F) + f] = (half_t)acc;
 }
 
 __global__ void k_zero_f32n(float *__restrict__ p, int64_t n) {
@@ -602,14 +660,18 @@ __global__ void k_stage_init(const double *__restrict__ res, int64_t nslot, int 
   }
 }
 
-// e += sum of the nwin values of t in the ring (+ (B P) csum when W is given: once
-// per refinement stage, with the coarse coefficients summed over the stage)
-constexpr int WIN = 8;
+// e += sum of the nwin values of t in the ring (+ the coarse part when W is given:
+// once per refinement stage, with the coarse coefficients summed over the stage,
+// (B P) csum of the upstream aggregate on U-type slots and P csum of the slot's
+// own aggregate on L-type slots, whose ring values already hold the corrected term)
+constexpr int WIN = 16;
 struct RingPtrs {
   const half_t *p[WIN];
 };
 __global__ void k_flush(RingPtrs ring, int nwin, int64_t nslot, int Kp8, int R, int F, const float *__restrict__ W,
-                        const int32_t *__restrict__ agg_up, const float *__restrict__ csum, float *__restrict__ e) {
+                        const float *__restrict__ Pv, const uint8_t *__restrict__ lmask,
+                        const int32_t *__restrict__ agg_slot, const int32_t *__restrict__ agg_up,
+                        const float *__restrict__ csum, float *__restrict__ e) {
   const int64_t n8 = nslot * R * Kp8 / 8;
   for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n8; q += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = 8 * q;
@@ -624,8 +686,9 @@ __global__ void k_flush(RingPtrs ring, int nwin, int64_t nslot, int Kp8, int R, 
       v[u + 4] = hi[u];
     }
     if (W) {
-      const float *w = W + (s * Kp8 + k0) * F;
-      const float *cs = csum + (int64_t)agg_up[s] * F * R + r;
+      const bool L = lmask[s] != 0;
+      const float *w = (L ? Pv : W) + (s * Kp8 + k0) * F;
+      const float *cs = csum + (int64_t)(L ? agg_slot[s] : agg_up[s]) * F * R + r;
       for (int f = 0; f < F; ++f) {
         const float cf = cs[(int64_t)f * R];
 #pragma unroll
@@ -704,7 +767,7 @@ __global__ void k_seg_norms2_d(const double *__restrict__ v, int64_t n, const in
 // atomic per rhs (R <= 4096); grid (x, instance)
 constexpr int NRM_RMAX = 4096;
 __global__ void k_seg_norms2_h(const half_t *__restrict__ t, int R, int Kp8, const int64_t *__restrict__ soff, int G,
-                               double *__restrict__ out) {
+                               const uint8_t *__restrict__ skip, double *__restrict__ out) {
   __shared__ double acc_r[NRM_RMAX];
   const int g = blockIdx.y;
   for (int r = threadIdx.x; r < R; r += blockDim.x) acc_r[r] = 0.0;
@@ -712,6 +775,7 @@ __global__ void k_seg_norms2_h(const half_t *__restrict__ t, int R, int Kp8, con
   const int ppr = Kp8 / 8;                               // 8-half pieces per (slot, rhs)
   const int64_t q0 = soff[g] * R * ppr, q1 = soff[g + 1] * R * ppr;
   for (int64_t q = q0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < q1; q += (int64_t)gridDim.x * blockDim.x) {
+    if (skip && skip[q / ((int64_t)R * ppr)]) continue;
     const h8 x = *reinterpret_cast<const h8 *>(t + 8 * q);
     double s2 = 0.0;
 #pragma unroll
@@ -865,7 +929,15 @@ struct Coarse {
   int32_t *agg_slot = nullptr, *agg_up = nullptr, *perm = nullptr, *blk_lo = nullptr, *blk_n = nullptr;
   int64_t *row_off = nullptr, *row_off1 = nullptr;
   float *Pv = nullptr, *W = nullptr, *Ai = nullptr, *Ai1 = nullptr;
+  // colouring of the tets (no two tets that share a face alike): the product
+  // runs colour by colour, tlist[col_off[q] ..] the tets of colour q
+  int ncol = 0;
+  std::vector<int64_t> col_off;
+  int32_t *tlist = nullptr;
+  uint8_t *lmask = nullptr;      // [4 nt] slot whose writer has a lower colour than its tet
   void release() {
+    (void)hipFree(tlist);
+    (void)hipFree(lmask);
     (void)hipFree(row_off1);
     (void)hipFree(Ai1);
     (void)hipFree(agg_slot);
@@ -951,11 +1023,11 @@ dfm_status ensure_coarse(dfm_op op, const std::vector<int64_t> &toff, hipStream_
   const int Kp8 = op->Kp8;
   const int G = (int)toff.size() - 1;
   // coarse functions per aggregate (1, 4, 6 or 9) and tets per aggregate
-  int F = env_int("DFM_COARSE_F", 9);
-  if (F != 1 && F != 4 && F != 6 && F != 9) F = 9;
+  int F = env_int("DFM_COARSE_F", 4);
+  if (F != 1 && F != 4 && F != 6 && F != 9) F = 4;
   const double tets_per_agg = (double)std::max(1, env_int("DFM_COARSE_TETS", 1536));
   const int R0 = std::min(M, ROWG);
-  const int NCH = (3 * Kp8 + 4 * F + KC - 1) / KC;
+  const int NCH = 3 * ((K + KC - 1) / KC) + (NAUG * fpad(F) + KC - 1) / KC;
   double *cent_d = nullptr, *Mm = nullptr, *W64 = nullptr, *Ac = nullptr;
   int32_t *agg_tet_d = nullptr;
   auto cleanup = [&]() {
@@ -1032,7 +1104,63 @@ dfm_status ensure_coarse(dfm_op op, const std::vector<int64_t> &toff, hipStream_
     }
     ai_size += (int64_t)n * F * n * F;
   }
-  // 2. maps, the coarse basis Pv, W = B P, and the FP16 copy with its columns
+  // 2. colouring: greedy over a breadth-first order of the face graph (two
+  //    colours on the Kuhn boxes, whose face graph is bipartite); the slots
+  //    written by a tet of a lower colour than their own are of L type
+  {
+    std::vector<int32_t> dh(nslot);
+    TRYC(hipMemcpyAsync(dh.data(), op->dest, sizeof(int32_t) * nslot, hipMemcpyDeviceToHost, st));
+    TRYC(hipStreamSynchronize(st));
+    std::vector<int32_t> writer(nslot, -1);
+    for (int64_t b = 0; b < nslot; ++b) writer[dh[b]] = (int32_t)(b >> 2);
+    std::vector<int32_t> nb(nslot, -1);        // the neighbour across each face, -1 on the boundary
+    for (int64_t sl = 0; sl < nslot; ++sl) {
+      const int32_t w = writer[sl];
+      if (w >= 0 && w != (int32_t)(sl >> 2)) nb[sl] = w;
+    }
+    std::vector<int8_t> color(nt, -1);
+    std::vector<int32_t> queue;
+    queue.reserve(nt);
+    for (int64_t t0 = 0; t0 < nt; ++t0) {
+      if (color[t0] >= 0) continue;
+      color[t0] = 0;
+      queue.clear();
+      queue.push_back((int32_t)t0);
+      for (size_t h = 0; h < queue.size(); ++h) {
+        const int32_t u = queue[h];
+        for (int l = 0; l < 4; ++l) {
+          const int32_t v = nb[4 * (int64_t)u + l];
+          if (v < 0 || color[v] >= 0) continue;
+          unsigned used = 0;
+          for (int l2 = 0; l2 < 4; ++l2) {
+            const int32_t x = nb[4 * (int64_t)v + l2];
+            if (x >= 0 && color[x] >= 0) used |= 1u << color[x];
+          }
+          int cq = 0;
+          while (used & (1u << cq)) ++cq;
+          color[v] = (int8_t)cq;
+          queue.push_back(v);
+        }
+      }
+    }
+    int ncol = 1;
+    for (int64_t t = 0; t < nt; ++t) ncol = std::max(ncol, (int)color[t] + 1);
+    C.ncol = ncol;
+    C.col_off.assign(ncol + 1, 0);
+    for (int64_t t = 0; t < nt; ++t) C.col_off[color[t] + 1]++;
+    for (int q = 0; q < ncol; ++q) C.col_off[q + 1] += C.col_off[q];
+    std::vector<int64_t> pos(C.col_off.begin(), C.col_off.end() - 1);
+    std::vector<int32_t> tl(nt);
+    for (int64_t t = 0; t < nt; ++t) tl[pos[color[t]]++] = (int32_t)t;
+    std::vector<uint8_t> lm(nslot, 0);
+    for (int64_t sl = 0; sl < nslot; ++sl) lm[sl] = (nb[sl] >= 0 && color[nb[sl]] < color[sl >> 2]) ? 1 : 0;
+    TRYC(hipMalloc(&C.tlist, sizeof(int32_t) * nt));
+    TRYC(hipMalloc(&C.lmask, sizeof(uint8_t) * nslot));
+    TRYC(hipMemcpyAsync(C.tlist, tl.data(), sizeof(int32_t) * nt, hipMemcpyHostToDevice, st));
+    TRYC(hipMemcpyAsync(C.lmask, lm.data(), sizeof(uint8_t) * nslot, hipMemcpyHostToDevice, st));
+    TRYC(hipStreamSynchronize(st));   // the host vectors must outlive their copies
+  }
+  // 3. maps, the coarse basis Pv, W = B P, and the FP16 copy with its columns
   TRYC(hipMalloc(&agg_tet_d, sizeof(int32_t) * nt));
   TRYC(hipMalloc(&C.agg_slot, sizeof(int32_t) * nslot));
   TRYC(hipMalloc(&C.agg_up, sizeof(int32_t) * nslot));
@@ -1057,16 +1185,16 @@ dfm_status ensure_coarse(dfm_op op, const std::vector<int64_t> &toff, hipStream_
   if (op->B) {
     hipLaunchKernelGGL(k_coarse_W<double>, dim3(ew_grid(nbr * Kp8)), dim3(256), 0, st, op->B, op->dest, C.Pv, nbr, K,
                        op->Kp, Kp8, R0, F, W64, C.W);
-    hipLaunchKernelGGL(k_to_b16_aug<double>, dim3(ew_grid(nbr * K)), dim3(256), 0, st, op->B, op->dest, W64, nbr, K,
-                       op->Kp, Kp8, F, NCH, reinterpret_cast<half_t *>(op->B16));
+    hipLaunchKernelGGL(k_to_b16_aug<double>, dim3(ew_grid(nbr * K)), dim3(256), 0, st, op->B, op->dest, W64, C.Pv,
+                       C.lmask, nbr, K, op->Kp, Kp8, R0, F, NCH, reinterpret_cast<half_t *>(op->B16));
   } else {
     hipLaunchKernelGGL(k_coarse_W<float>, dim3(ew_grid(nbr * Kp8)), dim3(256), 0, st, op->B32, op->dest, C.Pv, nbr, K,
                        op->Kp, Kp8, R0, F, W64, C.W);
-    hipLaunchKernelGGL(k_to_b16_aug<float>, dim3(ew_grid(nbr * K)), dim3(256), 0, st, op->B32, op->dest, W64, nbr, K,
-                       op->Kp, Kp8, F, NCH, reinterpret_cast<half_t *>(op->B16));
+    hipLaunchKernelGGL(k_to_b16_aug<float>, dim3(ew_grid(nbr * K)), dim3(256), 0, st, op->B32, op->dest, W64, C.Pv,
+                       C.lmask, nbr, K, op->Kp, Kp8, R0, F, NCH, reinterpret_cast<half_t *>(op->B16));
   }
   TRYC(hipGetLastError());
-  // 3. A_c block per instance on the device, inverted on the host
+  // 4. A_c block per instance on the device, inverted on the host
   hipLaunchKernelGGL(k_zero_f64n, dim3(ew_grid(std::max<int64_t>(ai_size, 1))), dim3(256), 0, st, Ac,
                      std::max<int64_t>(ai_size, 1));
   hipLaunchKernelGGL(k_coarse_Ac, dim3(ew_grid(nslot * F * F)), dim3(256), 0, st, C.Pv, W64, C.agg_slot, C.agg_up,
@@ -1128,8 +1256,9 @@ dfm_status ensure_coarse(dfm_op op, const std::vector<int64_t> &toff, hipStream_
 }
 
 namespace {
-hipError_t launch_product16(dfm_op op, const half_t *t, half_t *y, float *d0, int R, const float *c,
-                            const int32_t *gid, const uint8_t *gact, hipStream_t st) {
+hipError_t launch_product16(dfm_op op, half_t *t, half_t *y, float *d0, int R, const float *c,
+                            const half_t *c16, const half_t *zero16, const int32_t *gid, const uint8_t *gact,
+                            bool first, hipStream_t st) {
   const Coarse &C = *op->coarse;
   P16Args a{};
   a.B16 = reinterpret_cast<const half_t *>(op->B16);
@@ -1148,13 +1277,24 @@ hipError_t launch_product16(dfm_op op, const half_t *t, half_t *y, float *d0, in
   a.agg_slot = C.agg_slot;
   a.agg_up = C.agg_up;
   a.c = c;
+  a.c16 = c16;
+  a.zero16 = zero16;
   a.gid = gid;
   a.gact = gact;
-  dim3 grid((unsigned)(4 * op->nt), (unsigned)((R + P16_RT - 1) / P16_RT), (unsigned)((op->Kp8 + ROWG - 1) / ROWG));
-  hipError_t e = hipFuncSetAttribute((const void *)k_spmm16, hipFuncAttributeMaxDynamicSharedMemorySize, (int)P16_LDS);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_spmm16, grid, dim3(P16_THREADS), P16_LDS, st, a);
-  return hipGetLastError();
+  a.lmask = C.lmask;
+  a.first = first ? 1 : 0;
+  // one launch per colour, in colour order; one workgroup per (tet, 128
+  // right-hand sides, row group of 96)
+  for (int q = 0; q < C.ncol; ++q) {
+    const int64_t cnt = C.col_off[q + 1] - C.col_off[q];
+    if (cnt == 0) continue;
+    a.tlist = C.tlist + C.col_off[q];
+    const dim3 grid((unsigned)cnt, (unsigned)((R + P16_RT - 1) / P16_RT), (unsigned)((op->Kp8 + ROWG - 1) / ROWG));
+    hipLaunchKernelGGL((k_spmm16<2, 8>), grid, dim3(256), 0, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 }  // namespace
 
@@ -1180,7 +1320,7 @@ dfm_status solve_twolevel_impl(dfm_op op, const double *rho0, double *rho, int R
     set_error("the two-level solver takes at most 4096 right-hand sides per call");
     return DFM_E_UNSUPPORTED;
   }
-  half_t *ring_buf = nullptr;
+  half_t *ring_buf = nullptr, *c16 = nullptr;
   float *e = nullptr, *d0 = nullptr, *z = nullptr, *c = nullptr, *csum = nullptr;
   double *res = nullptr, *sc_d = nullptr, *nrm_d = nullptr;
   unsigned long long *mx_d = nullptr;
@@ -1189,6 +1329,7 @@ dfm_status solve_twolevel_impl(dfm_op op, const double *rho0, double *rho, int R
   int32_t *gid = nullptr;
   auto cleanup = [&]() {
     (void)hipFree(ring_buf);
+    (void)hipFree(c16);
     (void)hipFree(e);
     (void)hipFree(d0);
     (void)hipFree(z);
@@ -1231,6 +1372,10 @@ dfm_status solve_twolevel_impl(dfm_op op, const double *rho0, double *rho, int R
   TRYT(hipMalloc(&z, sizeof(float) * (size_t)zn));
   TRYT(hipMalloc(&c, sizeof(float) * (size_t)zn));
   TRYT(hipMalloc(&csum, sizeof(float) * (size_t)zn));
+  // c16, then 8 zero halves that the product reads in place of absent columns
+  const size_t c16n = (size_t)C.ng * R * fpad(F);
+  TRYT(hipMalloc(&c16, sizeof(half_t) * (c16n + 8)));
+  TRYT(hipMemsetAsync(c16, 0, sizeof(half_t) * (c16n + 8), st));   // padding stays zero
   TRYT(hipMalloc(&res, sizeof(double) * (size_t)R * n));
   TRYT(hipMalloc(&sc_d, sizeof(double) * RG));
   TRYT(hipMalloc(&nrm_d, sizeof(double) * RG));
@@ -1270,9 +1415,12 @@ dfm_status solve_twolevel_impl(dfm_op op, const double *rho0, double *rho, int R
     hipError_t er = hipGetLastError();
     return er != hipSuccess ? er : fetch(nrm_d);
   };
-  auto norms_t = [&](const half_t *t) -> hipError_t {
+  // |t|: at a stage start all of t_0; later the residual r_k = t_k has no L-type
+  // part (those slots of the ring entry are written in place during product k)
+  auto norms_t = [&](const half_t *t, bool skip_l) -> hipError_t {
     hipLaunchKernelGGL(k_zero_f64n, dim3(ew_grid((int64_t)RG)), dim3(256), 0, st, nrm_d, (int64_t)RG);
-    hipLaunchKernelGGL(k_seg_norms2_h, hgrid, dim3(256), 0, st, t, R, Kp8, soff_d, G, nrm_d);
+    hipLaunchKernelGGL(k_seg_norms2_h, hgrid, dim3(256), 0, st, t, R, Kp8, soff_d, G, skip_l ? C.lmask : nullptr,
+                       nrm_d);
     hipError_t er = hipGetLastError();
     return er != hipSuccess ? er : fetch(nrm_d);
   };
@@ -1335,6 +1483,7 @@ dfm_status solve_twolevel_impl(dfm_op op, const double *rho0, double *rho, int R
   // non-symmetric operator can amplify) restarts one level lower.
   constexpr double DIVERGE = 4.0;
   int level = F > 1 ? 2 : 1;
+  const bool verbose = env_int("DFM_VERBOSE", 0) != 0;   // one line per refinement stage on stderr
   for (int outer = 0; outer < 40 && iters < opts->max_iter && !all_done(); ++outer) {
   restart_stage:
     // scale every active pair to unit max norm; t_0 = half(scale * r)
@@ -1362,7 +1511,7 @@ dfm_status solve_twolevel_impl(dfm_op op, const double *rho0, double *rho, int R
                        d0);
     hipLaunchKernelGGL(k_zero_f32n, dim3(ew_grid(zn)), dim3(256), 0, st, csum, zn);
     TRYT(hipGetLastError());
-    TRYT(norms_t(ring(0)));
+    TRYT(norms_t(ring(0), false));
     for (size_t i = 0; i < RG; ++i) t0n[i] = std::sqrt(h[i]);
     TRYT(update_active());
     int k = 0, pending = 0;   // t_k in ring(k); t_{k-pending} .. t_{k-1} not yet added to e
@@ -1373,7 +1522,7 @@ dfm_status solve_twolevel_impl(dfm_op op, const double *rho0, double *rho, int R
       RingPtrs rp{};
       for (int m = 0; m < pending; ++m) rp.p[m] = ring(k - pending + m);
       hipLaunchKernelGGL(k_flush, dim3(egrid), dim3(256), 0, st, rp, pending, nslot, Kp8, R, F,
-                         (last && level > 0) ? C.W : nullptr, C.agg_up, csum, e);
+                         (last && level > 0) ? C.W : nullptr, C.Pv, C.lmask, C.agg_slot, C.agg_up, csum, e);
       pending = 0;
       return hipGetLastError();
     };
@@ -1385,19 +1534,22 @@ dfm_status solve_twolevel_impl(dfm_op op, const double *rho0, double *rho, int R
         hipLaunchKernelGGL(k_coarse_reduce, dim3(red_grid, gz), dim3(red_threads), 0, st, d0, C.perm, C.agg_slot,
                            nslot, FR, z);
         hipLaunchKernelGGL(k_coarse_solve, dim3((unsigned)((zn + 255) / 256)), dim3(256), 0, st, C.Ai, C.row_off,
-                           C.Ai1, C.row_off1, level == 1 ? 1 : 0, C.blk_lo, C.blk_n, C.ng, F, R, z, c, csum);
+                           C.Ai1, C.row_off1, level == 1 ? 1 : 0, C.blk_lo, C.blk_n, C.ng, F, R, z, c, csum, c16);
         TRYT(hipGetLastError());
       }
-      // t_{k+1} = B16 (t_k - P c + (B P) c); t_k joins the ring of pending e terms
-      TRYT(launch_product16(op, ring(k), ring(k + 1), d0, R, level > 0 ? c : nullptr, grouped ? gid : nullptr,
-                            grouped ? gact_d : nullptr, st));
+      // one coloured sweep: with r' = r_k - P c + (B P) c, the L-type slots of
+      // ring(k) become z = r' + L z (in place) and ring(k + 1) = r_{k+1} = U z
+      // (colour by colour); ring(k) then holds the k-th term of the sum and joins
+      // the pending e terms
+      TRYT(launch_product16(op, ring(k), ring(k + 1), d0, R, level > 0 ? c : nullptr, c16, c16 + c16n,
+                            grouped ? gid : nullptr, grouped ? gact_d : nullptr, k == 0, st));
       ++k;
       ++pending;
       ++iters;
       for (int g = 0; g < G; ++g) gprod[g] += gact[g];
       if (pending == WIN) TRYT(flush(false));
       if (k % CHECK) continue;
-      TRYT(norms_t(ring(k)));
+      TRYT(norms_t(ring(k), true));
       bool inner_done = true;
       for (size_t i = 0; i < RG; ++i) {
         if (inner[i]) continue;
@@ -1410,6 +1562,13 @@ dfm_status solve_twolevel_impl(dfm_op op, const double *rho0, double *rho, int R
       diverged = false;   // without a coarse correction the growth is B's own (left to max_iter)
       if (inner_done || !finite) break;
       TRYT(update_active());
+    }
+    if (verbose) {
+      double worst = 0.0;
+      for (size_t i = 0; i < RG; ++i)
+        if (!inner[i]) worst = std::max(worst, std::sqrt(h[i]) / std::max(t0n[i], 1e-300));
+      std::fprintf(stderr, "[dfm two-level] stage %d level %d products %d%s, inner residual %.2e\n", outer, level, k,
+                   diverged ? " (diverged)" : "", worst);
     }
     if (diverged && level > 0) {
       --level;   // the stage's e is discarded; start it again one level lower
