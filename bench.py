@@ -4,14 +4,22 @@ One step = the whole path on the 3072-tetrahedron box (8x8x8 Kuhn cells, jitter
 0.15h, piecewise-linear position basis x Legendre momentum basis of degree 8,
 12-point Gauss rule per cell, mu = 0.05, walls R = 0.9, Gaussian patch source):
     mesh build -> assembly of B -> source projection -> solve (I - B) rho = rho0
-to a relative residual of 1e-8 (FP64 GMRES).  Inputs are resident in HBM before
-the timed region starts.
+to a relative residual of 1e-8 (FP64 GMRES, then FP32 GMRES corrections inside
+FP64 refinement).  Inputs are resident in HBM before the timed region starts.
+
+After the timed steps the same run measures the batched case once: the
+49152-tet box (32x16x16 cells, P0 x Legendre degree 12, 128 point sources):
+assembly, the two-level solve of all 128 right-hand sides to 1e-8, and one plain
+FP64 Neumann solve of one right-hand side for the per-rhs comparison (object
+`batched_box32`; one solve of that case takes about 20 s, so it is not repeated
+per step).
 
 Prints ONE JSON line (rank 0).  `value` is B-assembly face-pair blocks per
 second (12 blocks per tet) over the timed steps; the solve time per right-hand
 side is reported beside it.  `roofline` describes the kernel that takes the most
-time per step; `cpu_baseline` is the CPU oracle timed on a bounded sample of the
-same workload on this host (before the GPU is touched).
+time per step; `cpu_baseline` is the CPU oracle timed on bounded samples of the
+same workloads on this host (before the GPU is touched): assembly of sampled
+tets, and the oracle's sparse product on a sub-box scaled to the full operator.
 """
 from __future__ import annotations
 
@@ -50,6 +58,7 @@ def parse():
     ap.add_argument("--restart", type=int, default=100)
     ap.add_argument("--cpu-tets", type=int, default=24, help="tets in the oracle's timed sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the one-off 49152-tet batched measurement")
     ap.add_argument("--copy-calib", action="store_true", help="only run a plain device copy of known size")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only one assembly and five products with B (for hardware counters)")
@@ -95,11 +104,40 @@ def _oracle_blocks(prob, rule, ntets, seed=6):
 
 
 def cpu_baseline(prob, rule, ntets, label="3072-tet box"):
-    """Blocks/s of the unmodified oracle on `ntets` sampled tets, one process per core."""
+    """Blocks/s of the unmodified oracle on `ntets` sampled tets, one process per core
+    (at most 16, the CPU share of one GPU; `host_cpus` is what the host offers)."""
     blocks, dt, cores = _oracle_blocks(prob, rule, ntets)
-    return {"value": blocks / dt, "unit": "blocks/s", "cores": cores, "kind": "oracle",
+    return {"value": blocks / dt, "unit": "blocks/s", "cores": cores, "host_cpus": len(os.sched_getaffinity(0)),
+            "kind": "oracle",
             "sample": f"{ntets} tets ({blocks} blocks) drawn with seed 6 from the same {label}, "
                       f"FP64 NumPy oracle, {cores} worker processes, {dt:.1f} s"}
+
+
+def oracle_product_ms(sub, K, full_nt, seed=7, min_s=1.0):
+    """The oracle's y = B x (its SciPy CSR operator, FP64, one thread) on the sub-box
+    `sub` (the workload's recipe on fewer cells), with random blocks of size K (the
+    time does not depend on the values), scaled to `full_nt` tets by the operator's
+    size.  Returns (ms per product at full size, ms on the sub-box, sub-box tets)."""
+    import numpy as np
+    from oracle import mesh as om
+    from oracle import solve as osv
+    M = om.build_mesh(sub.verts, sub.tets, sub.refl)
+    dest = np.array([[om.destination(M, j, l)[0] for l in range(4)] for j in range(sub.nt)], dtype=np.int64)
+    rng = np.random.default_rng(seed)
+    B = rng.uniform(0.0, 1.0 / (3 * K), size=(sub.nt, 4, 3, K, K))
+    A = osv.to_sparse(B, dest)
+    del B
+    x = rng.standard_normal(A.shape[0])
+    A @ x
+    n, t0 = 0, time.perf_counter()
+    while True:
+        A @ x
+        n += 1
+        dt = time.perf_counter() - t0
+        if dt >= min_s and n >= 3:
+            break
+    ms_sub = dt / n * 1e3
+    return ms_sub * full_nt / sub.nt, ms_sub, sub.nt
 
 
 # --------------------------------------------------------------------------- HBM byte counters
@@ -152,8 +190,23 @@ def main():
     prob = synth.problem_c2()
     rule = 1 if args.rule == "seam" else 0
     base = None
+    cpu_b32 = None
     if not args.no_cpu_baseline and not args.copy_calib and not args.kernels_only:
         base = cpu_baseline(prob, rule, args.cpu_tets)
+        base["product_ms"], ms_sub, nt_sub = oracle_product_ms(synth.problem_c2(n_cells=4), 135, prob.nt)
+        base["product_sample"] = (f"oracle CSR product on the same recipe with 4x4x4 cells ({nt_sub} tets, K = 135, "
+                                  f"random blocks) {ms_sub:.1f} ms, one thread, scaled by tets to {prob.nt}")
+        print(f"bench: cpu baseline {base['value']:.2f} blocks/s, product {base['product_ms']:.0f} ms",
+              file=sys.stderr, flush=True)
+        if not args.no_batched:
+            p3 = synth.problem_c3(nsrc=1)
+            cpu_b32 = cpu_baseline(p3, rule, 8, "49152-tet box")
+            cpu_b32["product_ms"], ms_sub, nt_sub = oracle_product_ms(synth.problem_c3(cells=(8, 4, 4), nsrc=1),
+                                                                      91, p3.nt)
+            cpu_b32["product_sample"] = (f"oracle CSR product on the same recipe with 8x4x4 cells ({nt_sub} tets, "
+                                         f"K = 91, random blocks) {ms_sub:.1f} ms, one thread, scaled by tets to "
+                                         f"{p3.nt}")
+            del p3
 
     import torch
 
@@ -310,133 +363,140 @@ def main():
         "roofline_other": other,
         "cpu_baseline": base,
     }
+    if base is not None:
+        # the oracle's solve: its product time times the plain FP64 solve's products
+        base["solve_ms_per_rhs"] = base["product_ms"] * info[0]
+        base["solve_sample"] = (f"oracle product time x the {info[0]} operator applications of the plain FP64 "
+                                "GMRES solve of this run")
+    if not args.no_batched:
+        print("bench: one batched 49152-tet measurement", file=sys.stderr, flush=True)
+        b32 = batched_box32_once(args, dfm, torch, stream)
+        if cpu_b32 is not None:
+            cpu_b32["solve_ms_per_rhs"] = cpu_b32["product_ms"] * b32["fp64_products"]
+            cpu_b32["solve_sample"] = (f"oracle product time x the {b32['fp64_products']} products of the plain "
+                                       "FP64 Neumann solve of this run")
+            base["batched_box32"] = cpu_b32
+        out["batched_box32"] = b32
     print(json.dumps(out))
+
+
+def batched_box32_once(args, dfm, torch, stream, prob=None):
+    """One measurement of the batched case on the 49152-tet box: mesh build,
+    assembly, 128 point sources, the two-level solve of all 128 to 1e-8, true FP64
+    residuals of three of them, and one plain FP64 Neumann solve of source 0 (the
+    per-rhs reference, same operator)."""
+    import synth
+    if prob is None:
+        prob = synth.problem_c3(nsrc=128)
+    dev = torch.device("cuda:0")
+    T = lambda a: torch.tensor(a, device=dev)  # noqa: E731
+    rule = 1 if args.rule == "seam" else 0
+    verts, tets, refl, mu, xyz = T(prob.verts), T(prob.tets), T(prob.refl), T(prob.mu), T(prob.source["xyz"])
+    R = xyz.shape[0]
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+    e[0].record(stream)
+    mesh = dfm.Mesh(verts, tets, refl=refl)
+    e[1].record(stream)
+    op = dfm.Operator(mesh, mu, prob.pos_order, dfm.LEGENDRE, prob.mom_degree, prob.quad_n, rule=rule)
+    e[2].record(stream)
+    rho0 = op.source_points(xyz)
+    e[3].record(stream)
+    rho, info = op.solve(rho0, method="twolevel", rtol=1e-8, max_iter=20000)
+    e[4].record(stream)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for r in (0, R // 2, R - 1):
+        res = rho0[r] - (rho[r] - op.apply(rho[r]))
+        worst = max(worst, float((res.norm() / rho0[r].norm()).item()))
+    print("bench: plain FP64 single-rhs Neumann reference on the 49152-tet box", file=sys.stderr, flush=True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    rho64, info64 = op.solve(rho0[0], method="neumann", rtol=1e-8, max_iter=40000)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t64 = e0.elapsed_time(e1)
+    diff = float(((rho[0] - rho64).norm() / rho64.norm()).item())
+    t_mesh, t_asm, t_src, t_solve = (e[i].elapsed_time(e[i + 1]) for i in range(4))
+    out = {
+        "workload": "box32x16x16-kuhn-49152tets-jitter0.1_P0xLegendreD12_n16_"
+                    f"{args.rule}-rule_mu-lognormal(ln0.02,0.5)_R0.9_128-point-sources_batched-1e-8",
+        "measured": "once, after the timed steps",
+        "tets": int(prob.nt), "blocks": int(op.nblocks), "K": int(op.K), "ndof": int(op.ndof), "nrhs": int(R),
+        "quadrature_directions": int(op.nodes),
+        "ms_mesh_build": t_mesh, "ms_assemble": t_asm, "assemble_blocks_per_s": op.nblocks / (t_asm / 1e3),
+        "ms_sources": t_src,
+        "solve_ms": t_solve, "solve_ms_per_rhs": t_solve / R,
+        "solve_method": "two-level: coloured Gauss-Seidel sweeps with a coarse correction, FP16 products on the "
+                        "matrix cores, FP64 refinement residuals",
+        "solve_products": int(info[0][0]), "solve_relres_worst": max(i[2] for i in info),
+        "solve_true_relres_sampled": worst,
+        "fp64_ms_per_rhs": t64, "fp64_method": "plain FP64 Neumann, one rhs", "fp64_products": int(info64[0][0]),
+        "fp64_relres": info64[0][2],
+        "speedup_per_rhs_vs_fp64": t64 / (t_solve / R),
+        "rel_diff_vs_fp64_rhs0": diff,
+    }
+    del rho, rho64
+    op.close()
+    mesh.close()
+    return out
 
 
 def main_box32(args):
     """49152-tet box (32x16x16 cells), P0 x Legendre D=12, n=16, lognormal mu, 128
     isotropic boundary point sources.  One step = mesh build -> assembly -> 128
-    sources -> batched solve of all 128 (FP32 Neumann corrections on the matrix
-    cores inside FP64 refinement) to relative residual 1e-8.  The plain FP64
-    reference is one single-rhs FP64 Neumann solve of the first source, timed
-    after the steps.  `value` is assembly blocks/s."""
+    sources -> two-level solve of all 128 (coloured sweeps with a coarse
+    correction, FP16 products on the matrix cores, FP64 refinement) to relative
+    residual 1e-8.  After the steps, one plain FP64 single-rhs Neumann solve of the
+    first source is the per-rhs reference.  `value` is assembly blocks/s."""
     import numpy as np
 
     import synth
     prob = synth.problem_c3(nsrc=128)
     base = None
+    rule = 1 if args.rule == "seam" else 0
     if not args.no_cpu_baseline:
-        base = cpu_baseline(prob, 1 if args.rule == "seam" else 0, min(args.cpu_tets, 8), "49152-tet box")
+        base = cpu_baseline(prob, rule, min(args.cpu_tets, 8), "49152-tet box")
+        base["product_ms"], ms_sub, nt_sub = oracle_product_ms(synth.problem_c3(cells=(8, 4, 4), nsrc=1), 91, prob.nt)
+        base["product_sample"] = (f"oracle CSR product on the same recipe with 8x4x4 cells ({nt_sub} tets, K = 91, "
+                                  f"random blocks) {ms_sub:.1f} ms, one thread, scaled by tets to {prob.nt}")
         print(f"bench: cpu baseline {base['value']:.2f} blocks/s", file=sys.stderr, flush=True)
 
     import torch
 
     from paper_1608_04607_amd import dfm
 
-    dev = torch.device("cuda:0")
+    os.environ.setdefault("DFM_VERBOSE", "1")      # one stderr line per refinement stage
     stream = torch.cuda.current_stream()
-    T = lambda a: torch.tensor(a, device=dev)  # noqa: E731
-    verts, tets, refl, mu, xyz = T(prob.verts), T(prob.tets), T(prob.refl), T(prob.mu), T(prob.source["xyz"])
-    rule = 1 if args.rule == "seam" else 0
-    R = xyz.shape[0]
     if args.kernels_only:
-        mesh = dfm.Mesh(verts, tets, refl=refl)
-        op = dfm.Operator(mesh, mu, prob.pos_order, dfm.LEGENDRE, prob.mom_degree, prob.quad_n, rule=rule)
-        rho0 = op.source_points(xyz)
-        x32 = rho0.float()
-        for _ in range(5):
-            op.apply_f32(x32)
-        for _ in range(5):
-            op.apply(rho0[0])
+        dev = torch.device("cuda:0")
+        T = lambda a: torch.tensor(a, device=dev)  # noqa: E731
+        mesh = dfm.Mesh(T(prob.verts), T(prob.tets), refl=T(prob.refl))
+        op = dfm.Operator(mesh, T(prob.mu), prob.pos_order, dfm.LEGENDRE, prob.mom_degree, prob.quad_n, rule=rule)
+        rho0 = op.source_points(T(prob.source["xyz"]))
+        op.solve(rho0, method="twolevel", rtol=1e-8, max_iter=int(os.environ.get("BENCH_PRODUCTS", "40")),
+                 raise_nonconv=False)
         torch.cuda.synchronize()
         print(json.dumps({"kernels_only": True, "workload": "box32", "nodes": op.nodes, "K": op.K, "ndof": op.ndof,
-                          "B_bytes": op.nbytes, "nrhs": R}))
+                          "B_bytes": op.nbytes, "nrhs": int(rho0.shape[0])}))
         return
-
-    def ev():
-        return torch.cuda.Event(enable_timing=True)
-
-    def step(record):
-        e = [ev() for _ in range(5)]
-        e[0].record(stream)
-        mesh = dfm.Mesh(verts, tets, refl=refl)
-        e[1].record(stream)
-        op = dfm.Operator(mesh, mu, prob.pos_order, dfm.LEGENDRE, prob.mom_degree, prob.quad_n, rule=rule)
-        e[2].record(stream)
-        rho0 = op.source_points(xyz)
-        e[3].record(stream)
-        # in segments of at most SEG batched products, each continuing from the last
-        # iterate (warm start), so that progress is reported while it runs
-        SEG = 2500
-        rho, total = None, 0
-        while True:
-            rho, info = op.solve(rho0, method="neumann", rtol=1e-8, precision=1, max_iter=SEG, rho=rho,
-                                 raise_nonconv=False)
-            total += info[0][0]
-            worst = max(i[2] for i in info)
-            print(f"bench: {total} batched products, worst relres {worst:.2e}", file=sys.stderr, flush=True)
-            if worst <= 1e-8 or total >= 40000:
-                break
-        info = [(total, 0, i[2]) for i in info]
-        e[4].record(stream)
-        torch.cuda.synchronize()
-        if record is not None:
-            record.append((e, info, op.nodes, op.nblocks, op.K, op.ndof))
-            return op, mesh, rho0, rho
-        op.close()
-        mesh.close()
-        return None
-
     for _ in range(args.warmup):
-        step(None)
+        batched_box32_once(args, dfm, torch, stream, prob)
     torch.cuda.synchronize()
     recs = []
     t0 = time.perf_counter()
-    for i in range(args.steps):
-        out = step(recs)
-        if i < args.steps - 1:
-            out[0].close()
-            out[1].close()
+    for _ in range(args.steps):
+        recs.append(batched_box32_once(args, dfm, torch, stream, prob))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    op, mesh, rho0, rho = out
-    phase = np.array([[r[0][i].elapsed_time(r[0][i + 1]) for i in range(4)] for r in recs])
-    t_mesh, t_asm, t_src, t_solve = phase.mean(axis=0)
-    info = recs[-1][1]
-    nodes, nblocks, K, ndof = recs[-1][2:]
-    # true FP64 residuals of a few right-hand sides
-    worst = 0.0
-    for r in (0, R // 2, R - 1):
-        res = rho0[r] - (rho[r] - op.apply(rho[r]))
-        worst = max(worst, float((res.norm() / rho0[r].norm()).item()))
-    del rho
-    # the batched product alone (HIP events on the library's stream)
-    x32 = rho0.float()
-    for _ in range(2):
-        op.apply_f32(x32)
-    e0, e1 = ev(), ev()
-    e0.record(stream)
-    for _ in range(5):
-        op.apply_f32(x32)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    t_spmm = e0.elapsed_time(e1) / 5
-    del x32
-    print("bench: plain FP64 single-rhs Neumann reference", file=sys.stderr, flush=True)
-    e0, e1 = ev(), ev()
-    e0.record(stream)
-    _, info64 = op.solve(rho0[0], method="neumann", rtol=1e-8, max_iter=40000)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    t64 = e0.elapsed_time(e1)
-    nt = prob.nt
-    Kp = (K + 3) // 4 * 4
-    flops = 2.0 * 12 * nt * K * K * R
-    spmm_tf = flops / (t_spmm / 1e3) / 1e12
-    spmm_bytes = 4.0 * (12 * nt * K * Kp + 2 * R * ndof)
+    last = recs[-1]
+    t_asm = np.mean([r["ms_assemble"] for r in recs])
+    t_solve = np.mean([r["solve_ms"] for r in recs])
+    flops_asm = 2.0 * last["quadrature_directions"] * last["K"] ** 2
+    asm_tf = flops_asm / (t_asm / 1e3) / 1e12
     out = {
         "metric": METRIC,
-        "value": nblocks * args.steps / (phase[:, 1].sum() / 1e3),
+        "value": last["blocks"] / (t_asm / 1e3),
         "unit": "blocks/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -445,31 +505,19 @@ def main_box32(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64 assembly; f32 batched corrections, f64 residuals",
+        "dtype": "f64 assembly; f16 batched sweeps, f64 residuals",
         "data": "synthetic",
-        "config": {"workload": f"box32x16x16-kuhn-49152tets-jitter0.1_P0xLegendreD12_n16_{args.rule}-rule"
-                               "_mu-lognormal(ln0.02,0.5)_R0.9_128-point-sources_batched-1e-8",
-                   "tets": int(nt), "blocks": int(nblocks), "K": int(K), "ndof": int(ndof), "nrhs": int(R),
-                   "quadrature_directions": int(nodes)},
-        "phase_ms": {"mesh_build": t_mesh, "assemble": t_asm, "sources": t_src, "solve_batched": t_solve},
-        "solve_ms_per_rhs": t_solve / R,
-        "solve_precision": "fp32 Neumann corrections (batched products on the fp32 matrix cores), fp64 refinement",
-        "solve_iters": info[0][0],
-        "solve_relres_worst": max(i[2] for i in info),
-        "solve_true_relres_sampled": worst,
-        "solve_fp64_ms_per_rhs": t64,
-        "solve_fp64_method": "plain fp64 Neumann, one rhs",
-        "solve_fp64_iters": info64[0][0],
-        "solve_speedup_per_rhs_vs_fp64": t64 / (t_solve / R),
-        "roofline": {"kernel": "k_spmm32", "bound": "mfma", "achieved": spmm_tf, "peak": FP32_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": spmm_tf / FP32_PEAK_TFLOPS, "traffic": None,
-                     "algorithmic": f"2*12*nt*K^2*R flop per launch, R = {R}; bytes 4*(12*nt*K*Kp + 2*R*ndof) = "
-                                    f"{spmm_bytes:.3e} ({spmm_bytes / (t_spmm / 1e3) / 1e9:.0f} GB/s)",
-                     "ms_per_launch": t_spmm},
+        "config": {"workload": last["workload"], "tets": last["tets"], "blocks": last["blocks"], "K": last["K"],
+                   "ndof": last["ndof"], "nrhs": last["nrhs"], "quadrature_directions": last["quadrature_directions"]},
+        "solve_ms_per_rhs": t_solve / last["nrhs"],
+        "steps_detail": recs,
+        "roofline": {"kernel": "k_assemble", "bound": "mfma", "achieved": asm_tf, "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": asm_tf / FP64_PEAK_TFLOPS, "traffic": None,
+                     "algorithmic": f"2*Q*K^2 flop per launch, Q = {last['quadrature_directions']}, K = {last['K']}"},
         "cpu_baseline": base,
     }
-    op.close()
-    mesh.close()
+    if base is not None:
+        base["solve_ms_per_rhs"] = base["product_ms"] * last["fp64_products"]
     print(json.dumps(out))
 
 

@@ -57,3 +57,21 @@ def test_measured_traffic_needs_the_counted_source(tmp_path):
     assert bench.measured_traffic("k", str(f), "ratio") == 1.5
     assert bench.measured_traffic("old", str(f)) is None
     assert bench.measured_traffic("missing", str(f)) is None
+
+
+def test_oracle_product_leg_scales_by_tets():
+    """The solve leg of the CPU baseline times the oracle's own sparse product on a
+    sub-box and scales it to the full tet count; it reports the host's CPUs too."""
+    import numpy as np
+
+    import synth
+    bench = _bench()
+    sub = synth.problem_c3(cells=(2, 1, 1), nsrc=1)
+    full_ms, sub_ms, nt_sub = bench.oracle_product_ms(sub, 6, 10 * sub.nt, min_s=0.05)
+    assert nt_sub == sub.nt == 12
+    assert sub_ms > 0 and np.isclose(full_ms, 10 * sub_ms)
+    v, t = synth.kuhn_box((1, 1, 1), (1.0, 1.0, 1.0), jitter=0.1, seed=1)
+    p = synth.Problem(name="tiny", verts=v, tets=t, mu=np.full(t.shape[0], 0.05), refl=np.full((t.shape[0], 4), 0.9),
+                      pos_order=0, mom_degree=2, quad_n=4)
+    out = bench.cpu_baseline(p, 1, 2, "one-cell test box")
+    assert out["host_cpus"] == len(os.sched_getaffinity(0)) and out["cores"] <= out["host_cpus"]
