@@ -219,9 +219,10 @@ def main():
         x = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
         y = torch.empty_like(x)
         for _ in range(5):
-            y.copy_(x)
+            torch.mul(x, 2.0, out=y)      # one elementwise kernel: reads 1 GiB, writes 1 GiB
         torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_read": x.numel() * 8, "copy_bytes_written": y.numel() * 8, "launches": 5}))
+        print(json.dumps({"copy_bytes_read": x.numel() * 8, "copy_bytes_written": y.numel() * 8, "launches": 5,
+                          "kernel": "elementwise mul"}))
         return
 
     verts = torch.tensor(prob.verts, device=dev)
