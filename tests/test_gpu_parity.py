@@ -1025,3 +1025,46 @@ def test_uneven_batch_matches_oracle():
     assert order == [g.key[2] for g in ub.groups] and sorted(piped) == list(range(len(probs)))
     for i in range(len(probs)):
         assert rel(piped[i].cpu().numpy(), ref[i][2]) < 2e-5
+
+
+def test_gradients_on_a_sub_box_of_the_receiver_case_match_oracle():
+    """The receiver-gradient case's own recipe (box [0,2]x[0,1]^2, jitter 0.1h,
+    lognormal mu, R = 0.9, P0 Legendre basis, seam rule, receiver
+    [1.6,1.9]x[0.4,0.6]^2, point sources) on a 6x3x3-cell sub-box (324 tets, the
+    coarsest whose tet centroids reach into the receiver), with the momentum degree
+    lowered to 6 (n = 10) so that the oracle's sparse LU stays small: dJ/dmu and
+    dJ/dw of the library against the FP64 oracle's adjoint gradient (blocks and
+    block derivatives computed in worker processes)."""
+    from tests.oracle_pool import pool_map, tet_blocks, tet_dB_terms
+    say("[adjoint] receiver-case recipe on a 6x3x3 sub-box, D = 6")
+    prob = synth.problem_c3(cells=(6, 3, 3), nsrc=4)
+    prob.mom_degree, prob.quad_n = 6, 10
+    box = (1.6, 1.9, 0.4, 0.6, 0.4, 0.6)
+    w = np.array([1.0, 0.5, 2.0, 1.5])
+    v, t, refl, mu, pts = prob.verts, prob.tets, prob.refl, prob.mu, prob.source["xyz"]
+    bs = oa.Basis(0, 0, prob.mom_degree, prob.quad_n, oq.SEAM_RULE)
+    op = gpu_op(gpu_mesh(v, t, refl), mu, bs)
+    src = op.source_points(torch.tensor(pts, device=DEV))
+    rho0 = torch.tensor(w, device=DEV) @ src
+    rho, _ = op.solve(rho0, rtol=1e-13, restart=60)
+    lam, dmu, dw, info = op.adjoint(rho, box, src=src, rtol=1e-13, restart=60)
+    say(f"    adjoint info {info}")
+    common = (v, t, refl, mu, 0, 0, prob.mom_degree, prob.quad_n, oq.SEAM_RULE)
+    chunks = [list(c) for c in np.array_split(np.arange(prob.nt), 32)]
+    parts = pool_map(tet_blocks, [common + (c,) for c in chunks])
+    B = np.concatenate([p[0] for p in parts])
+    dest = np.concatenate([p[1] for p in parts])
+    m = om.build_mesh(v, t, refl)
+    A = osv.to_sparse(B, dest)
+    rho0s = osrc.project(m, bs, {"kind": "points", "xyz": pts})
+    rho_o = osv.solve_direct(A, w @ rho0s)
+    g = oj.receiver_functional(m, bs, mu, box)
+    lam_o = osv.solve_direct(A.T.tocsr(), g)
+    terms = pool_map(tet_dB_terms, [common + (c, lam_o, rho_o) for c in chunks])
+    dg = oj.receiver_functional(m, bs, mu, box, derivative=True).reshape(prob.nt, -1)
+    dmu_o = np.concatenate(terms) + np.einsum("jk,jk->j", dg, rho_o.reshape(prob.nt, -1))
+    say(f"    |dJ/dmu| max {np.abs(dmu_o).max():.3e}, rel {rel(dmu.cpu().numpy(), dmu_o):.2e}; "
+        f"dJ/dw rel {rel(dw.cpu().numpy(), rho0s @ lam_o):.2e}")
+    assert np.abs(dmu_o).max() > 0.0
+    assert rel(dmu.cpu().numpy(), dmu_o) < 1e-9
+    assert rel(dw.cpu().numpy(), rho0s @ lam_o) < 1e-9
