@@ -87,9 +87,10 @@ typedef struct {
                         the Kuhn boxes, so a density crosses two tets per sweep),
                         each preceded by a coarse correction (Galerkin projection of
                         I - B on a few global-direction harmonics per aggregate of
-                        tets), all nrhs together; needs precision 2, dtype 0 and
-                        K <= 160, and is not available for transposed (adjoint)
-                        solves                                                      */
+                        tets), all nrhs together; needs precision 2 and K <= 160
+                        (either dtype: the refinement residual is that of the
+                        stored operator), and is not available for transposed
+                        (adjoint) solves                                            */
   int restart;    /* GMRES restart length (Krylov vectors kept), 1..200                 */
   int max_iter;   /* total iteration cap (operator applications)                        */
   double rtol;    /* stop when ||rho0 - (I-B) rho||_2 <= rtol ||rho0||_2                */
