@@ -343,11 +343,11 @@ __global__ void k_coarse_maps(const int32_t *__restrict__ agg_tet, const int32_t
 // row group of a U-type destination also
 // d0[dest][f][r] = sum_{k < R0} Pv[dest][k][f] y[r][k] (0 for L type).
 //
-// Workgroup = (tet, 128 right-hand sides, row group of 96), one wave per block
-// row (l_out = wave).  Each lane loads its MFMA fragments straight from memory,
+// Workgroup = (tet, tile of 16 CT right-hand sides, row group of 96), one wave
+// per block row (l_out = wave).  Each lane loads its MFMA fragments straight from memory,
 // 16 bytes at a time: B rows m0 + 16 rt + lane % 16, columns 8 (lane / 16) .. + 7
 // of a 32-column chunk, and the same 8 columns of right-hand side
-// r0 + 16 ct + lane % 16; v_mfma_f32_16x16x32_f16 takes them as they are (the
+// rw0 + 16 ct + lane % 16; v_mfma_f32_16x16x32_f16 takes them as they are (the
 // same column order on both sides).  No LDS and no barrier.
 //
 // Schedule: four phases, one per local face p of the tet.  In phase p the three
@@ -362,7 +362,6 @@ __global__ void k_coarse_maps(const int32_t *__restrict__ agg_tet, const int32_t
 // Rows of instances that are not multiplied (gact[gid[tet]] == 0) get y = 0 and
 // d0 = 0.
 // ---------------------------------------------------------------------------
-constexpr int P16_RT = 128;
 
 struct P16Args {
   const half_t *B16;
@@ -386,12 +385,11 @@ struct P16Args {
 };
 
 template <int DEPTH, int CT>
-__global__ __launch_bounds__(64 * 4 * (P16_RT / 16 / CT), 1) void k_spmm16(P16Args a) {
+__global__ __launch_bounds__(256, 1) void k_spmm16(P16Args a) {
   constexpr int RT = ROWG / 16;
   const int lane = threadIdx.x & 63;
-  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int l_out = wv & 3;
-  const int rw0 = blockIdx.y * P16_RT + (wv >> 2) * CT * 16;   // first right-hand side of this wave
+  const int l_out = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int rw0 = blockIdx.y * CT * 16;                   // first right-hand side of the workgroup
   const int64_t j = a.tlist[blockIdx.x];
   const int64_t br = 4 * j + l_out;
   const int m0 = blockIdx.z * ROWG;
@@ -1283,14 +1281,21 @@ hipError_t launch_product16(dfm_op op, half_t *t, half_t *y, float *d0, int R, c
   a.gact = gact;
   a.lmask = C.lmask;
   a.first = first ? 1 : 0;
-  // one launch per colour, in colour order; one workgroup per (tet, 128
-  // right-hand sides, row group of 96)
+  // one launch per colour, in colour order; one workgroup per (tet, tile of
+  // 16 CT right-hand sides, row group of 96): the tile follows R, so that a few
+  // right-hand sides do not pay for the matrix-core work of 128
+  const int CT = R <= 16 ? 1 : (R <= 32 ? 2 : (R <= 64 ? 4 : 8));
   for (int q = 0; q < C.ncol; ++q) {
     const int64_t cnt = C.col_off[q + 1] - C.col_off[q];
     if (cnt == 0) continue;
     a.tlist = C.tlist + C.col_off[q];
-    const dim3 grid((unsigned)cnt, (unsigned)((R + P16_RT - 1) / P16_RT), (unsigned)((op->Kp8 + ROWG - 1) / ROWG));
-    hipLaunchKernelGGL((k_spmm16<2, 8>), grid, dim3(256), 0, st, a);
+    const dim3 grid((unsigned)cnt, (unsigned)((R + 16 * CT - 1) / (16 * CT)), (unsigned)((op->Kp8 + ROWG - 1) / ROWG));
+    switch (CT) {
+      case 1: hipLaunchKernelGGL((k_spmm16<2, 1>), grid, dim3(256), 0, st, a); break;
+      case 2: hipLaunchKernelGGL((k_spmm16<2, 2>), grid, dim3(256), 0, st, a); break;
+      case 4: hipLaunchKernelGGL((k_spmm16<2, 4>), grid, dim3(256), 0, st, a); break;
+      default: hipLaunchKernelGGL((k_spmm16<2, 8>), grid, dim3(256), 0, st, a); break;
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
