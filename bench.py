@@ -410,6 +410,17 @@ def batched_box32_once(args, dfm, torch, stream, prob=None):
     for r in (0, R // 2, R - 1):
         res = rho0[r] - (rho[r] - op.apply(rho[r]))
         worst = max(worst, float((res.norm() / rho0[r].norm()).item()))
+    # the batched FP64 product the library has (the refinement residual: B streamed
+    # once per 8 right-hand sides, FP64 accumulation), timed on all R
+    op.residual(rho0, rho)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(2):
+        res = op.residual(rho0, rho)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_res = e0.elapsed_time(e1) / 2
+    del res
     print("bench: plain FP64 single-rhs Neumann reference on the 49152-tet box", file=sys.stderr, flush=True)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
@@ -436,6 +447,12 @@ def batched_box32_once(args, dfm, torch, stream, prob=None):
         "fp64_relres": info64[0][2],
         "speedup_per_rhs_vs_fp64": t64 / (t_solve / R),
         "rel_diff_vs_fp64_rhs0": diff,
+        "fp64_batched_product_ms": t_res,
+        "fp64_batched_ms_per_rhs_est": t_res * int(info64[0][0]) / R,
+        "fp64_batched_note": "plain FP64 Neumann over all R at once, estimated as the measured FP64 batched "
+                             "product of all R (dfm_residual: B streamed once per 8 rhs, plus the vector update) "
+                             "x the plain solve's products / R; splits the gain into batching "
+                             "(fp64_ms_per_rhs / this) and method + precision (this / solve_ms_per_rhs)",
     }
     del rho, rho64
     op.close()

@@ -229,6 +229,14 @@ dfm_status dfm_solve(dfm_op op, const double *rho0, double *rho, int nrhs, const
 dfm_status dfm_solve_groups(dfm_op op, const double *rho0, double *rho, int nrhs, const dfm_solve_opts *opts,
                             const int64_t *tet_offsets, int ngroups, dfm_solve_info *info, void *stream);
 
+/* The residual of Eq. GovIE for nrhs right-hand sides: res = rho0 - (I - B) rho
+ * (Sec. 2), with the stored operator (FP64, or FP32 entries when dtype = 1) and
+ * FP64 accumulation; B is streamed once per 8 right-hand sides.  This is the
+ * refinement residual of the batched solvers.
+ *   rho0, rho, res  device f64 [nrhs][ndof]; res aliases neither rho0 nor rho.
+ * Errors: DFM_E_INVALID.  Does not synchronise `stream`. */
+dfm_status dfm_residual(dfm_op op, const double *rho0, const double *rho, double *res, int nrhs, void *stream);
+
 /* Project sources onto the basis (Galerkin in ds cos(theta)dOmega, as the initial
  * densities of Sec. 4 are projected onto Eq. FBApprox).
  *

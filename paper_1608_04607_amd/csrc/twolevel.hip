@@ -917,6 +917,19 @@ hipError_t residual_batched(dfm_op op, const double *rho0, const double *x, doub
   return hipSuccess;
 }
 
+}  // namespace dfm
+
+extern "C" dfm_status dfm_residual(dfm_op op, const double *rho0, const double *rho, double *res, int nrhs,
+                                   void *stream) {
+  DFM_REQUIRE(op && rho0 && rho && res, DFM_E_INVALID, "null argument");
+  DFM_REQUIRE(nrhs >= 1, DFM_E_INVALID, "nrhs must be >= 1");
+  DFM_REQUIRE(res != rho && res != rho0, DFM_E_INVALID, "res must not alias rho0 or rho");
+  DFM_HIP(dfm::residual_batched(op, rho0, rho, res, nrhs, (hipStream_t)stream));
+  return DFM_OK;
+}
+
+namespace dfm {
+
 // ---------------------------------------------------------------------------
 // Coarse space of an operator for a given partition into instances (cached with
 // the FP16 copy of B, whose correction columns depend on it).

@@ -185,6 +185,16 @@ class Operator:
                 for r in range(nrhs)] for g in range(G)]
         return rho, out
 
+    def residual(self, rho0, rho, stream=None):
+        """rho0 - (I - B) rho for one or several right-hand sides (dfm_residual)."""
+        rho0, rho = _dev(rho0, torch.float64), _dev(rho, torch.float64)
+        if rho0.shape != rho.shape:
+            raise ValueError("rho0 and rho must have the same shape")
+        nrhs = 1 if rho0.dim() == 1 else rho0.shape[0]
+        res = torch.empty_like(rho0)
+        check(_lib.load().dfm_residual(self.handle, _ptr(rho0), _ptr(rho), _ptr(res), nrhs, _stream(stream)))
+        return res
+
     def source_points(self, xyz, flux=1.0, stream=None):
         xyz = _dev(xyz, torch.float64)
         ns = xyz.shape[0]

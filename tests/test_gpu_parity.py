@@ -526,6 +526,26 @@ def test_batched_mixed_neumann_warm_start(small):
         assert rel(rho[r].cpu().numpy(), osv.solve_direct(A, rhs[r])) < 1e-7
 
 
+@pytest.mark.parametrize("nrhs", [1, 11])
+def test_residual_matches_oracle(small, nrhs):
+    """dfm_residual: rho0 - (I - B) rho for several right-hand sides in one pass
+    per 8 (11 = one full pass and a tail of 3) against the oracle's sparse B."""
+    say(f"[residual] {nrhs} rhs")
+    g, op, m, bs, Bo, desto, mu = small
+    A = osv.to_sparse(Bo, desto)
+    rng = np.random.default_rng(41)
+    rho0 = rng.standard_normal((nrhs, A.shape[0]))
+    rho = rng.standard_normal((nrhs, A.shape[0]))
+    res = op.residual(torch.tensor(rho0, device=DEV), torch.tensor(rho, device=DEV)).cpu().numpy()
+    ref = rho0 - (rho - (A @ rho.T).T)
+    assert rel(res, ref) < TOL
+    with pytest.raises(RuntimeError):
+        x = torch.tensor(rho0, device=DEV)
+        from paper_1608_04607_amd import _lib
+        from paper_1608_04607_amd.dfm import check, _ptr, _stream
+        check(_lib.load().dfm_residual(op.handle, _ptr(x), _ptr(x), _ptr(x), nrhs, _stream(None)))
+
+
 @pytest.mark.parametrize("nrhs", [3, 130])
 def test_twolevel_solve_matches_oracle(small, nrhs):
     """Method 2: all right-hand sides together, the coarse-corrected iteration on
