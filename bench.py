@@ -586,8 +586,15 @@ def main_uneven(args):
         return torch.cuda.Event(enable_timing=True)
 
     if args.kernels_only:
-        # the largest group only: FP32 assembly and five 4-rhs streaming products
+        # FP32 assembly of every degree group (released after it), then the largest
+        # group again and five 4-rhs streaming products
         batch = UnevenBatch(probs, rule=rule, dtype=1)
+        for g in batch.groups:
+            batch.assemble(g)
+            torch.cuda.synchronize()
+            print(f"bench: assembled D={g.key[2]} ({g.mesh.nt} tets, {g.op.nodes} directions, K = {g.op.K})",
+                  file=sys.stderr, flush=True)
+            batch.release(g)
         g = max(batch.groups, key=lambda g: g.tet_offsets[-1] * (g.key[2] + 1) ** 4)
         batch.assemble(g)
         x32 = g.rho0.float()
