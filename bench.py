@@ -5,7 +5,8 @@ One step = the whole path on the 3072-tetrahedron box (8x8x8 Kuhn cells, jitter
 12-point Gauss rule per cell, mu = 0.05, walls R = 0.9, Gaussian patch source):
     mesh build -> assembly of B -> source projection -> solve (I - B) rho = rho0
 to a relative residual of 1e-8 (FP64 GMRES, then FP32 GMRES corrections inside
-FP64 refinement).  Inputs are resident in HBM before the timed region starts.
+FP64 refinement, then the two-level solver's FP16 sweeps inside FP64 refinement).
+Inputs are resident in HBM before the timed region starts.
 
 After the timed steps the same run measures the batched case once: the
 49152-tet box (32x16x16 cells, P0 x Legendre degree 12, 128 point sources):
@@ -246,7 +247,7 @@ def main():
         return torch.cuda.Event(enable_timing=True)
 
     def step(record):
-        e = [ev() for _ in range(6)]
+        e = [ev() for _ in range(7)]
         e[0].record(stream)
         mesh = dfm.Mesh(verts, tets, refl=refl)
         e[1].record(stream)
@@ -260,9 +261,13 @@ def main():
         rho_m, info_m = op.solve(rho0, method="gmres", rtol=1e-8, restart=args.restart, max_iter=20000,
                                  precision=1)
         e[5].record(stream)
+        # two-level sweeps (FP16 products on the matrix cores) inside FP64 refinement
+        rho_t, info_t = op.solve(rho0, method="twolevel", rtol=1e-8, max_iter=20000)
+        e[6].record(stream)
         if record is not None:
             diff = float(((rho_m - rho).norm() / rho.norm()).item())
-            record.append((e, info + info_m, op.nodes, op.nblocks, op.K, op.ndof, diff))
+            diff_t = float(((rho_t - rho).norm() / rho.norm()).item())
+            record.append((e, info + info_m + [info_t[0]], op.nodes, op.nblocks, op.K, op.ndof, diff, diff_t))
         op.close()
         mesh.close()
         return rho
@@ -277,10 +282,10 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 
-    phase = np.array([[r[0][i].elapsed_time(r[0][i + 1]) for i in range(5)] for r in recs])  # ms
-    t_mesh, t_asm, t_src, t_solve, t_mixed = phase.mean(axis=0)
-    info, info_m = recs[-1][1]
-    nodes, nblocks, K, ndof, diff = recs[-1][2:]
+    phase = np.array([[r[0][i].elapsed_time(r[0][i + 1]) for i in range(6)] for r in recs])  # ms
+    t_mesh, t_asm, t_src, t_solve, t_mixed, t_two = phase.mean(axis=0)
+    info, info_m, info_t = recs[-1][1]
+    nodes, nblocks, K, ndof, diff, diff_t = recs[-1][2:]
     blocks_per_s = nblocks * args.steps / (phase[:, 1].sum() / 1e3)
 
     # SpMV kernel: one dfm_apply launch per call, timed with events on the same stream
@@ -346,15 +351,21 @@ def main():
                    "tets": int(prob.nt), "blocks": int(nblocks), "K": int(K), "ndof": int(ndof),
                    "quadrature_directions": int(nodes)},
         "phase_ms": {"mesh_build": t_mesh, "assemble": t_asm, "source": t_src, "solve_fp64": t_solve,
-                     "solve_fp32_refined": t_mixed},
-        "solve_ms_per_rhs": t_mixed,
-        "solve_precision": "fp32 GMRES corrections, fp64 refinement residuals",
+                     "solve_fp32_refined": t_mixed, "solve_twolevel": t_two},
+        "solve_ms_per_rhs": min(t_mixed, t_two),
+        "solve_precision": "fastest of: fp32 GMRES corrections, fp64 refinement residuals (solve_fp32_refined); "
+                           "two-level sweeps with fp16 products, fp64 refinement residuals (solve_twolevel)",
         "solve_relres": info_m[2],
         "solve_iters": info_m[0],
+        "solve_twolevel_ms_per_rhs": t_two,
+        "solve_twolevel_relres": info_t[2],
+        "solve_twolevel_sweeps": info_t[0],
+        "solve_twolevel_rel_diff_vs_fp64": diff_t,
+        "solve_twolevel_speedup_vs_fp64": t_solve / t_two,
         "solve_fp64_ms_per_rhs": t_solve,
         "solve_fp64_iters": info[0],
         "solve_fp64_relres": info[2],
-        "solve_speedup_vs_fp64": t_solve / t_mixed,
+        "solve_speedup_vs_fp64": t_solve / min(t_mixed, t_two),
         "solve_rel_diff_vs_fp64": diff,
         "spmv_ms": t_spmv,
         "assemble_fp32_ms": t_asm32,
