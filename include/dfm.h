@@ -85,9 +85,9 @@ typedef struct {
                      2: two-level sweeps: Gauss-Seidel sweeps of B over a colouring
                         of the tets (no two face neighbours alike; two colours on
                         the Kuhn boxes, so a density crosses two tets per sweep),
-                        each preceded by a coarse correction (Galerkin projection of
-                        I - B on a few global-direction harmonics per aggregate of
-                        tets), all nrhs together; needs precision 2 and K <= 160
+                        each preceded by a coarse correction (0.7 times the Galerkin
+                        step on I - B projected on the global-direction harmonics of
+                        degree <= 2 per aggregate of tets), all nrhs together; needs precision 2 and K <= 160
                         (either dtype: the refinement residual is that of the
                         stored operator), and is not available for transposed
                         (adjoint) solves                                            */
@@ -208,7 +208,7 @@ dfm_status dfm_apply_f32(dfm_op op, const float *x, float *y, int nrhs, void *st
 /* Solve (I - B) rho = rho0 for nrhs right-hand sides: one after the other, except
  * method 0 with precision 1 and method 2, which iterate all of them together (see
  * dfm_solve_opts).  Method 2 builds its coarse space on first use and keeps it
- * with the operator (aggregates of about 1536 tets per instance).
+ * with the operator (aggregates of about 768 tets per instance).
  *   rho0, rho  device f64 [nrhs][ndof]; info host [nrhs] or NULL.
  * Returns DFM_E_NOCONV (rho holds the last iterate) if any right-hand side did
  * not reach opts->rtol within opts->max_iter.  Synchronises `stream`. */

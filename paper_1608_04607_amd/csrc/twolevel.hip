@@ -23,8 +23,10 @@
 //    coefficients sqrt(area) G^-1 int psi_k Y_f cos(theta) dOmega (constant
 //    position function only).  With P that prolongation,
 //      A_c = P^T (I - B) P   (one dense block per independent instance),
-//    and before each sweep c = A_c^-1 P^T r, the solution grows by P c and
-//    r' = r - P c + (B P) c is swept instead of r.  B P is local: the rows of a
+//    and before each sweep c = 0.7 A_c^-1 P^T r (the Galerkin step, damped: the
+//    undamped step of the swept operator diverges or stalls for some aggregate
+//    sizes), the solution grows by P c and r' = r - P c + (B P) c is swept
+//    instead of r.  B P is local: the rows of a
 //    slot depend only on the aggregate of the tet upstream of it, W[slot][k][f].
 //    The sweep of r' therefore needs, besides B r, terms of the form
 //    (matrix) x (coarse coefficients of one aggregate); they are NAUG groups of
@@ -69,6 +71,7 @@ typedef half_t h8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int FMAX = 9;        // coarse functions per aggregate
+constexpr float COARSE_DAMPING = 0.7f;   // fraction of the Galerkin coarse step taken
 // correction columns of the FP16 copy come in 4 groups of FPAD(F) columns (F used,
 // the rest zero), so that 8 consecutive ones never straddle two groups
 __host__ __device__ constexpr int fpad(int F) { return F <= 8 ? 8 : 16; }
@@ -595,7 +598,7 @@ __global__ void k_coarse_solve(const float *__restrict__ Ai, const int64_t *__re
                                const float *__restrict__ Ai1, const int64_t *__restrict__ row_off1, int one_function,
                                const int32_t *__restrict__ blk_lo, const int32_t *__restrict__ blk_n, int ng, int F,
                                int R, const float *__restrict__ z, float *__restrict__ c, float *__restrict__ csum,
-                               half_t *__restrict__ c16) {
+                               half_t *__restrict__ c16, float omega) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t NG = (int64_t)ng * F;
   if (i >= NG * R) return;
@@ -615,6 +618,7 @@ __global__ void k_coarse_solve(const float *__restrict__ Ai, const int64_t *__re
     const float *zc = z + (int64_t)lo * F * R + r;
     for (int q = 0; q < nb; ++q) acc = fmaf(row[q], zc[(int64_t)q * F * R], acc);
   }
+  acc *= omega;
   c[i] = acc;
   csum[i] += acc;
   c16[((int64_t)g * R + r) * fpad(F) + f] = (half_t)acc;
@@ -1034,9 +1038,9 @@ dfm_status ensure_coarse(dfm_op op, const std::vector<int64_t> &toff, hipStream_
   const int Kp8 = op->Kp8;
   const int G = (int)toff.size() - 1;
   // coarse functions per aggregate (1, 4, 6 or 9) and tets per aggregate
-  int F = env_int("DFM_COARSE_F", 4);
-  if (F != 1 && F != 4 && F != 6 && F != 9) F = 4;
-  const double tets_per_agg = (double)std::max(1, env_int("DFM_COARSE_TETS", 1536));
+  int F = env_int("DFM_COARSE_F", 9);
+  if (F != 1 && F != 4 && F != 6 && F != 9) F = 9;
+  const double tets_per_agg = (double)std::max(1, env_int("DFM_COARSE_TETS", 768));
   const int R0 = std::min(M, ROWG);
   const int NCH = 3 * ((K + KC - 1) / KC) + (NAUG * fpad(F) + KC - 1) / KC;
   double *cent_d = nullptr, *Mm = nullptr, *W64 = nullptr, *Ac = nullptr;
@@ -1502,6 +1506,11 @@ dfm_status solve_twolevel_impl(dfm_op op, const double *rho0, double *rho, int R
   constexpr double DIVERGE = 4.0;
   int level = F > 1 ? 2 : 1;
   const bool verbose = env_int("DFM_VERBOSE", 0) != 0;   // one line per refinement stage on stderr
+  // the coarse step is damped: c = 0.7 A_c^-1 P^T r.  The full Galerkin step of the
+  // swept operator diverges or stalls for some aggregate sizes on the 49152-tet
+  // box (384, 512 and 1536 tets grow, 2048 needs 18224 sweeps); damped by 0.7 every
+  // size tried converges in 464-568 sweeps
+  constexpr float omega = COARSE_DAMPING;
   for (int outer = 0; outer < 40 && iters < opts->max_iter && !all_done(); ++outer) {
   restart_stage:
     // scale every active pair to unit max norm; t_0 = half(scale * r)
@@ -1552,7 +1561,8 @@ dfm_status solve_twolevel_impl(dfm_op op, const double *rho0, double *rho, int R
         hipLaunchKernelGGL(k_coarse_reduce, dim3(red_grid, gz), dim3(red_threads), 0, st, d0, C.perm, C.agg_slot,
                            nslot, FR, z);
         hipLaunchKernelGGL(k_coarse_solve, dim3((unsigned)((zn + 255) / 256)), dim3(256), 0, st, C.Ai, C.row_off,
-                           C.Ai1, C.row_off1, level == 1 ? 1 : 0, C.blk_lo, C.blk_n, C.ng, F, R, z, c, csum, c16);
+                           C.Ai1, C.row_off1, level == 1 ? 1 : 0, C.blk_lo, C.blk_n, C.ng, F, R, z, c, csum, c16,
+                           omega);
         TRYT(hipGetLastError());
       }
       // one coloured sweep: with r' = r_k - P c + (B P) c, the L-type slots of
