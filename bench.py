@@ -1,26 +1,28 @@
 """Benchmark of the discrete flow mapping hot path on one MI355X.
 
-One step = the whole path on the 3072-tetrahedron box (8x8x8 Kuhn cells, jitter
-0.15h, piecewise-linear position basis x Legendre momentum basis of degree 8,
-12-point Gauss rule per cell, mu = 0.05, walls R = 0.9, Gaussian patch source):
-    mesh build -> assembly of B -> source projection -> solve (I - B) rho = rho0
-to a relative residual of 1e-8 (FP64 GMRES, then FP32 GMRES corrections inside
-FP64 refinement, then the two-level solver's FP16 sweeps inside FP64 refinement).
-Inputs are resident in HBM before the timed region starts.
+Default workload: the batched 49152-tetrahedron box (2 x 1 x 1, 32x16x16 Kuhn
+cells, jitter 0.1h, piecewise-constant position basis x Legendre momentum basis
+of degree 12, 16-point Gauss rule per cell, lognormal damping, walls R = 0.9,
+128 isotropic boundary point sources).  One step is the whole path:
+    mesh build -> FP64 assembly of B -> projection of the 128 sources -> the
+    two-level solve of all 128 right-hand sides to relative residual 1e-8
+(coloured Gauss-Seidel sweeps with a coarse correction, FP16 products on the
+matrix cores, FP64 refinement residuals of the stored operator).  Inputs are
+resident in HBM before the timed region starts.
 
-After the timed steps the same run measures the batched case once: the
-49152-tet box (32x16x16 cells, P0 x Legendre degree 12, 128 point sources):
-assembly, the two-level solve of all 128 right-hand sides to 1e-8, and one plain
-FP64 Neumann solve of one right-hand side for the per-rhs comparison (object
-`batched_box32`; one solve of that case takes about 20 s, so it is not repeated
-per step).
+After the timed steps, on the last step's operator: true FP64 residuals of three
+of its solutions, the batched FP64 product (dfm_residual) for an estimate of plain
+FP64 solving all 128 at once, and one plain FP64 Neumann solve of source 0, the
+per-right-hand-side reference.
 
-Prints ONE JSON line (rank 0).  `value` is B-assembly face-pair blocks per
-second (12 blocks per tet) over the timed steps; the solve time per right-hand
-side is reported beside it.  `roofline` describes the kernel that takes the most
-time per step; `cpu_baseline` is the CPU oracle timed on bounded samples of the
-same workloads on this host (before the GPU is touched): assembly of sampled
-tets, and the oracle's sparse product on a sub-box scaled to the full operator.
+Prints ONE JSON line.  `value` is B-assembly face-pair blocks per second (12 per
+tet) over the timed steps; the solve's ms per right-hand side and its ratio to
+plain FP64 are reported beside it.  `roofline` is the kernel with the most time
+per step: the FP16 product of the sweeps (timed per launch with HIP events on the
+solve's stream, dfm_product_timing) or the assembly; `cpu_baseline` is the CPU
+oracle timed on bounded samples of the same workload on this host, before the GPU
+is touched.  Other workloads: --workload box8 (3072 tets, one right-hand side),
+box32-adjoint, uneven.
 """
 from __future__ import annotations
 
@@ -43,11 +45,12 @@ FP32_PEAK_TFLOPS = 157.3
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--rule", choices=["seam", "paper"], default="seam")
-    ap.add_argument("--workload", choices=["box8", "box32-batched", "box32-adjoint", "uneven"], default="box8",
-                    help="box8: the 3072-tet single-rhs case (default); box32-batched: 49152 tets, 128 sources; "
+    ap.add_argument("--workload", choices=["box8", "box32-batched", "box32-adjoint", "uneven"],
+                    default="box32-batched",
+                    help="box32-batched: 49152 tets, 128 sources (default); box8: the 3072-tet single-rhs case; "
                          "box32-adjoint: receiver-energy gradients on the same box (64 sources); "
                          "uneven: 256 independent boxes of 384-20412 tets, degrees 4-10, 4 sources each")
     ap.add_argument("--instances", type=int, default=256, help="uneven: number of boxes")
@@ -59,7 +62,8 @@ def parse():
     ap.add_argument("--restart", type=int, default=100)
     ap.add_argument("--cpu-tets", type=int, default=24, help="tets in the oracle's timed sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-batched", action="store_true", help="skip the one-off 49152-tet batched measurement")
+    ap.add_argument("--no-fp64-reference", action="store_true",
+                    help="box32-batched: skip the plain FP64 single-rhs reference solve after the steps")
     ap.add_argument("--copy-calib", action="store_true", help="only run a plain device copy of known size")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only one assembly and five products with B (for hardware counters)")
@@ -145,6 +149,8 @@ def oracle_product_ms(sub, K, full_nt, seed=7, min_s=1.0):
 
 COUNTERS = os.path.join(ROOT, "profiles", "counters_box8x8x8_P1_D8_n12.txt")
 COUNTERS_UNEVEN = os.path.join(ROOT, "profiles", "counters_uneven16_D10group.txt")
+COUNTERS_B32 = os.path.join(ROOT, "profiles", "counters_box32x16x16_P0_D12_n16_two_level.txt")
+COUNTERS_B32_ASM = os.path.join(ROOT, "profiles", "counters_box32x16x16_P0_D12_n16_assembly_bytes.txt")
 
 
 def measured_traffic(label, path=COUNTERS, field="bytes"):
@@ -177,37 +183,48 @@ def main():
         print(f"bench.py: runs on one GPU only (--gpus {args.gpus} requested); sharding the assembly "
               "and solve over several GPUs is not implemented.", file=sys.stderr)
         sys.exit(2)
-
+    if args.copy_calib:
+        return copy_calib()
     if args.workload == "box32-batched":
         return main_box32(args)
     if args.workload == "uneven":
         return main_uneven(args)
     if args.workload == "box32-adjoint":
         return main_box32_adjoint(args)
+    return main_box8(args)
 
+
+def copy_calib():
+    """A plain elementwise kernel reading and writing 1 GiB each, for calibrating
+    the HBM byte counters."""
+    import torch
+    x = torch.empty(1 << 27, dtype=torch.float64, device="cuda:0").fill_(1.0)
+    y = torch.empty_like(x)
+    for _ in range(5):
+        torch.mul(x, 2.0, out=y)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": x.numel() * 8, "copy_bytes_written": y.numel() * 8, "launches": 5,
+                      "kernel": "elementwise mul"}))
+
+
+def main_box8(args):
+    """The 3072-tet box (8x8x8 Kuhn cells, jitter 0.15h, P1 x Legendre D = 8, n = 12,
+    mu = 0.05, walls R = 0.9, Gaussian patch source on x = 0).  One step = mesh
+    build -> assembly -> source -> plain FP64 GMRES, FP32 GMRES corrections in FP64
+    refinement, and the two-level solve, each to relative residual 1e-8."""
     import numpy as np
 
     import synth
     prob = synth.problem_c2()
     rule = 1 if args.rule == "seam" else 0
     base = None
-    cpu_b32 = None
-    if not args.no_cpu_baseline and not args.copy_calib and not args.kernels_only:
+    if not args.no_cpu_baseline and not args.kernels_only:
         base = cpu_baseline(prob, rule, args.cpu_tets)
         base["product_ms"], ms_sub, nt_sub = oracle_product_ms(synth.problem_c2(n_cells=4), 135, prob.nt)
         base["product_sample"] = (f"oracle CSR product on the same recipe with 4x4x4 cells ({nt_sub} tets, K = 135, "
                                   f"random blocks) {ms_sub:.1f} ms, one thread, scaled by tets to {prob.nt}")
         print(f"bench: cpu baseline {base['value']:.2f} blocks/s, product {base['product_ms']:.0f} ms",
               file=sys.stderr, flush=True)
-        if not args.no_batched:
-            p3 = synth.problem_c3(nsrc=1)
-            cpu_b32 = cpu_baseline(p3, rule, 8, "49152-tet box")
-            cpu_b32["product_ms"], ms_sub, nt_sub = oracle_product_ms(synth.problem_c3(cells=(8, 4, 4), nsrc=1),
-                                                                      91, p3.nt)
-            cpu_b32["product_sample"] = (f"oracle CSR product on the same recipe with 8x4x4 cells ({nt_sub} tets, "
-                                         f"K = 91, random blocks) {ms_sub:.1f} ms, one thread, scaled by tets to "
-                                         f"{p3.nt}")
-            del p3
 
     import torch
 
@@ -215,17 +232,6 @@ def main():
 
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
-    if args.copy_calib:
-        # plain copy of 1 GiB for calibrating the HBM byte counters
-        x = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
-        y = torch.empty_like(x)
-        for _ in range(5):
-            torch.mul(x, 2.0, out=y)      # one elementwise kernel: reads 1 GiB, writes 1 GiB
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_read": x.numel() * 8, "copy_bytes_written": y.numel() * 8, "launches": 5,
-                          "kernel": "elementwise mul"}))
-        return
-
     verts = torch.tensor(prob.verts, device=dev)
     tets = torch.tensor(prob.tets, device=dev)
     refl = torch.tensor(prob.refl, device=dev)
@@ -380,51 +386,125 @@ def main():
         base["solve_ms_per_rhs"] = base["product_ms"] * info[0]
         base["solve_sample"] = (f"oracle product time x the {info[0]} operator applications of the plain FP64 "
                                 "GMRES solve of this run")
-    if not args.no_batched:
-        print("bench: one batched 49152-tet measurement", file=sys.stderr, flush=True)
-        b32 = batched_box32_once(args, dfm, torch, stream)
-        if cpu_b32 is not None:
-            cpu_b32["solve_ms_per_rhs"] = cpu_b32["product_ms"] * b32["fp64_products"]
-            cpu_b32["solve_sample"] = (f"oracle product time x the {b32['fp64_products']} products of the plain "
-                                       "FP64 Neumann solve of this run")
-            base["batched_box32"] = cpu_b32
-        out["batched_box32"] = b32
     print(json.dumps(out))
 
 
-def batched_box32_once(args, dfm, torch, stream, prob=None):
-    """One measurement of the batched case on the 49152-tet box: mesh build,
-    assembly, 128 point sources, the two-level solve of all 128 to 1e-8, true FP64
-    residuals of three of them, and one plain FP64 Neumann solve of source 0 (the
-    per-rhs reference, same operator)."""
+def main_box32(args):
+    """The batched 49152-tet box (the default workload; see the module docstring).
+    One step = mesh build -> FP64 assembly -> 128 point sources -> two-level solve
+    of all 128 to relative residual 1e-8.  The per-rhs reference (one plain FP64
+    Neumann solve), the batched FP64 product and true residuals are measured once,
+    after the timed steps, on the last step's operator."""
+    import numpy as np
+
     import synth
-    if prob is None:
-        prob = synth.problem_c3(nsrc=128)
-    dev = torch.device("cuda:0")
-    T = lambda a: torch.tensor(a, device=dev)  # noqa: E731
+    prob = synth.problem_c3(nsrc=128)
     rule = 1 if args.rule == "seam" else 0
+    base = None
+    if not args.no_cpu_baseline and not args.kernels_only:
+        base = cpu_baseline(prob, rule, min(args.cpu_tets, 8), "49152-tet box")
+        base["product_ms"], ms_sub, nt_sub = oracle_product_ms(synth.problem_c3(cells=(8, 4, 4), nsrc=1), 91, prob.nt)
+        base["product_sample"] = (f"oracle CSR product on the same recipe with 8x4x4 cells ({nt_sub} tets, K = 91, "
+                                  f"random blocks) {ms_sub:.1f} ms, one thread, scaled by tets to {prob.nt}")
+        print(f"bench: cpu baseline {base['value']:.2f} blocks/s, product {base['product_ms']:.0f} ms",
+              file=sys.stderr, flush=True)
+
+    import torch
+
+    from paper_1608_04607_amd import dfm
+
+    os.environ.setdefault("DFM_VERBOSE", "1")      # one stderr line per refinement stage
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    T = lambda a: torch.tensor(a, device=dev)  # noqa: E731
     verts, tets, refl, mu, xyz = T(prob.verts), T(prob.tets), T(prob.refl), T(prob.mu), T(prob.source["xyz"])
-    R = xyz.shape[0]
+    R = int(xyz.shape[0])
+    if args.kernels_only:
+        mesh = dfm.Mesh(verts, tets, refl=refl)
+        op = dfm.Operator(mesh, mu, prob.pos_order, dfm.LEGENDRE, prob.mom_degree, prob.quad_n, rule=rule)
+        rho0 = op.source_points(xyz)
+        op.solve(rho0, method="twolevel", rtol=1e-8, max_iter=int(os.environ.get("BENCH_PRODUCTS", "40")),
+                 raise_nonconv=False)
+        torch.cuda.synchronize()
+        print(json.dumps({"kernels_only": True, "workload": "box32", "nodes": op.nodes, "K": op.K, "ndof": op.ndof,
+                          "B_bytes": op.nbytes, "nrhs": R}))
+        return
     torch.cuda.synchronize()
-    e = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
-    e[0].record(stream)
-    mesh = dfm.Mesh(verts, tets, refl=refl)
-    e[1].record(stream)
-    op = dfm.Operator(mesh, mu, prob.pos_order, dfm.LEGENDRE, prob.mom_degree, prob.quad_n, rule=rule)
-    e[2].record(stream)
-    rho0 = op.source_points(xyz)
-    e[3].record(stream)
-    rho, info = op.solve(rho0, method="twolevel", rtol=1e-8, max_iter=20000)
-    e[4].record(stream)
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    def step(record, keep=False):
+        e = [ev() for _ in range(5)]
+        e[0].record(stream)
+        mesh = dfm.Mesh(verts, tets, refl=refl)
+        e[1].record(stream)
+        op = dfm.Operator(mesh, mu, prob.pos_order, dfm.LEGENDRE, prob.mom_degree, prob.quad_n, rule=rule)
+        e[2].record(stream)
+        rho0 = op.source_points(xyz)
+        e[3].record(stream)
+        op.product_timing(1)
+        rho, info = op.solve(rho0, method="twolevel", rtol=1e-8, max_iter=20000)
+        e[4].record(stream)
+        timing = op.product_timing(0)
+        if record is not None:
+            record.append((e, info, timing))
+        print(f"bench: step done, {info[0][0]} products, worst relres {max(i[2] for i in info):.2e}",
+              file=sys.stderr, flush=True)
+        if keep:
+            return mesh, op, rho0, rho, info
+        del rho, rho0
+        op.close()
+        mesh.close()
+        return None
+
+    for _ in range(args.warmup):
+        step(None)
     torch.cuda.synchronize()
+    recs = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        kept = step(recs, keep=i == args.steps - 1)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    mesh, op, rho0, rho, info = kept
+
+    phase = np.array([[r[0][i].elapsed_time(r[0][i + 1]) for i in range(4)] for r in recs])  # ms
+    t_mesh, t_asm, t_src, t_solve = phase.mean(axis=0)
+    blocks, K, nodes, ndof = op.nblocks, op.K, op.nodes, op.ndof
+    prod_ms = sum(r[2][0] for r in recs)
+    prod_launches = sum(r[2][1] for r in recs)
+    prod_bytes = sum(r[2][2] for r in recs)
+    launch_ms = prod_ms / prod_launches
+    spmm_gbs = prod_bytes / (prod_ms / 1e3) / 1e9
+    flops_asm = 2.0 * nodes * K * K
+    asm_tf = flops_asm / (t_asm / 1e3) / 1e12
+    roof_spmm = {"kernel": "k_spmm16", "bound": "hbm", "achieved": spmm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                 "frac": spmm_gbs / HBM_PEAK_GBS, "traffic": measured_traffic("k_spmm16", COUNTERS_B32),
+                 "avg_launch_ms": launch_ms, "launches": prod_launches,
+                 "algorithmic_bytes_per_launch": prod_bytes / prod_launches,
+                 "algorithmic": "per tet of a launch (one colour): 4 block rows x (3 ceil(K/32) slot chunks + "
+                                "3 correction chunks) x K x 32 x 2 B of FP16 B, 4 x nrhs x Kp8 x 2 B of x read, "
+                                "as much of y written, 4 x F x nrhs x 4 B of coarse projections (K = 91, Kp8 = 96, "
+                                "F = 9, nrhs = 128)",
+                 "timed": "every product launch of the timed steps' solves, HIP events on the solve's stream"}
+    roof_asm = {"kernel": "k_assemble", "bound": "mfma", "achieved": asm_tf, "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": asm_tf / FP64_PEAK_TFLOPS,
+                "traffic": measured_traffic("k_assemble", COUNTERS_B32_ASM),
+                "algorithmic": f"2*Q*K^2 flop per launch, Q = {nodes} directions summed over blocks, K = {K}",
+                "timed": "the assembly phase of each timed step (HIP events)"}
+    t_spmm_step = prod_ms / len(recs)
+    dominant, other = (roof_spmm, roof_asm) if t_spmm_step >= t_asm else (roof_asm, roof_spmm)
+
+    # true FP64 residuals of three of the last step's solutions
     worst = 0.0
     for r in (0, R // 2, R - 1):
         res = rho0[r] - (rho[r] - op.apply(rho[r]))
         worst = max(worst, float((res.norm() / rho0[r].norm()).item()))
-    # the batched FP64 product the library has (the refinement residual: B streamed
-    # once per 8 right-hand sides, FP64 accumulation), timed on all R
+    # the batched FP64 product (dfm_residual: B streamed once per 8 right-hand
+    # sides, FP64 accumulation) over all R
     op.residual(rho0, rho)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0, e1 = ev(), ev()
     e0.record(stream)
     for _ in range(2):
         res = op.residual(rho0, rho)
@@ -432,100 +512,9 @@ def batched_box32_once(args, dfm, torch, stream, prob=None):
     torch.cuda.synchronize()
     t_res = e0.elapsed_time(e1) / 2
     del res
-    print("bench: plain FP64 single-rhs Neumann reference on the 49152-tet box", file=sys.stderr, flush=True)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    rho64, info64 = op.solve(rho0[0], method="neumann", rtol=1e-8, max_iter=40000)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    t64 = e0.elapsed_time(e1)
-    diff = float(((rho[0] - rho64).norm() / rho64.norm()).item())
-    t_mesh, t_asm, t_src, t_solve = (e[i].elapsed_time(e[i + 1]) for i in range(4))
-    out = {
-        "workload": "box32x16x16-kuhn-49152tets-jitter0.1_P0xLegendreD12_n16_"
-                    f"{args.rule}-rule_mu-lognormal(ln0.02,0.5)_R0.9_128-point-sources_batched-1e-8",
-        "measured": "once, after the timed steps",
-        "tets": int(prob.nt), "blocks": int(op.nblocks), "K": int(op.K), "ndof": int(op.ndof), "nrhs": int(R),
-        "quadrature_directions": int(op.nodes),
-        "ms_mesh_build": t_mesh, "ms_assemble": t_asm, "assemble_blocks_per_s": op.nblocks / (t_asm / 1e3),
-        "ms_sources": t_src,
-        "solve_ms": t_solve, "solve_ms_per_rhs": t_solve / R,
-        "solve_method": "two-level: coloured Gauss-Seidel sweeps with a coarse correction, FP16 products on the "
-                        "matrix cores, FP64 refinement residuals",
-        "solve_products": int(info[0][0]), "solve_relres_worst": max(i[2] for i in info),
-        "solve_true_relres_sampled": worst,
-        "fp64_ms_per_rhs": t64, "fp64_method": "plain FP64 Neumann, one rhs", "fp64_products": int(info64[0][0]),
-        "fp64_relres": info64[0][2],
-        "speedup_per_rhs_vs_fp64": t64 / (t_solve / R),
-        "rel_diff_vs_fp64_rhs0": diff,
-        "fp64_batched_product_ms": t_res,
-        "fp64_batched_ms_per_rhs_est": t_res * int(info64[0][0]) / R,
-        "fp64_batched_note": "plain FP64 Neumann over all R at once, estimated as the measured FP64 batched "
-                             "product of all R (dfm_residual: B streamed once per 8 rhs, plus the vector update) "
-                             "x the plain solve's products / R; splits the gain into batching "
-                             "(fp64_ms_per_rhs / this) and method + precision (this / solve_ms_per_rhs)",
-    }
-    del rho, rho64
-    op.close()
-    mesh.close()
-    return out
-
-
-def main_box32(args):
-    """49152-tet box (32x16x16 cells), P0 x Legendre D=12, n=16, lognormal mu, 128
-    isotropic boundary point sources.  One step = mesh build -> assembly -> 128
-    sources -> two-level solve of all 128 (coloured sweeps with a coarse
-    correction, FP16 products on the matrix cores, FP64 refinement) to relative
-    residual 1e-8.  After the steps, one plain FP64 single-rhs Neumann solve of the
-    first source is the per-rhs reference.  `value` is assembly blocks/s."""
-    import numpy as np
-
-    import synth
-    prob = synth.problem_c3(nsrc=128)
-    base = None
-    rule = 1 if args.rule == "seam" else 0
-    if not args.no_cpu_baseline:
-        base = cpu_baseline(prob, rule, min(args.cpu_tets, 8), "49152-tet box")
-        base["product_ms"], ms_sub, nt_sub = oracle_product_ms(synth.problem_c3(cells=(8, 4, 4), nsrc=1), 91, prob.nt)
-        base["product_sample"] = (f"oracle CSR product on the same recipe with 8x4x4 cells ({nt_sub} tets, K = 91, "
-                                  f"random blocks) {ms_sub:.1f} ms, one thread, scaled by tets to {prob.nt}")
-        print(f"bench: cpu baseline {base['value']:.2f} blocks/s", file=sys.stderr, flush=True)
-
-    import torch
-
-    from paper_1608_04607_amd import dfm
-
-    os.environ.setdefault("DFM_VERBOSE", "1")      # one stderr line per refinement stage
-    stream = torch.cuda.current_stream()
-    if args.kernels_only:
-        dev = torch.device("cuda:0")
-        T = lambda a: torch.tensor(a, device=dev)  # noqa: E731
-        mesh = dfm.Mesh(T(prob.verts), T(prob.tets), refl=T(prob.refl))
-        op = dfm.Operator(mesh, T(prob.mu), prob.pos_order, dfm.LEGENDRE, prob.mom_degree, prob.quad_n, rule=rule)
-        rho0 = op.source_points(T(prob.source["xyz"]))
-        op.solve(rho0, method="twolevel", rtol=1e-8, max_iter=int(os.environ.get("BENCH_PRODUCTS", "40")),
-                 raise_nonconv=False)
-        torch.cuda.synchronize()
-        print(json.dumps({"kernels_only": True, "workload": "box32", "nodes": op.nodes, "K": op.K, "ndof": op.ndof,
-                          "B_bytes": op.nbytes, "nrhs": int(rho0.shape[0])}))
-        return
-    for _ in range(args.warmup):
-        batched_box32_once(args, dfm, torch, stream, prob)
-    torch.cuda.synchronize()
-    recs = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        recs.append(batched_box32_once(args, dfm, torch, stream, prob))
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    last = recs[-1]
-    t_asm = np.mean([r["ms_assemble"] for r in recs])
-    t_solve = np.mean([r["solve_ms"] for r in recs])
-    flops_asm = 2.0 * last["quadrature_directions"] * last["K"] ** 2
-    asm_tf = flops_asm / (t_asm / 1e3) / 1e12
     out = {
         "metric": METRIC,
-        "value": last["blocks"] / (t_asm / 1e3),
+        "value": blocks / (t_asm / 1e3),
         "unit": "blocks/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -534,19 +523,55 @@ def main_box32(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64 assembly; f16 batched sweeps, f64 residuals",
+        "dtype": "f64 assembly; f16 products with f32 accumulation in the solve, f64 residuals",
         "data": "synthetic",
-        "config": {"workload": last["workload"], "tets": last["tets"], "blocks": last["blocks"], "K": last["K"],
-                   "ndof": last["ndof"], "nrhs": last["nrhs"], "quadrature_directions": last["quadrature_directions"]},
-        "solve_ms_per_rhs": t_solve / last["nrhs"],
-        "steps_detail": recs,
-        "roofline": {"kernel": "k_assemble", "bound": "mfma", "achieved": asm_tf, "peak": FP64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": asm_tf / FP64_PEAK_TFLOPS, "traffic": None,
-                     "algorithmic": f"2*Q*K^2 flop per launch, Q = {last['quadrature_directions']}, K = {last['K']}"},
+        "config": {"workload": "box32x16x16-kuhn-49152tets-jitter0.1_P0xLegendreD12_n16_"
+                               f"{args.rule}-rule_mu-lognormal(ln0.02,0.5)_R0.9_128-point-sources_batched-1e-8",
+                   "tets": int(prob.nt), "blocks": int(blocks), "K": int(K), "ndof": int(ndof), "nrhs": R,
+                   "quadrature_directions": int(nodes)},
+        "phase_ms": {"mesh_build": t_mesh, "assemble": t_asm, "sources": t_src, "solve_128rhs": t_solve},
+        "step_ms_per_rhs": wall * 1e3 / args.steps / R,
+        "solve_ms_per_rhs": t_solve / R,
+        "solve_method": "two-level: coloured Gauss-Seidel sweeps with a coarse correction, FP16 products on the "
+                        "matrix cores, FP64 refinement residuals",
+        "solve_products": int(info[0][0]),
+        "solve_relres_worst": max(i[2] for i in info),
+        "solve_true_relres_sampled": worst,
+        "product_ms_per_step": t_spmm_step,
+        "fp64_batched_product_ms": t_res,
+        "roofline": dominant,
+        "roofline_other": other,
         "cpu_baseline": base,
     }
-    if base is not None:
-        base["solve_ms_per_rhs"] = base["product_ms"] * last["fp64_products"]
+    if not args.no_fp64_reference:
+        print("bench: plain FP64 single-rhs Neumann reference", file=sys.stderr, flush=True)
+        e0, e1 = ev(), ev()
+        e0.record(stream)
+        rho64, info64 = op.solve(rho0[0], method="neumann", rtol=1e-8, max_iter=40000)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t64 = e0.elapsed_time(e1)
+        n64 = int(info64[0][0])
+        out.update({
+            "fp64_ms_per_rhs": t64, "fp64_method": "plain FP64 Neumann, one rhs", "fp64_products": n64,
+            "fp64_relres": info64[0][2],
+            "speedup_per_rhs_vs_fp64": t64 / (t_solve / R),
+            "rel_diff_vs_fp64_rhs0": float(((rho[0] - rho64).norm() / rho64.norm()).item()),
+            "fp64_batched_ms_per_rhs_est": t_res * n64 / R,
+            "speedup_per_rhs_vs_fp64_batched_est": t_res * n64 / t_solve,
+            "fp64_batched_note": "plain FP64 Neumann over all 128 at once, estimated as the measured batched FP64 "
+                                 "product (dfm_residual) x the plain solve's products / 128: "
+                                 "fp64_ms_per_rhs / this is the gain of batching alone, this / solve_ms_per_rhs "
+                                 "that of the method and precision",
+        })
+        if base is not None:
+            base["solve_ms_per_rhs"] = base["product_ms"] * n64
+            base["solve_sample"] = (f"oracle product time x the {n64} products of the plain FP64 Neumann solve of "
+                                    "this run")
+        del rho64
+    del rho, rho0
+    op.close()
+    mesh.close()
     print(json.dumps(out))
 
 

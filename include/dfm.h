@@ -205,6 +205,37 @@ dfm_status dfm_apply(dfm_op op, const double *x, double *y, int nrhs, int transp
  * Errors: DFM_E_INVALID, DFM_E_NOMEM (the FP32 copy). */
 dfm_status dfm_apply_f32(dfm_op op, const float *x, float *y, int nrhs, void *stream);
 
+/* y = B16 x for nrhs right-hand sides on the FP16 matrix cores, with B16 the FP16
+ * copy of B (Sec. 2, Eq. GovIE) that method 2 sweeps with: the same product kernel,
+ * over every tet in one launch, without the coarse columns or the colour order.
+ * The first call makes B16 (with the coarse space of the whole operator, kept with
+ * the operator) and synchronises `stream`; later calls do not.
+ *   x, y  device f16 [4 nt][nrhs][Kp8], Kp8 = K rounded up to a multiple of 8:
+ *         entry (s, r, k) is unknown k of slot s (dof s K + k of the f64 layout) for
+ *         right-hand side r.  Entries k >= K of x must be finite (they meet zero
+ *         columns); those of y are written 0.  x and y do not alias.
+ * FP32 accumulation, y rounded to FP16; each block row of B16 is read once per 128
+ * right-hand sides.
+ * Errors: DFM_E_INVALID (nrhs outside 1..1048560, aliasing), DFM_E_UNSUPPORTED
+ * (K > 160), DFM_E_NOMEM. */
+dfm_status dfm_apply_f16(dfm_op op, const void *x, void *y, int nrhs, void *stream);
+
+/* Event timing of the FP16 product launches inside method-2 solves on op (the
+ * kernel that takes most of their time), for measurement.  Each call first returns
+ * the totals since timing was last started (host outputs, each may be NULL; zeros
+ * when timing is off): ms = the summed durations of the launches, each taken
+ * between two HIP events recorded on the solve's stream around it; launches;
+ * bytes = their algorithmic HBM bytes, per tet of a launch: its 4 block rows of
+ * B16, (3 ceil(K/32) + c) chunks of K x 32 halves each, where c = ceil(5 P/32) while
+ * the coarse correction is on (P = 16 for the 9 harmonics of degree <= 2, 8 for
+ * fewer) and 0 after a fallback without it; 4 nrhs Kp8 2 B of x read, as much of
+ * y written, and 4 F nrhs 4 B of coarse projections written (F harmonics).  It then applies `enable`: 1 zeroes the totals and starts
+ * timing, 0 stops it, -1 changes nothing.  A solve adds its launches when it
+ * returns (after synchronising its stream); a solve that fails adds none.  In
+ * dfm_solve_groups the bytes count every tet of a launch as multiplied.
+ * Errors: DFM_E_INVALID. */
+dfm_status dfm_product_timing(dfm_op op, int enable, double *ms, int64_t *launches, double *bytes);
+
 /* Solve (I - B) rho = rho0 for nrhs right-hand sides: one after the other, except
  * method 0 with precision 1 and method 2, which iterate all of them together (see
  * dfm_solve_opts).  Method 2 builds its coarse space on first use and keeps it

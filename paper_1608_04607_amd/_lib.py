@@ -61,6 +61,8 @@ _PROTOS = [
     ("dfm_receiver_energy", C.c_int, [_P, _P, C.POINTER(C.c_double), _P, C.c_int, _P, _P]),
     ("dfm_weighted_sum", C.c_int, [_P, _I64, C.c_int, _P, _P, _P]),
     ("dfm_residual", C.c_int, [_P, _P, _P, _P, C.c_int, _P]),
+    ("dfm_apply_f16", C.c_int, [_P, _P, _P, C.c_int, _P]),
+    ("dfm_product_timing", C.c_int, [_P, C.c_int, _P, _P, _P]),
     ("dfm_last_error", C.c_char_p, []),
 ]
 

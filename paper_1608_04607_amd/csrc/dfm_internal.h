@@ -53,6 +53,7 @@ enum : unsigned {
 };
 
 struct Coarse;
+struct ProdTiming;
 void free_twolevel(dfm_op op);
 
 }  // namespace dfm
@@ -84,4 +85,5 @@ struct dfm_op_s {
   void *B16 = nullptr;        // FP16 copy with the coarse-correction columns (two-level solver)
   int Kp8 = 8;                // K rounded up to a multiple of 8
   dfm::Coarse *coarse = nullptr;  // aggregation coarse space of the two-level solver
+  dfm::ProdTiming *ptiming = nullptr;  // event timing of the two-level product launches, when on
 };

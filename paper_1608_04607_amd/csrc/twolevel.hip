@@ -398,7 +398,7 @@ __global__ __launch_bounds__(256, 1) void k_spmm16(P16Args a) {
   const int m0 = blockIdx.z * ROWG;
   const int K = a.K, Kp8 = a.Kp8, F = a.F, R = a.R;
   const int64_t dslot = a.dest[br];
-  const bool dl = a.lmask[dslot] != 0;
+  const bool dl = a.lmask != nullptr && a.lmask[dslot] != 0;
   const int64_t ldr = (int64_t)R * Kp8;
   const int nrows = min(ROWG, Kp8 - m0);
   const int col = lane & 15, kq = lane >> 4;
@@ -950,7 +950,9 @@ struct Coarse {
   std::vector<int64_t> col_off;
   int32_t *tlist = nullptr;
   uint8_t *lmask = nullptr;      // [4 nt] slot whose writer has a lower colour than its tet
+  half_t *zero16 = nullptr;      // 8 zero halves (read in place of absent columns)
   void release() {
+    (void)hipFree(zero16);
     (void)hipFree(tlist);
     (void)hipFree(lmask);
     (void)hipFree(row_off1);
@@ -968,8 +970,53 @@ struct Coarse {
   }
 };
 
+// Event timing of the product launches of method-2 solves (dfm_product_timing).
+// Two events per launch from a pool kept with the operator; a solve records them
+// as it goes (pending), and adds their durations to the totals once it has
+// synchronised its stream at the end.
+struct ProdTiming {
+  std::vector<hipEvent_t> ev;
+  std::vector<double> pending_bytes;   // algorithmic bytes of each launch recorded in this solve
+  double ms = 0.0, bytes = 0.0;
+  int64_t launches = 0;
+  hipError_t begin(hipStream_t st) {
+    const size_t i = 2 * pending_bytes.size();
+    while (ev.size() < i + 2) {
+      hipEvent_t e;
+      hipError_t er = hipEventCreate(&e);
+      if (er != hipSuccess) return er;
+      ev.push_back(e);
+    }
+    return hipEventRecord(ev[i], st);
+  }
+  hipError_t end(hipStream_t st, double b) {
+    pending_bytes.push_back(b);
+    return hipEventRecord(ev[2 * pending_bytes.size() - 1], st);
+  }
+  // after the stream has synchronised
+  void harvest() {
+    for (size_t q = 0; q < pending_bytes.size(); ++q) {
+      float t = 0.0f;
+      if (hipEventElapsedTime(&t, ev[2 * q], ev[2 * q + 1]) != hipSuccess) continue;
+      ms += t;
+      bytes += pending_bytes[q];
+      ++launches;
+    }
+    pending_bytes.clear();
+  }
+  void release() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    ev.clear();
+  }
+};
+
 void free_twolevel(dfm_op op) {
   if (!op) return;
+  if (op->ptiming) {
+    op->ptiming->release();
+    delete op->ptiming;
+    op->ptiming = nullptr;
+  }
   if (op->coarse) {
     op->coarse->release();
     delete op->coarse;
@@ -1169,6 +1216,8 @@ dfm_status ensure_coarse(dfm_op op, const std::vector<int64_t> &toff, hipStream_
     for (int64_t t = 0; t < nt; ++t) tl[pos[color[t]]++] = (int32_t)t;
     std::vector<uint8_t> lm(nslot, 0);
     for (int64_t sl = 0; sl < nslot; ++sl) lm[sl] = (nb[sl] >= 0 && color[nb[sl]] < color[sl >> 2]) ? 1 : 0;
+    TRYC(hipMalloc(&C.zero16, 64));
+    TRYC(hipMemsetAsync(C.zero16, 0, 64, st));
     TRYC(hipMalloc(&C.tlist, sizeof(int32_t) * nt));
     TRYC(hipMalloc(&C.lmask, sizeof(uint8_t) * nslot));
     TRYC(hipMemcpyAsync(C.tlist, tl.data(), sizeof(int32_t) * nt, hipMemcpyHostToDevice, st));
@@ -1302,11 +1351,22 @@ hipError_t launch_product16(dfm_op op, half_t *t, half_t *y, float *d0, int R, c
   // 16 CT right-hand sides, row group of 96): the tile follows R, so that a few
   // right-hand sides do not pay for the matrix-core work of 128
   const int CT = R <= 16 ? 1 : (R <= 32 ? 2 : (R <= 64 ? 4 : 8));
+  ProdTiming *tm = op->ptiming;
+  // algorithmic bytes per tet: its 4 block rows of B16 (slot chunks, and the
+  // correction chunks when c is given), x of its 4 inbound slots and y of its 4
+  // destinations once each, and d0 of its destinations
+  const int nsub = (op->K + KC - 1) / KC, naug = (NAUG * fpad(C.F) + KC - 1) / KC;
+  const double tet_bytes = 4.0 * (3 * nsub + (c ? naug : 0)) * op->K * KC * sizeof(half_t) +
+                           2.0 * 4.0 * R * op->Kp8 * sizeof(half_t) + (d0 ? 4.0 * C.F * R * sizeof(float) : 0.0);
   for (int q = 0; q < C.ncol; ++q) {
     const int64_t cnt = C.col_off[q + 1] - C.col_off[q];
     if (cnt == 0) continue;
     a.tlist = C.tlist + C.col_off[q];
     const dim3 grid((unsigned)cnt, (unsigned)((R + 16 * CT - 1) / (16 * CT)), (unsigned)((op->Kp8 + ROWG - 1) / ROWG));
+    if (tm) {
+      hipError_t e = tm->begin(st);
+      if (e != hipSuccess) return e;
+    }
     switch (CT) {
       case 1: hipLaunchKernelGGL((k_spmm16<2, 1>), grid, dim3(256), 0, st, a); break;
       case 2: hipLaunchKernelGGL((k_spmm16<2, 2>), grid, dim3(256), 0, st, a); break;
@@ -1315,10 +1375,87 @@ hipError_t launch_product16(dfm_op op, half_t *t, half_t *y, float *d0, int R, c
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (tm) {
+      e = tm->end(st, tet_bytes * (double)cnt);
+      if (e != hipSuccess) return e;
+    }
   }
   return hipSuccess;
 }
+// y = B16 x (slot columns only: no correction, no colour order), one launch over
+// every tet
+hipError_t launch_plain16(dfm_op op, const half_t *x, half_t *y, int R, hipStream_t st) {
+  const Coarse &C = *op->coarse;
+  P16Args a{};
+  a.B16 = reinterpret_cast<const half_t *>(op->B16);
+  a.dest = op->dest;
+  a.nt = op->nt;
+  a.K = op->K;
+  a.Kp8 = op->Kp8;
+  a.R = R;
+  a.F = C.F;
+  a.NCH = C.NCH;
+  a.R0 = C.R0;
+  a.t = x;
+  a.y = y;
+  a.Pv = C.Pv;
+  a.agg_slot = C.agg_slot;
+  a.agg_up = C.agg_up;
+  a.zero16 = C.zero16;
+  a.tlist = C.tlist;
+  const int CT = R <= 16 ? 1 : (R <= 32 ? 2 : (R <= 64 ? 4 : 8));
+  const dim3 grid((unsigned)op->nt, (unsigned)((R + 16 * CT - 1) / (16 * CT)), (unsigned)((op->Kp8 + ROWG - 1) / ROWG));
+  switch (CT) {
+    case 1: hipLaunchKernelGGL((k_spmm16<2, 1>), grid, dim3(256), 0, st, a); break;
+    case 2: hipLaunchKernelGGL((k_spmm16<2, 2>), grid, dim3(256), 0, st, a); break;
+    case 4: hipLaunchKernelGGL((k_spmm16<2, 4>), grid, dim3(256), 0, st, a); break;
+    default: hipLaunchKernelGGL((k_spmm16<2, 8>), grid, dim3(256), 0, st, a); break;
+  }
+  return hipGetLastError();
+}
 }  // namespace
+
+}  // namespace dfm
+
+extern "C" dfm_status dfm_apply_f16(dfm_op op, const void *x, void *y, int nrhs, void *stream) {
+  DFM_REQUIRE(op && x && y, DFM_E_INVALID, "null argument");
+  DFM_REQUIRE(nrhs >= 1 && nrhs <= 65535 * 16, DFM_E_INVALID, "nrhs must be in 1..1048560");
+  DFM_REQUIRE(x != y, DFM_E_INVALID, "x and y must not alias");
+  DFM_REQUIRE((op->K + 7) / 8 * 8 <= dfm::KP8MAX, DFM_E_UNSUPPORTED, "the FP16 product supports K <= 160");
+  hipStream_t st = (hipStream_t)stream;
+  {
+    // the FP16 copy of B is made with the coarse space of the whole operator
+    const std::vector<int64_t> whole{0, op->nt};
+    if (!op->coarse || !op->B16) {
+      dfm_status cs = dfm::ensure_coarse(op, whole, st);
+      if (cs != DFM_OK) return cs;
+    }
+  }
+  DFM_HIP(dfm::launch_plain16(op, static_cast<const dfm::half_t *>(x), static_cast<dfm::half_t *>(y), nrhs, st));
+  return DFM_OK;
+}
+
+extern "C" dfm_status dfm_product_timing(dfm_op op, int enable, double *ms, int64_t *launches, double *bytes) {
+  DFM_REQUIRE(op, DFM_E_INVALID, "null operator");
+  DFM_REQUIRE(enable >= -1 && enable <= 1, DFM_E_INVALID, "enable must be -1, 0 or 1");
+  const dfm::ProdTiming *t = op->ptiming;
+  if (ms) *ms = t ? t->ms : 0.0;
+  if (launches) *launches = t ? t->launches : 0;
+  if (bytes) *bytes = t ? t->bytes : 0.0;
+  if (enable == 1) {
+    if (!op->ptiming) op->ptiming = new dfm::ProdTiming();
+    op->ptiming->ms = op->ptiming->bytes = 0.0;
+    op->ptiming->launches = 0;
+    op->ptiming->pending_bytes.clear();
+  } else if (enable == 0 && op->ptiming) {
+    op->ptiming->release();
+    delete op->ptiming;
+    op->ptiming = nullptr;
+  }
+  return DFM_OK;
+}
+
+namespace dfm {
 
 // ---------------------------------------------------------------------------
 // The two-level solve inside FP64 refinement (method 2), R right-hand sides on
@@ -1383,6 +1520,7 @@ dfm_status solve_twolevel_impl(dfm_op op, const double *rho0, double *rho, int R
       return cs;
     }
   }
+  if (op->ptiming) op->ptiming->pending_bytes.clear();   // launches of an earlier solve that failed
   const Coarse &C = *op->coarse;
   const int Kp8 = op->Kp8, K = op->K, F = C.F;
   const int64_t vlen = nslot * R * Kp8;               // elements of one slot-major vector
@@ -1621,6 +1759,11 @@ dfm_status solve_twolevel_impl(dfm_op op, const double *rho0, double *rho, int R
   }
 #undef TRYT
   cleanup();
+  if (op->ptiming) {
+    // every event of this solve is behind the stream synchronisation of its last residual norms
+    if (hipStreamSynchronize(st) == hipSuccess) op->ptiming->harvest();
+    else op->ptiming->pending_bytes.clear();
+  }
   dfm_status status = DFM_OK;
   for (int g = 0; g < G; ++g)
     for (int r = 0; r < R; ++r) {

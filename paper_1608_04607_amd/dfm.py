@@ -132,6 +132,23 @@ class Operator:
         check(_lib.load().dfm_apply_f32(self.handle, _ptr(x), _ptr(y), nrhs, _stream(stream)))
         return y
 
+    def apply_f16(self, x, stream=None):
+        """y = B16 x for a slot-major FP16 block x [4 nt][nrhs][Kp8] (dfm_apply_f16)."""
+        x = _dev(x, torch.float16)
+        if x.dim() != 3 or x.shape[0] != 4 * self.mesh.nt or x.shape[2] != (self.K + 7) // 8 * 8:
+            raise ValueError("x must be [4 nt][nrhs][Kp8]")
+        y = torch.empty_like(x)
+        check(_lib.load().dfm_apply_f16(self.handle, _ptr(x), _ptr(y), x.shape[1], _stream(stream)))
+        return y
+
+    def product_timing(self, enable=-1):
+        """Totals (ms, launches, bytes) of the timed FP16 product launches of method-2
+        solves since timing was started, then enable: 1 restart, 0 stop, -1 keep
+        (dfm_product_timing)."""
+        ms, n, b = C.c_double(), C.c_int64(), C.c_double()
+        check(_lib.load().dfm_product_timing(self.handle, int(enable), C.byref(ms), C.byref(n), C.byref(b)))
+        return ms.value, n.value, b.value
+
     def solve(self, rho0, method="gmres", rtol=1e-8, restart=50, max_iter=20000, precision=0, stream=None,
               raise_nonconv=True, rho=None):
         """Solve (I - B) rho = rho0 with method "neumann", "gmres" or "twolevel" (the

@@ -368,6 +368,27 @@ def test_full_size_box32_sampled():
             say(f"    FP32 matrix-core product, 128 rhs: rel err {err:.3e} on {len(got)} block rows")
             assert err < 1e-5
             del x, y
+            # the FP16 product the two-level sweeps run on, 128 right-hand sides
+            Kp8 = (K + 7) // 8 * 8
+            x16 = (torch.rand(4 * p.nt, 128, Kp8, generator=gen, device=DEV, dtype=torch.float32) - 0.5).half()
+            x16[:, :, K:] = 0
+            y16 = op.apply_f16(x16)
+            worst = 0.0
+            for a, j in enumerate(sample):
+                for lo in range(4):
+                    q = int(desto[a, lo])
+                    ins = [l for l in range(4) if l != lo]
+                    xs = [x16[4 * j + li, :, :K].double().cpu().numpy() for li in ins]
+                    ref = sum(xs[s] @ Bo[a, lo, s].T for s in range(3))
+                    aax = sum(np.abs(xs[s]) @ np.abs(Bo[a, lo, s]).T for s in range(3))
+                    nzx = sum(np.abs(xs[s]) @ (Bo[a, lo, s] != 0).T.astype(np.float64) for s in range(3))
+                    got16 = y16[q, :, :K].double().cpu().numpy()
+                    bound = fp16_bound(aax, nzx, ref, 3 * ((K + 31) // 32 * 32))
+                    worst = max(worst, float((np.abs(got16 - ref) / bound).max()))
+                    assert not y16[q, :, K:].any()
+            say(f"    FP16 product, 128 rhs: worst |err| / bound {worst:.3f} on 16 block rows")
+            assert worst <= 1.0
+            del x16, y16
         op.close()
 
 
@@ -487,6 +508,61 @@ def test_batched_fp32_product_matches_oracle(order, degree, nrhs):
     assert err.max() < 1e-5
 
 
+def fp16_bound(absA_absx, nz_absx, ref, ncol):
+    """Elementwise bound on |fl16(B16 x) - B x| for x already in FP16: each entry of
+    B rounded to FP16 (relative 2^-11, or 2^-25 absolute in the subnormal range),
+    exact FP16 x FP16 products summed in FP32 over ncol terms, y rounded to FP16."""
+    u16, u32 = 2.0 ** -11, 2.0 ** -24
+    return (u16 + ncol * u32) * 1.01 * absA_absx + 2.0 ** -25 * nz_absx + u16 * 1.01 * np.abs(ref) + 2.0 ** -24
+
+
+def to_slot_major(x, K, Kp8, pad=0.0):
+    """[nrhs][4 nt K] -> [4 nt][nrhs][Kp8] with the padding entries set to pad."""
+    nrhs = x.shape[0]
+    ns = x.shape[1] // K
+    out = np.full((ns, nrhs, Kp8), pad)
+    out[:, :, :K] = x.reshape(nrhs, ns, K).transpose(1, 0, 2)
+    return out
+
+
+@pytest.mark.parametrize("order,degree,nrhs", [(1, 8, 130), (0, 4, 3), (1, 3, 40)])
+def test_fp16_product_matches_oracle(order, degree, nrhs):
+    """dfm_apply_f16 (the product kernel of the two-level sweeps, every tet in one
+    launch) against the oracle's B applied in FP64 to the same FP16 inputs, every
+    element within the rounding bound of FP16 storage and FP32 accumulation.
+    K = 135 spans two 96-row groups and 130 right-hand sides two 128-wide tiles;
+    3 and 40 take the 16- and 64-wide tiles.  The padding entries of x hold 7.0
+    (they meet zero columns); those of y come out 0."""
+    say(f"[apply f16] P{order} D{degree} nrhs {nrhs}")
+    v, t, refl = box(2, 0.15, seed=4)
+    mu = np.full(t.shape[0], 0.05)
+    bs = oa.Basis(order, 0, degree, 4, oq.SEAM_RULE)
+    op = gpu_op(gpu_mesh(v, t, refl), mu, bs)
+    m = om.build_mesh(v, t, refl)
+    A = osv.to_sparse(*oa.assemble(m, bs, mu))
+    K = op.K
+    Kp8 = (K + 7) // 8 * 8
+    x = np.random.default_rng(7).standard_normal((nrhs, A.shape[0])).astype(np.float16).astype(np.float64)
+    x16 = torch.tensor(to_slot_major(x, K, Kp8, pad=7.0), dtype=torch.float16, device=DEV)
+    y = op.apply_f16(x16).double().cpu().numpy()
+    assert not y[:, :, K:].any()
+    got = y[:, :, :K].transpose(1, 0, 2).reshape(nrhs, -1)
+    ref = (A @ x.T).T
+    absA = abs(A)
+    bound = fp16_bound((absA @ np.abs(x).T).T, ((absA > 0).astype(np.float64) @ np.abs(x).T).T, ref,
+                       3 * ((K + 31) // 32 * 32))
+    err = np.abs(got - ref)
+    say(f"    worst |err| / bound {float((err / bound).max()):.3f}, rel {err.max() / np.abs(ref).max():.2e}")
+    assert (err <= bound).all()
+    from paper_1608_04607_amd import _lib
+    from paper_1608_04607_amd.dfm import check, _ptr, _stream
+    with pytest.raises(RuntimeError):
+        check(_lib.load().dfm_apply_f16(op.handle, _ptr(x16), _ptr(x16), nrhs, _stream(None)))
+    with pytest.raises(RuntimeError):
+        check(_lib.load().dfm_apply_f16(op.handle, _ptr(x16), _ptr(torch.empty_like(x16)), 0, _stream(None)))
+    op.close()
+
+
 @pytest.mark.parametrize("nrhs", [5, 20])
 def test_batched_mixed_neumann_matches_oracle(small, nrhs):
     """Method 0 with precision 1: all right-hand sides together, FP32 Neumann
@@ -592,6 +668,31 @@ def test_twolevel_solve_two_row_groups():
     for r in range(4):
         assert info[r][2] <= 1e-10
         assert rel(rho[r], osv.solve_direct(A, rhs[r])) < 1e-7
+
+
+def test_product_timing_counts_the_solves_launches(small):
+    """dfm_product_timing: with timing on, a method-2 solve adds one timed launch
+    per colour per product, and the algorithmic bytes of every tet once per
+    product (all products with the correction columns, unless a stage fell back
+    without them); stopping returns the totals and clears them."""
+    say("[solve] two-level product timing")
+    g, op, m, bs, Bo, desto, mu = small
+    n = 4 * g.nt * op.K
+    rhs = np.random.default_rng(43).standard_normal((3, n))
+    assert op.product_timing(1) == (0.0, 0, 0.0)
+    rho, info = op.solve(torch.tensor(rhs, device=DEV), method="twolevel", rtol=1e-10)
+    ms, launches, nbytes = op.product_timing(0)
+    prods = info[0][0]
+    say(f"    {prods} products, {launches} launches, {ms:.2f} ms, {nbytes:.3e} B")
+    assert prods > 0 and launches % prods == 0 and 2 <= launches // prods <= 4
+    assert ms > 0.0
+    K, R, F, nt = op.K, 3, 9, g.nt
+    kp8, nsub, naug = (K + 7) // 8 * 8, (K + 31) // 32, (5 * 16 + 31) // 32
+    vec = 2 * 4 * R * kp8 * 2 + 4 * F * R * 4
+    full = prods * nt * (4 * (3 * nsub + naug) * K * 64 + vec)
+    bare = prods * nt * (4 * 3 * nsub * K * 64 + vec)
+    assert bare * (1 - 1e-12) <= nbytes <= full * (1 + 1e-12)
+    assert op.product_timing(-1) == (0.0, 0, 0.0)
 
 
 def test_solve_groups_matches_oracle():
