@@ -501,8 +501,8 @@ def main_box32(args):
     for r in (0, R // 2, R - 1):
         res = rho0[r] - (rho[r] - op.apply(rho[r]))
         worst = max(worst, float((res.norm() / rho0[r].norm()).item()))
-    # the batched FP64 product (dfm_residual: B streamed once per 8 right-hand
-    # sides, FP64 accumulation) over all R
+    # the batched FP64 product (dfm_residual: every block row read once per 128
+    # right-hand sides on the FP64 matrix cores, FP64 accumulation) over all R
     op.residual(rho0, rho)
     e0, e1 = ev(), ev()
     e0.record(stream)

@@ -262,8 +262,9 @@ dfm_status dfm_solve_groups(dfm_op op, const double *rho0, double *rho, int nrhs
 
 /* The residual of Eq. GovIE for nrhs right-hand sides: res = rho0 - (I - B) rho
  * (Sec. 2), with the stored operator (FP64, or FP32 entries when dtype = 1) and
- * FP64 accumulation; B is streamed once per 8 right-hand sides.  This is the
- * refinement residual of the batched solvers.
+ * FP64 accumulation: below 16 right-hand sides B is streamed once per 8 of them;
+ * from 16 on, the FP64 matrix cores read each block row once per 128.  This is
+ * the refinement residual of the batched solvers.
  *   rho0, rho, res  device f64 [nrhs][ndof]; res aliases neither rho0 nor rho.
  * Errors: DFM_E_INVALID.  Does not synchronise `stream`. */
 dfm_status dfm_residual(dfm_op op, const double *rho0, const double *rho, double *res, int nrhs, void *stream);

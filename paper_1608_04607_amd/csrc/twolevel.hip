@@ -881,6 +881,142 @@ __global__ __launch_bounds__(RES_THREADS) void k_resid(const TB *__restrict__ B,
   }
 }
 
+// The same residual on the FP64 matrix cores (v_mfma_f64_16x16x4f64) for 16 or
+// more right-hand sides, every block row read once per RM_RT of them:
+// workgroup = (block row, tile of RM_RT right-hand sides, group of RM_ROWS output
+// rows); its 8 waves form 2 row halves (3 row tiles of 16) x 4 rhs quarters (2
+// rhs tiles of 16).  The block row's 3K columns go in chunks of RM_KC: the chunk of
+// B (converted to FP64) and of x is loaded coalesced one chunk ahead into
+// registers, stored to LDS and read back as fragments; accumulation in FP64.  The
+// four block rows of a tet run back to back on one XCD (workgroups are dealt to
+// the 8 XCDs in turn), so the x panels they share come from that XCD's L2.
+constexpr int RM_THREADS = 512, RM_RT = 128, RM_ROWS = 96, RM_KC = 32;
+constexpr int RM_BLD = RM_ROWS + 4;      // LDS row stride of the B chunk [column][row] (doubles)
+constexpr int RM_XLD = RM_KC + 1;        // LDS row stride of the x chunk [rhs][column]
+constexpr int RM_NX = RM_KC * RM_RT / RM_THREADS;
+constexpr size_t RM_LDS = sizeof(double) * (size_t)(RM_KC * RM_BLD + RM_RT * RM_XLD);
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+template <typename TB>
+__global__ __launch_bounds__(RM_THREADS, 2) void k_resid_mm(const TB *__restrict__ B, const int32_t *__restrict__ dest,
+                                                           int64_t nt, int K, int Kp, int64_t ndof, int R,
+                                                           const double *__restrict__ x,
+                                                           const double *__restrict__ rho0,
+                                                           double *__restrict__ res) {
+  extern __shared__ double rm_lds[];
+  double *bs = rm_lds;                     // [RM_KC][RM_BLD]
+  double *xs = rm_lds + RM_KC * RM_BLD;    // [RM_RT][RM_XLD]
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t bid = blockIdx.x;
+  int64_t br = bid;
+  if ((nt & 7) == 0) {
+    const int64_t slot = bid >> 3, xcd = bid & 7;
+    br = 4 * (8 * (slot >> 2) + xcd) + (slot & 3);
+  }
+  const int r0 = blockIdx.y * RM_RT;
+  const int m0 = blockIdx.z * RM_ROWS;
+  const int64_t j = br >> 2;
+  const int l_out = (int)(br & 3);
+  const int ncol = 3 * K;
+  const int nchunk = (ncol + RM_KC - 1) / RM_KC;
+  const TB *Bbr = B + br * 3 * (int64_t)K * Kp;
+  // B chunk in 16-byte pieces: piece i -> (column i / PC, rows m0 + PW (i % PC) .. + PW - 1);
+  // Kp, 3 K Kp and m0 are multiples of 4, so a piece lies wholly inside or outside
+  // the column's Kp rows
+  constexpr int PW = 16 / (int)sizeof(TB);
+  constexpr int PC = RM_ROWS / PW;
+  constexpr int NP = RM_KC * PC;
+  constexpr int NPT = (NP + RM_THREADS - 1) / RM_THREADS;
+  typedef TB vp __attribute__((ext_vector_type(PW)));
+  int bcol[NPT], brow[NPT];
+#pragma unroll
+  for (int u = 0; u < NPT; ++u) {
+    const int i = tid + u * RM_THREADS;
+    bcol[u] = i < NP ? i / PC : RM_KC;
+    brow[u] = m0 + PW * (i % PC);
+  }
+  const int xc = tid % RM_KC, xr = r0 + tid / RM_KC;
+  constexpr int XRS = RM_THREADS / RM_KC;
+  vp pb[NPT];
+  double px[RM_NX];
+  auto load_chunk = [&](int ch) {
+    const int c0 = ch * RM_KC;
+#pragma unroll
+    for (int u = 0; u < NPT; ++u) {
+      const int c = c0 + bcol[u];
+      pb[u] = (bcol[u] < RM_KC && c < ncol && brow[u] < Kp)
+                  ? __builtin_nontemporal_load(reinterpret_cast<const vp *>(Bbr + (int64_t)c * Kp + brow[u]))
+                  : vp{};
+    }
+    const int c = c0 + xc;
+    const int s = c / K;
+    const double *xp = x + (int64_t)xr * ndof + (4 * j + in_face2(l_out, s < 3 ? s : 2)) * (int64_t)K + (c - s * K);
+#pragma unroll
+    for (int u = 0; u < RM_NX; ++u) px[u] = (c < ncol && xr + u * XRS < R) ? xp[(int64_t)u * XRS * ndof] : 0.0;
+  };
+  auto store_chunk = [&]() {
+#pragma unroll
+    for (int u = 0; u < NPT; ++u)
+      if (bcol[u] < RM_KC)
+#pragma unroll
+        for (int e = 0; e < PW; ++e) bs[bcol[u] * RM_BLD + brow[u] - m0 + e] = (double)pb[u][e];
+#pragma unroll
+    for (int u = 0; u < RM_NX; ++u) xs[(xr - r0 + u * XRS) * RM_XLD + xc] = px[u];
+  };
+  const int wr = wave >> 2, wc = wave & 3;
+  const int col = lane & 15, kq = lane >> 4;
+  v4d acc[3][2];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+  auto contract = [&]() {
+#pragma unroll
+    for (int ks = 0; ks < RM_KC / 4; ++ks) {
+      const int c = ks * 4 + kq;
+      double av[3], bv[2];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) av[a] = bs[c * RM_BLD + (wr * 3 + a) * 16 + col];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) bv[b] = xs[((wc * 2 + b) * 16 + col) * RM_XLD + c];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+  };
+  load_chunk(0);
+  for (int ch = 0; ch + 1 < nchunk; ++ch) {
+    store_chunk();
+    __syncthreads();
+    load_chunk(ch + 1);   // in flight while this chunk is contracted
+    contract();
+    __syncthreads();
+  }
+  store_chunk();
+  __syncthreads();
+  contract();
+  // the FP64 result layout: lane holds rows lane / 16 + 4 q of each 16-row tile,
+  // rhs lane % 16
+  const int64_t ob = (int64_t)dest[br] * K;
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    const int r = r0 + (wc * 2 + b) * 16 + col;
+    if (r >= R) continue;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int m = m0 + (wr * 3 + a) * 16 + kq + 4 * q;
+        if (m < K) {
+          const int64_t o = (int64_t)r * ndof + ob + m;
+          res[o] = rho0[o] - x[o] + acc[a][b][q];
+        }
+      }
+  }
+}
+
 // gid[j] = g for the tets j of instance g (tet offsets toff; grid z = instance)
 __global__ void k_fill_gid2(const int64_t *__restrict__ toff, int32_t *__restrict__ gid) {
   const int g = blockIdx.z;
@@ -893,6 +1029,23 @@ __global__ void k_fill_gid2(const int64_t *__restrict__ toff, int32_t *__restric
 
 // res = rho0 - (I - B) x for R right-hand sides (FP64 vectors, the stored operator)
 hipError_t residual_batched(dfm_op op, const double *rho0, const double *x, double *res, int R, hipStream_t st) {
+  if (R >= 16) {
+    const dim3 grid((unsigned)(4 * op->nt), (unsigned)((R + RM_RT - 1) / RM_RT),
+                    (unsigned)((op->K + RM_ROWS - 1) / RM_ROWS));
+    hipError_t e;
+    if (op->B) {
+      e = hipFuncSetAttribute((const void *)k_resid_mm<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)RM_LDS);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(k_resid_mm<double>, grid, dim3(RM_THREADS), RM_LDS, st, op->B, op->dest, op->nt, op->K,
+                         op->Kp, op->ndof, R, x, rho0, res);
+    } else {
+      e = hipFuncSetAttribute((const void *)k_resid_mm<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)RM_LDS);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(k_resid_mm<float>, grid, dim3(RM_THREADS), RM_LDS, st, op->B32, op->dest, op->nt, op->K,
+                         op->Kp, op->ndof, R, x, rho0, res);
+    }
+    return hipGetLastError();
+  }
   constexpr int NR = 8;
   for (int r0 = 0; r0 < R; r0 += NR) {
     const int nr = std::min(NR, R - r0);

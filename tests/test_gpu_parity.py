@@ -602,10 +602,12 @@ def test_batched_mixed_neumann_warm_start(small):
         assert rel(rho[r].cpu().numpy(), osv.solve_direct(A, rhs[r])) < 1e-7
 
 
-@pytest.mark.parametrize("nrhs", [1, 11])
+@pytest.mark.parametrize("nrhs", [1, 11, 37, 130])
 def test_residual_matches_oracle(small, nrhs):
-    """dfm_residual: rho0 - (I - B) rho for several right-hand sides in one pass
-    per 8 (11 = one full pass and a tail of 3) against the oracle's sparse B."""
+    """dfm_residual: rho0 - (I - B) rho against the oracle's sparse B; 1 and 11
+    right-hand sides take the streaming kernel (one pass per 8: 11 = one full pass
+    and a tail of 3), 37 and 130 the FP64 matrix cores (a ragged 128-wide tile,
+    and two tiles)."""
     say(f"[residual] {nrhs} rhs")
     g, op, m, bs, Bo, desto, mu = small
     A = osv.to_sparse(Bo, desto)
@@ -620,6 +622,30 @@ def test_residual_matches_oracle(small, nrhs):
         from paper_1608_04607_amd import _lib
         from paper_1608_04607_amd.dfm import check, _ptr, _stream
         check(_lib.load().dfm_residual(op.handle, _ptr(x), _ptr(x), _ptr(x), nrhs, _stream(None)))
+
+
+@pytest.mark.parametrize("dtype,tol", [(0, TOL), (1, 2e-5)])
+def test_residual_two_row_groups_matches_oracle(dtype, tol):
+    """The matrix-core residual with K = 135 (P1, Legendre D = 8: two 96-row
+    groups), 20 right-hand sides, for B stored in FP64 (1e-10) and in FP32 (the
+    FP32 assembly's own 1e-5 bound on B carries over to B rho)."""
+    from paper_1608_04607_amd import dfm
+    say(f"[residual] K = 135, dtype {dtype}")
+    v, t, refl = box(1, 0.1, seed=44)
+    bs = oa.Basis(1, 0, 8, 3, oq.SEAM_RULE)
+    mu = np.full(t.shape[0], 0.1)
+    op = dfm.Operator(gpu_mesh(v, t, refl), torch.tensor(mu, device=DEV), 1, dfm.LEGENDRE, 8, 3, rule=oq.SEAM_RULE,
+                      dtype=dtype)
+    A = osv.to_sparse(*oa.assemble(om.build_mesh(v, t, refl), bs, mu))
+    rng = np.random.default_rng(45)
+    rho0 = rng.standard_normal((20, A.shape[0]))
+    rho = rng.standard_normal((20, A.shape[0]))
+    res = op.residual(torch.tensor(rho0, device=DEV), torch.tensor(rho, device=DEV)).cpu().numpy()
+    ref = rho0 - (rho - (A @ rho.T).T)
+    err = rel(res, ref)
+    say(f"    rel err {err:.2e}")
+    assert err < tol
+    op.close()
 
 
 @pytest.mark.parametrize("nrhs", [3, 130])
