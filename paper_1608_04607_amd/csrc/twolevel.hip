@@ -346,24 +346,28 @@ __global__ void k_coarse_maps(const int32_t *__restrict__ agg_tet, const int32_t
 // row group of a U-type destination also
 // d0[dest][f][r] = sum_{k < R0} Pv[dest][k][f] y[r][k] (0 for L type).
 //
-// Workgroup = (tet, tile of 16 CT right-hand sides, row group of 96), one wave
-// per block row (l_out = wave).  Each lane loads its MFMA fragments straight from memory,
-// 16 bytes at a time: B rows m0 + 16 rt + lane % 16, columns 8 (lane / 16) .. + 7
-// of a 32-column chunk, and the same 8 columns of right-hand side
-// rw0 + 16 ct + lane % 16; v_mfma_f32_16x16x32_f16 takes them as they are (the
-// same column order on both sides).  No LDS and no barrier.
+// Persistent workgroups: grid = (P, tiles of 16 CT right-hand sides, row groups
+// of 96) with P about one workgroup per compute unit; workgroup b takes the
+// launch's tets b, b + P, b + 2P, ...  One wave per block row (l_out = wave).
+// Each lane loads its MFMA fragments straight from memory, 16 bytes at a time:
+// B rows m0 + 16 rt + lane % 16, columns 8 (lane / 16) .. + 7 of a 32-column
+// chunk, and the same 8 columns of right-hand side rw0 + 16 ct + lane % 16;
+// v_mfma_f32_16x16x32_f16 takes them as they are.  No LDS and no barrier.
 //
-// Schedule: four phases, one per local face p of the tet.  In phase p the three
-// waves with l_out != p contract the chunks of inbound slot p, all at the same
-// step, so each slot run of x is fetched from memory once and the other two
-// waves find it in cache; wave l_out = p contracts its correction chunks
-// meanwhile.  Steps past a wave's chunks (and whole phases without correction)
-// read 16 zero bytes.  No load is conditional and every loop trip issues the
-// same loads: a load under a condition makes the compiler wait for it at once,
-// which leaves one load in flight.  DEPTH chunks are in flight per wave.
+// Schedule of a tet: four phases of L steps, one phase per local face p.  In
+// phase p the three waves with l_out != p contract the chunks of inbound slot p,
+// all at the same step, so each slot run of x is fetched from memory once and the
+// other two waves find it in cache; wave l_out = p contracts its correction
+// chunks meanwhile.  Steps past a wave's chunks read 16 zero bytes.  The steps
+// are unrolled (L is a template parameter) and DEPTH steps are in flight: the
+// last DEPTH steps of a tet load the first of the next, so the stores of one tet
+// overlap the loads of the next instead of ending the workgroup.  No load is
+// conditional (a load under a condition makes the compiler wait for it at once).
+// The Pv^T fragments of d0 are loaded with the tet's first step and used after
+// its last.
 //
-// Rows of instances that are not multiplied (gact[gid[tet]] == 0) get y = 0 and
-// d0 = 0.
+// Tets of instances that are not multiplied (gact[gid[tet]] == 0) load nothing
+// and write y = 0 and d0 = 0.
 // ---------------------------------------------------------------------------
 
 struct P16Args {
@@ -374,7 +378,7 @@ struct P16Args {
   const half_t *t;          // [4 nt][R][Kp8]
   half_t *y;                // [4 nt][R][Kp8]
   float *d0;                // [4 nt][F][R] or null
-  const float *Pv;          // [4 nt][Kp8][F]
+  const half_t *PvT16;      // [4 nt][16][ROWG]: Pv^T in FP16, rows >= F and columns >= R0 zero
   const int32_t *agg_slot;  // [4 nt]
   const int32_t *agg_up;    // [4 nt]
   const float *c;           // [ng F][R] or null (no correction)
@@ -382,95 +386,85 @@ struct P16Args {
   const half_t *zero16;     // 8 zero halves
   const int32_t *gid;       // tet -> instance, or null
   const uint8_t *gact;      // instance -> multiplied, or null
-  const int32_t *tlist;     // tets of this launch's colour
-  const uint8_t *lmask;     // [4 nt] slot written in place (L type)
+  const int32_t *tlist;     // tets of this launch
+  int64_t ntl;              // their number
+  const uint8_t *lmask;     // [4 nt] slot written in place (L type), or null
   int first;                // first product of a stage: L-type slots add their old value
 };
 
-template <int DEPTH, int CT>
+template <int DEPTH, int CT, int L>
 __global__ __launch_bounds__(256, 1) void k_spmm16(P16Args a) {
   constexpr int RT = ROWG / 16;
+  constexpr int NST = 4 * L;
+  static_assert(DEPTH < NST, "the prefetch reaches at most into the next tet");
   const int lane = threadIdx.x & 63;
   const int l_out = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int rw0 = blockIdx.y * CT * 16;                   // first right-hand side of the workgroup
-  const int64_t j = a.tlist[blockIdx.x];
-  const int64_t br = 4 * j + l_out;
   const int m0 = blockIdx.z * ROWG;
   const int K = a.K, Kp8 = a.Kp8, F = a.F, R = a.R;
-  const int64_t dslot = a.dest[br];
-  const bool dl = a.lmask != nullptr && a.lmask[dslot] != 0;
   const int64_t ldr = (int64_t)R * Kp8;
   const int nrows = min(ROWG, Kp8 - m0);
   const int col = lane & 15, kq = lane >> 4;
-  half_t *ybase = (dl ? const_cast<half_t *>(a.t) : a.y) + dslot * ldr + m0;
-  if (a.gact != nullptr && a.gact[a.gid[j]] == 0) {
-#pragma unroll
-    for (int ct = 0; ct < CT; ++ct) {
-      const int r = rw0 + ct * 16 + col;
-      if (r >= R) continue;
-#pragma unroll
-      for (int rt = 0; rt < RT; ++rt)
-        if (rt * 16 + 4 * kq < nrows)
-          *reinterpret_cast<h4 *>(ybase + (int64_t)r * Kp8 + rt * 16 + 4 * kq) = h4{0, 0, 0, 0};
-    }
-    if (m0 == 0 && a.d0)
-      for (int i = lane; i < F * CT * 16; i += 64) {
-        const int f = i / (CT * 16), r = i - f * (CT * 16);
-        if (rw0 + r < R) a.d0[(dslot * F + f) * R + rw0 + r] = 0.0f;
-      }
-    return;
-  }
   const bool corr = a.c != nullptr;
   const int FP = fpad(F);
-  int gagg[NAUG];
-#pragma unroll
-  for (int s = 0; s < 3; ++s) gagg[s] = corr ? a.agg_up[4 * j + in_face2(l_out, s)] : 0;
-  gagg[3] = corr ? a.agg_slot[4 * j] : 0;
-  gagg[4] = corr ? a.agg_slot[dslot] : 0;
   const int brows = min(ROWG, K - m0);
   const int nsub = (K + KC - 1) / KC;                     // chunks per slot
   const int naug = (NAUG * FP + KC - 1) / KC;             // correction chunks
-  const int L = max(nsub, naug);                          // steps per phase
-  const int nsteps = (4 * L + DEPTH - 1) / DEPTH * DEPTH;
+  const int64_t P = gridDim.x;
+  const int64_t ntet = (a.ntl - (int64_t)blockIdx.x + P - 1) / P;   // tets of this workgroup
+  if (ntet <= 0) return;
   const half_t *zero = a.zero16;
-  const half_t *Bbr = a.B16 + br * (int64_t)a.NCH * K * KC;
-  const half_t *abase = Bbr + (int64_t)(m0 + col) * KC + 8 * kq;
-  const half_t *tj = a.t + 4 * j * ldr;
+  const int64_t cstride = (int64_t)K * KC;                // halves per chunk
+  const int64_t bstride = (int64_t)a.NCH * K * KC;        // halves per block row
   int rofs[CT];
 #pragma unroll
   for (int ct = 0; ct < CT; ++ct) rofs[ct] = min(rw0 + ct * 16 + col, R - 1);   // past R: never stored
 
-  h8 A[DEPTH][RT], X[DEPTH][CT];
-  auto load = [&](int it, h8 (&Ab)[RT], h8 (&Xb)[CT]) {
+  // what the loads of a tet need: its index (-1 past the workgroup's last tet),
+  // whether it is multiplied, and the aggregates of its correction groups
+  struct TetL {
+    int64_t j;
+    bool act;
+    int gagg[NAUG];
+  };
+  auto tet_info = [&](int64_t q, TetL &T) {
+    const bool v = q < ntet;
+    T.j = v ? (int64_t)a.tlist[blockIdx.x + q * P] : -1;
+    const int64_t jj = v ? T.j : 0;
+    T.act = v && (a.gact == nullptr || a.gact[a.gid[jj]] != 0);
+#pragma unroll
+    for (int s = 0; s < 3; ++s) T.gagg[s] = (v && corr) ? a.agg_up[4 * jj + in_face2(l_out, s)] : 0;
+    T.gagg[3] = (v && corr) ? a.agg_slot[4 * jj] : 0;
+    T.gagg[4] = (v && corr) ? a.agg_slot[a.dest[4 * jj + l_out]] : 0;
+  };
+  auto load = [&](const TetL &T, int it, h8 (&Ab)[RT], h8 (&Xb)[CT]) {
     // wave-uniform: phase, step in it, chunk of B16 (-1: none)
     const int p = it / L, c = it - p * L;
     const bool aug = p == l_out;
     int bch = -1;
-    if (it < 4 * L) {
+    if (T.act) {
       if (!aug && c < nsub) bch = (p < l_out ? p : p - 1) * nsub + c;
       if (aug && corr && c < naug) bch = 3 * nsub + c;
     }
+    const int64_t jj = T.j >= 0 ? T.j : 0;
+    const half_t *abase = a.B16 + (4 * jj + l_out) * bstride + (int64_t)(m0 + col) * KC + 8 * kq;
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
       const bool ok = bch >= 0 && rt * 16 + col < brows;
-      Ab[rt] = *reinterpret_cast<const h8 *>(ok ? abase + (int64_t)bch * K * KC + rt * 16 * KC : zero);
+      Ab[rt] = *reinterpret_cast<const h8 *>(ok ? abase + (int64_t)bch * cstride + rt * 16 * KC : zero);
     }
     // per lane: 8 columns starting at 32 c + 8 kq of slot p, or of the correction
     const int e = c * KC + 8 * kq;
     const int g = min(e / FP, NAUG - 1);
-    const int ga = g == 0 ? gagg[0] : (g == 1 ? gagg[1] : (g == 2 ? gagg[2] : (g == 3 ? gagg[3] : gagg[4])));
+    const int ga = g == 0 ? T.gagg[0] : (g == 1 ? T.gagg[1] : (g == 2 ? T.gagg[2] : (g == 3 ? T.gagg[3] : T.gagg[4])));
     const bool xs = bch >= 0 && !aug && e < Kp8;
     const bool xc = bch >= 0 && aug && e < NAUG * FP;
-    const half_t *xp = xs ? tj + p * ldr + e : (xc ? a.c16 + (int64_t)ga * R * FP + (e - g * FP) : zero);
+    const half_t *xp = xs ? a.t + (4 * jj + p) * ldr + e : (xc ? a.c16 + (int64_t)ga * R * FP + (e - g * FP) : zero);
     const int xstride = xs ? Kp8 : (xc ? FP : 0);
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) Xb[ct] = *reinterpret_cast<const h8 *>(xp + (int64_t)rofs[ct] * xstride);
   };
   f4 acc[RT][CT];
-#pragma unroll
-  for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-    for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = f4{0.0f, 0.0f, 0.0f, 0.0f};
   auto contract = [&](const h8 (&Ab)[RT], const h8 (&Xb)[CT]) {
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
@@ -478,69 +472,92 @@ __global__ __launch_bounds__(256, 1) void k_spmm16(P16Args a) {
       for (int ct = 0; ct < CT; ++ct)
         acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_f16(Ab[rt], Xb[ct], acc[rt][ct], 0, 0, 0);
   };
+  TetL cur, nxt;
+  tet_info(0, cur);
+  h8 A[DEPTH][RT], X[DEPTH][CT];
 #pragma unroll
-  for (int u = 0; u < DEPTH; ++u) load(u, A[u], X[u]);
-  for (int it0 = 0; it0 < nsteps; it0 += DEPTH) {
-#pragma unroll
-    for (int u = 0; u < DEPTH; ++u) {
-      contract(A[u], X[u]);
-      load(it0 + u + DEPTH, A[u], X[u]);
-    }
-  }
-  // store y (rows 16 rt + 4 kq + q, right-hand side rw0 + 16 ct + col), one rhs
-  // tile at a time; for the first row group also d0 = Pv^T y with the A operand
-  // Pv^T: row f = lane % 16 (< F), columns k = 16 rt + 4 (lane / 16) .. + 3 (< R0);
-  // the accumulator layout of y is the B-operand layout of v_mfma_f32_16x16x16_f16
-  const bool want_d0 = m0 == 0 && a.d0 != nullptr && !dl;
-  h4 pa[RT];
-  if (want_d0) {
-    const float *pv = a.Pv + dslot * Kp8 * F;
+  for (int u = 0; u < DEPTH; ++u) load(cur, u, A[u], X[u]);
+  tet_info(1, nxt);
+  for (int64_t q = 0; q < ntet; ++q) {
+    const int64_t j = cur.j;
+    const bool act = cur.act;
+    const int64_t dslot = a.dest[4 * j + l_out];
+    const bool dl = a.lmask != nullptr && a.lmask[dslot] != 0;
+    const bool want_d0 = m0 == 0 && a.d0 != nullptr && !dl;
+    half_t *ybase = (dl ? const_cast<half_t *>(a.t) : a.y) + dslot * ldr + m0;
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int k = rt * 16 + 4 * kq + q;
-        pa[rt][q] = (col < F && k < a.R0) ? (half_t)pv[k * F + col] : (half_t)0.0f;
+      for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    h4 pa[RT];
+#pragma unroll
+    for (int it = 0; it < NST; ++it) {
+      contract(A[it % DEPTH], X[it % DEPTH]);
+      if (it + DEPTH < NST) load(cur, it + DEPTH, A[it % DEPTH], X[it % DEPTH]);
+      else load(nxt, it + DEPTH - NST, A[it % DEPTH], X[it % DEPTH]);
+      if (it == 0) {
+        // A operand of d0 = Pv^T y: row f = lane % 16, columns k = 16 rt + 4 (lane / 16) .. + 3
+        const half_t *pv = want_d0 ? a.PvT16 + (dslot * 16 + col) * (int64_t)ROWG + 4 * kq : zero;
+        const int pstride = want_d0 ? 16 : 0;
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) pa[rt] = *reinterpret_cast<const h4 *>(pv + rt * pstride);
       }
-  }
+    }
+    // store y (rows 16 rt + 4 kq + q, right-hand side rw0 + 16 ct + col), one rhs
+    // tile at a time, and d0 with one more MFMA per tile: the accumulator layout
+    // of y is the B-operand layout of v_mfma_f32_16x16x16_f16
 #pragma unroll
-  for (int ct = 0; ct < CT; ++ct) {
-    const int r = rw0 + ct * 16 + col;
-    if (dl && a.first && r < R) {
+    for (int ct = 0; ct < CT; ++ct) {
+      const int r = rw0 + ct * 16 + col;
+      if (act && dl && a.first && r < R) {
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+          if (rt * 16 + 4 * kq < nrows) {
+            const h4 o = *reinterpret_cast<const h4 *>(ybase + (int64_t)r * Kp8 + rt * 16 + 4 * kq);
+#pragma unroll
+            for (int qq = 0; qq < 4; ++qq) acc[rt][ct][qq] += (float)o[qq];
+          }
+      }
+      h4 yh[RT];
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt)
-        if (rt * 16 + 4 * kq < nrows) {
-          const h4 o = *reinterpret_cast<const h4 *>(ybase + (int64_t)r * Kp8 + rt * 16 + 4 * kq);
-#pragma unroll
-          for (int q = 0; q < 4; ++q) acc[rt][ct][q] += (float)o[q];
-        }
-    }
-    h4 yh[RT];
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-      yh[rt] = h4{(half_t)acc[rt][ct][0], (half_t)acc[rt][ct][1], (half_t)acc[rt][ct][2], (half_t)acc[rt][ct][3]};
-    if (r < R) {
-#pragma unroll
-      for (int rt = 0; rt < RT; ++rt)
-        if (rt * 16 + 4 * kq < nrows) *reinterpret_cast<h4 *>(ybase + (int64_t)r * Kp8 + rt * 16 + 4 * kq) = yh[rt];
-    }
-    if (m0 == 0 && a.d0 != nullptr && dl && r < R) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if (4 * kq + q < F) a.d0[(dslot * F + 4 * kq + q) * R + r] = 0.0f;
-    }
-    if (want_d0) {
-      f4 dacc = f4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-      for (int rt = 0; rt < RT; ++rt) dacc = __builtin_amdgcn_mfma_f32_16x16x16f16(pa[rt], yh[rt], dacc, 0, 0, 0);
+        yh[rt] = act ? h4{(half_t)acc[rt][ct][0], (half_t)acc[rt][ct][1], (half_t)acc[rt][ct][2], (half_t)acc[rt][ct][3]}
+                     : h4{0, 0, 0, 0};
       if (r < R) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int f = 4 * kq + q;
-          if (f < F) a.d0[(dslot * F + f) * R + r] = dacc[q];
+        for (int rt = 0; rt < RT; ++rt)
+          if (rt * 16 + 4 * kq < nrows) *reinterpret_cast<h4 *>(ybase + (int64_t)r * Kp8 + rt * 16 + 4 * kq) = yh[rt];
+      }
+      if (m0 == 0 && a.d0 != nullptr && dl && r < R) {
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq)
+          if (4 * kq + qq < F) a.d0[(dslot * F + 4 * kq + qq) * R + r] = 0.0f;
+      }
+      if (want_d0) {
+        f4 dacc = f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) dacc = __builtin_amdgcn_mfma_f32_16x16x16f16(pa[rt], yh[rt], dacc, 0, 0, 0);
+        if (r < R) {
+#pragma unroll
+          for (int qq = 0; qq < 4; ++qq) {
+            const int f = 4 * kq + qq;
+            if (f < F) a.d0[(dslot * F + f) * R + r] = dacc[qq];
+          }
         }
       }
     }
+    cur = nxt;
+    tet_info(q + 2, nxt);
+  }
+}
+
+// PvT16[s][f][k] = half(Pv[s][k][f]) for f < F and k < R0, else 0 (rows of ROWG)
+__global__ void k_pvt16(const float *__restrict__ Pv, int64_t nslot, int Kp8, int F, int R0, half_t *__restrict__ PvT) {
+  const int64_t tot = nslot * 16 * ROWG;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t s = i / (16 * ROWG);
+    const int f = (int)((i / ROWG) % 16), k = (int)(i % ROWG);
+    PvT[i] = (f < F && k < R0 && k < Kp8) ? (half_t)Pv[(s * Kp8 + k) * F + f] : (half_t)0.0f;
   }
 }
 
@@ -1104,7 +1121,9 @@ struct Coarse {
   int32_t *tlist = nullptr;
   uint8_t *lmask = nullptr;      // [4 nt] slot whose writer has a lower colour than its tet
   half_t *zero16 = nullptr;      // 8 zero halves (read in place of absent columns)
+  half_t *PvT16 = nullptr;       // [4 nt][16][ROWG] Pv^T in FP16 (the d0 fragments of the product)
   void release() {
+    (void)hipFree(PvT16);
     (void)hipFree(zero16);
     (void)hipFree(tlist);
     (void)hipFree(lmask);
@@ -1383,6 +1402,7 @@ dfm_status ensure_coarse(dfm_op op, const std::vector<int64_t> &toff, hipStream_
   TRYC(hipMalloc(&C.agg_up, sizeof(int32_t) * nslot));
   TRYC(hipMalloc(&Mm, sizeof(double) * M * NMONO));
   TRYC(hipMalloc(&C.Pv, sizeof(float) * nslot * Kp8 * F));
+  TRYC(hipMalloc(&C.PvT16, sizeof(half_t) * nslot * 16 * ROWG));
   TRYC(hipMalloc(&C.W, sizeof(float) * nslot * Kp8 * F));
   TRYC(hipMalloc(&W64, sizeof(double) * nslot * Kp8 * F));
   TRYC(hipMalloc(&C.row_off, sizeof(int64_t) * ng));
@@ -1399,6 +1419,7 @@ dfm_status ensure_coarse(dfm_op op, const std::vector<int64_t> &toff, hipStream_
   hipLaunchKernelGGL(k_mono_table, dim3(1), dim3(256), 0, st, op->basis.mom_degree, op->basis.mom_family, op->thom, Mm);
   hipLaunchKernelGGL(k_coarse_pv, dim3(ew_grid(nslot)), dim3(256), 0, st, op->mesh->face, nslot, M, R0, Kp8, F, Mm,
                      C.Pv);
+  hipLaunchKernelGGL(k_pvt16, dim3(ew_grid(nslot * 16 * ROWG)), dim3(256), 0, st, C.Pv, nslot, Kp8, F, R0, C.PvT16);
   if (op->B) {
     hipLaunchKernelGGL(k_coarse_W<double>, dim3(ew_grid(nbr * Kp8)), dim3(256), 0, st, op->B, op->dest, C.Pv, nbr, K,
                        op->Kp, Kp8, R0, F, W64, C.W);
@@ -1473,9 +1494,46 @@ dfm_status ensure_coarse(dfm_op op, const std::vector<int64_t> &toff, hipStream_
 }
 
 namespace {
-hipError_t launch_product16(dfm_op op, half_t *t, half_t *y, float *d0, int R, const float *c,
-                            const half_t *c16, const half_t *zero16, const int32_t *gid, const uint8_t *gact,
-                            bool first, hipStream_t st) {
+// compute units of the current device (cached per device)
+int cu_count() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  if (cached[dev] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    cached[dev] = n;
+  }
+  return cached[dev];
+}
+
+// one launch of the product over a.ntl tets: the tile follows R (16, 32, 64 or
+// 128 right-hand sides per workgroup), so that a few right-hand sides do not pay
+// for the matrix-core work of 128; about one persistent workgroup per compute
+// unit and tile (two where the tile's registers let two share a unit)
+hipError_t launch_spmm16(const P16Args &a, hipStream_t st) {
+  const int R = a.R;
+  const int CT = R <= 16 ? 1 : (R <= 32 ? 2 : (R <= 64 ? 4 : 8));
+  const int nsub = (a.K + KC - 1) / KC, naug = (NAUG * fpad(a.F) + KC - 1) / KC;
+  const int L = std::max(nsub, naug);
+  const unsigned ny = (unsigned)((R + 16 * CT - 1) / (16 * CT)), nz = (unsigned)((a.Kp8 + ROWG - 1) / ROWG);
+  const int64_t per_cu = CT <= 2 ? 2 : 1;   // CT <= 2 fits in 256 registers: two waves per SIMD
+  const int64_t P = std::max<int64_t>(1, std::min<int64_t>(a.ntl, per_cu * cu_count() / (int64_t)(ny * nz)));
+  const dim3 grid((unsigned)P, ny, nz);
+#define DFM_SPMM16(CTV, LV) \
+  case CTV * 10 + LV: hipLaunchKernelGGL((k_spmm16<2, CTV, LV>), grid, dim3(256), 0, st, a); break;
+  switch (CT * 10 + L) {
+    DFM_SPMM16(1, 2) DFM_SPMM16(1, 3) DFM_SPMM16(1, 4) DFM_SPMM16(1, 5)
+    DFM_SPMM16(2, 2) DFM_SPMM16(2, 3) DFM_SPMM16(2, 4) DFM_SPMM16(2, 5)
+    DFM_SPMM16(4, 2) DFM_SPMM16(4, 3) DFM_SPMM16(4, 4) DFM_SPMM16(4, 5)
+    DFM_SPMM16(8, 2) DFM_SPMM16(8, 3) DFM_SPMM16(8, 4) DFM_SPMM16(8, 5)
+    default: return hipErrorInvalidValue;
+  }
+#undef DFM_SPMM16
+  return hipGetLastError();
+}
+
+P16Args product_args(dfm_op op, int R) {
   const Coarse &C = *op->coarse;
   P16Args a{};
   a.B16 = reinterpret_cast<const half_t *>(op->B16);
@@ -1487,12 +1545,21 @@ hipError_t launch_product16(dfm_op op, half_t *t, half_t *y, float *d0, int R, c
   a.F = C.F;
   a.NCH = C.NCH;
   a.R0 = C.R0;
+  a.PvT16 = C.PvT16;
+  a.agg_slot = C.agg_slot;
+  a.agg_up = C.agg_up;
+  a.zero16 = C.zero16;
+  return a;
+}
+
+hipError_t launch_product16(dfm_op op, half_t *t, half_t *y, float *d0, int R, const float *c,
+                            const half_t *c16, const half_t *zero16, const int32_t *gid, const uint8_t *gact,
+                            bool first, hipStream_t st) {
+  const Coarse &C = *op->coarse;
+  P16Args a = product_args(op, R);
   a.t = t;
   a.y = y;
   a.d0 = d0;
-  a.Pv = C.Pv;
-  a.agg_slot = C.agg_slot;
-  a.agg_up = C.agg_up;
   a.c = c;
   a.c16 = c16;
   a.zero16 = zero16;
@@ -1500,10 +1567,6 @@ hipError_t launch_product16(dfm_op op, half_t *t, half_t *y, float *d0, int R, c
   a.gact = gact;
   a.lmask = C.lmask;
   a.first = first ? 1 : 0;
-  // one launch per colour, in colour order; one workgroup per (tet, tile of
-  // 16 CT right-hand sides, row group of 96): the tile follows R, so that a few
-  // right-hand sides do not pay for the matrix-core work of 128
-  const int CT = R <= 16 ? 1 : (R <= 32 ? 2 : (R <= 64 ? 4 : 8));
   ProdTiming *tm = op->ptiming;
   // algorithmic bytes per tet: its 4 block rows of B16 (slot chunks, and the
   // correction chunks when c is given), x of its 4 inbound slots and y of its 4
@@ -1511,22 +1574,17 @@ hipError_t launch_product16(dfm_op op, half_t *t, half_t *y, float *d0, int R, c
   const int nsub = (op->K + KC - 1) / KC, naug = (NAUG * fpad(C.F) + KC - 1) / KC;
   const double tet_bytes = 4.0 * (3 * nsub + (c ? naug : 0)) * op->K * KC * sizeof(half_t) +
                            2.0 * 4.0 * R * op->Kp8 * sizeof(half_t) + (d0 ? 4.0 * C.F * R * sizeof(float) : 0.0);
+  // one launch per colour, in colour order
   for (int q = 0; q < C.ncol; ++q) {
     const int64_t cnt = C.col_off[q + 1] - C.col_off[q];
     if (cnt == 0) continue;
     a.tlist = C.tlist + C.col_off[q];
-    const dim3 grid((unsigned)cnt, (unsigned)((R + 16 * CT - 1) / (16 * CT)), (unsigned)((op->Kp8 + ROWG - 1) / ROWG));
+    a.ntl = cnt;
     if (tm) {
       hipError_t e = tm->begin(st);
       if (e != hipSuccess) return e;
     }
-    switch (CT) {
-      case 1: hipLaunchKernelGGL((k_spmm16<2, 1>), grid, dim3(256), 0, st, a); break;
-      case 2: hipLaunchKernelGGL((k_spmm16<2, 2>), grid, dim3(256), 0, st, a); break;
-      case 4: hipLaunchKernelGGL((k_spmm16<2, 4>), grid, dim3(256), 0, st, a); break;
-      default: hipLaunchKernelGGL((k_spmm16<2, 8>), grid, dim3(256), 0, st, a); break;
-    }
-    hipError_t e = hipGetLastError();
+    hipError_t e = launch_spmm16(a, st);
     if (e != hipSuccess) return e;
     if (tm) {
       e = tm->end(st, tet_bytes * (double)cnt);
@@ -1539,32 +1597,12 @@ hipError_t launch_product16(dfm_op op, half_t *t, half_t *y, float *d0, int R, c
 // every tet
 hipError_t launch_plain16(dfm_op op, const half_t *x, half_t *y, int R, hipStream_t st) {
   const Coarse &C = *op->coarse;
-  P16Args a{};
-  a.B16 = reinterpret_cast<const half_t *>(op->B16);
-  a.dest = op->dest;
-  a.nt = op->nt;
-  a.K = op->K;
-  a.Kp8 = op->Kp8;
-  a.R = R;
-  a.F = C.F;
-  a.NCH = C.NCH;
-  a.R0 = C.R0;
+  P16Args a = product_args(op, R);
   a.t = x;
   a.y = y;
-  a.Pv = C.Pv;
-  a.agg_slot = C.agg_slot;
-  a.agg_up = C.agg_up;
-  a.zero16 = C.zero16;
   a.tlist = C.tlist;
-  const int CT = R <= 16 ? 1 : (R <= 32 ? 2 : (R <= 64 ? 4 : 8));
-  const dim3 grid((unsigned)op->nt, (unsigned)((R + 16 * CT - 1) / (16 * CT)), (unsigned)((op->Kp8 + ROWG - 1) / ROWG));
-  switch (CT) {
-    case 1: hipLaunchKernelGGL((k_spmm16<2, 1>), grid, dim3(256), 0, st, a); break;
-    case 2: hipLaunchKernelGGL((k_spmm16<2, 2>), grid, dim3(256), 0, st, a); break;
-    case 4: hipLaunchKernelGGL((k_spmm16<2, 4>), grid, dim3(256), 0, st, a); break;
-    default: hipLaunchKernelGGL((k_spmm16<2, 8>), grid, dim3(256), 0, st, a); break;
-  }
-  return hipGetLastError();
+  a.ntl = op->nt;
+  return launch_spmm16(a, st);
 }
 }  // namespace
 
