@@ -562,22 +562,36 @@ __global__ void k_pvt16(const float *__restrict__ Pv, int64_t nslot, int Kp8, in
 }
 
 // d0[s][f][r] = sum_{k < R0} Pv[s][k][f] t[s][r][k] (the coarse right-hand side of
-// a vector that did not come out of the product); one thread per (slot, rhs)
-__global__ void k_d0_from_t(const half_t *__restrict__ t, const float *__restrict__ Pv, int64_t nslot, int R, int Kp8,
-                            int R0, int F, float *__restrict__ d0) {
-  const int64_t tot = nslot * R;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t s = i / R;
-    const int r = (int)(i - s * R);
-    const half_t *tp = t + (s * R + r) * Kp8;
-    const float *pv = Pv + s * Kp8 * F;
-    float acc[FMAX];
-    for (int f = 0; f < FMAX; ++f) acc[f] = 0.0f;
-    for (int k = 0; k < R0; ++k) {
-      const float v = (float)tp[k];
-      for (int f = 0; f < F; ++f) acc[f] = fmaf(pv[k * F + f], v, acc[f]);
+// a vector that did not come out of the product); one workgroup per slot (grid
+// stride) with the slot's Pv in LDS, one thread per right-hand side reading its
+// run of t 16 bytes at a time
+constexpr int D0_THREADS = 128;
+__global__ __launch_bounds__(D0_THREADS) void k_d0_from_t(const half_t *__restrict__ t, const float *__restrict__ Pv,
+                                                          int64_t nslot, int R, int Kp8, int R0, int F,
+                                                          float *__restrict__ d0) {
+  __shared__ float pvs[KP8MAX * FMAX];
+  for (int64_t s = blockIdx.x; s < nslot; s += gridDim.x) {
+    __syncthreads();   // the previous slot's Pv is no longer read
+    for (int i = threadIdx.x; i < Kp8 * F; i += D0_THREADS) pvs[i] = i / F < R0 ? Pv[s * Kp8 * F + i] : 0.0f;
+    __syncthreads();
+    for (int r = threadIdx.x; r < R; r += D0_THREADS) {
+      const half_t *tp = t + (s * R + r) * Kp8;
+      float acc[FMAX];
+#pragma unroll
+      for (int f = 0; f < FMAX; ++f) acc[f] = 0.0f;
+      for (int k8 = 0; k8 < Kp8; k8 += 8) {
+        const h8 v = *reinterpret_cast<const h8 *>(tp + k8);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const float x = (float)v[u];
+          const float *pw = pvs + (k8 + u) * F;
+#pragma unroll
+          for (int f = 0; f < FMAX; ++f)
+            if (f < F) acc[f] = fmaf(pw[f], x, acc[f]);
+        }
+      }
+      for (int f = 0; f < F; ++f) d0[(s * F + f) * R + r] = acc[f];
     }
-    for (int f = 0; f < F; ++f) d0[(s * F + f) * R + r] = acc[f];
   }
 }
 
@@ -687,6 +701,9 @@ constexpr int WIN = 16;
 struct RingPtrs {
   const half_t *p[WIN];
 };
+// NW > 0: exactly NW pending terms, all loaded before the first is added (the
+// full window, most flushes); NW = 0: nwin terms one after another (stage ends)
+template <int NW>
 __global__ void k_flush(RingPtrs ring, int nwin, int64_t nslot, int Kp8, int R, int F, const float *__restrict__ W,
                         const float *__restrict__ Pv, const uint8_t *__restrict__ lmask,
                         const int32_t *__restrict__ agg_slot, const int32_t *__restrict__ agg_up,
@@ -714,10 +731,20 @@ __global__ void k_flush(RingPtrs ring, int nwin, int64_t nslot, int Kp8, int R, 
         for (int u = 0; u < 8; ++u) v[u] = fmaf(w[u * F + f], cf, v[u]);
       }
     }
-    for (int m = 0; m < nwin; ++m) {
-      const h8 x = *reinterpret_cast<const h8 *>(ring.p[m] + i);
+    if constexpr (NW > 0) {
+      h8 x[NW];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] += (float)x[u];
+      for (int m = 0; m < NW; ++m) x[m] = __builtin_nontemporal_load(reinterpret_cast<const h8 *>(ring.p[m] + i));
+#pragma unroll
+      for (int m = 0; m < NW; ++m)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] += (float)x[m][u];
+    } else {
+      for (int m = 0; m < nwin; ++m) {
+        const h8 x = *reinterpret_cast<const h8 *>(ring.p[m] + i);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] += (float)x[u];
+      }
     }
     *reinterpret_cast<f4 *>(e + i) = f4{v[0], v[1], v[2], v[3]};
     *reinterpret_cast<f4 *>(e + i + 4) = f4{v[4], v[5], v[6], v[7]};
@@ -1863,7 +1890,8 @@ dfm_status solve_twolevel_impl(dfm_op op, const double *rho0, double *rho, int R
     TRYT(hipMemcpyAsync(sc_d, scale.data(), sizeof(double) * RG, hipMemcpyHostToDevice, st));
     hipLaunchKernelGGL(k_stage_init, dim3(ew_grid(vlen)), dim3(256), 0, st, res, nslot, K, Kp8, soff_d, G, sc_d, R,
                        ring(0), e);
-    hipLaunchKernelGGL(k_d0_from_t, dim3(ew_grid(nslot * R)), dim3(256), 0, st, ring(0), C.Pv, nslot, R, Kp8, C.R0, F,
+    hipLaunchKernelGGL(k_d0_from_t, dim3((unsigned)std::min<int64_t>(nslot, 65536)), dim3(D0_THREADS), 0, st, ring(0),
+                       C.Pv, nslot, R, Kp8, C.R0, F,
                        d0);
     hipLaunchKernelGGL(k_zero_f32n, dim3(ew_grid(zn)), dim3(256), 0, st, csum, zn);
     TRYT(hipGetLastError());
@@ -1877,7 +1905,11 @@ dfm_status solve_twolevel_impl(dfm_op op, const double *rho0, double *rho, int R
       if (pending == 0 && !last) return hipSuccess;
       RingPtrs rp{};
       for (int m = 0; m < pending; ++m) rp.p[m] = ring(k - pending + m);
-      hipLaunchKernelGGL(k_flush, dim3(egrid), dim3(256), 0, st, rp, pending, nslot, Kp8, R, F,
+      if (pending == WIN)
+        hipLaunchKernelGGL(k_flush<WIN>, dim3(egrid), dim3(256), 0, st, rp, pending, nslot, Kp8, R, F,
+                         (last && level > 0) ? C.W : nullptr, C.Pv, C.lmask, C.agg_slot, C.agg_up, csum, e);
+      else
+        hipLaunchKernelGGL(k_flush<0>, dim3(egrid), dim3(256), 0, st, rp, pending, nslot, Kp8, R, F,
                          (last && level > 0) ? C.W : nullptr, C.Pv, C.lmask, C.agg_slot, C.agg_up, csum, e);
       pending = 0;
       return hipGetLastError();
