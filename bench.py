@@ -581,9 +581,10 @@ def main_uneven(args):
     Legendre of degree uniform in {4,6,8,10} with n = D + 4, 4 isotropic point
     sources per box.  Instances of one degree form one mesh (block-diagonal B,
     assembled in FP32 by one launch); one step = for every group: mesh build ->
-    FP32 assembly -> sources -> batched warm-started Neumann solve (FP32 products,
-    FP64 residuals) until every instance's own relative residual is <= 1e-8 ->
-    release.  Warmup runs the same on the first 8 boxes.  The plain FP64 reference
+    FP32 assembly -> sources -> two-level solve of the group's instances (coloured
+    sweeps with a coarse correction per instance, FP16 products of the 4 right-hand
+    sides, FP64 residuals of the FP32-stored operator) until every instance's own
+    relative residual is <= 1e-8 -> release.  Warmup runs the same on the first 8 boxes.  The plain FP64 reference
     solves a few boxes per degree one by one (FP64 assembly, FP64 Neumann per
     source); its whole-batch time is extrapolated per degree by tet count.
     `value` is assembly blocks/s over all groups."""
@@ -642,6 +643,14 @@ def main_uneven(args):
                           "B_bytes": g.op.nbytes, "product_bytes": g.op.nbytes + 16.0 * g.nsrc * g.op.ndof}))
         return
 
+    class TimedBatch(UnevenBatch):
+        """Turns on the event timing of the FP16 product launches of each group's
+        solves as soon as the group's operator exists."""
+
+        def assemble(self, g, stream=None):
+            super().assemble(g, stream=stream)
+            g.op.product_timing(1)
+
     def run(batch, label):
         """Every group once (with --overlap the next group is assembled beside the solve of
         this one); per group (mesh+assembly, sources, solve) ms and stats."""
@@ -653,7 +662,9 @@ def main_uneven(args):
 
         def on_group(g, t_solve):
             ev = g.events
+            pt_ms, pt_n, pt_b = g.op.product_timing(0)
             rows.append({"degree": g.key[2], "boxes": len(g.members), "tets": g.mesh.nt, "K": g.op.K,
+                         "product16_ms": pt_ms, "product16_launches": pt_n, "product16_bytes": pt_b,
                          "blocks": g.op.nblocks, "nodes": g.op.nodes, "B_bytes": g.op.nbytes, "nrhs": g.nsrc,
                          "ms_assemble": ev[0].elapsed_time(ev[1]), "ms_sources": ev[1].elapsed_time(ev[2]),
                          "ms_solve": t_solve, "products": g.products,
@@ -679,11 +690,11 @@ def main_uneven(args):
         return rows
 
     for _ in range(args.warmup):
-        run(UnevenBatch(probs[:8], rule=rule, dtype=1), "warmup")
+        run(TimedBatch(probs[:8], rule=rule, dtype=1), "warmup")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        batch = UnevenBatch(probs, rule=rule, dtype=1)
+        batch = TimedBatch(probs, rule=rule, dtype=1)
         rows = run(batch, "step")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -728,6 +739,23 @@ def main_uneven(args):
     flops_asm = sum(2.0 * r["nodes"] * r["K"] ** 2 for r in rows)
     for r in rows:
         r.pop("rho", None)
+    # the two rooflines of the step: the FP32 assembly (matrix cores) and the FP16
+    # product of the group solves (HBM), timed with events inside the library
+    asm_tf = flops_asm / (t_asm / 1e3) / 1e12
+    roof_asm = {"kernel": "k_assemble (dtype 1)", "bound": "mfma", "achieved": asm_tf, "peak": FP32_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": asm_tf / FP32_PEAK_TFLOPS, "traffic": None,
+                "algorithmic": "2*Q*K^2 flop per group launch, summed over the four degree groups",
+                "timed": "the mesh build + assembly events of every group (the node phase is FP64)"}
+    p16_ms = sum(r["product16_ms"] for r in rows)
+    p16_n = sum(r["product16_launches"] for r in rows)
+    p16_b = sum(r["product16_bytes"] for r in rows)
+    p16_gbs = p16_b / (p16_ms / 1e3) / 1e9 if p16_ms > 0 else 0.0
+    roof_p16 = {"kernel": "k_spmm16", "bound": "hbm", "achieved": p16_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": p16_gbs / HBM_PEAK_GBS, "traffic": None, "launches": p16_n,
+                "avg_launch_ms": p16_ms / max(p16_n, 1),
+                "algorithmic": "per tet of a launch: its 4 block rows of FP16 B (slot and correction chunks), "
+                               "x read and y written once for the 4 rhs, d0 (dfm_product_timing)",
+                "timed": "every product launch of the step's group solves, HIP events on the solve's stream"}
     out = {
         "metric": METRIC,
         "value": nblocks * args.steps / (t_asm / 1e3),
@@ -750,7 +778,8 @@ def main_uneven(args):
         "overlap": args.overlap,
         "assemble_tflops_fp32": flops_asm / (t_asm / 1e3) / 1e12,
         "solve_ms_per_rhs": t_solve / nrhs,
-        "solve_precision": "fp32 Neumann products on fp32-stored B, fp64 residuals; every box's own relres <= 1e-8; "
+        "solve_precision": "two-level sweeps per degree group (FP16 products of 4 rhs, coarse correction per "
+                           "instance), fp64 residuals of the fp32-stored B; every box's own relres <= 1e-8; "
                            "converged boxes leave the products",
         "solve_work_fraction": sum(r["work_fraction"] * r["products"] * r["tets"] for r in rows)
                                / sum(r["products"] * r["tets"] for r in rows),
@@ -761,15 +790,16 @@ def main_uneven(args):
         "solve_fp64_sample_ms": {f"D{d}": v[0] for d, v in ref.items()},
         "speedup_vs_fp64_box_by_box_est": t64_est / (t_asm + t_src + t_solve),
         "rel_diff_vs_fp64_sampled": worst_diff,
-        "roofline": {"kernel": "k_spmv_rhs<4>", "bound": "hbm", "achieved": prod_gbs, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": prod_gbs / HBM_PEAK_GBS, "traffic": None,
-                     "algorithmic": "B32 bytes + 16*R*ndof (x, y, e read+write in fp32) per launch, R = 4, "
-                                    f"degree-{big['degree']} group, every box multiplied: {prod_bytes:.3e} B",
-                     "ms_per_launch": prod_ms,
-                     "traffic_ratio_small_group": measured_traffic("k_spmv_rhs4", COUNTERS_UNEVEN, "ratio"),
-                     "traffic_note": "traffic is not measured at this size; traffic_ratio_small_group is HBM bytes / "
-                                     "algorithmic bytes of the same kernel on the degree-10 group of the first 16 boxes",
-                     "per_group_GBs": {f"D{r['degree']}": b / r["ms_product"] / 1e6 for r, b in zip(rows, pb)}},
+        "roofline": roof_asm if t_asm >= p16_ms else roof_p16,
+        "roofline_other": roof_p16 if t_asm >= p16_ms else roof_asm,
+        "streaming_product_fp32": {"kernel": "k_spmv_rhs<4>", "bound": "hbm", "achieved": prod_gbs,
+                                   "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": prod_gbs / HBM_PEAK_GBS,
+                                   "note": "the FP32 Neumann product of method 0 (not used by this step's solve), "
+                                           "five launches on the largest group with every box multiplied",
+                                   "algorithmic": f"B32 bytes + 16*R*ndof per launch, R = 4: {prod_bytes:.3e} B",
+                                   "ms_per_launch": prod_ms,
+                                   "traffic_ratio_small_group": measured_traffic("k_spmv_rhs4", COUNTERS_UNEVEN,
+                                                                                 "ratio")},
         "cpu_baseline": base,
     }
     print(json.dumps(out))
