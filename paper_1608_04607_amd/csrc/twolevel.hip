@@ -551,6 +551,227 @@ __global__ __launch_bounds__(256, 1) void k_spmm16(P16Args a) {
   }
 }
 
+// The same product for tiles of 128 right-hand sides with the operands staged in
+// LDS: every load of a step goes straight from memory into LDS (global_load_lds,
+// 16 bytes per lane, nothing held in registers while in flight), three stages
+// deep, so two steps are in flight while one is contracted.  A step's slot run of
+// x and its correction coefficients are loaded once for the workgroup (each wave
+// loads two of the eight 16-row tiles of each) instead of once per reading wave.
+// Per step: wait for this wave's loads of the step (every wave issues the same 10
+// loads per step, so the count is fixed), barrier (the other waves' loads have
+// landed, and the stage read two steps ago is free), issue the loads of the step
+// two ahead, read the fragments.  The fragment reads sit in one asm block with
+// their own wait, so the compiler neither orders them against the pending LDS
+// loads nor sees them in flight; their outputs are early-clobber, as the block
+// still reads its address registers after the first result may have landed.
+// Same arithmetic in the same order as k_spmm16, so the results are identical.
+template <int L>
+__global__ __launch_bounds__(256, 1) void k_spmm16_lds(P16Args a) {
+  constexpr int CT = 8, NS = 3;
+  constexpr int RT = ROWG / 16;
+  constexpr int NST = 4 * L;
+  constexpr int TPW = (CT + 3) / 4;                     // x tiles each wave loads per region
+  constexpr int NL = RT + 2 * TPW;                      // loads per wave per step
+  __shared__ h8 sA[NS][4][RT * 64];
+  __shared__ h8 sX[NS][2][4 * TPW * 64];                // [0] slot run, [1] correction coefficients
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int rw0 = blockIdx.y * CT * 16;
+  const int m0 = blockIdx.z * ROWG;
+  const int K = a.K, Kp8 = a.Kp8, F = a.F, R = a.R;
+  const int64_t ldr = (int64_t)R * Kp8;
+  const int nrows = min(ROWG, Kp8 - m0);
+  const int col = lane & 15, kq = lane >> 4;
+  const bool corr = a.c != nullptr;
+  const int FP = fpad(F);
+  const int brows = min(ROWG, K - m0);
+  const int nsub = (K + KC - 1) / KC;
+  const int naug = (NAUG * FP + KC - 1) / KC;
+  const int64_t P = gridDim.x;
+  const int64_t ntet = (a.ntl - (int64_t)blockIdx.x + P - 1) / P;
+  if (ntet <= 0) return;
+  const half_t *zero = a.zero16;
+  const int64_t cstride = (int64_t)K * KC;
+  const int64_t bstride = (int64_t)a.NCH * K * KC;
+  // rows of x this wave loads for the workgroup: tiles t = w + 4 u (u < TPW)
+  int xrow[TPW];
+#pragma unroll
+  for (int u = 0; u < TPW; ++u) xrow[u] = min(rw0 + (w + 4 * u) * 16 + col, R - 1);
+  struct TetL {
+    int64_t j;
+    bool act;
+    int gagg[4][NAUG];   // correction aggregates of each block row's wave
+  };
+  auto tet_info = [&](int64_t q, TetL &T) {
+    const bool v = q < ntet;
+    T.j = v ? (int64_t)a.tlist[blockIdx.x + q * P] : -1;
+    const int64_t jj = v ? T.j : 0;
+    T.act = v && (a.gact == nullptr || a.gact[a.gid[jj]] != 0);
+#pragma unroll
+    for (int lo = 0; lo < 4; ++lo) {
+#pragma unroll
+      for (int s = 0; s < 3; ++s) T.gagg[lo][s] = (v && corr) ? a.agg_up[4 * jj + in_face2(lo, s)] : 0;
+      T.gagg[lo][3] = (v && corr) ? a.agg_slot[4 * jj] : 0;
+      T.gagg[lo][4] = (v && corr) ? a.agg_slot[a.dest[4 * jj + lo]] : 0;
+    }
+  };
+  typedef __attribute__((address_space(3))) void lds_t;
+  // the loads of step it of tet T into stage st
+  auto issue = [&](const TetL &T, int it, int st) {
+    const int p = it / L, c = it - p * L;
+    const int64_t jj = T.j >= 0 ? T.j : 0;
+    // own block row's chunk: slot chunk of phase p, or a correction chunk in own phase
+    int bch = -1;
+    if (T.act) {
+      if (p != w && c < nsub) bch = (p < w ? p : p - 1) * nsub + c;
+      if (p == w && corr && c < naug) bch = 3 * nsub + c;
+    }
+    const half_t *abase = a.B16 + (4 * jj + w) * bstride + (int64_t)(m0 + col) * KC + 8 * kq;
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      const bool ok = bch >= 0 && rt * 16 + col < brows;
+      __builtin_amdgcn_global_load_lds(ok ? abase + (int64_t)bch * cstride + rt * 16 * KC : zero,
+                                       (lds_t *)&sA[st][w][rt * 64], 16, 0, 0);
+    }
+    // slot run of phase p, chunk c (read by the three waves other than p)
+    const int e = c * KC + 8 * kq;
+    const bool xs = T.act && c < nsub && e < Kp8;
+    const half_t *xsb = a.t + (4 * jj + p) * ldr + e;
+#pragma unroll
+    for (int u = 0; u < TPW; ++u)
+      __builtin_amdgcn_global_load_lds(xs ? xsb + (int64_t)xrow[u] * Kp8 : zero, (lds_t *)&sX[st][0][(w + 4 * u) * 64],
+                                       16, 0, 0);
+    // correction coefficients of wave p's groups, chunk c
+    const int g = min(e / FP, NAUG - 1);
+    const int ga = g == 0 ? T.gagg[p][0] : (g == 1 ? T.gagg[p][1] : (g == 2 ? T.gagg[p][2] : (g == 3 ? T.gagg[p][3] : T.gagg[p][4])));
+    const bool xc = T.act && corr && c < naug && e < NAUG * FP;
+    const half_t *xcb = a.c16 + (int64_t)ga * R * FP + (e - g * FP);
+#pragma unroll
+    for (int u = 0; u < TPW; ++u)
+      __builtin_amdgcn_global_load_lds(xc ? xcb + (int64_t)xrow[u] * FP : zero, (lds_t *)&sX[st][1][(w + 4 * u) * 64],
+                                       16, 0, 0);
+  };
+  f4 acc[RT][CT];
+  TetL cur, nxt;
+  tet_info(0, cur);
+  tet_info(1, nxt);
+  // prologue: steps 0 .. NS - 2 of tet 0
+#pragma unroll
+  for (int u = 0; u < NS - 1; ++u) issue(cur, u, u);
+  constexpr unsigned WAIT = (NL * (NS - 2) & 15) | (((NL * (NS - 2)) >> 4) << 14) | (7 << 4) | (15 << 8);
+  int st0 = 0;   // stage of the tet's step 0 (steps go through the stages in turn)
+  for (int64_t q = 0; q < ntet; ++q) {
+    const int64_t j = cur.j;
+    const bool act = cur.act;
+    const int64_t dslot = a.dest[4 * j + w];
+    const bool dl = a.lmask != nullptr && a.lmask[dslot] != 0;
+    const bool want_d0 = m0 == 0 && a.d0 != nullptr && !dl;
+    half_t *ybase = (dl ? const_cast<half_t *>(a.t) : a.y) + dslot * ldr + m0;
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    h4 pa[RT];
+#pragma unroll
+    for (int it = 0; it < NST; ++it) {
+      const int st = (st0 + it) % NS;
+      // this step's loads (own) have landed; the barrier makes everyone's visible
+      // and frees the stage read NS - 1 steps ago
+      __builtin_amdgcn_s_waitcnt(WAIT);
+      asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+      {
+        const int ia = it + NS - 1;
+        const int sn = (st0 + it + NS - 1) % NS;
+        if (ia < NST) issue(cur, ia, sn);
+        else issue(nxt, ia - NST, sn);
+      }
+      if (it == 0) {
+        const half_t *pv = want_d0 ? a.PvT16 + (dslot * 16 + col) * (int64_t)ROWG + 4 * kq : zero;
+        const int pstride = want_d0 ? 16 : 0;
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) pa[rt] = *reinterpret_cast<const h4 *>(pv + rt * pstride);
+      }
+      const int p = it / L;
+      h8 A[RT], X[CT];
+      {
+        // LDS byte addresses of the lane's fragments; the reads and their wait in one
+        // block, so the compiler does not order them against the pending LDS loads
+        const unsigned aad = (unsigned)(size_t)(lds_t *)&sA[st][w][lane];
+        const unsigned xad = (unsigned)(size_t)(lds_t *)&sX[st][p == w ? 1 : 0][lane];
+        asm volatile(
+            "ds_read_b128 %0, %14 offset:0\n\t"
+            "ds_read_b128 %1, %14 offset:1024\n\t"
+            "ds_read_b128 %2, %14 offset:2048\n\t"
+            "ds_read_b128 %3, %14 offset:3072\n\t"
+            "ds_read_b128 %4, %14 offset:4096\n\t"
+            "ds_read_b128 %5, %14 offset:5120\n\t"
+            "ds_read_b128 %6, %15 offset:0\n\t"
+            "ds_read_b128 %7, %15 offset:1024\n\t"
+            "ds_read_b128 %8, %15 offset:2048\n\t"
+            "ds_read_b128 %9, %15 offset:3072\n\t"
+            "ds_read_b128 %10, %15 offset:4096\n\t"
+            "ds_read_b128 %11, %15 offset:5120\n\t"
+            "ds_read_b128 %12, %15 offset:6144\n\t"
+            "ds_read_b128 %13, %15 offset:7168\n\t"
+            "s_waitcnt lgkmcnt(0)"
+            : "=&v"(A[0]), "=&v"(A[1]), "=&v"(A[2]), "=&v"(A[3]), "=&v"(A[4]), "=&v"(A[5]), "=&v"(X[0]), "=&v"(X[1]),
+              "=&v"(X[2]), "=&v"(X[3]), "=&v"(X[4]), "=&v"(X[5]), "=&v"(X[6]), "=&v"(X[7])
+            : "v"(aad), "v"(xad)
+            : "memory");
+      }
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
+          acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[rt], X[ct], acc[rt][ct], 0, 0, 0);
+    }
+    st0 = (st0 + NST) % NS;
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      const int r = rw0 + ct * 16 + col;
+      if (act && dl && a.first && r < R) {
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+          if (rt * 16 + 4 * kq < nrows) {
+            const h4 o = *reinterpret_cast<const h4 *>(ybase + (int64_t)r * Kp8 + rt * 16 + 4 * kq);
+#pragma unroll
+            for (int qq = 0; qq < 4; ++qq) acc[rt][ct][qq] += (float)o[qq];
+          }
+      }
+      h4 yh[RT];
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+        yh[rt] = act ? h4{(half_t)acc[rt][ct][0], (half_t)acc[rt][ct][1], (half_t)acc[rt][ct][2], (half_t)acc[rt][ct][3]}
+                     : h4{0, 0, 0, 0};
+      if (r < R) {
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+          if (rt * 16 + 4 * kq < nrows) *reinterpret_cast<h4 *>(ybase + (int64_t)r * Kp8 + rt * 16 + 4 * kq) = yh[rt];
+      }
+      if (m0 == 0 && a.d0 != nullptr && dl && r < R) {
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq)
+          if (4 * kq + qq < F) a.d0[(dslot * F + 4 * kq + qq) * R + r] = 0.0f;
+      }
+      if (want_d0) {
+        f4 dacc = f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) dacc = __builtin_amdgcn_mfma_f32_16x16x16f16(pa[rt], yh[rt], dacc, 0, 0, 0);
+        if (r < R) {
+#pragma unroll
+          for (int qq = 0; qq < 4; ++qq) {
+            const int f = 4 * kq + qq;
+            if (f < F) a.d0[(dslot * F + f) * R + r] = dacc[qq];
+          }
+        }
+      }
+    }
+    cur = nxt;
+    tet_info(q + 2, nxt);
+  }
+  __builtin_amdgcn_s_waitcnt(0);   // no load into LDS outlives the workgroup
+}
+
 // PvT16[s][f][k] = half(Pv[s][k][f]) for f < F and k < R0, else 0 (rows of ROWG)
 __global__ void k_pvt16(const float *__restrict__ Pv, int64_t nslot, int Kp8, int F, int R0, half_t *__restrict__ PvT) {
   const int64_t tot = nslot * 16 * ROWG;
@@ -1549,14 +1770,17 @@ hipError_t launch_spmm16(const P16Args &a, hipStream_t st) {
   const dim3 grid((unsigned)P, ny, nz);
 #define DFM_SPMM16(CTV, LV) \
   case CTV * 10 + LV: hipLaunchKernelGGL((k_spmm16<2, CTV, LV>), grid, dim3(256), 0, st, a); break;
+#define DFM_SPMM16_LDS(LV) \
+  case 80 + LV: hipLaunchKernelGGL((k_spmm16_lds<LV>), grid, dim3(256), 0, st, a); break;
   switch (CT * 10 + L) {
     DFM_SPMM16(1, 2) DFM_SPMM16(1, 3) DFM_SPMM16(1, 4) DFM_SPMM16(1, 5)
     DFM_SPMM16(2, 2) DFM_SPMM16(2, 3) DFM_SPMM16(2, 4) DFM_SPMM16(2, 5)
     DFM_SPMM16(4, 2) DFM_SPMM16(4, 3) DFM_SPMM16(4, 4) DFM_SPMM16(4, 5)
-    DFM_SPMM16(8, 2) DFM_SPMM16(8, 3) DFM_SPMM16(8, 4) DFM_SPMM16(8, 5)
+    DFM_SPMM16_LDS(2) DFM_SPMM16_LDS(3) DFM_SPMM16_LDS(4) DFM_SPMM16_LDS(5)
     default: return hipErrorInvalidValue;
   }
 #undef DFM_SPMM16
+#undef DFM_SPMM16_LDS
   return hipGetLastError();
 }
 
