@@ -479,8 +479,8 @@ def main_box32(args):
     spmm_gbs = prod_bytes / (prod_ms / 1e3) / 1e9
     flops_asm = 2.0 * nodes * K * K
     asm_tf = flops_asm / (t_asm / 1e3) / 1e12
-    roof_spmm = {"kernel": "k_spmm16", "bound": "hbm", "achieved": spmm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                 "frac": spmm_gbs / HBM_PEAK_GBS, "traffic": measured_traffic("k_spmm16", COUNTERS_B32),
+    roof_spmm = {"kernel": "k_spmm16_lds", "bound": "hbm", "achieved": spmm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                 "frac": spmm_gbs / HBM_PEAK_GBS, "traffic": measured_traffic("k_spmm16_lds", COUNTERS_B32),
                  "avg_launch_ms": launch_ms, "launches": prod_launches,
                  "algorithmic_bytes_per_launch": prod_bytes / prod_launches,
                  "algorithmic": "per tet of a launch (one colour): 4 block rows x (3 ceil(K/32) slot chunks + "
