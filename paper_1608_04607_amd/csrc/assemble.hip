@@ -871,6 +871,94 @@ __device__ __forceinline__ void contract_chunk(v4d (&acc)[CB][RB], const TA *__r
   }
 }
 
+// factor indices of basis row k (< Mp) of the Legendre family in a factor row of
+// 2 DM + 3 doubles: k = t(t+1)/2 + b, a = t - b; rows k >= M take the zero entry
+template <int DM>
+__device__ __forceinline__ void factor_index(int k, int M, int &ia, int &ib) {
+  if (k >= M) {
+    ia = ib = 2 * DM + 2;
+    return;
+  }
+  int t = 0;
+  while ((t + 1) * (t + 2) / 2 <= k) ++t;
+  const int b = k - t * (t + 1) / 2;
+  ia = t - b;
+  ib = DM + 1 + b;
+}
+
+// The same MFMAs with the Legendre family's basis rows kept as their two factors:
+// at, bt point at the lane's factor rows (2 DM + 3 doubles, stride TW) of psi' and
+// psi; a row fragment is at[ra] * at[rb], a column fragment bt[ca] * bt[cb] times
+// the spatial weight, formed while the MFMAs of the previous step run.  The
+// products round as the stored rows of contract_chunk do, so both give the same T.
+template <int R, int C, int RB, int CB, int PQ, int DM, typename TA>
+__device__ __forceinline__ void contract_chunk_sep(v4d (&acc)[CB][RB], const double *__restrict__ at,
+                                                   const double *__restrict__ bt, const TA *__restrict__ sp,
+                                                   int row0, const int (&boff)[CB], const int (&spq)[CB], int M,
+                                                   int steps, int TW) {
+  if constexpr (R > 0 && C > 0) {
+    // factor indices of the lane's rows row0 + 16 i and columns boff[c]
+    int ra[R], rb[R], ca[C], cb[C];
+#pragma unroll
+    for (int i = 0; i < R; ++i) factor_index<DM>(row0 + 16 * i, M, ra[i], rb[i]);
+#pragma unroll
+    for (int c = 0; c < C; ++c) factor_index<DM>(boff[c], M, ca[c], cb[c]);
+    typedef typename Mfma<TA>::acc_t acc_t;
+    acc_t cacc[C][R];
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        if constexpr (sizeof(TA) == 8) cacc[c][i] = acc[c][i];
+        else cacc[c][i] = acc_t{0, 0, 0, 0};
+      }
+    TA a0[R], b0[C];
+#pragma unroll
+    for (int i = 0; i < R; ++i) a0[i] = (TA)(at[ra[i]] * at[rb[i]]);
+#pragma unroll
+    for (int c = 0; c < C; ++c) b0[c] = (TA)(bt[ca[c]] * bt[cb[c]]) * sp[spq[c]];
+    const int sa = 4 * TW;
+    for (int s = 1; s < steps; ++s) {
+      at += sa;
+      bt += sa;
+      sp += 4 * PQ;
+      double ax[R], ay[R], bx[C], by[C];
+      TA s1[C];
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        ax[i] = at[ra[i]];
+        ay[i] = at[rb[i]];
+      }
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        bx[c] = bt[ca[c]];
+        by[c] = bt[cb[c]];
+        s1[c] = sp[spq[c]];
+      }
+#pragma unroll
+      for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int i = 0; i < R; ++i) cacc[c][i] = Mfma<TA>::step(a0[i], b0[c], cacc[c][i]);
+#pragma unroll
+      for (int i = 0; i < R; ++i) a0[i] = (TA)(ax[i] * ay[i]);
+#pragma unroll
+      for (int c = 0; c < C; ++c) b0[c] = (TA)(bx[c] * by[c]) * s1[c];
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        cacc[c][i] = Mfma<TA>::step(a0[i], b0[c], cacc[c][i]);
+        if constexpr (sizeof(TA) == 8) {
+          acc[c][i] = cacc[c][i];
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc[c][i][e] += (double)cacc[c][i][e];
+        }
+      }
+  }
+}
+
 // Tiles of the rectangle that fall in column tiles [t0, t1) into the LDS slab
 // Ts[(ct - t0) * 16 + column][row] (row stride Ml), in FP64.
 template <int R, int C, int RB, int CB, typename TA>
@@ -900,7 +988,7 @@ __device__ __forceinline__ float *out_blocks<float>(const AsmArgs &A) {
   return A.B32;
 }
 
-template <int RB, int CB, int PQ, int DM, typename TA>
+template <int RB, int CB, int PQ, int DM, typename TA, bool SEP>
 __global__ __launch_bounds__(NTHREADS) void k_assemble(AsmArgs A) {
   __shared__ BlockGeo G;
   __shared__ double cells[CMAX][4][3];
@@ -945,9 +1033,15 @@ __global__ __launch_bounds__(NTHREADS) void k_assemble(AsmArgs A) {
   __syncthreads();
 
   const int chunk = A.chunk;
+  // SEP (the Legendre family, launch_fam): the nodes keep the two factors of each
+  // basis row (TW doubles per node) instead of the row, so a chunk of 128 fits
+  constexpr bool sep = SEP;
+  constexpr int TW = 2 * DM + 3;
   TA *Apsi = reinterpret_cast<TA *>(dyn);   // [chunk][Mp + 1]  psi'(d')
   TA *Bpsi = Apsi + chunk * Ml;              // [chunk][Mp + 1]  psi(d)
-  TA *Sw = Apsi + 2 * chunk * Ml;            // [chunk][PQ]  W S
+  double *Af = dyn;                          // [chunk][TW]  factors of psi'(d')
+  double *Bf = dyn + chunk * TW;             // [chunk][TW]  factors of psi(d)
+  TA *Sw = sep ? reinterpret_cast<TA *>(dyn + 2 * chunk * TW) : Apsi + 2 * chunk * Ml;   // [chunk][PQ]  W S
   const int Q = __builtin_amdgcn_readfirstlane(G.ncells * n * n);
   const int WR = A.wr_waves, WC = 8 / WR;
   const int wr = wave / WC, wc = wave - (wave / WC) * WC;
@@ -988,28 +1082,41 @@ __global__ __launch_bounds__(NTHREADS) void k_assemble(AsmArgs A) {
 #pragma unroll
           for (int i = 0; i < PQ; ++i) Sw[ql * PQ + i] = (TA)sw[i];
         } else if (role == 1) {
-          TA *o = Bpsi + ql * Ml;
-          if (D == DM)
-            momentum_row<DM, false, true, TA>(dot3(d, G.xin), dot3(d, G.yin), dot3(d, G.zin), D, A.family, thom, o);
-          else
-            momentum_row<DM, false, false, TA>(dot3(d, G.xin), dot3(d, G.yin), dot3(d, G.zin), D, A.family, thom, o);
-          for (int k = M; k < Mp; ++k) o[k] = (TA)0;
+          const double fx = dot3(d, G.xin), fy = dot3(d, G.yin), fz = dot3(d, G.zin);
+          if constexpr (sep) {
+            double *o = Bf + ql * TW;
+            if (D == DM) momentum_factors<DM, true>(fx, fy, fz, D, o);
+            else momentum_factors<DM, false>(fx, fy, fz, D, o);
+          } else {
+            TA *o = Bpsi + ql * Ml;
+            if (D == DM) momentum_row<DM, false, true, TA>(fx, fy, fz, D, A.family, thom, o);
+            else momentum_row<DM, false, false, TA>(fx, fy, fz, D, A.family, thom, o);
+            for (int k = M; k < Mp; ++k) o[k] = (TA)0;
+          }
         } else {
           double dd[3] = {d[0], d[1], d[2]};
           if (!G.transmit) {
             double dn = dot3(d, G.nrm[l_out]);
             for (int i = 0; i < 3; ++i) dd[i] = d[i] - 2.0 * dn * G.nrm[l_out][i];
           }
-          TA *o = Apsi + ql * Ml;
-          if (D == DM)
-            momentum_row<DM, false, true, TA>(dot3(dd, G.xd), dot3(dd, G.yd), dot3(dd, G.zd), D, A.family, thom, o);
-          else
-            momentum_row<DM, false, false, TA>(dot3(dd, G.xd), dot3(dd, G.yd), dot3(dd, G.zd), D, A.family, thom, o);
-          for (int k = M; k < Mp; ++k) o[k] = (TA)0;
+          const double fx = dot3(dd, G.xd), fy = dot3(dd, G.yd), fz = dot3(dd, G.zd);
+          if constexpr (sep) {
+            double *o = Af + ql * TW;
+            if (D == DM) momentum_factors<DM, true>(fx, fy, fz, D, o);
+            else momentum_factors<DM, false>(fx, fy, fz, D, o);
+          } else {
+            TA *o = Apsi + ql * Ml;
+            if (D == DM) momentum_row<DM, false, true, TA>(fx, fy, fz, D, A.family, thom, o);
+            else momentum_row<DM, false, false, TA>(fx, fy, fz, D, A.family, thom, o);
+            for (int k = M; k < Mp; ++k) o[k] = (TA)0;
+          }
         }
       } else {
         if (role == 0) {
           for (int i = 0; i < PQ; ++i) Sw[ql * PQ + i] = (TA)0;
+        } else if (sep) {
+          double *o = (role == 1 ? Bf : Af) + ql * TW;
+          for (int k = 0; k < TW; ++k) o[k] = 0.0;
         } else if (role == 1) {
           for (int k = 0; k < Mp; ++k) Bpsi[ql * Ml + k] = (TA)0;
         } else {
@@ -1022,7 +1129,16 @@ __global__ __launch_bounds__(NTHREADS) void k_assemble(AsmArgs A) {
     const TA *ap = Apsi + qrow * Ml + r0 * 16 + col;
     const TA *bp = Bpsi + qrow * Ml;
     const TA *sp = Sw + qrow * PQ;
-    if (rb == RB) {
+    if constexpr (sep) {
+      const double *at = Af + qrow * TW, *bt = Bf + qrow * TW;
+      if (rb == RB) {
+        if (cb == CB) contract_chunk_sep<RB, CB, RB, CB, PQ, DM, TA>(acc, at, bt, sp, r0 * 16 + col, boff, spq, M, steps, TW);
+        else contract_chunk_sep<RB, CB - 1, RB, CB, PQ, DM, TA>(acc, at, bt, sp, r0 * 16 + col, boff, spq, M, steps, TW);
+      } else {
+        if (cb == CB) contract_chunk_sep<RB - 1, CB, RB, CB, PQ, DM, TA>(acc, at, bt, sp, r0 * 16 + col, boff, spq, M, steps, TW);
+        else contract_chunk_sep<RB - 1, CB - 1, RB, CB, PQ, DM, TA>(acc, at, bt, sp, r0 * 16 + col, boff, spq, M, steps, TW);
+      }
+    } else if (rb == RB) {
       if (cb == CB) contract_chunk<RB, CB, RB, CB, PQ, TA>(acc, ap, bp, sp, boff, spq, steps, Ml);
       else contract_chunk<RB, CB - 1, RB, CB, PQ, TA>(acc, ap, bp, sp, boff, spq, steps, Ml);
     } else {
@@ -1340,9 +1456,9 @@ __global__ void k_dest(const int32_t *nbr, int64_t nslot, int32_t *dest) {
   dest[s] = (k >= 0) ? k : (int32_t)s;
 }
 
-template <int RB, int CB, int PQ, int DM, typename TA>
+template <int RB, int CB, int PQ, int DM, typename TA, bool SEP>
 hipError_t launch_t(const AsmArgs &a, size_t lds, hipStream_t st) {
-  auto kern = k_assemble<RB, CB, PQ, DM, TA>;
+  auto kern = k_assemble<RB, CB, PQ, DM, TA, SEP>;
   hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   unsigned grid = (unsigned)(a.nblocks * a.nsplit);
@@ -1365,10 +1481,24 @@ hipError_t launch_t(const AsmArgs &a, size_t lds, hipStream_t st) {
 constexpr int SHAPES[][4] = {DFM_SHAPES(DFM_SHAPE_ROW)};
 constexpr int NSHAPES = sizeof(SHAPES) / sizeof(SHAPES[0]);
 
+// The factor-row node layout (SEP) for the Legendre family with one position pair
+// and degree bound 16 (D >= 13), where full basis rows leave room for only 32
+// nodes per chunk.  Below that the rows fit 64 or 128 nodes, and the rows win:
+// forming the fragments costs the contraction five FP64 multiplies per step,
+// which the FP64 matrix cores do not hide (timed at 1.1-1.5x slower for D = 4-12,
+// 3x faster at D = 14 and 1.14x at D = 16).  With P1 the rows are kept.
+template <int RB, int CB, int PQ, int DM, typename TA>
+hipError_t launch_fam(const AsmArgs &a, size_t lds, hipStream_t st) {
+  if constexpr (PQ == 1 && DM == 16) {
+    if (a.family == 0) return launch_t<RB, CB, PQ, DM, TA, true>(a, lds, st);
+  }
+  return launch_t<RB, CB, PQ, DM, TA, false>(a, lds, st);
+}
+
 hipError_t launch_shape(int shape, bool fp32, const AsmArgs &a, size_t lds, hipStream_t st) {
   int idx = 0;
 #define DFM_SHAPE_CASE(r, c, pq, d) \
-  if (shape == idx++) return fp32 ? launch_t<r, c, pq, d, float>(a, lds, st) : launch_t<r, c, pq, d, double>(a, lds, st);
+  if (shape == idx++) return fp32 ? launch_fam<r, c, pq, d, float>(a, lds, st) : launch_fam<r, c, pq, d, double>(a, lds, st);
   DFM_SHAPES(DFM_SHAPE_CASE)
 #undef DFM_SHAPE_CASE
   return hipErrorInvalidValue;
@@ -1661,10 +1791,17 @@ extern "C" dfm_status dfm_assemble(dfm_mesh mesh, const dfm_basis *basis, const 
   DFM_REQUIRE(!cands.empty(), DFM_E_UNSUPPORTED, "no contraction layout for this basis size");
   for (TileLayout &c : cands) c.shape = exact_shape(c.shape, PQ, D);
   TileLayout lay = cands[0];
-  // nodes per chunk: two halves of 64 when the LDS allows
+  // nodes per chunk: two halves of 64 when the LDS allows; the Legendre family
+  // with one position pair and degree bound 16 keeps two factor rows per node
+  // (launch_fam), so 128 fit
   int chunk;
   size_t lds;
   block_layout(Mp, PQ, chunk, lds);
+  if (bs.mom_family == 0 && PQ == 1 && D > 12) {
+    chunk = 128;
+    const size_t lds_f = sizeof(double) * (size_t)(2 * chunk * (2 * DMAX + 3) + chunk * PQ);
+    lds = lds_f > lds ? lds_f : lds;
+  }
 
   dfm_op op = new dfm_op_s();
   op->mesh = mesh;

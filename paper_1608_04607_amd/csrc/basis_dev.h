@@ -32,6 +32,34 @@ __device__ __forceinline__ void legendre_table(double x, int D, double *p) {
   }
 }
 
+// The two one-dimensional factors of the Legendre family at a direction with frame
+// components (dx, dy, dz): out[a] = p_a(2 dz - 1) and out[DM + 1 + b] =
+// sqrt(2b+1) P_b(phi/pi - 1) for a, b <= D, zero up to DM and in out[2 DM + 2], so
+// that psi_(a,b) = out[a] * out[DM + 1 + b] is the value momentum_row stores (the
+// same expressions in the same order, hence the same rounding), and index 2 DM + 2
+// gives 0 for padding rows.  2 DM + 3 doubles.
+template <int DM, bool EXACT = false>
+__device__ __forceinline__ void momentum_factors(double dx, double dy, double dz, int D_, double *__restrict__ out) {
+  const int D = EXACT ? DM : D_;
+  double phi = atan2(dy, dx);
+  if (phi < 0.0) phi += 2.0 * M_PI;
+  if (fabs(dy) <= SEAM_SNAP && dx > 0.0) phi = 0.0;
+  double px[DM + 1];
+  legendre_table<DM>(2.0 * dz - 1.0, D, px);
+  const double y = phi * (1.0 / M_PI) - 1.0;
+  double Pb = 1.0, Pbm1 = 0.0;  // P_b(y), P_{b-1}(y)
+#pragma unroll
+  for (int b = 0; b <= DM; ++b) {
+    const bool on = b <= D;
+    out[b] = on ? px[b] : 0.0;
+    out[DM + 1 + b] = on ? sqrt(2.0 * b + 1.0) * Pb : 0.0;
+    const double Pn = ((2.0 * b + 1.0) / (b + 1.0)) * y * Pb - (b / (b + 1.0)) * Pbm1;
+    Pbm1 = Pb;
+    Pb = Pn;
+  }
+  out[2 * DM + 2] = 0.0;
+}
+
 // One row of the momentum basis at a direction with frame components (dx, dy, dz):
 // out[k] = psi_k, or (G^-1 psi)_k when GINV, for k < M = (D+1)(D+2)/2, D <= DM.
 // Every loop is unrolled to the compile-time bound DM, so the basis values stay

@@ -179,6 +179,10 @@ CASES = [
     ("box1-p0-leg10-n6-seam", (1, 0.1), 0.1, oa.Basis(0, 0, 10, 6, oq.SEAM_RULE)),
     ("box1-p1-leg10-n4-paper", (1, 0.1), 0.1, oa.Basis(1, 0, 10, 4, oq.PAPER_RULE)),
     ("box1-p0-zern10-n5-seam", (1, 0.2), 0.4, oa.Basis(0, 1, 10, 5, oq.SEAM_RULE)),
+    # degrees 13..16 with P0 x Legendre: the nodes keep the two factors of each
+    # basis row and the contraction forms the fragments (128 nodes per chunk)
+    ("box1-p0-leg14-n4-seam-factors", (1, 0.1), 0.2, oa.Basis(0, 0, 14, 4, oq.SEAM_RULE)),
+    ("box2-p0-leg13-n3-paper-factors", (2, 0.15), 1.5, oa.Basis(0, 0, 13, 3, oq.PAPER_RULE)),
 ]
 
 
@@ -800,7 +804,7 @@ def test_solve_groups_matches_oracle():
     op.close()
 
 
-@pytest.mark.parametrize("order,family,degree", [(1, 0, 8), (0, 1, 6), (0, 0, 10), (0, 0, 4)])
+@pytest.mark.parametrize("order,family,degree", [(1, 0, 8), (0, 1, 6), (0, 0, 10), (0, 0, 4), (0, 0, 14)])
 def test_fp32_assembly_matches_oracle(order, family, degree):
     """dtype 1: contraction on the FP32 matrix cores, B stored in FP32 -- blocks within
     1e-5 of the oracle (relative to the largest entry), and the mixed solves refine
