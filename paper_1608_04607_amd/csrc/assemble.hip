@@ -1456,10 +1456,20 @@ __global__ void k_dest(const int32_t *nbr, int64_t nslot, int32_t *dest) {
   dest[s] = (k >= 0) ? k : (int32_t)s;
 }
 
+// LDS of one workgroup, and the static LDS arrays of k_assemble (frames, cells,
+// quadrature rule, Thomas tables, moment series) with room for their alignment
+constexpr size_t LDS_BYTES = 160 * 1024;
+constexpr size_t ASM_STATIC_LDS = sizeof(BlockGeo) + sizeof(double) * (CMAX * 12 + 64 + 3 * (DMAX + 1) * (DMAX + 1) +
+                                                                       NMOM * NSERIES) + 256;
+
 template <int RB, int CB, int PQ, int DM, typename TA, bool SEP>
 hipError_t launch_t(const AsmArgs &a, size_t lds, hipStream_t st) {
   auto kern = k_assemble<RB, CB, PQ, DM, TA, SEP>;
-  hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipFuncAttributes fa;
+  hipError_t e = hipFuncGetAttributes(&fa, (const void *)kern);
+  if (e != hipSuccess) return e;
+  if (fa.sharedSizeBytes + lds > LDS_BYTES) return hipErrorInvalidConfiguration;   // the chunk does not fit
+  e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   unsigned grid = (unsigned)(a.nblocks * a.nsplit);
   hipLaunchKernelGGL(kern, dim3(grid), dim3(NTHREADS), lds, st, a);
@@ -1666,6 +1676,22 @@ inline void block_layout(int Mp, int PQ, int &chunk, size_t &lds) {
   lds = lds_nodes > lds_clip ? lds_nodes : lds_clip;
 }
 
+// node-chunk length and dynamic LDS bytes of k_assemble with basis rows of ta
+// bytes per entry: the most directions (a multiple of 4, at most the two halves of
+// 64) whose rows and weights fit beside the static arrays.  The node phase takes
+// about as long for 92 directions as for 64 (each node wave runs one dependent
+// chain per lane, and the second half's waves run beside the first's on the same
+// SIMDs), so the longest chunk that fits is the cheapest per direction.
+inline void assemble_layout(int Mp, int PQ, size_t ta, int &chunk, size_t &lds) {
+  const size_t per = ta * (size_t)(2 * (Mp + 1) + PQ);
+  size_t c = (LDS_BYTES - ASM_STATIC_LDS) / per;
+  c = c >= 128 ? 128 : (c & ~(size_t)3);
+  chunk = (int)c;
+  lds = per * c;
+  const size_t lds_clip = sizeof(double) * CELL_WORK;
+  lds = lds_clip > lds ? lds_clip : lds;
+}
+
 AsmArgs op_args(dfm_op op, const double *mu, unsigned *flags) {
   dfm_mesh mesh = op->mesh;
   AsmArgs a{};
@@ -1791,12 +1817,13 @@ extern "C" dfm_status dfm_assemble(dfm_mesh mesh, const dfm_basis *basis, const 
   DFM_REQUIRE(!cands.empty(), DFM_E_UNSUPPORTED, "no contraction layout for this basis size");
   for (TileLayout &c : cands) c.shape = exact_shape(c.shape, PQ, D);
   TileLayout lay = cands[0];
-  // nodes per chunk: two halves of 64 when the LDS allows; the Legendre family
-  // with one position pair and degree bound 16 keeps two factor rows per node
-  // (launch_fam), so 128 fit
+  // nodes per chunk: as many as the LDS holds, up to two halves of 64; the
+  // Legendre family with one position pair and degree bound 16 keeps two factor
+  // rows per node (launch_fam), so 128 fit
   int chunk;
   size_t lds;
-  block_layout(Mp, PQ, chunk, lds);
+  assemble_layout(Mp, PQ, bs.dtype == 1 ? sizeof(float) : sizeof(double), chunk, lds);
+  DFM_REQUIRE(chunk >= 4, DFM_E_UNSUPPORTED, "basis rows too long for the LDS");
   if (bs.mom_family == 0 && PQ == 1 && D > 12) {
     chunk = 128;
     const size_t lds_f = sizeof(double) * (size_t)(2 * chunk * (2 * DMAX + 3) + chunk * PQ);
