@@ -745,7 +745,7 @@ def main_uneven(args):
     roof_asm = {"kernel": "k_assemble (dtype 1)", "bound": "mfma", "achieved": asm_tf, "peak": FP32_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": asm_tf / FP32_PEAK_TFLOPS, "traffic": None,
                 "algorithmic": "2*Q*K^2 flop per group launch, summed over the four degree groups",
-                "timed": "the mesh build + assembly events of every group (the node phase is FP64)"}
+                "timed": "the mesh build + assembly events of every group (basis rows FP32, node geometry FP64)"}
     p16_ms = sum(r["product16_ms"] for r in rows)
     p16_n = sum(r["product16_launches"] for r in rows)
     p16_b = sum(r["product16_bytes"] for r in rows)
@@ -767,7 +767,7 @@ def main_uneven(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 contraction and storage (f64 geometry, basis, Gram solve); f32 products, f64 residuals",
+        "dtype": "f32 basis rows, contraction and storage (f64 geometry, weights, Gram solve); f32 products, f64 residuals",
         "data": "synthetic",
         "config": {"workload": f"uneven-{len(probs)}-boxes-(1,U[1,4],U[1,4])-logU[500,20000]tets-jitter0.2"
                                f"_P0xLegendreD{{4,6,8,10}}_n=D+4_{args.rule}-rule_mu-U[0,0.1]_R0.9"

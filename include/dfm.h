@@ -72,9 +72,10 @@ typedef struct {
                      1: those regions cut at the momentum-basis seams and around both
                         poles, each cell touching a pole fanned from it                 */
   int dtype;      /* 0: B assembled and stored in FP64;
-                     1: node geometry, basis values and the Gram solve in FP64, the
-                        contraction over the directions on the FP32 matrix cores and
-                        B stored in FP32 only (half the memory).  Products and
+                     1: node geometry, spatial weights and the Gram solve in FP64,
+                        the basis values in FP32, the contraction over the
+                        directions on the FP32 matrix cores (FP64 sums per chunk)
+                        and B stored in FP32 only (half the memory).  Products and
                         residuals still accumulate in FP64; transposed products
                         (and so dfm_adjoint) need dtype 0 (DFM_E_UNSUPPORTED).        */
 } dfm_basis;

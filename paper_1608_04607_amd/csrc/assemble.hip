@@ -959,6 +959,21 @@ __device__ __forceinline__ void contract_chunk_sep(v4d (&acc)[CB][RB], const dou
   }
 }
 
+// One basis row of a node for k_assemble: in FP64 for an FP64 operator, in FP32
+// (momentum_row_f32) when B is stored in FP32; compiled for the degree itself when
+// D equals the bound DM.
+template <int DM, typename TA>
+__device__ __forceinline__ void node_row(double fx, double fy, double fz, int D, int family, const double *thom,
+                                         TA *o) {
+  if constexpr (sizeof(TA) == 8) {
+    if (D == DM) momentum_row<DM, false, true, TA>(fx, fy, fz, D, family, thom, o);
+    else momentum_row<DM, false, false, TA>(fx, fy, fz, D, family, thom, o);
+  } else {
+    if (D == DM) momentum_row_f32<DM, true>(fx, fy, fz, D, family, o);
+    else momentum_row_f32<DM, false>(fx, fy, fz, D, family, o);
+  }
+}
+
 // Tiles of the rectangle that fall in column tiles [t0, t1) into the LDS slab
 // Ts[(ct - t0) * 16 + column][row] (row stride Ml), in FP64.
 template <int R, int C, int RB, int CB, typename TA>
@@ -1089,8 +1104,7 @@ __global__ __launch_bounds__(NTHREADS) void k_assemble(AsmArgs A) {
             else momentum_factors<DM, false>(fx, fy, fz, D, o);
           } else {
             TA *o = Bpsi + ql * Ml;
-            if (D == DM) momentum_row<DM, false, true, TA>(fx, fy, fz, D, A.family, thom, o);
-            else momentum_row<DM, false, false, TA>(fx, fy, fz, D, A.family, thom, o);
+            node_row<DM, TA>(fx, fy, fz, D, A.family, thom, o);
             for (int k = M; k < Mp; ++k) o[k] = (TA)0;
           }
         } else {
@@ -1106,8 +1120,7 @@ __global__ __launch_bounds__(NTHREADS) void k_assemble(AsmArgs A) {
             else momentum_factors<DM, false>(fx, fy, fz, D, o);
           } else {
             TA *o = Apsi + ql * Ml;
-            if (D == DM) momentum_row<DM, false, true, TA>(fx, fy, fz, D, A.family, thom, o);
-            else momentum_row<DM, false, false, TA>(fx, fy, fz, D, A.family, thom, o);
+            node_row<DM, TA>(fx, fy, fz, D, A.family, thom, o);
             for (int k = M; k < Mp; ++k) o[k] = (TA)0;
           }
         }

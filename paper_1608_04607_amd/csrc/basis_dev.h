@@ -161,6 +161,86 @@ __device__ __forceinline__ void momentum_row(double dx, double dy, double dz, in
   }
 }
 
+// The row of momentum_row (no Gram solve) computed in FP32, for operators stored
+// in FP32: the same recurrences with float arithmetic (the frame components and
+// the seam test stay FP64).  Entries carry about 1e-7 relative error instead of
+// the one rounding to FP32 of the FP64 row, well inside the 1e-5 the FP32-stored
+// operator is held to.
+template <int DM, bool EXACT = false>
+__device__ __forceinline__ void momentum_row_f32(double dx_, double dy_, double dz_, int D_, int family,
+                                                 float *__restrict__ out) {
+  const int D = EXACT ? DM : D_;
+  const float dx = (float)dx_, dy = (float)dy_, dz = (float)dz_;
+  if (family == 0) {
+    float phi = atan2f(dy, dx);
+    if (phi < 0.0f) phi += (float)(2.0 * M_PI);
+    if (fabs(dy_) <= SEAM_SNAP && dx_ > 0.0) phi = 0.0f;
+    float px[DM + 1];
+    {
+      const float x = 2.0f * dz - 1.0f;
+      float pm1 = 1.0f, pc = x;
+      px[0] = 1.0f;
+#pragma unroll
+      for (int a = 1; a <= DM; ++a) {
+        if (a > D) break;
+        px[a] = (float)sqrt(2.0 * a + 1.0) * pc;
+        const float pn = (float)((2.0 * a + 1.0) / (a + 1.0)) * x * pc - (float)(a / (a + 1.0)) * pm1;
+        pm1 = pc;
+        pc = pn;
+      }
+    }
+    const float y = phi * (float)(1.0 / M_PI) - 1.0f;
+    float Pb = 1.0f, Pbm1 = 0.0f;
+#pragma unroll
+    for (int b = 0; b <= DM; ++b) {
+      if (b > D) break;
+      const int N = D - b;
+      const float qb = (float)sqrt(2.0 * b + 1.0) * Pb;
+#pragma unroll
+      for (int a = 0; a <= DM - b; ++a)
+        if (a <= N) out[(a + b) * (a + b + 1) / 2 + b] = px[a] * qb;
+      const float Pn = (float)((2.0 * b + 1.0) / (b + 1.0)) * y * Pb - (float)(b / (b + 1.0)) * Pbm1;
+      Pbm1 = Pb;
+      Pb = Pn;
+    }
+  } else {
+    const float tt = 2.0f * (dx * dx + dy * dy) - 1.0f;
+    float cm = 1.0f, sm = 0.0f;
+#pragma unroll
+    for (int m = 0; m <= DM; ++m) {
+      if (m <= D) {
+        float pkm1 = 0.0f, pk = 1.0f;
+#pragma unroll
+        for (int k = 0; 2 * k + m <= DM; ++k) {
+          const int n = m + 2 * k;
+          if (n <= D) {
+            if (k == 1) {
+              pkm1 = pk;
+              pk = 1.0f + (float)((m + 2.0) * 0.5) * (tt - 1.0f);
+            } else if (k >= 2) {
+              const double kk = k, mm = m;
+              const double a1 = 2.0 * kk * (kk + mm) * (2.0 * kk + mm - 2.0);
+              const double a2 = (2.0 * kk + mm - 1.0) * (2.0 * kk + mm) * (2.0 * kk + mm - 2.0);
+              const double a2c = (2.0 * kk + mm - 1.0) * mm * mm;
+              const double a3 = 2.0 * (kk + mm - 1.0) * (kk - 1.0) * (2.0 * kk + mm);
+              const float pn = ((float)(a2 / a1) * tt - (float)(a2c / a1)) * pk - (float)(a3 / a1) * pkm1;
+              pkm1 = pk;
+              pk = pn;
+            }
+            const int base = n * (n + 1) / 2;
+            out[base + (m + n) / 2] = pk * cm;
+            if (m > 0) out[base + (n - m) / 2] = pk * sm;
+          }
+        }
+      }
+      const float cn = cm * dx - sm * dy;
+      const float sn = cm * dy + sm * dx;
+      cm = cn;
+      sm = sn;
+    }
+  }
+}
+
 // psi' premultiplied by G^-1 (in place on out[0..M))
 __device__ void apply_gram_inverse(double *out, int D, int family, const double *thom) {
   if (family == 1) {
