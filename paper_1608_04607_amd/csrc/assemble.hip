@@ -105,7 +105,8 @@ struct AsmArgs {
   int P, D, M, Mp, K, Kp, n, family, rule;
   int chunk;
   // contraction layout: nsplit workgroups per block share the column tiles;
-  // inside one, the 8 waves form a wr_waves x (8 / wr_waves) grid of rectangles
+  // inside one, the 8 waves form a wr_waves x (8 / wr_waves) grid of rectangles,
+  // or (wr_waves 0) one quadrant per SIMD (wave_rect)
   int nsplit, row_tiles, col_tiles, wr_waves, slab_tiles;
 };
 
@@ -799,15 +800,41 @@ __global__ __launch_bounds__(CELL_THREADS) void k_cells(AsmArgs A) {
 // The kernel: 8 waves.  Node phase: wave w takes role w % 4 (0 geometry and S,
 // 1 psi, 2 psi', 3 idle) for the nodes of half w / 4 of the chunk.
 // Contraction: the output T (Mp rows x PQ Mp columns, 16 x 16 tiles) is cut into
-// nsplit column ranges, one per workgroup; wave w owns the rectangle of row
-// range w / WC and column range w % WC of its workgroup's range (balanced
-// partitions, WC = 8 / wr_waves, so a wave's rectangle is RB or RB - 1 rows by
-// CB or CB - 1 columns).  Per 4 nodes a wave loads each of its row fragments and
+// nsplit column ranges, one per workgroup; wave w owns the rectangle wave_rect
+// gives it in its workgroup's range (a cell of a wr_waves x (8 / wr_waves) grid of
+// balanced partitions, or half of its SIMD's quadrant), RB or RB - 1 rows by CB or
+// CB - 1 columns.  Per 4 nodes a wave loads each of its row fragments and
 // column fragments once and issues rows x cols MFMAs.
 // Epilogue: T goes through LDS in slabs of column tiles, where one thread per
 // column applies the weight and G^-1 (the Galerkin solve of Eq. Bapprox), and
 // leaves as contiguous column segments of the block.
 // ---------------------------------------------------------------------------
+
+// The rectangle of output tiles of wave w (r0, rb rows from the R row tiles; c0, cb
+// columns from the ncs column tiles starting at cs0).  WR = 1, 2, 4, 8: the waves
+// form a WR x (8 / WR) grid of balanced partitions.  WR = 0: SIMD quadrants -- waves
+// w and w + 4 share SIMD w % 4, and each SIMD takes one quadrant of the rows x
+// columns, its first wave the first half (rounded up) of the quadrant's columns
+// and its second wave the rest, so the four SIMDs get equal matrix-core work
+// where the grid gives two of them twice that of the others (6 x 6 tiles: 9 tiles
+// per SIMD against 6 and 12).
+__host__ __device__ inline void wave_rect(int WR, int w, int R, int cs0, int ncs, int &r0, int &rb, int &c0,
+                                          int &cb) {
+  if (WR == 0) {
+    const int s = w & 3, h = w >> 2, rh = s >> 1, ch = s & 1;
+    r0 = (rh * R) / 2;
+    rb = ((rh + 1) * R) / 2 - r0;
+    const int q0 = cs0 + (ch * ncs) / 2, qc = cs0 + ((ch + 1) * ncs) / 2 - q0, first = (qc + 1) / 2;
+    c0 = h == 0 ? q0 : q0 + first;
+    cb = h == 0 ? first : qc - first;
+    return;
+  }
+  const int WC = 8 / WR, wr = w / WC, wc = w % WC;
+  r0 = (wr * R) / WR;
+  rb = ((wr + 1) * R) / WR - r0;
+  c0 = cs0 + (wc * ncs) / WC;
+  cb = cs0 + ((wc + 1) * ncs) / WC - c0;
+}
 
 // The MFMAs of one chunk for an R x C rectangle (compile-time); the fragments of
 // step s + 1 are loaded while the MFMAs of step s run.  ap, bp, sp point at the
@@ -1058,12 +1085,10 @@ __global__ __launch_bounds__(NTHREADS) void k_assemble(AsmArgs A) {
   double *Bf = dyn + chunk * TW;             // [chunk][TW]  factors of psi(d)
   TA *Sw = sep ? reinterpret_cast<TA *>(dyn + 2 * chunk * TW) : Apsi + 2 * chunk * Ml;   // [chunk][PQ]  W S
   const int Q = __builtin_amdgcn_readfirstlane(G.ncells * n * n);
-  const int WR = A.wr_waves, WC = 8 / WR;
-  const int wr = wave / WC, wc = wave - (wave / WC) * WC;
   const int cs0 = (split * A.col_tiles) / A.nsplit, cs1 = ((split + 1) * A.col_tiles) / A.nsplit;
   const int ncs = cs1 - cs0;
-  const int r0 = (wr * A.row_tiles) / WR, rb = ((wr + 1) * A.row_tiles) / WR - r0;
-  const int c0 = cs0 + (wc * ncs) / WC, cb = cs0 + ((wc + 1) * ncs) / WC - c0;
+  int r0, rb, c0, cb;
+  wave_rect(A.wr_waves, wave, A.row_tiles, cs0, ncs, r0, rb, c0, cb);
   const int role = wave & 3;
   const int half = wave >> 2;
   const int col = lane & 15;
@@ -1547,17 +1572,15 @@ std::vector<TileLayout> layout_candidates(int R, int C, int pq, int dm) {
   std::vector<Cand> all;
   int first = 0;
   for (int nsplit = 1; nsplit <= C && (first == 0 || nsplit <= first + 2); ++nsplit) {
-    for (int WR : {1, 2, 4, 8}) {
-      const int WC = 8 / WR;
+    for (int WR : {0, 1, 2, 4, 8}) {
       int rbmax = 0, cbmax = 0, rbmin = 1 << 30, cbmin = 1 << 30;
       int simd_mfma[4] = {0, 0, 0, 0}, simd_load[4] = {0, 0, 0, 0};
       for (int split = 0; split < nsplit; ++split) {
         const int cs0 = (split * C) / nsplit, ncs = ((split + 1) * C) / nsplit - cs0;
         int sm[4] = {0, 0, 0, 0}, sl[4] = {0, 0, 0, 0};
         for (int w = 0; w < 8; ++w) {
-          const int wr = w / WC, wc = w % WC;
-          const int rb = ((wr + 1) * R) / WR - (wr * R) / WR;
-          const int cb = ((wc + 1) * ncs) / WC - (wc * ncs) / WC;
+          int r0, rb, c0, cb;
+          wave_rect(WR, w, R, cs0, ncs, r0, rb, c0, cb);
           rbmax = rb > rbmax ? rb : rbmax;
           cbmax = cb > cbmax ? cb : cbmax;
           rbmin = rb < rbmin ? rb : rbmin;
@@ -1672,7 +1695,7 @@ hipError_t tune_layout(const TuneKey &key, const std::vector<TileLayout> &cand, 
     fprintf(stderr, "dfm: layout for R=%d C=%d PQ=%d D=%d dtype=%d n=%d:", key.R, key.C, key.PQ, key.D, key.dtype,
             key.n);
     for (int i = 0; i < nc; ++i)
-      fprintf(stderr, " [%dx%d rect, %d split, %d wave rows] %.3f ms%s", SHAPES[cand[i].shape][0],
+      fprintf(stderr, " [%dx%d rect, %d split, %d wave rows (0: SIMD quadrants)] %.3f ms%s", SHAPES[cand[i].shape][0],
               SHAPES[cand[i].shape][1], cand[i].nsplit, cand[i].wr_waves, ms[i], i == 0 ? " (search)" : "");
     fprintf(stderr, " -> %dx%d, %d split\n", SHAPES[chosen.shape][0], SHAPES[chosen.shape][1], chosen.nsplit);
   }

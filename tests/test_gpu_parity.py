@@ -209,23 +209,24 @@ def test_assembly_matches_oracle(name, meshspec, mu, bs):
     assert berr < BLOCK_TOL
 
 
-@pytest.mark.parametrize("order,dtype", [(1, 0), (0, 1)])
-def test_assembly_independent_of_layout(order, dtype, monkeypatch):
+@pytest.mark.parametrize("order,dtype,degree", [(1, 0, 8), (0, 1, 8), (0, 0, 12)])
+def test_assembly_independent_of_layout(order, dtype, degree, monkeypatch):
     """Every contraction layout sums each entry over the same directions in the
     same order: B is bit-identical whichever candidate layout runs (the autotuner
-    only changes speed)."""
+    only changes speed).  At D = 12 with P0 (6 x 6 output tiles) the candidates
+    include the SIMD-quadrant layout and the wave grids."""
     from paper_1608_04607_amd import dfm
-    say(f"[assemble] layout independence P{order} dtype {dtype}")
+    say(f"[assemble] layout independence P{order} dtype {dtype} D{degree}")
     v, t, refl = box(2, 0.15, seed=6)
     mu = torch.full((t.shape[0],), 0.3, dtype=torch.float64, device=DEV)
     mesh = gpu_mesh(v, t, refl)
     out = []
-    for k in ("0", "1"):
+    for k in ("0", "1", "2"):
         monkeypatch.setenv("DFM_LAYOUT", k)
-        op = dfm.Operator(mesh, mu, order, dfm.LEGENDRE, 8, 4, rule=oq.SEAM_RULE, dtype=dtype)
+        op = dfm.Operator(mesh, mu, order, dfm.LEGENDRE, degree, 4, rule=oq.SEAM_RULE, dtype=dtype)
         out.append(op.export()[0].cpu().numpy())
         op.close()
-    assert np.array_equal(out[0], out[1])
+    assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
 
 
 def test_assembly_max_degree_p1_split():
