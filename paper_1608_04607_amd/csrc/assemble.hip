@@ -106,7 +106,7 @@ struct AsmArgs {
   int chunk;
   // contraction layout: nsplit workgroups per block share the column tiles;
   // inside one, the 8 waves form a wr_waves x (8 / wr_waves) grid of rectangles,
-  // or (wr_waves 0) one quadrant per SIMD (wave_rect)
+  // or (wr_waves 0) one quadrant per SIMD, or (wr_waves 16) two row bands (wave_rect)
   int nsplit, row_tiles, col_tiles, wr_waves, slab_tiles;
 };
 
@@ -817,9 +817,21 @@ __global__ __launch_bounds__(CELL_THREADS) void k_cells(AsmArgs A) {
 // columns, its first wave the first half (rounded up) of the quadrant's columns
 // and its second wave the rest, so the four SIMDs get equal matrix-core work
 // where the grid gives two of them twice that of the others (6 x 6 tiles: 9 tiles
-// per SIMD against 6 and 12).
+// per SIMD against 6 and 12).  WR = 16: row bands -- waves w < 4 take the top
+// ceil(R/2) rows, waves w >= 4 the rest, each band's columns cut in four balanced
+// parts, the bottom band's in reverse order, so that a SIMD pairs a narrow part of
+// one band with a wide part of the other (5 x 5 tiles: at most 8 per SIMD against
+// 9 for the quadrants and 10 for the grids).
 __host__ __device__ inline void wave_rect(int WR, int w, int R, int cs0, int ncs, int &r0, int &rb, int &c0,
                                           int &cb) {
+  if (WR == 16) {
+    const int s = w & 3, h = w >> 2, rtop = (R + 1) / 2, k = h == 0 ? s : 3 - s;
+    r0 = h == 0 ? 0 : rtop;
+    rb = h == 0 ? rtop : R - rtop;
+    c0 = cs0 + (k * ncs) / 4;
+    cb = cs0 + ((k + 1) * ncs) / 4 - c0;
+    return;
+  }
   if (WR == 0) {
     const int s = w & 3, h = w >> 2, rh = s >> 1, ch = s & 1;
     r0 = (rh * R) / 2;
@@ -1572,7 +1584,7 @@ std::vector<TileLayout> layout_candidates(int R, int C, int pq, int dm) {
   std::vector<Cand> all;
   int first = 0;
   for (int nsplit = 1; nsplit <= C && (first == 0 || nsplit <= first + 2); ++nsplit) {
-    for (int WR : {0, 1, 2, 4, 8}) {
+    for (int WR : {0, 16, 1, 2, 4, 8}) {
       int rbmax = 0, cbmax = 0, rbmin = 1 << 30, cbmin = 1 << 30;
       int simd_mfma[4] = {0, 0, 0, 0}, simd_load[4] = {0, 0, 0, 0};
       for (int split = 0; split < nsplit; ++split) {
@@ -1607,6 +1619,19 @@ std::vector<TileLayout> layout_candidates(int R, int C, int pq, int dm) {
       if (first == 0) first = nsplit;
       all.push_back(Cand{TileLayout{nsplit, WR, shape}, mm, ml});
     }
+  }
+  // row bands only where they give the busiest SIMD less work than the quadrants
+  // (5 x 5 tiles); where both balance equally the quadrants measured faster
+  {
+    std::vector<Cand> kept;
+    for (const Cand &x : all) {
+      bool drop = false;
+      if (x.lay.wr_waves == 16)
+        for (const Cand &y : all)
+          if (y.lay.wr_waves == 0 && y.lay.nsplit == x.lay.nsplit && y.mm <= x.mm) drop = true;
+      if (!drop) kept.push_back(x);
+    }
+    all.swap(kept);
   }
   std::stable_sort(all.begin(), all.end(), [](const Cand &x, const Cand &y) {
     if (x.lay.nsplit != y.lay.nsplit) return x.lay.nsplit < y.lay.nsplit;
@@ -1695,7 +1720,7 @@ hipError_t tune_layout(const TuneKey &key, const std::vector<TileLayout> &cand, 
     fprintf(stderr, "dfm: layout for R=%d C=%d PQ=%d D=%d dtype=%d n=%d:", key.R, key.C, key.PQ, key.D, key.dtype,
             key.n);
     for (int i = 0; i < nc; ++i)
-      fprintf(stderr, " [%dx%d rect, %d split, %d wave rows (0: SIMD quadrants)] %.3f ms%s", SHAPES[cand[i].shape][0],
+      fprintf(stderr, " [%dx%d rect, %d split, %d wave rows (0: SIMD quadrants, 16: row bands)] %.3f ms%s", SHAPES[cand[i].shape][0],
               SHAPES[cand[i].shape][1], cand[i].nsplit, cand[i].wr_waves, ms[i], i == 0 ? " (search)" : "");
     fprintf(stderr, " -> %dx%d, %d split\n", SHAPES[chosen.shape][0], SHAPES[chosen.shape][1], chosen.nsplit);
   }

@@ -209,12 +209,13 @@ def test_assembly_matches_oracle(name, meshspec, mu, bs):
     assert berr < BLOCK_TOL
 
 
-@pytest.mark.parametrize("order,dtype,degree", [(1, 0, 8), (0, 1, 8), (0, 0, 12)])
+@pytest.mark.parametrize("order,dtype,degree", [(1, 0, 8), (0, 1, 8), (0, 0, 12), (0, 1, 10)])
 def test_assembly_independent_of_layout(order, dtype, degree, monkeypatch):
     """Every contraction layout sums each entry over the same directions in the
     same order: B is bit-identical whichever candidate layout runs (the autotuner
-    only changes speed).  At D = 12 with P0 (6 x 6 output tiles) the candidates
-    include the SIMD-quadrant layout and the wave grids."""
+    only changes speed).  At D = 12 and D = 10 with P0 (6 x 6 and 5 x 5 output
+    tiles) the candidates include the row-band and SIMD-quadrant layouts and the
+    wave grids."""
     from paper_1608_04607_amd import dfm
     say(f"[assemble] layout independence P{order} dtype {dtype} D{degree}")
     v, t, refl = box(2, 0.15, seed=6)
